@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the MORSE map-build + trajectory-search hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic input of the large workload
+(s=0.8, q=5e-3): ray shooting of 32768^2 rays into a 2048^2 count map, normalisation
+and rho=2e-3 disk convolution, the batched (persistent, graph-replayed) chi-square
+search of the 64x64x16x8 = 524288-trajectory grid against a 3000-point light curve
+with a top-4096 selection, and 50 L-BFGS rounds on those 4096 candidates.
+
+value = grid-search light-curve point-evaluations per second of the whole step (the
+map build and the refinement are charged to the same clock).  The JSON line also
+carries rays/s of the ray kernel, the batched and plain search rates, the adjoint
+rate, the roofline of the dominant kernel and the CPU oracle timed on this host.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic lane-operations per unit (one FP32/FP64 add, mul, compare, floor,
+# convert, divide or square root = 1; derivation in the design notes):
+OPS_PER_RAY = 31          # lattice point, Eq. 2 with two divisions, bin rule, count
+OPS_PER_POINT_EVAL = 37   # tau, zeta, grid coordinate, cell, bilinear, 3 FP64 sums
+OPS_PER_ADJOINT_EVAL = 87  # pass 1 as the search + pass 2 (sample, residual, 6 sums)
+# 256 CUs x 64 lanes x 2.4 GHz: one lane-operation per lane per clock (FP32 or FP64).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
+# copy-kernel calibration), keyed by the SHA-256 of the kernel source it was taken on.
+TRAFFIC = {}
+
+
+def kernel_sha(name):
+    path = os.path.join(ROOT, "paper_1511_01157_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--top-k", type=int, default=4096)
+    ap.add_argument("--refine-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(c, ev, axes, P_sample_every=128, rows=8192, n_refine=2):
+    """The oracle as it stands, on a bounded sample of one step, scaled to the step."""
+    import numpy as np
+    import workloads as W
+    from oracle.lbfgs import LbfgsOptions, refine
+    from oracle.maps import disk_pixel_weights, map_scale, normalize_convolve_mirror32
+    from oracle.rays import rayshoot_mirror32_c
+    from oracle.search import grid_params, search_mirror32
+
+    nthreads = max(1, min(16, os.cpu_count() or 1))
+    ny = c["rays"][5]
+    j0 = ny // 2 - rows // 2
+    t = time.perf_counter()
+    rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], rows=(j0, j0 + rows), nthreads=nthreads)
+    t_rays = (time.perf_counter() - t) * ny / rows
+    counts, _ = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], rows=(j0, j0 + 64), nthreads=nthreads)
+    dx = c["window"][2] / c["window"][4]
+    t = time.perf_counter()
+    amap = normalize_convolve_mirror32(counts, map_scale(c["rays"], c["window"]), disk_pixel_weights(c["rho"], dx, dx))
+    t_norm = time.perf_counter() - t
+    P = grid_params(*axes)
+    sample = P[::P_sample_every]
+    t = time.perf_counter()
+    search_mirror32(amap, c["window"], ev["tt"], ev["F"], ev["w"], sample, ev["t_ref"])
+    t_search = (time.perf_counter() - t) * len(P) / len(sample)
+    cand = P[:: len(P) // n_refine][:n_refine]
+    t = time.perf_counter()
+    refine(amap, c["window"], ev["tt"], ev["F"], ev["w"], ev["t_ref"], cand, LbfgsOptions(steps=50))
+    t_refine = (time.perf_counter() - t) * 4096 / n_refine
+    t_step = t_rays + t_norm + t_search + t_refine
+    evals = len(P) * len(ev["tt"])
+    return {
+        "value": evals / t_step, "unit": "point-evals/s", "cores": nthreads, "kind": "oracle",
+        "sample": (f"large workload step scaled from: C FP32-mirror ray shooting of {rows} of "
+                   f"{ny} lattice rows on {nthreads} threads ({t_rays:.1f} s scaled), numpy "
+                   f"normalise/convolve of the 2048^2 map ({t_norm:.2f} s), numpy binary32 "
+                   f"search of every {P_sample_every}th grid trajectory ({len(sample)} of "
+                   f"{len(P)}, {t_search:.1f} s scaled), L-BFGS of {n_refine} of 4096 "
+                   f"candidates ({t_refine:.1f} s scaled); numpy parts single-threaded"),
+        "step_s": t_step,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the path shards per map or per ray row, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1511_01157_amd as M
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    c = W.config("large")
+    ev = W.load_lightcurve("large")
+    axes = W.grid_axes("large")
+    n_traj = int(np.prod([len(a) for a in axes]))
+    n_pts = len(ev["tt"])
+    k = args.top_k
+    rays_per_step = c["rays"][4] * c["rays"][5]
+    evals_per_step = n_traj * n_pts
+
+    with torch.cuda.stream(stream):
+        lcs = M.LightCurveBatch.from_events([ev], dev)
+        trajs = M.grid_trajectories(*axes)
+        counts = torch.empty((c["window"][5], c["window"][4]), dtype=torch.int32, device=dev)
+        amap = torch.empty((c["window"][5], c["window"][4]), dtype=torch.float32, device=dev)
+        maps = [(amap, c["window"])]
+        ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
+                   for _ in range(args.steps)]
+
+        def step(evs=None):
+            mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
+            mark(0)
+            M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts)
+            mark(1)
+            M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap)
+            mark(2)
+            r = M.search(maps, lcs, trajs, "batched", chi2=False, top_k=k)
+            mark(3)
+            P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1)
+            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps)
+            mark(4)
+            return r, out, chi2, chi2_0
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        wall0 = time.perf_counter()
+        for i in range(args.steps):
+            res = step(ev_sets[i])
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_step = t_start.elapsed_time(t_end) / args.steps
+        stage = np.mean([[e[j].elapsed_time(e[j + 1]) for j in range(4)] for e in ev_sets], axis=0)
+        r, out, chi2, chi2_0 = res
+        improved = float((chi2 <= chi2_0).float().mean())
+
+        plain_ms = None
+        if not args.no_plain:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
+            e0.record(stream)
+            for _ in range(3):
+                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            plain_ms = e0.elapsed_time(e1) / 3
+
+    rays_ms, norm_ms, search_ms, refine_ms = stage
+    adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
+    stages = {"rayshoot": (rays_ms, OPS_PER_RAY * rays_per_step),
+              "search_batched": (search_ms, OPS_PER_POINT_EVAL * evals_per_step),
+              "refine": (refine_ms, OPS_PER_ADJOINT_EVAL * adjoint_evals)}
+    dom = max(stages, key=lambda s: stages[s][0])
+    dom_ms, dom_ops = stages[dom]
+    kfile = {"rayshoot": "maps.hip", "search_batched": "search.hip", "refine": "refine.hip"}[dom]
+    traffic = TRAFFIC.get((dom, kernel_sha(kfile)))
+    achieved = dom_ops / (dom_ms * 1e-3) / 1e12
+    line = {
+        "metric": "light-curve point-evals/s (chi2 search) + rays/s (map build); batched vs plain",
+        "value": evals_per_step / (ms_step * 1e-3),
+        "unit": "point-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 samples, f64 sums",
+        "data": "synthetic (seeded light curve, oracle-computed magnifications)",
+        "config": {"workload": "large: s=0.8 q=5e-3, 32768^2 rays -> 2048^2 map, rho=2e-3, "
+                               "3000-point light curve, 524288-trajectory grid, top-4096 + 50 L-BFGS rounds",
+                   "rays": rays_per_step, "map": [c["window"][5], c["window"][4]],
+                   "n_traj": n_traj, "n_points": n_pts, "top_k": k,
+                   "refine_rounds": args.refine_steps, "parallelism": "single GPU"},
+        "stages_ms": {"rayshoot": rays_ms, "normalize_convolve": norm_ms,
+                      "search_batched": search_ms, "candidates_refine": refine_ms},
+        "rays_per_s": rays_per_step / (rays_ms * 1e-3),
+        "search_point_evals_per_s": {"batched": evals_per_step / (search_ms * 1e-3),
+                                     "plain": evals_per_step / (plain_ms * 1e-3) if plain_ms else None},
+        "adjoint_point_evals_per_s_upper": adjoint_evals / (refine_ms * 1e-3),
+        "refine_improved_fraction": improved,
+        "wall_s_timed": wall,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / (PEAK_LANE_OPS / 1e12), "traffic": traffic,
+                     "op_note": "lane-ops: one FP32/FP64 add, mul, compare, floor, cvt, div "
+                                "or sqrt per lane; peak 256 CU x 64 lanes x 2.4 GHz"},
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(c, ev, axes)
+        cb.pop("step_s")
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,255 @@
+/*
+ * morse.h -- C ABI of the MI355X (gfx950) map-build and trajectory-search library.
+ *
+ * Method: McDougall & Albrow (2015), "Microlensing Observations Rapid Search for
+ * Exoplanets: MORSE code for GPUs".  The library builds a source-plane
+ * magnification map of one binary lens by inverse ray shooting and searches source
+ * trajectories over it, scoring each against a light curve.
+ *
+ * Conventions shared by every entry point
+ *   - Units: angles on the sky in Einstein radii, times in days.
+ *   - Lens placement (sec. 4.1): centre of mass at the origin, both masses on the x
+ *     axis; separation s (the paper's d), mass ratio q = m2/m1 in [0, 1]; the primary
+ *     m1 = 1/(1+q) sits at x1 = -s q/(1+q), the secondary at x2 = s/(1+q).
+ *   - Pointers prefixed d_ are device memory on the context's device, h_ host memory.
+ *     All buffers are owned by the caller; the library only reads h_ memory during
+ *     the call.  The context owns a workspace it grows on demand.
+ *   - Work is enqueued on the context's stream and is asynchronous unless stated.
+ *   - Every entry point returns MORSE_OK (0) or a negative status; arguments are
+ *     validated on the host before anything is enqueued, and a failing call
+ *     enqueues nothing.  morse_last_error() gives a message.  Nothing aborts.
+ *   - Not thread safe per context: use one context per host thread.
+ */
+#ifndef MORSE_H
+#define MORSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MORSE_ABI_VERSION 1
+
+enum morse_status {
+  MORSE_OK = 0,
+  MORSE_EINVAL = -1,       /* invalid argument (message says which) */
+  MORSE_ENOMEM = -2,       /* device workspace allocation failed */
+  MORSE_EHIP = -3,         /* a HIP runtime call failed */
+  MORSE_ERANGE = -4,       /* a size limit would be exceeded (e.g. counts > 2^24) */
+  MORSE_EUNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+typedef struct morse_ctx morse_ctx;
+
+/* A regular 2-D grid: centre (cx, cy), full widths (wx, wy), nx x ny cells, both
+ * counts even and >= 2, widths finite and > 0.  Cell i spans
+ * [cx - wx/2 + i wx/nx, cx - wx/2 + (i+1) wx/nx). */
+typedef struct {
+  double cx, cy, wx, wy;
+  int32_t nx, ny;
+} morse_grid2d;
+
+int morse_abi_version(void);
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to enqueue on
+ * (NULL: the context creates its own stream at default priority). */
+int morse_ctx_create(int device, void* stream, morse_ctx** out);
+/* Frees the workspace and the own stream (after synchronising it).  NULL is a no-op. */
+int morse_ctx_destroy(morse_ctx* ctx);
+/* Enqueue later work on `stream` (NULL: the device's null stream); waits for the
+ * previous stream first when it changes. */
+int morse_ctx_set_stream(morse_ctx* ctx, void* stream);
+/* Blocks until all work enqueued on the context's stream has finished. */
+int morse_ctx_synchronize(morse_ctx* ctx);
+/* Message of the last failing call on ctx (ctx == NULL: on this host thread). */
+const char* morse_last_error(const morse_ctx* ctx);
+
+/* ------------------------------------------------------------------------------
+ * Map build (ray-shooting magnification maps, sec. 3; lens equation Eq. 2;
+ * finite-source convolution, sec. 4.1).
+ * --------------------------------------------------------------------------- */
+
+/* Ray statistics of one build.  rays_in + rays_out + rays_nonfinite = rays_total;
+ * rays_zero_axis counts binned rays that landed exactly on the window's horizontal
+ * centre line (they break the exact mirror symmetry of the counts). */
+typedef struct {
+  uint64_t rays_total, rays_in, rays_out, rays_nonfinite, rays_zero_axis;
+  uint32_t max_count;
+  uint32_t reserved;
+} morse_map_stats;
+
+/* Inverse ray shooting (Eq. 2) of lattice rows [row_begin, row_end) of `rays` (the
+ * image-plane lattice: ray (i, j) at cx + (i - nx/2 + 1/2) wx/nx, likewise y) into
+ * the uint32 histogram d_counts[window.ny][window.nx] (row-major, y rows).
+ * Arithmetic: binary32 without fused multiply-add and with correctly rounded
+ * division, constants rounded once from FP64; bin rule symmetric about the window
+ * centre (v = (zeta - c) nx/wx; v >= 0 -> nx/2 + floor(v), v < 0 ->
+ * nx/2 - 1 - floor(-v), |v| >= nx/2 outside).  Counts are exact integers in any
+ * launch order.  accumulate = 0 clears d_counts first.  d_stats (nullable, device
+ * uint64[3]) accumulates {out of window, non-finite, on the centre line}.
+ * Errors: EINVAL for bad grids, s <= 0, q outside [0, 1], bad row range. */
+int morse_rayshoot(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
+                   const morse_grid2d* window, int32_t row_begin, int32_t row_end,
+                   uint32_t* d_counts, int32_t accumulate, uint64_t* d_stats);
+
+/* Normalise counts to magnification and convolve with a uniform disk of radius rho
+ * (sec. 4.1 convolution with a source profile).  A = scale * sum_k w_k c_{p+k}, with
+ * scale = (hx hy)/(dx dy) (lattice cell over pixel area, hx the binary32 lattice
+ * spacing) and w_k = area(disk(rho) ∩ pixel k)/(pi rho^2) renormalised to sum 1;
+ * taps row-major over the stencil, neighbours beyond the edge clamp to the edge
+ * pixel.  rho <= half a pixel reduces to A = c * scale.  Output float
+ * d_map[window.ny][window.nx].  Errors: EINVAL (rho < 0 or not finite), ERANGE
+ * (stencil wider than 31 pixels). */
+int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const morse_grid2d* rays,
+                             const morse_grid2d* window, double rho, float* d_map);
+
+/* build_map(s, q, window, rays): morse_rayshoot over all rows, then
+ * morse_normalize_convolve.  d_counts may be NULL (workspace is used).  h_stats
+ * (nullable) is filled after the context's stream is synchronised; max_count > 2^24
+ * returns ERANGE (the FP32 normalisation would no longer be exact). */
+int morse_build_map(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
+                    const morse_grid2d* window, double rho, uint32_t* d_counts, float* d_map,
+                    morse_map_stats* h_stats);
+
+/* ------------------------------------------------------------------------------
+ * Trajectory search (sec. 4.2: chi-square of each trajectory through a map by
+ * bilinear interpolation; Eqs. 5-6: flux linear in magnification, so F_s and F_b are
+ * profiled out by weighted least squares).
+ * --------------------------------------------------------------------------- */
+
+/* One map: device pointer to float[window.ny][window.nx] and its source-plane grid. */
+typedef struct {
+  const float* d_map;
+  morse_grid2d window;
+} morse_map_view;
+
+/* Light curves of n_events events, concatenated (CSR).  Event e owns points
+ * [h_offsets[e], h_offsets[e+1]), at least 3 each, times non-decreasing.
+ * d_t: binary32 offsets t - h_t_ref[e]; d_flux: FP64 flux; d_weight: FP64
+ * w = 1/sigma^2 > 0.  h_offsets and h_t_ref are host arrays. */
+typedef struct {
+  int32_t n_events;
+  int32_t reserved;
+  const int64_t* h_offsets;
+  const double* h_t_ref;
+  const float* d_t;
+  const double* d_flux;
+  const double* d_weight;
+} morse_lightcurves;
+
+enum { MORSE_TRAJ_GRID = 0, MORSE_TRAJ_LIST = 1 };
+
+/* Trajectories (t0, u0, tE, alpha): zeta(t) = tau (cos a, sin a) + u0 (-sin a, cos a),
+ * tau = (t - t0)/tE, tE > 0.
+ * GRID: product of host FP64 axes, shared by all events, trajectory index
+ *   ((iu0 * n_alpha + ia) * n_t0 + it0) * n_tE + itE; t0 absolute.
+ * LIST: n trajectories per event, device FP64 rows (t0, u0, tE, alpha); shared = 1:
+ *   one list [n][4] for all events; shared = 0: [n_events][n][4]. */
+typedef struct {
+  int32_t kind;
+  int32_t n_u0, n_alpha, n_t0, n_tE;
+  int32_t shared;
+  const double* h_u0;
+  const double* h_alpha;
+  const double* h_t0;
+  const double* h_tE;
+  int64_t n;
+  const double* d_params;
+} morse_trajectories;
+
+/* Outputs, each nullable; n_traj = trajectories per event.
+ *   d_chi2, d_fs, d_fb:      [n_events][n_maps][n_traj] chi2 and profiled F_s, F_b;
+ *   d_best_chi2, d_best_idx: [n_events][n_maps] smallest (chi2, trajectory index);
+ *   top_k > 0: d_topk_chi2, d_topk_idx [n_events][top_k], the top_k smallest
+ *     (chi2, map * n_traj + traj) of each event in ascending order (NaN last).
+ * chi2 = sum w (F - F_s A - F_b)^2 at the unconstrained minimiser (F_s, F_b); when
+ * det = S_AA S_w - S_A^2 <= 1e-12 S_AA S_w, F_s = 0 and F_b = S_F/S_w. */
+typedef struct {
+  double* d_chi2;
+  double* d_fs;
+  double* d_fb;
+  double* d_best_chi2;
+  int64_t* d_best_idx;
+  int32_t top_k;
+  int32_t reserved;
+  double* d_topk_chi2;
+  int64_t* d_topk_idx;
+} morse_search_out;
+
+enum { MORSE_SEARCH_PLAIN = 0, MORSE_SEARCH_BATCHED = 1 };
+
+/* search(map, lightcurve, traj_grid) over n_maps maps and all events.
+ * PLAIN: one launch per (event, map).  BATCHED: one persistent launch over a work
+ * queue of (event, map, trajectory block) items, captured once into a HIP graph
+ * per argument set and replayed; tile shapes from the context's autotune table.
+ * Both modes give bitwise identical results.  Errors: EINVAL (shapes, null
+ * pointers, w <= 0 is not checked on device), EUNSUPPORTED (top_k > 4096). */
+int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                 const morse_lightcurves* lcs, const morse_trajectories* trajs, int32_t mode,
+                 morse_search_out* out);
+
+/* Autotune the batched search on this problem: times the candidate tile /
+ * trajectory-block shapes, keeps the fastest in the context (used by later BATCHED
+ * searches of the same shape class) and, if cache_path is not NULL, merges it into
+ * that JSON file.  Synchronises.  h_best_config (nullable) receives the index. */
+int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                   const morse_lightcurves* lcs, const morse_trajectories* trajs,
+                   const char* cache_path, int32_t* h_best_config);
+
+/* Candidates from a top-k result (sec. 4.4: the best grid solutions seed the next
+ * stage): for every event e and rank r, the trajectory d_topk_idx[e][r] =
+ * map * n_traj + traj of `trajs` is written as FP64 row d_params[e*top_k + r] =
+ * (t0, u0, tE, alpha) with d_event = e and d_map_index = map.  Ranks with index -1
+ * (events with fewer than top_k trajectories) get trajectory 0 of map 0.
+ * Errors: EINVAL (shapes, NULL pointers). */
+int morse_candidates_from_topk(morse_ctx* ctx, const morse_trajectories* trajs, int32_t n_events,
+                               int32_t n_maps, int32_t top_k, const int64_t* d_topk_idx,
+                               double* d_params, int32_t* d_event, int32_t* d_map_index);
+
+/* ------------------------------------------------------------------------------
+ * Gradient and refinement (candidates from the search refined on their maps).
+ * --------------------------------------------------------------------------- */
+
+/* chi2 and d chi2/d (t0, u0, tE, alpha) of n candidates: d_params [n][4] FP64
+ * natural parameters, candidate i on map d_map_index[i] for event d_event[i].
+ * Gradient by the envelope theorem (F_s, F_b are exact minimisers):
+ * -2 F_s sum w r dA/dtheta, r = F - F_s A - F_b, through the bilinear sample (or the
+ * single-lens magnification off the map).  Samples as in morse_search; sums FP64.
+ * Outputs (device, nullable): d_chi2 [n], d_grad [n][4], d_fs [n], d_fb [n]. */
+int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, int64_t n, const double* d_params,
+                    const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
+                    double* d_grad, double* d_fs, double* d_fb);
+
+typedef struct {
+  int32_t steps;    /* evaluation rounds after the initial one (e.g. 50) */
+  int32_t history;  /* L-BFGS memory m, 1..16 */
+  int32_t max_ls;   /* failed Armijo trials before a candidate stops */
+  int32_t reserved;
+  double c1;        /* Armijo constant, in (0, 1) */
+  double shrink;    /* step reduction per failed trial, in (0, 1) */
+} morse_lbfgs_opts;
+
+/* refine(...): batched L-BFGS on p (binary32), the scaled displacement from each
+ * candidate's start (t0 = t0_i + p0 tE_i, u0 = u0_i + p1, tE = tE_i exp(p2),
+ * alpha = alpha_i + p3), with FP64 chi2 and gradients from the adjoint above.  One
+ * round = one evaluation of every active candidate, then one update: round 0 accepts
+ * p = 0; later rounds accept the trial if f_t <= f + c1 t (g.d) (storing the pair
+ * s = p_t - p, y = g_t - g when s.y > 1e-12 |s||y|), else halve-by-`shrink` the
+ * step t, stopping the candidate after max_ls failures.  After an accept the new
+ * direction is the two-loop recursion d = -H g with H0 = (s.y / y.y) I of the newest
+ * pair, or -(1e-2/|g|) g with no pairs or no descent; t = 1, p_t = fl32(p + t d).
+ * Dot products are left-to-right FP64 without fused multiply-add.  d_params
+ * [n][4] FP64 is read as the start and overwritten with the refined parameters;
+ * d_chi2_out [n] receives the final chi2, d_chi2_init [n] (nullable) the initial. */
+int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                 const morse_lightcurves* lcs, int64_t n, double* d_params,
+                 const int32_t* d_event, const int32_t* d_map_index,
+                 const morse_lbfgs_opts* opts, double* d_chi2_out, double* d_chi2_init);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MORSE_H */

@@ -1,0 +1,329 @@
+"""Python binding of the gfx950 MORSE map-build / trajectory-search library.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libmorse.so`` (C ABI in ``include/morse.h``).  PyTorch provides device memory and
+streams.  There is no CPU fallback; importing works without a GPU, calling does not.
+
+Entry points (same names as the C ABI):
+  build_map(s, q, rays, window, rho)        ray-shooting magnification map (float32)
+  rayshoot / normalize_convolve             the two stages of build_map
+  search(maps, lcs, trajs, mode)            chi-square of every trajectory on every map
+  autotune(maps, lcs, trajs)                pick the batched-search tile shape
+  chi2_grad(maps, lcs, params, ev, mi)      chi-square and its gradient
+  refine(maps, lcs, params, ev, mi)         batched L-BFGS refinement
+  Chi2Fn                                    torch.autograd.Function over chi2_grad
+Grids are tuples (cx, cy, wx, wy, nx, ny).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut, Trajectories,
+                   SEARCH_BATCHED, SEARCH_PLAIN, TRAJ_GRID, TRAJ_LIST)
+
+__all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
+           "normalize_convolve", "search", "autotune", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "grid_trajectories", "list_trajectories", "abi_version"]
+
+
+class MorseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"morse error {code}: {msg}")
+        self.code = code
+
+
+def abi_version() -> int:
+    return _abi.load().morse_abi_version()
+
+
+def _grid(g) -> Grid2D:
+    cx, cy, wx, wy, nx, ny = g
+    return Grid2D(float(cx), float(cy), float(wx), float(wy), int(nx), int(ny))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context per device, enqueuing on torch's current stream."""
+
+    _by_device: dict = {}
+
+    def __init__(self, device: int):
+        lib = _abi.load()
+        self.device = device
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib.morse_ctx_create(device, ctypes.c_void_p(stream or None), ctypes.byref(handle))
+        if rc != 0:
+            raise MorseError(rc, lib.morse_last_error(None).decode())
+        self.handle = handle
+        self.stream = stream
+        self.lib = lib
+
+    @classmethod
+    def get(cls, device) -> "Context":
+        dev = torch.device(device).index if not isinstance(device, int) else device
+        dev = torch.cuda.current_device() if dev is None else dev
+        ctx = cls._by_device.get(dev)
+        if ctx is None:
+            ctx = cls._by_device[dev] = Context(dev)
+        ctx.follow_stream()
+        return ctx
+
+    def follow_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self.stream:
+            self.check(self.lib.morse_ctx_set_stream(self.handle, ctypes.c_void_p(s or None)))
+            self.stream = s
+
+    def check(self, rc):
+        if rc != 0:
+            raise MorseError(rc, self.lib.morse_last_error(self.handle).decode())
+
+    def synchronize(self):
+        self.check(self.lib.morse_ctx_synchronize(self.handle))
+
+
+def _device_of(t):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.device.index
+
+
+# ----------------------------------------------------------------------------- maps
+def rayshoot(s, q, rays, window, counts, rows=None, accumulate=False, stats=None):
+    """Ray counts of lattice rows ``rows`` (default all) into ``counts`` (uint32 as int32)."""
+    ctx = Context.get(_device_of(counts))
+    r0, r1 = rows if rows is not None else (0, int(rays[5]))
+    ctx.check(ctx.lib.morse_rayshoot(ctx.handle, float(s), float(q), ctypes.byref(_grid(rays)),
+                                     ctypes.byref(_grid(window)), int(r0), int(r1), _ptr(counts),
+                                     int(bool(accumulate)), _ptr(stats)))
+    return counts
+
+
+def normalize_convolve(counts, rays, window, rho=0.0, out=None):
+    ctx = Context.get(_device_of(counts))
+    if out is None:
+        out = torch.empty((int(window[5]), int(window[4])), dtype=torch.float32, device=counts.device)
+    ctx.check(ctx.lib.morse_normalize_convolve(ctx.handle, _ptr(counts), ctypes.byref(_grid(rays)),
+                                               ctypes.byref(_grid(window)), float(rho), _ptr(out)))
+    return out
+
+
+def build_map(s, q, rays, window, rho=0.0, device="cuda", out=None, counts=None, stats=False):
+    """Magnification map float32[ny, nx]; with stats=True also a dict of ray statistics."""
+    dev = torch.device(device)
+    if out is None:
+        out = torch.empty((int(window[5]), int(window[4])), dtype=torch.float32, device=dev)
+    ctx = Context.get(_device_of(out))
+    st = MapStats() if stats else None
+    ctx.check(ctx.lib.morse_build_map(ctx.handle, float(s), float(q), ctypes.byref(_grid(rays)),
+                                      ctypes.byref(_grid(window)), float(rho), _ptr(counts),
+                                      _ptr(out), ctypes.byref(st) if st is not None else None))
+    if stats:
+        return out, {k: int(getattr(st, k)) for k, _ in MapStats._fields_ if k != "reserved"}
+    return out
+
+
+# --------------------------------------------------------------------------- search
+@dataclass
+class LightCurveBatch:
+    """Concatenated light curves: device t (float32 offsets), flux, weight (float64)."""
+    t: torch.Tensor
+    flux: torch.Tensor
+    weight: torch.Tensor
+    offsets: np.ndarray  # host int64 [n_events + 1]
+    t_ref: np.ndarray    # host float64 [n_events]
+
+    @classmethod
+    def from_events(cls, events, device="cuda"):
+        """events: iterable of dicts with tt (float32 offsets), F, w, t_ref."""
+        events = list(events)
+        offs = np.zeros(len(events) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum([len(e["tt"]) for e in events])
+        cat = lambda k, dt: torch.from_numpy(np.concatenate([np.asarray(e[k], dt) for e in events])).to(device)
+        return cls(cat("tt", np.float32), cat("F", np.float64), cat("w", np.float64), offs,
+                   np.array([e["t_ref"] for e in events], dtype=np.float64))
+
+    @property
+    def n_events(self):
+        return len(self.t_ref)
+
+    def abi(self):
+        self._keep = (np.ascontiguousarray(self.offsets, np.int64), np.ascontiguousarray(self.t_ref, np.float64))
+        return LightCurves(self.n_events, 0, self._keep[0].ctypes.data, self._keep[1].ctypes.data,
+                           self.t.data_ptr(), self.flux.data_ptr(), self.weight.data_ptr())
+
+
+class _Trajs:
+    def __init__(self, kind, n, axes=None, params=None, shared=True):
+        self.kind, self.n, self.axes, self.params, self.shared = kind, n, axes, params, shared
+
+    def abi(self):
+        if self.kind == TRAJ_GRID:
+            self._keep = [np.ascontiguousarray(a, np.float64) for a in self.axes]
+            u, a, t0, te = self._keep
+            return Trajectories(TRAJ_GRID, len(u), len(a), len(t0), len(te), 1, u.ctypes.data,
+                                a.ctypes.data, t0.ctypes.data, te.ctypes.data, 0, None)
+        return Trajectories(TRAJ_LIST, 0, 0, 0, 0, int(self.shared), None, None, None, None,
+                            int(self.n), self.params.data_ptr())
+
+
+def grid_trajectories(u0s, alphas, t0s, tEs):
+    """Product grid, index ((iu0 * n_alpha + ia) * n_t0 + it0) * n_tE + itE."""
+    axes = [np.asarray(v, np.float64).ravel() for v in (u0s, alphas, t0s, tEs)]
+    return _Trajs(TRAJ_GRID, int(np.prod([len(a) for a in axes])), axes=axes)
+
+
+def list_trajectories(params: torch.Tensor, shared=True):
+    """Device float64 rows (t0, u0, tE, alpha): [n, 4] shared, or [n_events, n, 4]."""
+    if params.dtype != torch.float64 or not params.is_contiguous():
+        raise ValueError("params must be contiguous float64")
+    n = params.shape[-2]
+    return _Trajs(TRAJ_LIST, n, params=params, shared=shared)
+
+
+def _map_views(maps):
+    views = (MapView * len(maps))()
+    for i, (m, w) in enumerate(maps):
+        if m.dtype != torch.float32 or not m.is_contiguous() or tuple(m.shape) != (int(w[5]), int(w[4])):
+            raise ValueError(f"map {i} must be contiguous float32 [ny, nx] matching its window")
+        views[i] = MapView(m.data_ptr(), _grid(w))
+    return views
+
+
+def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,
+           best=False, top_k=0):
+    """Chi-square of every trajectory on every map for every event.
+
+    maps: list of (map tensor, window).  Returns a dict with the requested outputs:
+    chi2/fs/fb [n_events, n_maps, n_traj], best_chi2/best_idx [n_events, n_maps],
+    topk_chi2/topk_idx [n_events, top_k] (index = map * n_traj + traj).
+    """
+    dev = lcs.t.device
+    ctx = Context.get(_device_of(lcs.t))
+    ne, nm, nt = lcs.n_events, len(maps), trajs.n
+    res = {}
+    f64 = lambda *s: torch.empty(s, dtype=torch.float64, device=dev)
+    if chi2:
+        res["chi2"] = f64(ne, nm, nt)
+    if fs:
+        res["fs"] = f64(ne, nm, nt)
+    if fb:
+        res["fb"] = f64(ne, nm, nt)
+    if best:
+        res["best_chi2"] = f64(ne, nm)
+        res["best_idx"] = torch.empty((ne, nm), dtype=torch.int64, device=dev)
+    if top_k:
+        res["topk_chi2"] = f64(ne, top_k)
+        res["topk_idx"] = torch.empty((ne, top_k), dtype=torch.int64, device=dev)
+    out = SearchOut(*(res[k].data_ptr() if k in res else None
+                      for k in ("chi2", "fs", "fb", "best_chi2", "best_idx")),
+                    int(top_k), 0, res["topk_chi2"].data_ptr() if top_k else None,
+                    res["topk_idx"].data_ptr() if top_k else None)
+    views = _map_views(maps)
+    lca = lcs.abi()
+    ta = trajs.abi()
+    m = {"plain": SEARCH_PLAIN, "batched": SEARCH_BATCHED}[mode]
+    ctx.check(ctx.lib.morse_search(ctx.handle, views, nm, ctypes.byref(lca), ctypes.byref(ta), m,
+                                   ctypes.byref(out)))
+    return res
+
+
+def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None):
+    ctx = Context.get(_device_of(lcs.t))
+    best = ctypes.c_int32(-1)
+    views = _map_views(maps)
+    lca = lcs.abi()
+    ta = trajs.abi()
+    ctx.check(ctx.lib.morse_autotune(ctx.handle, views, len(maps), ctypes.byref(lca), ctypes.byref(ta),
+                                     cache_path.encode() if cache_path else None, ctypes.byref(best)))
+    return best.value
+
+
+def candidates_from_topk(trajs, topk_idx, n_maps):
+    """Refinement candidates from a search's top-k: params [n_events*k, 4] float64,
+    event and map index [n_events*k] int32."""
+    ne, k = topk_idx.shape
+    dev = topk_idx.device
+    ctx = Context.get(_device_of(topk_idx))
+    params = torch.empty((ne * k, 4), dtype=torch.float64, device=dev)
+    event = torch.empty(ne * k, dtype=torch.int32, device=dev)
+    mapi = torch.empty(ne * k, dtype=torch.int32, device=dev)
+    ta = trajs.abi()
+    ctx.check(ctx.lib.morse_candidates_from_topk(ctx.handle, ctypes.byref(ta), int(ne), int(n_maps),
+                                                 int(k), _ptr(topk_idx.contiguous()), _ptr(params),
+                                                 _ptr(event), _ptr(mapi)))
+    return params, event, mapi
+
+
+# ------------------------------------------------------------------ gradient / refine
+def _cand_args(params, event, map_index):
+    if params.dtype != torch.float64 or params.dim() != 2 or params.shape[1] != 4 or not params.is_contiguous():
+        raise ValueError("params must be contiguous float64 [n, 4]")
+    n = params.shape[0]
+    for name, t in (("event", event), ("map_index", map_index)):
+        if t.dtype != torch.int32 or t.shape != (n,) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous int32 [n]")
+    return n
+
+
+def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True):
+    """chi2 [n], grad [n, 4] (d/d t0, u0, tE, alpha), Fs [n], Fb [n]."""
+    n = _cand_args(params, event, map_index)
+    ctx = Context.get(_device_of(params))
+    dev = params.device
+    chi2 = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty((n, 4), dtype=torch.float64, device=dev) if grad else None
+    fs = torch.empty(n, dtype=torch.float64, device=dev)
+    fb = torch.empty(n, dtype=torch.float64, device=dev)
+    views = _map_views(maps)
+    lca = lcs.abi()
+    ctx.check(ctx.lib.morse_chi2_grad(ctx.handle, views, len(maps), ctypes.byref(lca), n,
+                                      _ptr(params), _ptr(event), _ptr(map_index), _ptr(chi2),
+                                      _ptr(g), _ptr(fs), _ptr(fb)))
+    return chi2, g, fs, fb
+
+
+def refine(maps, lcs: LightCurveBatch, params, event, map_index, steps=50, history=8, max_ls=10,
+           c1=1e-4, shrink=0.5):
+    """Refined params (new tensor), final chi2 and initial chi2."""
+    n = _cand_args(params, event, map_index)
+    ctx = Context.get(_device_of(params))
+    out = params.clone()
+    chi2 = torch.empty(n, dtype=torch.float64, device=params.device)
+    chi2_0 = torch.empty(n, dtype=torch.float64, device=params.device)
+    opts = LbfgsOpts(int(steps), int(history), int(max_ls), 0, float(c1), float(shrink))
+    views = _map_views(maps)
+    lca = lcs.abi()
+    ctx.check(ctx.lib.morse_refine(ctx.handle, views, len(maps), ctypes.byref(lca), n, _ptr(out),
+                                   _ptr(event), _ptr(map_index), ctypes.byref(opts), _ptr(chi2),
+                                   _ptr(chi2_0)))
+    return out, chi2, chi2_0
+
+
+class Chi2Fn(torch.autograd.Function):
+    """chi2 = Chi2Fn.apply(params [n, 4] float64, maps, lcs, event, map_index).
+
+    Forward runs the gradient kernel once and saves d chi2 / d params; backward
+    returns grad_out[:, None] * saved gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, params, maps, lcs, event, map_index):
+        chi2, g, _, _ = chi2_grad(maps, lcs, params.detach().contiguous(), event, map_index)
+        ctx.save_for_backward(g)
+        return chi2
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out[:, None] * g, None, None, None, None

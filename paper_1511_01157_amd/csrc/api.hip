@@ -1,0 +1,1081 @@
+// C ABI of the gfx950 map-build / trajectory-search library (declared in
+// include/morse.h): context and workspace management, host-side validation, the
+// small host preparations (binary32 constants, disk-overlap weights) and the launch
+// sequences of each entry point.  Every numerical step of the path runs in the HIP
+// kernels of maps.hip, search.hip and refine.hip.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace morse;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct TuneCfg {
+  int traj_per_item;
+  int waves_per_block;
+  int blocks_per_cu;
+};
+// Candidate shapes of the batched search tried by the autotuner; index 0 is the
+// default before tuning.
+const TuneCfg kTune[] = {
+    {128, 4, 4}, {64, 4, 4}, {256, 4, 4}, {64, 8, 2},
+    {128, 8, 2}, {256, 8, 4}, {32, 4, 8}, {512, 8, 2},
+};
+constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
+
+}  // namespace
+
+struct morse_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t capture_stream = nullptr;  // private stream for graph capture
+  int num_cu = 256;
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  uint64_t ws_epoch = 0;  // bumps when the workspace moves
+  std::string err;
+  // host metadata already resident in the workspace (skip re-uploads)
+  uint64_t upload_key = 0;
+  uint64_t upload_epoch = ~0ull;
+  // batched-search graph
+  hipGraphExec_t gexec = nullptr;
+  uint64_t graph_key = 0;
+  // autotune choices per shape class
+  std::map<std::string, int> tune;
+  // small auxiliary device buffer, separate from the workspace
+  char* aux = nullptr;
+  size_t aux_size = 0;
+};
+
+namespace {
+
+int fail(morse_ctx* ctx, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_thread_error = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((ctx), MORSE_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+// FNV-1a over raw bytes, for keys of uploaded metadata and captured graphs.
+struct Hasher {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  }
+  template <class T>
+  void pod(const T& v) {
+    bytes(&v, sizeof(T));
+  }
+};
+
+// Bump allocator over the context workspace: first collect sizes, then reserve.
+struct Plan {
+  std::vector<size_t> sizes;
+  size_t add(size_t bytes) {
+    sizes.push_back((bytes + 255) & ~size_t(255));
+    return sizes.size() - 1;
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (size_t s : sizes) t += s;
+    return t;
+  }
+  char* ptr(morse_ctx* ctx, size_t id) const {
+    size_t off = 0;
+    for (size_t i = 0; i < id; ++i) off += sizes[i];
+    return ctx->ws + off;
+  }
+};
+
+int reserve(morse_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_size) return MORSE_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->gexec) {
+    (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->graph_key = 0;
+  }
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_size = 0;
+  size_t want = std::max(bytes, size_t(1) << 20);
+  want = (want + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+  if (hipMalloc((void**)&ctx->ws, want) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(ctx, MORSE_ENOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  ctx->ws_size = want;
+  ctx->ws_epoch++;
+  return MORSE_OK;
+}
+
+int reserve_aux(morse_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->aux_size) return MORSE_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->aux) (void)hipFree(ctx->aux);
+  ctx->aux = nullptr;
+  ctx->aux_size = 0;
+  const size_t want = std::max(bytes, size_t(1) << 16);
+  if (hipMalloc((void**)&ctx->aux, want) != hipSuccess) {
+    ctx->aux = nullptr;
+    return fail(ctx, MORSE_ENOMEM, "auxiliary allocation of %zu bytes failed", want);
+  }
+  ctx->aux_size = want;
+  return MORSE_OK;
+}
+
+int upload(morse_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (!bytes) return MORSE_OK;
+  HIP_TRY(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  return MORSE_OK;
+}
+
+bool grid_ok(const morse_grid2d* g) {
+  return g && std::isfinite(g->cx) && std::isfinite(g->cy) && std::isfinite(g->wx) &&
+         std::isfinite(g->wy) && g->wx > 0 && g->wy > 0 && g->nx >= 2 && g->ny >= 2 &&
+         (g->nx % 2) == 0 && (g->ny % 2) == 0;
+}
+
+int check_lens(morse_ctx* ctx, double s, double q) {
+  if (!(std::isfinite(s) && s > 0)) return fail(ctx, MORSE_EINVAL, "s must be finite and > 0");
+  if (!(q >= 0.0 && q <= 1.0)) return fail(ctx, MORSE_EINVAL, "q must lie in [0, 1]");
+  return MORSE_OK;
+}
+
+int check_window(morse_ctx* ctx, const morse_grid2d* w, const char* what) {
+  if (!grid_ok(w)) return fail(ctx, MORSE_EINVAL, "%s: invalid grid (even counts >= 2, finite widths > 0)", what);
+  if (w->nx > 32768 || w->ny > 32768)
+    return fail(ctx, MORSE_ERANGE, "%s: at most 32768 pixels per side", what);
+  return MORSE_OK;
+}
+
+MapC make_mapc(const float* map, const morse_grid2d& w) {
+  MapC m;
+  m.map = map;
+  m.mx = w.nx;
+  m.my = w.ny;
+  m.sx = (float)w.cx;
+  m.sy = (float)w.cy;
+  m.kx = (float)((double)w.nx / w.wx);
+  m.ky = (float)((double)w.ny / w.wy);
+  m.ox = (float)(w.nx / 2) - 0.5f;
+  m.oy = (float)(w.ny / 2) - 0.5f;
+  m.lx = (float)(w.nx - 1);
+  m.ly = (float)(w.ny - 1);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// Uniform-disk / pixel overlap weights.  Area of disk(0, R) ∩ [x1,x2] x [y1,y2] as
+// the integral over x of the chord length clipped to [y1, y2]; with x = R sin(th)
+// the chord half-length is R cos(th) and the integrand is smooth between the angles
+// where the clipped chord changes form, so each piece is integrated by 24-point
+// Gauss-Legendre (nodes by Newton iteration on the Legendre polynomial).
+struct Gauss {
+  double x[24], w[24];
+  Gauss() {
+    const int n = 24;
+    for (int i = 0; i < n; ++i) {
+      double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-16) break;
+      }
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+};
+
+double chord_clip(double R, double th, double y1, double y2) {
+  double h = R * std::cos(th);
+  double top = std::min(y2, h), bot = std::max(y1, -h);
+  return top > bot ? top - bot : 0.0;
+}
+
+double rect_disk_area(double R, double x1, double x2, double y1, double y2) {
+  static const Gauss G;
+  double a = std::max(x1, -R), b = std::min(x2, R);
+  if (!(b > a)) return 0.0;
+  double ta = std::asin(a / R), tb = std::asin(b / R);
+  std::vector<double> cuts = {ta, tb};
+  for (double y : {y1, y2})
+    if (std::fabs(y) < R) {
+      double c = std::acos(std::fabs(y) / R);
+      for (double th : {c, -c})
+        if (th > ta && th < tb) cuts.push_back(th);
+    }
+  std::sort(cuts.begin(), cuts.end());
+  double area = 0.0;
+  for (size_t k = 0; k + 1 < cuts.size(); ++k) {
+    double lo = cuts[k], hi = cuts[k + 1];
+    double half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    for (int i = 0; i < 24; ++i) {
+      double th = mid + half * G.x[i];
+      area += half * G.w[i] * chord_clip(R, th, y1, y2) * R * std::cos(th);
+    }
+  }
+  return area;
+}
+
+// Taps (dx, dy offsets and binary32 weights), row-major over the stencil, zero taps
+// dropped; rho within half a pixel gives the single tap 1.
+int disk_taps(morse_ctx* ctx, double rho, double dx, double dy, std::vector<float>& w,
+              std::vector<int32_t>& off) {
+  w.clear();
+  off.clear();
+  const int Rx = (int)std::ceil(rho / dx + 0.5), Ry = (int)std::ceil(rho / dy + 0.5);
+  if (rho <= 0.0) {
+    w.push_back(1.0f);
+    off.push_back(0);
+    off.push_back(0);
+    return MORSE_OK;
+  }
+  if (Rx > 15 || Ry > 15)
+    return fail(ctx, MORSE_ERANGE, "disk radius spans more than 15 pixels (stencil > 31)");
+  std::vector<double> wd;
+  std::vector<int32_t> od;
+  double sum = 0.0;
+  for (int b = -Ry; b <= Ry; ++b)
+    for (int a = -Rx; a <= Rx; ++a) {
+      double nx = std::max(0.0, (std::abs(a) - 0.5) * dx), ny = std::max(0.0, (std::abs(b) - 0.5) * dy);
+      double fx = (std::abs(a) + 0.5) * dx, fy = (std::abs(b) + 0.5) * dy;
+      double area;
+      if (nx * nx + ny * ny >= rho * rho)
+        area = 0.0;
+      else if (fx * fx + fy * fy <= rho * rho)
+        area = dx * dy;
+      else
+        area = rect_disk_area(rho, (a - 0.5) * dx, (a + 0.5) * dx, (b - 0.5) * dy, (b + 0.5) * dy);
+      wd.push_back(area);
+      od.push_back(a);
+      od.push_back(b);
+      sum += area;
+    }
+  for (size_t k = 0; k < wd.size(); ++k) {
+    if (wd[k] == 0.0) continue;
+    w.push_back((float)(wd[k] / sum));
+    off.push_back(od[2 * k]);
+    off.push_back(od[2 * k + 1]);
+  }
+  return MORSE_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int morse_abi_version(void) { return MORSE_ABI_VERSION; }
+
+const char* morse_last_error(const morse_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_thread_error.c_str();
+}
+
+int morse_ctx_create(int device, void* stream, morse_ctx** out) {
+  if (!out) return fail(nullptr, MORSE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(nullptr, MORSE_EINVAL, "no HIP device %d", device);
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, MORSE_EHIP, "hipSetDevice failed");
+  morse_ctx* c = new morse_ctx();
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return fail(nullptr, MORSE_EHIP, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  if (hipStreamCreate(&c->capture_stream) != hipSuccess) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return fail(nullptr, MORSE_EHIP, "hipStreamCreate failed");
+  }
+  *out = c;
+  return MORSE_OK;
+}
+
+int morse_ctx_destroy(morse_ctx* ctx) {
+  if (!ctx) return MORSE_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
+  (void)hipStreamDestroy(ctx->capture_stream);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return MORSE_OK;
+}
+
+int morse_ctx_set_stream(morse_ctx* ctx, void* stream) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if ((hipStream_t)stream == ctx->stream) return MORSE_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  ctx->own_stream = false;
+  ctx->stream = (hipStream_t)stream;
+  return MORSE_OK;
+}
+
+int morse_ctx_synchronize(morse_ctx* ctx) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MORSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+int morse_rayshoot(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
+                   const morse_grid2d* window, int32_t row_begin, int32_t row_end,
+                   uint32_t* d_counts, int32_t accumulate, uint64_t* d_stats) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check_lens(ctx, s, q))) return rc;
+  if (!grid_ok(rays)) return fail(ctx, MORSE_EINVAL, "rays: invalid grid");
+  if ((rc = check_window(ctx, window, "window"))) return rc;
+  if (!d_counts) return fail(ctx, MORSE_EINVAL, "d_counts is NULL");
+  if (row_begin < 0 || row_end > rays->ny || row_begin > row_end)
+    return fail(ctx, MORSE_EINVAL, "row range [%d, %d) outside [0, %d]", row_begin, row_end, rays->ny);
+  if ((double)rays->nx * (double)(row_end - row_begin) >= 4294967296.0)
+    return fail(ctx, MORSE_ERANGE, "more than 2^32 - 1 rays in one call");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);
+  RayParams p;
+  p.m1 = (float)m1;
+  p.m2 = (float)m2;
+  p.x1 = (float)(-s * q / (1.0 + q));
+  p.x2 = (float)(s / (1.0 + q));
+  p.cx = (float)rays->cx;
+  p.cy = (float)rays->cy;
+  p.hx = (float)(rays->wx / rays->nx);
+  p.hy = (float)(rays->wy / rays->ny);
+  p.sx = (float)window->cx;
+  p.sy = (float)window->cy;
+  p.kx = (float)((double)window->nx / window->wx);
+  p.ky = (float)((double)window->ny / window->wy);
+  p.nx = rays->nx;
+  p.ny = rays->ny;
+  p.mx = window->nx;
+  p.my = window->ny;
+  p.row0 = row_begin;
+  p.row1 = row_end;
+  if (!accumulate) HIP_TRY(ctx, launch_fill_u32(d_counts, (size_t)window->nx * window->ny, 0u, ctx->stream));
+  HIP_TRY(ctx, launch_rayshoot(p, d_counts, (unsigned long long*)d_stats, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const morse_grid2d* rays,
+                             const morse_grid2d* window, double rho, float* d_map) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if (!grid_ok(rays)) return fail(ctx, MORSE_EINVAL, "rays: invalid grid");
+  if ((rc = check_window(ctx, window, "window"))) return rc;
+  if (!(std::isfinite(rho) && rho >= 0.0)) return fail(ctx, MORSE_EINVAL, "rho must be finite and >= 0");
+  if (!d_counts || !d_map) return fail(ctx, MORSE_EINVAL, "d_counts / d_map is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const double dx = window->wx / window->nx, dy = window->wy / window->ny;
+  std::vector<float> w;
+  std::vector<int32_t> off;
+  if ((rc = disk_taps(ctx, rho, dx, dy, w, off))) return rc;
+  const double hx = (double)(float)(rays->wx / rays->nx), hy = (double)(float)(rays->wy / rays->ny);
+  const float scale = (float)(hx * hy / (dx * dy));
+  Plan pl;
+  const size_t iw = pl.add(w.size() * sizeof(float)), io = pl.add(off.size() * sizeof(int32_t));
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  float* d_w = (float*)pl.ptr(ctx, iw);
+  int32_t* d_off = (int32_t*)pl.ptr(ctx, io);
+  if ((rc = upload(ctx, d_w, w.data(), w.size() * sizeof(float)))) return rc;
+  if ((rc = upload(ctx, d_off, off.data(), off.size() * sizeof(int32_t)))) return rc;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
+  HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_map, window->nx, window->ny, d_w, d_off,
+                                         (int32_t)w.size(), scale, nullptr, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_build_map(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
+                    const morse_grid2d* window, double rho, uint32_t* d_counts, float* d_map,
+                    morse_map_stats* h_stats) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check_lens(ctx, s, q))) return rc;
+  if (!grid_ok(rays)) return fail(ctx, MORSE_EINVAL, "rays: invalid grid");
+  if ((rc = check_window(ctx, window, "window"))) return rc;
+  if (!(std::isfinite(rho) && rho >= 0.0)) return fail(ctx, MORSE_EINVAL, "rho must be finite and >= 0");
+  if (!d_map) return fail(ctx, MORSE_EINVAL, "d_map is NULL");
+  if ((double)rays->nx * (double)rays->ny >= 4294967296.0)
+    return fail(ctx, MORSE_ERANGE, "more than 2^32 - 1 rays");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const double dx = window->wx / window->nx, dy = window->wy / window->ny;
+  std::vector<float> w;
+  std::vector<int32_t> off;
+  if ((rc = disk_taps(ctx, rho, dx, dy, w, off))) return rc;
+  const size_t npx = (size_t)window->nx * window->ny;
+  Plan pl;
+  const size_t ic = pl.add(d_counts ? 0 : npx * 4), is = pl.add(3 * 8 + 8),
+               iw = pl.add(w.size() * 4), io = pl.add(off.size() * 4);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  uint32_t* counts = d_counts ? d_counts : (uint32_t*)pl.ptr(ctx, ic);
+  uint64_t* stats = (uint64_t*)pl.ptr(ctx, is);
+  uint32_t* maxc = (uint32_t*)(stats + 3);
+  float* d_w = (float*)pl.ptr(ctx, iw);
+  int32_t* d_off = (int32_t*)pl.ptr(ctx, io);
+  if ((rc = upload(ctx, d_w, w.data(), w.size() * 4))) return rc;
+  if ((rc = upload(ctx, d_off, off.data(), off.size() * 4))) return rc;
+  HIP_TRY(ctx, launch_fill_u64(stats, 4, 0ull, ctx->stream));
+  if ((rc = morse_rayshoot(ctx, s, q, rays, window, 0, rays->ny, counts, 0, stats))) return rc;
+  const double hx = (double)(float)(rays->wx / rays->nx), hy = (double)(float)(rays->wy / rays->ny);
+  const float scale = (float)(hx * hy / (dx * dy));
+  HIP_TRY(ctx, launch_normalize_convolve(counts, d_map, window->nx, window->ny, d_w, d_off,
+                                         (int32_t)w.size(), scale, maxc, ctx->stream));
+  // the small host vectors must outlive their (possibly staged) copies
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (h_stats) {
+    uint64_t hs[4];
+    HIP_TRY(ctx, hipMemcpy(hs, stats, sizeof(hs), hipMemcpyDeviceToHost));
+    h_stats->rays_total = (uint64_t)rays->nx * (uint64_t)rays->ny;
+    h_stats->rays_out = hs[0];
+    h_stats->rays_nonfinite = hs[1];
+    h_stats->rays_zero_axis = hs[2];
+    h_stats->rays_in = h_stats->rays_total - hs[0] - hs[1];
+    h_stats->max_count = (uint32_t)(hs[3] & 0xffffffffu);
+    h_stats->reserved = 0;
+    if (h_stats->max_count > (1u << 24))
+      return fail(ctx, MORSE_ERANGE, "a pixel holds %u > 2^24 rays (FP32 normalisation inexact)",
+                  h_stats->max_count);
+  }
+  return MORSE_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================
+// Search planning shared by search / autotune.
+namespace {
+
+struct SearchPlan {
+  int64_t n_traj = 0;
+  int32_t n_events = 0, n_maps = 0;
+  int64_t n_pts = 0;
+  TrajC* tc = nullptr;
+  MapC* d_maps = nullptr;
+  std::vector<MapC> h_maps;
+  LcView lc{};
+  double* chi2 = nullptr;  // output or workspace
+  uint64_t* tk_keys = nullptr;
+  int64_t* tk_idx = nullptr;
+  uint32_t* counter = nullptr;
+  double* axes = nullptr;
+};
+
+int validate_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, const morse_trajectories* trajs) {
+  int rc;
+  if (!maps || n_maps <= 0) return fail(ctx, MORSE_EINVAL, "need n_maps >= 1 maps");
+  for (int i = 0; i < n_maps; ++i) {
+    if (!maps[i].d_map) return fail(ctx, MORSE_EINVAL, "map %d: d_map is NULL", i);
+    if ((rc = check_window(ctx, &maps[i].window, "map window"))) return rc;
+  }
+  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
+      !lcs->d_weight)
+    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
+  if (lcs->h_offsets[0] != 0) return fail(ctx, MORSE_EINVAL, "light curves: offsets[0] must be 0");
+  for (int e = 0; e < lcs->n_events; ++e) {
+    const int64_t n = lcs->h_offsets[e + 1] - lcs->h_offsets[e];
+    if (n < 3) return fail(ctx, MORSE_EINVAL, "event %d has %lld < 3 points", e, (long long)n);
+    if (n > (1ll << 30)) return fail(ctx, MORSE_ERANGE, "event %d too long", e);
+    if (!std::isfinite(lcs->h_t_ref[e])) return fail(ctx, MORSE_EINVAL, "event %d: t_ref not finite", e);
+  }
+  if (!trajs) return fail(ctx, MORSE_EINVAL, "trajs is NULL");
+  if (trajs->kind == MORSE_TRAJ_GRID) {
+    if (trajs->n_u0 <= 0 || trajs->n_alpha <= 0 || trajs->n_t0 <= 0 || trajs->n_tE <= 0 ||
+        !trajs->h_u0 || !trajs->h_alpha || !trajs->h_t0 || !trajs->h_tE)
+      return fail(ctx, MORSE_EINVAL, "grid trajectories: empty axis or NULL array");
+    for (int i = 0; i < trajs->n_tE; ++i)
+      if (!(trajs->h_tE[i] > 0 && std::isfinite(trajs->h_tE[i])))
+        return fail(ctx, MORSE_EINVAL, "grid trajectories: tE must be finite and > 0");
+    for (int i = 0; i < trajs->n_u0; ++i)
+      if (!std::isfinite(trajs->h_u0[i])) return fail(ctx, MORSE_EINVAL, "grid: u0 not finite");
+    for (int i = 0; i < trajs->n_alpha; ++i)
+      if (!std::isfinite(trajs->h_alpha[i])) return fail(ctx, MORSE_EINVAL, "grid: alpha not finite");
+    for (int i = 0; i < trajs->n_t0; ++i)
+      if (!std::isfinite(trajs->h_t0[i])) return fail(ctx, MORSE_EINVAL, "grid: t0 not finite");
+  } else if (trajs->kind == MORSE_TRAJ_LIST) {
+    if (trajs->n <= 0 || !trajs->d_params) return fail(ctx, MORSE_EINVAL, "list trajectories: n <= 0 or NULL");
+  } else {
+    return fail(ctx, MORSE_EINVAL, "unknown trajectory kind %d", trajs->kind);
+  }
+  return MORSE_OK;
+}
+
+int64_t traj_count(const morse_trajectories* t) {
+  return t->kind == MORSE_TRAJ_GRID ? (int64_t)t->n_u0 * t->n_alpha * t->n_t0 * t->n_tE : t->n;
+}
+
+uint64_t metadata_key(const morse_map_view* maps, int32_t n_maps, const morse_lightcurves* lcs,
+                      const morse_trajectories* trajs) {
+  Hasher h;
+  h.pod(n_maps);
+  for (int i = 0; i < n_maps; ++i) {
+    h.pod(maps[i].d_map);
+    h.pod(maps[i].window);
+  }
+  h.pod(lcs->n_events);
+  h.bytes(lcs->h_offsets, sizeof(int64_t) * (lcs->n_events + 1));
+  h.bytes(lcs->h_t_ref, sizeof(double) * lcs->n_events);
+  h.pod(trajs->kind);
+  if (trajs->kind == MORSE_TRAJ_GRID) {
+    h.pod(trajs->n_u0);
+    h.pod(trajs->n_alpha);
+    h.pod(trajs->n_t0);
+    h.pod(trajs->n_tE);
+    h.bytes(trajs->h_u0, 8 * trajs->n_u0);
+    h.bytes(trajs->h_alpha, 8 * trajs->n_alpha);
+    h.bytes(trajs->h_t0, 8 * trajs->n_t0);
+    h.bytes(trajs->h_tE, 8 * trajs->n_tE);
+  }
+  return h.h;
+}
+
+// Reserve the workspace and upload the host metadata of a search (skipped when the
+// same metadata is already resident).  Enqueues nothing else.
+int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                const morse_lightcurves* lcs, const morse_trajectories* trajs,
+                const morse_search_out* out, SearchPlan& sp) {
+  int rc;
+  sp.n_traj = traj_count(trajs);
+  sp.n_events = lcs->n_events;
+  sp.n_maps = n_maps;
+  sp.n_pts = lcs->h_offsets[lcs->n_events];
+  const int64_t n_tc = (trajs->kind == MORSE_TRAJ_LIST && !trajs->shared)
+                           ? sp.n_traj * lcs->n_events
+                           : sp.n_traj;
+  const int64_t n_out = (int64_t)sp.n_events * n_maps * sp.n_traj;
+  const bool need_chi2 = !out->d_chi2 && (out->d_best_chi2 || out->d_best_idx || out->top_k > 0);
+  const int32_t k = out->top_k;
+  const int n_axes = trajs->kind == MORSE_TRAJ_GRID
+                         ? trajs->n_u0 + trajs->n_alpha + trajs->n_t0 + trajs->n_tE
+                         : 0;
+  Plan pl;
+  // metadata first, so its offsets do not depend on the output sizes
+  const size_t i_off = pl.add(8 * (sp.n_events + 1)), i_tref = pl.add(8 * sp.n_events),
+               i_maps = pl.add(sizeof(MapC) * n_maps), i_axes = pl.add(8 * (size_t)n_axes),
+               i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(256),
+               i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
+               i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
+               i_tkk = pl.add(k > 0 ? 8 * (size_t)k * sp.n_events : 0),
+               i_tki = pl.add(k > 0 ? 8 * (size_t)k * sp.n_events : 0);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
+  double* d_tref = (double*)pl.ptr(ctx, i_tref);
+  sp.d_maps = (MapC*)pl.ptr(ctx, i_maps);
+  sp.axes = (double*)pl.ptr(ctx, i_axes);
+  double* d_sums = (double*)pl.ptr(ctx, i_sums);
+  sp.counter = (uint32_t*)pl.ptr(ctx, i_cnt);
+  double* d_wF = (double*)pl.ptr(ctx, i_wF);
+  sp.tc = (TrajC*)pl.ptr(ctx, i_tc);
+  sp.chi2 = out->d_chi2 ? out->d_chi2 : (double*)pl.ptr(ctx, i_chi);
+  sp.tk_keys = (uint64_t*)pl.ptr(ctx, i_tkk);
+  sp.tk_idx = (int64_t*)pl.ptr(ctx, i_tki);
+  sp.h_maps.resize(n_maps);
+  for (int i = 0; i < n_maps; ++i) sp.h_maps[i] = make_mapc(maps[i].d_map, maps[i].window);
+  const uint64_t key = metadata_key(maps, n_maps, lcs, trajs);
+  if (key != ctx->upload_key || ctx->upload_epoch != ctx->ws_epoch) {
+    std::vector<double> axes;
+    if (n_axes) {
+      axes.insert(axes.end(), trajs->h_u0, trajs->h_u0 + trajs->n_u0);
+      axes.insert(axes.end(), trajs->h_alpha, trajs->h_alpha + trajs->n_alpha);
+      axes.insert(axes.end(), trajs->h_t0, trajs->h_t0 + trajs->n_t0);
+      axes.insert(axes.end(), trajs->h_tE, trajs->h_tE + trajs->n_tE);
+    }
+    if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (sp.n_events + 1)))) return rc;
+    if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * sp.n_events))) return rc;
+    if ((rc = upload(ctx, sp.d_maps, sp.h_maps.data(), sizeof(MapC) * n_maps))) return rc;
+    if ((rc = upload(ctx, sp.axes, axes.data(), 8 * axes.size()))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->upload_key = key;
+    ctx->upload_epoch = ctx->ws_epoch;
+  }
+  sp.lc.t = lcs->d_t;
+  sp.lc.w = lcs->d_weight;
+  sp.lc.F = lcs->d_flux;
+  sp.lc.wF = d_wF;
+  sp.lc.off = d_off;
+  sp.lc.sums = d_sums;
+  sp.lc.t_ref = d_tref;
+  return MORSE_OK;
+}
+
+// Preparation kernels (light-curve sums, trajectory constants).
+hipError_t enqueue_prep(const SearchPlan& sp, const morse_trajectories* trajs, hipStream_t st) {
+  hipError_t e = launch_lc_prep(sp.lc.t, sp.lc.F, sp.lc.w, sp.lc.off, sp.n_events,
+                                (double*)sp.lc.wF, (double*)sp.lc.sums, st);
+  if (e != hipSuccess) return e;
+  if (trajs->kind == MORSE_TRAJ_GRID)
+    return launch_traj_prep_grid(sp.axes, trajs->n_u0, trajs->n_alpha, trajs->n_t0, trajs->n_tE,
+                                 sp.tc, st);
+  const int64_t n = trajs->shared ? sp.n_traj : sp.n_traj * sp.n_events;
+  return launch_traj_prep_list(trajs->d_params, n, sp.tc, st);
+}
+
+hipError_t enqueue_select(const SearchPlan& sp, const morse_search_out* out, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (out->d_best_chi2 || out->d_best_idx)
+    e = launch_best(sp.chi2, (int64_t)sp.n_events * sp.n_maps, sp.n_traj, out->d_best_chi2,
+                    out->d_best_idx, st);
+  if (e == hipSuccess && out->top_k > 0)
+    e = launch_topk(sp.chi2, sp.n_events, (int64_t)sp.n_maps * sp.n_traj, out->top_k,
+                    out->d_topk_chi2, out->d_topk_idx, sp.tk_keys, sp.tk_idx, st);
+  return e;
+}
+
+BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_trajectories* trajs,
+                         const morse_search_out* out, const TuneCfg& cfg) {
+  BatchedArgs a;
+  a.tc = sp.tc;
+  a.n_traj = sp.n_traj;
+  a.shared = (trajs->kind == MORSE_TRAJ_GRID || trajs->shared) ? 1 : 0;
+  a.n_events = sp.n_events;
+  a.n_maps = sp.n_maps;
+  a.maps = sp.d_maps;
+  a.lc = sp.lc;
+  a.out.chi2 = sp.chi2;
+  a.out.fs = out->d_fs;
+  a.out.fb = out->d_fb;
+  a.counter = sp.counter;
+  a.traj_per_item = cfg.traj_per_item;
+  a.waves_per_block = cfg.waves_per_block;
+  const int64_t nb = (sp.n_traj + cfg.traj_per_item - 1) / cfg.traj_per_item;
+  const int64_t items = nb * sp.n_events * sp.n_maps;
+  int64_t blocks = (int64_t)ctx->num_cu * cfg.blocks_per_cu;
+  if (blocks > items) blocks = items;
+  a.grid_blocks = (int32_t)std::max<int64_t>(blocks, 1);
+  return a;
+}
+
+std::string shape_class(const SearchPlan& sp) {
+  auto bucket = [](double v) { return (int)std::floor(std::log2(std::max(v, 1.0))); };
+  std::ostringstream s;
+  s << "gfx950|maps" << bucket(sp.n_maps) << "|pts" << bucket((double)sp.n_pts / sp.n_events)
+    << "|traj" << bucket((double)sp.n_traj) << "|ev" << bucket(sp.n_events);
+  return s.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                 const morse_lightcurves* lcs, const morse_trajectories* trajs, int32_t mode,
+                 morse_search_out* out) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!out) return fail(ctx, MORSE_EINVAL, "out is NULL");
+  int rc;
+  if ((rc = validate_search(ctx, maps, n_maps, lcs, trajs))) return rc;
+  if (mode != MORSE_SEARCH_PLAIN && mode != MORSE_SEARCH_BATCHED)
+    return fail(ctx, MORSE_EINVAL, "unknown search mode %d", mode);
+  if (out->top_k < 0 || out->top_k > 4096)
+    return fail(ctx, out->top_k < 0 ? MORSE_EINVAL : MORSE_EUNSUPPORTED, "top_k must be in [0, 4096]");
+  if (out->top_k > 0 && (!out->d_topk_chi2 || !out->d_topk_idx))
+    return fail(ctx, MORSE_EINVAL, "top_k > 0 needs d_topk_chi2 and d_topk_idx");
+  {
+    const int64_t nt = traj_count(trajs);
+    if ((double)nt * lcs->n_events * n_maps >= 9.0e18 ||
+        (double)((nt + 31) / 32) * lcs->n_events * n_maps >= 2147483647.0)
+      return fail(ctx, MORSE_ERANGE, "too many (event, map, trajectory) items");
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  SearchPlan sp;
+  if ((rc = plan_search(ctx, maps, n_maps, lcs, trajs, out, sp))) return rc;
+
+  if (mode == MORSE_SEARCH_PLAIN) {
+    HIP_TRY(ctx, enqueue_prep(sp, trajs, ctx->stream));
+    for (int32_t e = 0; e < sp.n_events; ++e) {
+      const TrajC* tc = sp.tc + ((trajs->kind == MORSE_TRAJ_LIST && !trajs->shared) ? (int64_t)e * sp.n_traj : 0);
+      for (int32_t m = 0; m < n_maps; ++m) {
+        const int64_t base = ((int64_t)e * n_maps + m) * sp.n_traj;
+        SearchOut so{sp.chi2 + base, out->d_fs ? out->d_fs + base : nullptr,
+                     out->d_fb ? out->d_fb + base : nullptr};
+        HIP_TRY(ctx, launch_search_plain(tc, sp.n_traj, sp.lc, e, sp.h_maps[m], so, 4, ctx->stream));
+      }
+    }
+    HIP_TRY(ctx, enqueue_select(sp, out, ctx->stream));
+    return MORSE_OK;
+  }
+
+  // batched: one persistent launch, captured into a graph per argument set
+  auto it = ctx->tune.find(shape_class(sp));
+  const int cfg_idx = it == ctx->tune.end() ? 0 : it->second;
+  const TuneCfg& cfg = kTune[cfg_idx];
+  Hasher h;
+  h.pod(metadata_key(maps, n_maps, lcs, trajs));
+  h.pod(ctx->ws_epoch);
+  h.pod(cfg_idx);
+  h.pod(*out);
+  h.pod(lcs->d_t);
+  h.pod(lcs->d_flux);
+  h.pod(lcs->d_weight);
+  h.pod(trajs->d_params);
+  h.pod(trajs->shared);
+  h.pod(trajs->n);
+  if (!ctx->gexec || ctx->graph_key != h.h) {
+    if (ctx->gexec) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipGraphExecDestroy(ctx->gexec);
+      ctx->gexec = nullptr;
+    }
+    const BatchedArgs a = batched_args(ctx, sp, trajs, out, cfg);
+    hipGraph_t g = nullptr;
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_prep(sp, trajs, ctx->capture_stream);
+    if (e == hipSuccess) e = launch_fill_u32(sp.counter, 1, 0u, ctx->capture_stream);
+    if (e == hipSuccess) e = launch_search_batched(a, ctx->capture_stream);
+    if (e == hipSuccess) e = enqueue_select(sp, out, ctx->capture_stream);
+    hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ctx, MORSE_EHIP, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ctx->gexec = nullptr;
+      return fail(ctx, MORSE_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->graph_key = h.h;
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->gexec, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                   const morse_lightcurves* lcs, const morse_trajectories* trajs,
+                   const char* cache_path, int32_t* h_best_config) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = validate_search(ctx, maps, n_maps, lcs, trajs))) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  morse_search_out out{};
+  SearchPlan sp;
+  if ((rc = plan_search(ctx, maps, n_maps, lcs, trajs, &out, sp))) return rc;
+  const std::string cls = shape_class(sp);
+  // time each candidate on (at most) the first 16 events x 8 maps of the problem
+  SearchPlan sub = sp;
+  sub.n_events = std::min(sp.n_events, 16);
+  sub.n_maps = std::min(sp.n_maps, 8);
+  const size_t need = (size_t)sub.n_events * sub.n_maps * sp.n_traj * 8;
+  double* scratch = nullptr;
+  HIP_TRY(ctx, hipMalloc((void**)&scratch, need));
+  sub.chi2 = scratch;
+  hipError_t e = enqueue_prep(sp, trajs, ctx->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int c = 0; c < kNumTune && e == hipSuccess; ++c) {
+    const BatchedArgs a = batched_args(ctx, sub, trajs, &out, kTune[c]);
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      e = launch_fill_u32(sub.counter, 1, 0u, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+      if (e == hipSuccess) e = launch_search_batched(a, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return fail(ctx, MORSE_EHIP, "autotune: %s", hipGetErrorString(e));
+  ctx->tune[cls] = best;
+  if (h_best_config) *h_best_config = best;
+  if (cache_path) {
+    // JSON object {"class": index, ...}: merge with the existing file
+    std::map<std::string, int> all;
+    std::ifstream in(cache_path);
+    if (in) {
+      std::string txt((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
+      size_t p = 0;
+      while ((p = txt.find('"', p)) != std::string::npos) {
+        size_t q = txt.find('"', p + 1);
+        if (q == std::string::npos) break;
+        std::string k = txt.substr(p + 1, q - p - 1);
+        size_t colon = txt.find(':', q);
+        if (colon == std::string::npos) break;
+        all[k] = std::atoi(txt.c_str() + colon + 1);
+        p = txt.find_first_of(",}", colon);
+        if (p == std::string::npos) break;
+      }
+    }
+    all[cls] = best;
+    std::ofstream o(cache_path);
+    o << "{";
+    bool first = true;
+    for (auto& kv : all) {
+      o << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+      first = false;
+    }
+    o << "}\n";
+  }
+  return MORSE_OK;
+}
+
+int morse_candidates_from_topk(morse_ctx* ctx, const morse_trajectories* trajs, int32_t n_events,
+                               int32_t n_maps, int32_t top_k, const int64_t* d_topk_idx,
+                               double* d_params, int32_t* d_event, int32_t* d_map_index) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!trajs) return fail(ctx, MORSE_EINVAL, "trajs is NULL");
+  if (n_events <= 0 || n_maps <= 0 || top_k <= 0)
+    return fail(ctx, MORSE_EINVAL, "n_events, n_maps and top_k must be >= 1");
+  if (!d_topk_idx || !d_params || !d_event || !d_map_index)
+    return fail(ctx, MORSE_EINVAL, "NULL device pointer");
+  const int64_t n_traj = traj_count(trajs);
+  if (n_traj <= 0) return fail(ctx, MORSE_EINVAL, "empty trajectory set");
+  if (trajs->kind == MORSE_TRAJ_LIST && !trajs->d_params)
+    return fail(ctx, MORSE_EINVAL, "list trajectories: d_params is NULL");
+  if (trajs->kind == MORSE_TRAJ_GRID &&
+      (!trajs->h_u0 || !trajs->h_alpha || !trajs->h_t0 || !trajs->h_tE))
+    return fail(ctx, MORSE_EINVAL, "grid trajectories: NULL axis");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const double* axes = nullptr;
+  int rc;
+  if (trajs->kind == MORSE_TRAJ_GRID) {
+    std::vector<double> h;
+    h.insert(h.end(), trajs->h_u0, trajs->h_u0 + trajs->n_u0);
+    h.insert(h.end(), trajs->h_alpha, trajs->h_alpha + trajs->n_alpha);
+    h.insert(h.end(), trajs->h_t0, trajs->h_t0 + trajs->n_t0);
+    h.insert(h.end(), trajs->h_tE, trajs->h_tE + trajs->n_tE);
+    // the auxiliary buffer keeps the search's resident workspace intact
+    if ((rc = reserve_aux(ctx, 8 * h.size()))) return rc;
+    double* d = (double*)ctx->aux;
+    if ((rc = upload(ctx, d, h.data(), 8 * h.size()))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    axes = d;
+  }
+  HIP_TRY(ctx, launch_candidates(axes, trajs->n_u0, trajs->n_alpha, trajs->n_t0, trajs->n_tE,
+                                 trajs->d_params, trajs->shared, n_traj, n_events, n_maps, top_k,
+                                 d_topk_idx, d_params, d_event, d_map_index, ctx->stream));
+  return MORSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, int64_t n, Plan& pl, size_t& i_off,
+                    size_t& i_tref, size_t& i_maps, size_t& i_sums, size_t& i_wF) {
+  if (!maps || n_maps <= 0) return fail(ctx, MORSE_EINVAL, "need n_maps >= 1 maps");
+  int rc;
+  for (int i = 0; i < n_maps; ++i) {
+    if (!maps[i].d_map) return fail(ctx, MORSE_EINVAL, "map %d: d_map is NULL", i);
+    if ((rc = check_window(ctx, &maps[i].window, "map window"))) return rc;
+  }
+  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
+      !lcs->d_weight)
+    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
+  for (int e = 0; e < lcs->n_events; ++e)
+    if (lcs->h_offsets[e + 1] - lcs->h_offsets[e] < 3)
+      return fail(ctx, MORSE_EINVAL, "event %d has fewer than 3 points", e);
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  i_off = pl.add(8 * (lcs->n_events + 1));
+  i_tref = pl.add(8 * lcs->n_events);
+  i_maps = pl.add(sizeof(MapC) * n_maps);
+  i_sums = pl.add(24 * (size_t)lcs->n_events);
+  i_wF = pl.add(8 * (size_t)lcs->h_offsets[lcs->n_events]);
+  return MORSE_OK;
+}
+
+int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                     const morse_lightcurves* lcs, const Plan& pl, size_t i_off, size_t i_tref,
+                     size_t i_maps, size_t i_sums, size_t i_wF, LcView& lc, MapC*& d_maps) {
+  int rc;
+  int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
+  double* d_tref = (double*)pl.ptr(ctx, i_tref);
+  d_maps = (MapC*)pl.ptr(ctx, i_maps);
+  std::vector<MapC> hm(n_maps);
+  for (int i = 0; i < n_maps; ++i) hm[i] = make_mapc(maps[i].d_map, maps[i].window);
+  if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (lcs->n_events + 1)))) return rc;
+  if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * lcs->n_events))) return rc;
+  if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->upload_key = 0;  // the search metadata region was overwritten
+  lc.t = lcs->d_t;
+  lc.w = lcs->d_weight;
+  lc.F = lcs->d_flux;
+  lc.wF = (double*)pl.ptr(ctx, i_wF);
+  lc.off = d_off;
+  lc.sums = (double*)pl.ptr(ctx, i_sums);
+  lc.t_ref = d_tref;
+  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, lcs->n_events, (double*)lc.wF,
+                              (double*)lc.sums, ctx->stream));
+  return MORSE_OK;
+}
+}  // namespace
+
+int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, int64_t n, const double* d_params,
+                    const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
+                    double* d_grad, double* d_fs, double* d_fb) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  Plan pl;
+  size_t i_off, i_tref, i_maps, i_sums, i_wF;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF))) return rc;
+  if (n > 0 && (!d_params || !d_event || !d_map_index))
+    return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  GradArgs a{};
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
+  a.n = n;
+  a.params = d_params;
+  a.event = d_event;
+  a.mapidx = d_map_index;
+  a.maps = d_maps;
+  a.n_events = lcs->n_events;
+  a.n_maps = n_maps;
+  a.chi2 = d_chi2;
+  a.grad = d_grad;
+  a.fs = d_fs;
+  a.fb = d_fb;
+  HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                 const morse_lightcurves* lcs, int64_t n, double* d_params,
+                 const int32_t* d_event, const int32_t* d_map_index,
+                 const morse_lbfgs_opts* opts, double* d_chi2_out, double* d_chi2_init) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
+  if (opts->steps < 0 || opts->history < 1 || opts->history > 16 || opts->max_ls < 1 ||
+      !(opts->c1 > 0 && opts->c1 < 1) || !(opts->shrink > 0 && opts->shrink < 1))
+    return fail(ctx, MORSE_EINVAL, "invalid L-BFGS options");
+  int rc;
+  Plan pl;
+  size_t i_off, i_tref, i_maps, i_sums, i_wF;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF))) return rc;
+  if (n > 0 && (!d_params || !d_event || !d_map_index || !d_chi2_out))
+    return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index / d_chi2_out is NULL");
+  if (n == 0) return MORSE_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int m = opts->history;
+  const size_t i_anchor = pl.add(32 * n), i_p = pl.add(16 * n), i_pt = pl.add(16 * n),
+               i_f = pl.add(8 * n), i_g = pl.add(32 * n), i_d = pl.add(32 * n), i_step = pl.add(8 * n),
+               i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
+               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n), i_ft = pl.add(8 * n),
+               i_gt = pl.add(32 * n);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  GradArgs a{};
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
+  LbfgsState s;
+  s.n = n;
+  s.m = m;
+  s.max_ls = opts->max_ls;
+  s.c1 = opts->c1;
+  s.shrink = opts->shrink;
+  double* anchor = (double*)pl.ptr(ctx, i_anchor);
+  s.anchor = anchor;
+  s.p = (float*)pl.ptr(ctx, i_p);
+  s.pt = (float*)pl.ptr(ctx, i_pt);
+  s.f = (double*)pl.ptr(ctx, i_f);
+  s.g = (double*)pl.ptr(ctx, i_g);
+  s.d = (double*)pl.ptr(ctx, i_d);
+  s.step = (double*)pl.ptr(ctx, i_step);
+  s.S = (double*)pl.ptr(ctx, i_S);
+  s.Y = (double*)pl.ptr(ctx, i_Y);
+  s.R = (double*)pl.ptr(ctx, i_R);
+  int32_t* ints = (int32_t*)pl.ptr(ctx, i_int);
+  s.nhist = ints;
+  s.start = ints + n;
+  s.nls = ints + 2 * n;
+  s.active = ints + 3 * n;
+  double* ft = (double*)pl.ptr(ctx, i_ft);
+  double* gt = (double*)pl.ptr(ctx, i_gt);
+  s.ft = ft;
+  s.gt = gt;
+  HIP_TRY(ctx, hipMemcpyAsync(anchor, d_params, 32 * n, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32((uint32_t*)s.pt, 4 * n, 0u, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32((uint32_t*)ints, 3 * n, 0u, ctx->stream));
+  HIP_TRY(ctx, launch_fill_u32((uint32_t*)s.active, n, 1u, ctx->stream));
+  a.n = n;
+  a.anchor = anchor;
+  a.pt = s.pt;
+  a.active = s.active;
+  a.event = d_event;
+  a.mapidx = d_map_index;
+  a.maps = d_maps;
+  a.n_events = lcs->n_events;
+  a.n_maps = n_maps;
+  a.chi2 = ft;
+  a.grad = gt;
+  for (int r = 0; r <= opts->steps; ++r) {
+    HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
+    if (r == 0 && d_chi2_init)
+      HIP_TRY(ctx, hipMemcpyAsync(d_chi2_init, ft, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, launch_lbfgs_update(s, r, ctx->stream));
+  }
+  HIP_TRY(ctx, launch_lbfgs_finish(s, d_params, d_chi2_out, ctx->stream));
+  return MORSE_OK;
+}
+
+}  // extern "C"

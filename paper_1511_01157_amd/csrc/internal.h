@@ -1,0 +1,250 @@
+// Internal declarations of the gfx950 library: device-side data layouts, the
+// per-sample arithmetic shared by the search and gradient kernels, and the host
+// launchers each kernel file exports to api.hip.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/morse.h"
+
+namespace morse {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// ---------------------------------------------------------------------------
+// Ray shooting constants, each rounded once from FP64 to binary32 on the host.
+struct RayParams {
+  float m1, m2, x1, x2;  // lens masses and positions
+  float cx, cy, hx, hy;  // lattice centre and spacing
+  float sx, sy, kx, ky;  // window centre and pixels per Einstein radius
+  int32_t nx, ny, mx, my;
+  int32_t row0, row1;    // lattice rows [row0, row1)
+};
+
+// Per-trajectory constants: binary32 geometry rounded once from FP64, t0 kept FP64
+// so each event subtracts its own reference time before rounding.
+struct TrajC {
+  double t0;
+  float iE, ca, sa, bx, by, pad;
+};
+static_assert(sizeof(TrajC) == 32, "TrajC layout");
+
+// A map as the sampling kernels see it.
+struct MapC {
+  const float* map;
+  int32_t mx, my;
+  float sx, sy, kx, ky, ox, oy;  // grid coordinate g = (zeta - s) k + o
+  float lx, ly;                  // on-map bound: g < M - 1
+};
+
+// Light curves after preparation: per point binary32 time offset, w and w*F;
+// per event the constant sums S_w, S_F, S_FF.
+struct LcView {
+  const float* t;
+  const double* w;
+  const double* wF;
+  const double* F;
+  const int64_t* off;   // device CSR offsets [n_events + 1]
+  const double* sums;   // [n_events][3]: S_w, S_F, S_FF
+  const double* t_ref;  // [n_events]
+};
+
+// ---------------------------------------------------------------------------
+// Sampling along a trajectory (binary32, no fused multiply-add: the library is
+// compiled with -ffp-contract=off, so every operation below rounds on its own).
+//   tau = (t - t0')*iE; zeta = tau (ca, sa) + (bx, by); g = (zeta - s) k + o;
+//   bilinear between pixel-centre values inside [0, M-1), else the single-lens
+//   magnification (uu + 2)/sqrt(uu (uu + 4)) about the barycentre.
+struct Sample {
+  float A;
+  float tau, zx, zy;
+  float fx, fy, e0, e1, ax0, ax1;
+  bool on;
+};
+
+__device__ __forceinline__ float sample_A(const MapC& m, float tt, float t0p, float iE, float ca,
+                                          float sa, float bx, float by) {
+  float tau = (tt - t0p) * iE;
+  float zx = tau * ca + bx;
+  float zy = tau * sa + by;
+  float gx = ((zx - m.sx) * m.kx) + m.ox;
+  float gy = ((zy - m.sy) * m.ky) + m.oy;
+  if (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly) {
+    float fi = floorf(gx);
+    float fj = floorf(gy);
+    float fx = gx - fi;
+    float fy = gy - fj;
+    const float* p = m.map + (size_t)(int)fj * (size_t)m.mx + (int)fi;
+    float v00 = p[0], v10 = p[1];
+    float v01 = p[m.mx], v11 = p[m.mx + 1];
+    float e0 = v10 - v00;
+    float e1 = v11 - v01;
+    float ax0 = v00 + fx * e0;
+    float ax1 = v01 + fx * e1;
+    return ax0 + fy * (ax1 - ax0);
+  }
+  float uu = zx * zx + zy * zy;
+  return (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
+}
+
+__device__ __forceinline__ Sample sample_full(const MapC& m, float tt, float t0p, float iE,
+                                              float ca, float sa, float bx, float by) {
+  Sample s;
+  s.tau = (tt - t0p) * iE;
+  s.zx = s.tau * ca + bx;
+  s.zy = s.tau * sa + by;
+  float gx = ((s.zx - m.sx) * m.kx) + m.ox;
+  float gy = ((s.zy - m.sy) * m.ky) + m.oy;
+  s.on = (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly);
+  if (s.on) {
+    float fi = floorf(gx);
+    float fj = floorf(gy);
+    s.fx = gx - fi;
+    s.fy = gy - fj;
+    const float* p = m.map + (size_t)(int)fj * (size_t)m.mx + (int)fi;
+    float v00 = p[0], v10 = p[1];
+    float v01 = p[m.mx], v11 = p[m.mx + 1];
+    s.e0 = v10 - v00;
+    s.e1 = v11 - v01;
+    s.ax0 = v00 + s.fx * s.e0;
+    s.ax1 = v01 + s.fx * s.e1;
+    s.A = s.ax0 + s.fy * (s.ax1 - s.ax0);
+  } else {
+    float uu = s.zx * s.zx + s.zy * s.zy;
+    s.A = (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
+    s.fx = s.fy = s.e0 = s.e1 = s.ax0 = s.ax1 = 0.0f;
+  }
+  return s;
+}
+
+// Deterministic wavefront sum (butterfly over 64 lanes, same order on every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Profiled fit (Eqs. 5-6) from the five sums; degenerate when
+// det <= 1e-12 S_AA S_w.  Returns true when degenerate.
+__device__ __forceinline__ bool profiled_fit(double Sw, double SA, double SAA, double SF,
+                                             double SAF, double& Fs, double& Fb) {
+  double det = SAA * Sw - SA * SA;
+  if (!(det > 1e-12 * SAA * Sw)) {
+    Fs = 0.0;
+    Fb = SF / Sw;
+    return true;
+  }
+  Fs = (SAF * Sw - SA * SF) / det;
+  Fb = (SAA * SF - SA * SAF) / det;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (one per kernel family); all enqueue on `st` and return the
+// first HIP error.
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
+hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
+                           hipStream_t st);
+hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
+                                     const float* d_w, const int32_t* d_off, int32_t ntaps,
+                                     float scale, uint32_t* d_maxc, hipStream_t st);
+hipError_t launch_lc_prep(const float* t, const double* F, const double* w, const int64_t* off,
+                          int32_t n_events, double* wF, double* sums, hipStream_t st);
+hipError_t launch_traj_prep_list(const double* params, int64_t n, TrajC* out, hipStream_t st);
+hipError_t launch_traj_prep_grid(const double* axes, int32_t nu, int32_t na, int32_t nt,
+                                 int32_t ne, TrajC* out, hipStream_t st);
+
+struct SearchOut {
+  double* chi2;
+  double* fs;
+  double* fb;
+};
+
+// Plain search: one launch for one (event, map); outputs for that segment.
+hipError_t launch_search_plain(const TrajC* tc, int64_t n_traj, LcView lc, int32_t event,
+                               MapC map, SearchOut out, int waves_per_block, hipStream_t st);
+
+// Batched persistent search over (event, map, trajectory block) items.
+struct BatchedArgs {
+  const TrajC* tc;          // per event if !shared
+  int64_t n_traj;
+  int32_t shared;
+  int32_t n_events, n_maps;
+  const MapC* maps;         // device table [n_maps]
+  LcView lc;
+  SearchOut out;            // full [e][m][traj] arrays
+  uint32_t* counter;        // work-queue counter (cleared by a fill kernel)
+  int32_t traj_per_item;
+  int32_t waves_per_block;
+  int32_t grid_blocks;
+};
+hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st);
+
+// Best (chi2, index) per segment of length seg_len; n_seg segments.
+hipError_t launch_best(const double* chi2, int64_t n_seg, int64_t seg_len, double* best_chi2,
+                       int64_t* best_idx, hipStream_t st);
+// Top-k per segment (k <= 4096).
+hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32_t k,
+                       double* out_chi2, int64_t* out_idx, uint64_t* scratch_keys,
+                       int64_t* scratch_idx, hipStream_t st);
+
+// Expand top-k flat indices (map * n_traj + traj) into parameter rows.
+hipError_t launch_candidates(const double* axes, int32_t nu, int32_t na, int32_t nt, int32_t ne,
+                             const double* list, int32_t shared, int64_t n_traj, int32_t n_events,
+                             int32_t n_maps, int32_t k, const int64_t* idx, double* params,
+                             int32_t* event, int32_t* mapidx, hipStream_t st);
+
+// Gradient evaluation.  When `anchor`/`pt` are given the parameters are the
+// L-BFGS variables (natural = anchor mapped by pt) and the gradient is written with
+// respect to pt; `active` (nullable) skips finished candidates.
+struct GradArgs {
+  int64_t n;
+  const double* params;     // natural [n][4] (when anchor == nullptr)
+  const double* anchor;     // [n][4] or nullptr
+  const float* pt;          // [n][4] or nullptr
+  const int32_t* active;    // [n] or nullptr
+  const int32_t* event;
+  const int32_t* mapidx;
+  const MapC* maps;
+  int32_t n_events, n_maps;  // out-of-range event / map indices give NaN outputs
+  LcView lc;
+  double* chi2;
+  double* grad;             // [n][4] or nullptr
+  double* fs;
+  double* fb;
+};
+hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st);
+
+struct LbfgsState {
+  int64_t n;
+  int32_t m;
+  int32_t max_ls;
+  double c1, shrink;
+  const double* anchor;  // [n][4]
+  float* p;              // [n][4] accepted point
+  float* pt;             // [n][4] trial point
+  double* f;             // [n]
+  double* g;             // [n][4]
+  double* d;             // [n][4]
+  double* step;          // [n]
+  double* S;             // [n][m][4]
+  double* Y;             // [n][m][4]
+  double* R;             // [n][m]
+  int32_t* nhist;        // [n]
+  int32_t* start;        // [n]
+  int32_t* nls;          // [n]
+  int32_t* active;       // [n]
+  const double* ft;      // [n] evaluation at pt
+  const double* gt;      // [n][4]
+};
+hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, hipStream_t st);
+hipError_t launch_lbfgs_finish(const LbfgsState& s, double* params, double* chi2_out,
+                               hipStream_t st);
+
+}  // namespace morse

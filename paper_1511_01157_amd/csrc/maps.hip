@@ -1,0 +1,280 @@
+// Map build on gfx950: inverse ray shooting into LDS-privatised uint32 histogram
+// tiles merged with global atomics, then normalisation + uniform-disk convolution.
+//
+// Method: ray-shooting magnification maps (the family cited in sec. 3 of McDougall &
+// Albrow 2015) of the binary-lens equation Eq. 2 with the lens placement of sec. 4.1;
+// finite-source maps by convolution with the source profile (sec. 4.1).
+//
+// Ray kernel layout.  A 256-thread workgroup owns a 128 x 64 tile of the image-plane
+// lattice (32 rays per thread).  Rays are generated from their indices (no input
+// arrays).  Thread (tx, ty) of a 16 x 16 arrangement takes rays x0 + tx + 16a,
+// y0 + ty + 16b, so the 64 lanes of a wave at one (a, b) are spread over a 16 x 4
+// patch of rays, i.e. over several source pixels, which keeps LDS atomics of one
+// instruction off a single address.  Pass 1 computes every ray's bin and the
+// workgroup's bounding box of in-window bins.  If the box fits in the LDS tile
+// (8192 bins) the rays are counted with LDS atomics and the non-zero bins merged
+// with one global atomic each; otherwise (tiles straddling a lens, whose rays scatter
+// over the whole source plane) each ray goes to a global atomic directly.  Integer
+// addition is order-free, so the counts are bit-identical whatever the schedule.
+
+#include "internal.h"
+
+#include <climits>
+
+namespace morse {
+
+namespace {
+
+constexpr int RS_TX = 128;
+constexpr int RS_TY = 64;
+constexpr int RS_THREADS = 256;
+constexpr int RS_A = RS_TX / 16;  // rays per thread along x
+constexpr int RS_B = RS_TY / 16;  // rays per thread along y
+constexpr int RS_CAP = 8192;      // LDS histogram bins (32 KiB)
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Symmetric bin rule: v >= 0 (also -0) -> m/2 + floor(v) if v < m/2;
+// v < 0 -> m/2 - 1 - floor(-v) if -v < m/2.  floor(|v|) serves both branches.
+__device__ __forceinline__ bool bin1(float v, int32_t m, int32_t& out) {
+  float av = fabsf(v);
+  int32_t h = m >> 1;
+  int32_t f = (int32_t)floorf(fminf(av, (float)h));  // clamp keeps the cast in range
+  out = (v >= 0.0f) ? h + f : h - 1 - f;
+  return av < (float)h;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* __restrict__ counts,
+                                                         unsigned long long* __restrict__ stats) {
+  __shared__ uint32_t hist[RS_CAP];
+  __shared__ int s_box[4][4];
+
+  const int tid = threadIdx.x;
+  const int tx = tid & 15;
+  const int ty = tid >> 4;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int x0 = blockIdx.x * RS_TX;
+  const int y0 = p.row0 + blockIdx.y * RS_TY;
+
+  // packed bin (by << 16 | bx), -1 when the ray is not binned
+  int bins[RS_A * RS_B];
+  int bxmin = INT_MAX, bxmax = -1, bymin = INT_MAX, bymax = -1;
+  uint32_t n_out = 0, n_nf = 0, n_zero = 0;
+
+#pragma unroll
+  for (int b = 0; b < RS_B; ++b) {
+    const int j = y0 + ty + 16 * b;
+    const float gy = (float)(j - (p.ny >> 1)) + 0.5f;
+    const float y = p.cy + gy * p.hy;
+    const float yy = y * y;
+#pragma unroll
+    for (int a = 0; a < RS_A; ++a) {
+      const int i = x0 + tx + 16 * a;
+      int bin = -1;
+      if (i < p.nx && j < p.row1) {
+        const float gx = (float)(i - (p.nx >> 1)) + 0.5f;
+        const float x = p.cx + gx * p.hx;
+        const float d1 = x - p.x1;
+        const float d2 = x - p.x2;
+        const float r1 = d1 * d1 + yy;
+        const float r2 = d2 * d2 + yy;
+        const float a1 = p.m1 / r1;
+        const float a2 = p.m2 / r2;
+        const float zx = (x - a1 * d1) - a2 * d2;
+        const float zy = (y - a1 * y) - a2 * y;
+        const float vx = (zx - p.sx) * p.kx;
+        const float vy = (zy - p.sy) * p.ky;
+        if (!(isfinite(vx) && isfinite(vy))) {
+          ++n_nf;
+        } else {
+          int32_t bx, by;
+          const bool inx = bin1(vx, p.mx, bx);
+          const bool iny = bin1(vy, p.my, by);
+          if (inx && iny) {
+            bin = (by << 16) | bx;
+            n_zero += (vy == 0.0f) ? 1u : 0u;
+            bxmin = min(bxmin, bx);
+            bxmax = max(bxmax, bx);
+            bymin = min(bymin, by);
+            bymax = max(bymax, by);
+          } else {
+            ++n_out;
+          }
+        }
+      }
+      bins[b * RS_A + a] = bin;
+    }
+  }
+
+  // ray statistics: one 64-bit atomic per wave and counter, only when non-zero
+  n_out = wave_sum_u32(n_out);
+  n_nf = wave_sum_u32(n_nf);
+  n_zero = wave_sum_u32(n_zero);
+  if (lane == 0 && stats) {
+    if (n_out) atomicAdd(&stats[0], (unsigned long long)n_out);
+    if (n_nf) atomicAdd(&stats[1], (unsigned long long)n_nf);
+    if (n_zero) atomicAdd(&stats[2], (unsigned long long)n_zero);
+  }
+
+  // workgroup bounding box of binned rays
+  bxmin = wave_min(bxmin);
+  bxmax = wave_max(bxmax);
+  bymin = wave_min(bymin);
+  bymax = wave_max(bymax);
+  if (lane == 0) {
+    s_box[wave][0] = bxmin;
+    s_box[wave][1] = bxmax;
+    s_box[wave][2] = bymin;
+    s_box[wave][3] = bymax;
+  }
+  __syncthreads();
+  bxmin = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
+  bxmax = max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1]));
+  bymin = min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2]));
+  bymax = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
+  if (bxmax < 0) return;  // no ray of this tile landed in the window
+
+  const int pitch = bxmax - bxmin + 1;
+  const int rows = bymax - bymin + 1;
+  const int area = pitch * rows;
+  if (area <= RS_CAP) {
+    for (int k = tid; k < area; k += RS_THREADS) hist[k] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RS_A * RS_B; ++k) {
+      const int bin = bins[k];
+      if (bin >= 0) {
+        const int bx = bin & 0xffff;
+        const int by = bin >> 16;
+        atomicAdd(&hist[(by - bymin) * pitch + (bx - bxmin)], 1u);
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < area; k += RS_THREADS) {
+      const uint32_t v = hist[k];
+      if (v) {
+        const int r = k / pitch;
+        const int c = k - r * pitch;
+        atomicAdd(&counts[(size_t)(bymin + r) * (size_t)p.mx + (size_t)(bxmin + c)], v);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < RS_A * RS_B; ++k) {
+      const int bin = bins[k];
+      if (bin >= 0) {
+        const int bx = bin & 0xffff;
+        const int by = bin >> 16;
+        atomicAdd(&counts[(size_t)by * (size_t)p.mx + (size_t)bx], 1u);
+      }
+    }
+  }
+}
+
+// Normalise + convolve: one thread per output pixel, 16 x 16 pixel blocks; taps
+// (row-major over the stencil, zero taps dropped on the host) come from a small
+// device table; neighbours clamp to the edge.  acc accumulates left to right in
+// binary32 and A = acc * scale.  Also reduces the largest count of the map.
+__global__ __launch_bounds__(256) void k_normalize_convolve(const uint32_t* __restrict__ counts,
+                                                            float* __restrict__ map, int32_t mx,
+                                                            int32_t my, const float* __restrict__ w,
+                                                            const int32_t* __restrict__ off,
+                                                            int32_t ntaps, float scale,
+                                                            uint32_t* __restrict__ maxc) {
+  __shared__ uint32_t s_max[4];
+  const int i = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  uint32_t cmax = 0;
+  if (i < mx && j < my) {
+    const uint32_t c0 = counts[(size_t)j * mx + i];
+    cmax = c0;
+    float acc;
+    if (ntaps == 1) {
+      acc = w[0] * (float)c0;
+    } else {
+      acc = 0.0f;
+      for (int k = 0; k < ntaps; ++k) {
+        int ii = i + off[2 * k];
+        int jj = j + off[2 * k + 1];
+        ii = min(max(ii, 0), mx - 1);
+        jj = min(max(jj, 0), my - 1);
+        const float term = w[k] * (float)counts[(size_t)jj * mx + ii];
+        acc = (k == 0) ? term : acc + term;
+      }
+    }
+    map[(size_t)j * mx + i] = acc * scale;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, kWave));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = cmax;
+  __syncthreads();
+  if (threadIdx.x == 0 && maxc) {
+    cmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    atomicMax(maxc, cmax);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
+                           hipStream_t st) {
+  const int rows = p.row1 - p.row0;
+  if (rows <= 0) return hipSuccess;
+  dim3 grid((p.nx + RS_TX - 1) / RS_TX, (rows + RS_TY - 1) / RS_TY);
+  hipLaunchKernelGGL(k_rayshoot, grid, dim3(RS_THREADS), 0, st, p, counts, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
+                                     const float* d_w, const int32_t* d_off, int32_t ntaps,
+                                     float scale, uint32_t* d_maxc, hipStream_t st) {
+  dim3 grid((mx + 15) / 16, (my + 15) / 16);
+  hipLaunchKernelGGL(k_normalize_convolve, grid, dim3(256), 0, st, counts, map, mx, my, d_w, d_off,
+                     ntaps, scale, d_maxc);
+  return hipGetLastError();
+}
+
+}  // namespace morse

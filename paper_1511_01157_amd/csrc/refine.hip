@@ -1,0 +1,318 @@
+// Gradient refinement of search candidates on gfx950.
+//
+// Chi-square gradient.  The profiled chi-square (Eqs. 5-6 of McDougall & Albrow 2015;
+// sec. 4.2 bilinear map sampling) has (F_s, F_b) at their exact minimisers, so by the
+// envelope theorem d chi2/d theta = -2 F_s sum w r dA/d theta with r = F - F_s A - F_b.
+// One wavefront per candidate: pass 1 accumulates the normal-equation sums and solves
+// for (F_s, F_b); pass 2 re-samples each point, forms r, and accumulates in FP64
+//   chi2 = sum w r^2,  Gx = sum w r dA/dzx,  Gy = sum w r dA/dzy,
+//   Gxt = sum w r tau dA/dzx,  Gyt = sum w r tau dA/dzy,
+//   Ga = sum w r (zx dA/dzy - zy dA/dzx),
+// from which, with zeta = tau (ca, sa) + u0 (-sa, ca) and tau = (t - t0)/tE,
+//   d/dt0 = -2 F_s (-(ca Gx + sa Gy)/tE),  d/du0 = -2 F_s (-sa Gx + ca Gy),
+//   d/dtE = -2 F_s (-(ca Gxt + sa Gyt)/tE), d/dalpha = -2 F_s Ga.
+// dA/dzeta: on the map, k (e0 + fy (e1 - e0), ax1 - ax0) from the bilinear cell;
+// off the map, A(u) = (u^2+2)/(u sqrt(u^2+4)) gives dA/du = -8/(u^2 (u^2+4)^(3/2)).
+//
+// L-BFGS.  One thread per candidate runs the update of the state machine (accept on
+// the Armijo test or backtrack; two-loop recursion for the next direction), keeping
+// the binary32 variables p and the FP64 history in structure-of-arrays form.
+
+#include "internal.h"
+
+namespace morse {
+
+namespace {
+
+__device__ __forceinline__ double dot4(const double* a, const double* b) {
+  return ((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3];
+}
+
+__global__ __launch_bounds__(256) void k_chi2_grad(GradArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wpb = blockDim.x / kWave;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  for (int64_t c = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; c < a.n; c += nw) {
+    if (a.active && !a.active[c]) continue;
+    const int32_t e = a.event[c];
+    const int32_t mi = a.mapidx[c];
+    if (e < 0 || e >= a.n_events || mi < 0 || mi >= a.n_maps) {
+      if (lane == 0) {
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
+        if (a.chi2) a.chi2[c] = nan;
+        if (a.grad)
+          for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = nan;
+        if (a.fs) a.fs[c] = nan;
+        if (a.fb) a.fb[c] = nan;
+      }
+      continue;
+    }
+    const MapC m = a.maps[mi];
+    double t0, u0, tE, al, tE_anchor = 0.0;
+    if (a.anchor) {
+      const double* an = a.anchor + 4 * c;
+      const float* p = a.pt + 4 * c;
+      tE_anchor = an[2];
+      t0 = an[0] + (double)p[0] * an[2];
+      u0 = an[1] + (double)p[1];
+      tE = an[2] * exp((double)p[2]);
+      al = an[3] + (double)p[3];
+    } else {
+      const double* p = a.params + 4 * c;
+      t0 = p[0];
+      u0 = p[1];
+      tE = p[2];
+      al = p[3];
+    }
+    double sn, cs;
+    sincos(al, &sn, &cs);
+    const float iE = (float)(1.0 / tE);
+    const float ca = (float)cs;
+    const float sa = (float)sn;
+    const float bx = (float)(-u0 * sn);
+    const float by = (float)(u0 * cs);
+    const float t0p = (float)(t0 - a.lc.t_ref[e]);
+
+    const int64_t p0 = a.lc.off[e];
+    const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
+    const float* t = a.lc.t + p0;
+    const double* w = a.lc.w + p0;
+    const double* wF = a.lc.wF + p0;
+    const double* F = a.lc.F + p0;
+    const double Sw = a.lc.sums[3 * e], SF = a.lc.sums[3 * e + 1];
+
+    // pass 1: normal-equation sums
+    double sA = 0.0, sAA = 0.0, sAF = 0.0;
+    for (int32_t i = lane; i < np; i += kWave) {
+      const double A = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by);
+      const double wa = w[i] * A;
+      sA += wa;
+      sAA = fma(wa, A, sAA);
+      sAF = fma(A, wF[i], sAF);
+    }
+    sA = wave_sum(sA);
+    sAA = wave_sum(sAA);
+    sAF = wave_sum(sAF);
+    double Fs, Fb;
+    profiled_fit(Sw, sA, sAA, SF, sAF, Fs, Fb);
+
+    // pass 2: residuals, direct chi-square and gradient sums
+    const double kx = (double)m.kx, ky = (double)m.ky;
+    double chi = 0.0, Gx = 0.0, Gy = 0.0, Gxt = 0.0, Gyt = 0.0, Ga = 0.0;
+    for (int32_t i = lane; i < np; i += kWave) {
+      const Sample s = sample_full(m, t[i], t0p, iE, ca, sa, bx, by);
+      const double A = (double)s.A;
+      const double r = F[i] - Fs * A - Fb;
+      const double wr = w[i] * r;
+      const double zx = (double)s.zx, zy = (double)s.zy, tau = (double)s.tau;
+      double dAx, dAy;
+      if (s.on) {
+        const double e0 = (double)s.e0, e1 = (double)s.e1;
+        dAx = kx * (e0 + (double)s.fy * (e1 - e0));
+        dAy = ky * ((double)s.ax1 - (double)s.ax0);
+      } else {
+        const double u2 = zx * zx + zy * zy;
+        const double u = sqrt(u2);
+        const double q = u2 + 4.0;
+        const double dAdu = -8.0 / (u2 * (q * sqrt(q)));
+        dAx = dAdu * zx / u;
+        dAy = dAdu * zy / u;
+      }
+      chi = fma(wr, r, chi);
+      Gx = fma(wr, dAx, Gx);
+      Gy = fma(wr, dAy, Gy);
+      Gxt = fma(wr * dAx, tau, Gxt);
+      Gyt = fma(wr * dAy, tau, Gyt);
+      Ga = fma(wr, zx * dAy - zy * dAx, Ga);
+    }
+    chi = wave_sum(chi);
+    Gx = wave_sum(Gx);
+    Gy = wave_sum(Gy);
+    Gxt = wave_sum(Gxt);
+    Gyt = wave_sum(Gyt);
+    Ga = wave_sum(Ga);
+    if (lane == 0) {
+      const double c64 = (double)ca, s64 = (double)sa;
+      const double k2 = -2.0 * Fs;
+      double g[4];
+      g[0] = k2 * (-(c64 * Gx + s64 * Gy) / tE);
+      g[1] = k2 * (-s64 * Gx + c64 * Gy);
+      g[2] = k2 * (-(c64 * Gxt + s64 * Gyt) / tE);
+      g[3] = k2 * Ga;
+      if (a.anchor) {  // gradient with respect to the scaled variables
+        g[0] = g[0] * tE_anchor;
+        g[2] = g[2] * tE;
+      }
+      if (a.chi2) a.chi2[c] = chi;
+      if (a.grad)
+        for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = g[q];
+      if (a.fs) a.fs[c] = Fs;
+      if (a.fb) a.fb[c] = Fb;
+    }
+  }
+}
+
+constexpr int kMaxHist = 16;
+
+struct Cand {
+  const LbfgsState& s;
+  int64_t c;
+  __device__ double* S(int slot) const { return s.S + ((c * s.m + slot) * 4); }
+  __device__ double* Y(int slot) const { return s.Y + ((c * s.m + slot) * 4); }
+};
+
+// New search direction at the accepted point (p, g); sets d, step, nls, pt and may
+// stop the candidate when the trial would not move it.
+__device__ void new_direction(const LbfgsState& s, int64_t c) {
+  Cand cd{s, c};
+  double g[4], q[4], r[4], d[4], alph[kMaxHist];
+  for (int k = 0; k < 4; ++k) g[k] = s.g[4 * c + k];
+  int nh = s.nhist[c];
+  int st = s.start[c];
+  for (int k = 0; k < 4; ++k) q[k] = g[k];
+  for (int h = nh - 1; h >= 0; --h) {
+    const int slot = (st + h) % s.m;
+    const double a = s.R[c * s.m + slot] * dot4(cd.S(slot), q);
+    alph[h] = a;
+    for (int k = 0; k < 4; ++k) q[k] = q[k] - a * cd.Y(slot)[k];
+  }
+  const double gn = sqrt(dot4(g, g));
+  double gamma;
+  if (nh > 0) {
+    const int slot = (st + nh - 1) % s.m;
+    gamma = dot4(cd.S(slot), cd.Y(slot)) / dot4(cd.Y(slot), cd.Y(slot));
+  } else {
+    gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
+  }
+  for (int k = 0; k < 4; ++k) r[k] = gamma * q[k];
+  for (int h = 0; h < nh; ++h) {
+    const int slot = (st + h) % s.m;
+    const double b = s.R[c * s.m + slot] * dot4(cd.Y(slot), r);
+    for (int k = 0; k < 4; ++k) r[k] = r[k] + cd.S(slot)[k] * (alph[h] - b);
+  }
+  for (int k = 0; k < 4; ++k) d[k] = -r[k];
+  const double gd = dot4(g, d);
+  bool finite = true;
+  for (int k = 0; k < 4; ++k) finite = finite && isfinite(d[k]);
+  if (!(gd < 0.0) || !finite) {
+    s.nhist[c] = 0;
+    s.start[c] = 0;
+    gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
+    for (int k = 0; k < 4; ++k) d[k] = -(gamma * g[k]);
+  }
+  s.step[c] = 1.0;
+  s.nls[c] = 0;
+  bool moved = false;
+  for (int k = 0; k < 4; ++k) {
+    s.d[4 * c + k] = d[k];
+    const float pk = s.p[4 * c + k];
+    const float v = (float)((double)pk + 1.0 * d[k]);
+    s.pt[4 * c + k] = v;
+    moved = moved || (v != pk);
+  }
+  if (!moved) s.active[c] = 0;
+}
+
+__global__ void k_lbfgs_update(LbfgsState s, int32_t round) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= s.n || !s.active[c]) return;
+  const double ft = s.ft[c];
+  if (round == 0) {
+    for (int k = 0; k < 4; ++k) {
+      s.p[4 * c + k] = s.pt[4 * c + k];
+      s.g[4 * c + k] = s.gt[4 * c + k];
+    }
+    s.f[c] = ft;
+    new_direction(s, c);
+    return;
+  }
+  double g[4], d[4];
+  for (int k = 0; k < 4; ++k) {
+    g[k] = s.g[4 * c + k];
+    d[k] = s.d[4 * c + k];
+  }
+  const double gd = dot4(g, d);
+  const double t = s.step[c];
+  if (isfinite(ft) && ft <= s.f[c] + (s.c1 * t) * gd) {
+    double sv[4], yv[4];
+    for (int k = 0; k < 4; ++k) {
+      sv[k] = (double)s.pt[4 * c + k] - (double)s.p[4 * c + k];
+      yv[k] = s.gt[4 * c + k] - g[k];
+    }
+    const double sy = dot4(sv, yv);
+    if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
+      int nh = s.nhist[c];
+      int st = s.start[c];
+      int slot;
+      if (nh < s.m) {
+        slot = (st + nh) % s.m;
+        s.nhist[c] = nh + 1;
+      } else {
+        slot = st;
+        s.start[c] = (st + 1) % s.m;
+      }
+      Cand cd{s, c};
+      for (int k = 0; k < 4; ++k) {
+        cd.S(slot)[k] = sv[k];
+        cd.Y(slot)[k] = yv[k];
+      }
+      s.R[c * s.m + slot] = 1.0 / sy;
+    }
+    for (int k = 0; k < 4; ++k) {
+      s.p[4 * c + k] = s.pt[4 * c + k];
+      s.g[4 * c + k] = s.gt[4 * c + k];
+    }
+    s.f[c] = ft;
+    new_direction(s, c);
+  } else {
+    const int n = s.nls[c] + 1;
+    s.nls[c] = n;
+    if (n >= s.max_ls) {
+      s.active[c] = 0;
+    } else {
+      const double tn = t * s.shrink;
+      s.step[c] = tn;
+      for (int k = 0; k < 4; ++k)
+        s.pt[4 * c + k] = (float)((double)s.p[4 * c + k] + tn * d[k]);
+    }
+  }
+}
+
+__global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= s.n) return;
+  const double* an = s.anchor + 4 * c;
+  const float* p = s.p + 4 * c;
+  params[4 * c + 0] = an[0] + (double)p[0] * an[2];
+  params[4 * c + 1] = an[1] + (double)p[1];
+  params[4 * c + 2] = an[2] * exp((double)p[2]);
+  params[4 * c + 3] = an[3] + (double)p[3];
+  if (chi2_out) chi2_out[c] = s.f[c];
+}
+
+}  // namespace
+
+hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  int64_t blocks = (a.n + 3) / 4;
+  if (blocks > 1 << 18) blocks = 1 << 18;
+  hipLaunchKernelGGL(k_chi2_grad, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s,
+                     round);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_finish(const LbfgsState& s, double* params, double* chi2_out,
+                               hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lbfgs_finish, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s,
+                     params, chi2_out);
+  return hipGetLastError();
+}
+
+}  // namespace morse

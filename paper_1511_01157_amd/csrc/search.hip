@@ -1,0 +1,516 @@
+// Trajectory search on gfx950 (sec. 4.2 of McDougall & Albrow 2015: the chi-square of
+// every trajectory through a map, sampled by bilinear interpolation; Eqs. 5-6: the flux
+// is linear in the magnification, so (F_s, F_b) are profiled out by weighted least
+// squares).
+//
+// Layout.  One wavefront scores one trajectory at a time: its 64 lanes stride over the
+// light-curve points (time-ordered, so a wave's lanes sample neighbouring map cells and
+// leave the map together), each lane keeps FP64 partial sums S_A, S_AA, S_AF, and a
+// butterfly shuffle reduces them in a fixed order.  S_w, S_F and S_FF depend only on
+// the light curve and are computed once per event.  The 2x2 solve and the chi-square
+//   chi2 = S_FF - 2 F_s S_AF - 2 F_b S_F + F_s^2 S_AA + 2 F_s F_b S_A + F_b^2 S_w
+// (the expansion of sum w (F - F_s a - F_b)^2) are FP64; this is one pass over the
+// points instead of two.
+//
+// Plain mode launches one grid per (event, map).  Batched mode launches one persistent
+// grid whose workgroups pull (map, event, trajectory block) items from an atomic
+// counter, so thousands of (event, map) pairs of uneven length share one launch; the
+// per-trajectory arithmetic and reduction order are the same, so results are
+// bitwise identical between the modes.
+
+#include "internal.h"
+
+namespace morse {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Light-curve preparation: wF = w F per point and, per event, S_w, S_F, S_FF with
+// Neumaier-compensated partial sums combined in a fixed order.
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
+  double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
+__global__ __launch_bounds__(256) void k_lc_prep(const double* __restrict__ F,
+                                                 const double* __restrict__ w,
+                                                 const int64_t* __restrict__ off,
+                                                 double* __restrict__ wF, double* __restrict__ sums) {
+  __shared__ double s_part[256][6];
+  const int e = blockIdx.x;
+  const int64_t a = off[e], b = off[e + 1];
+  double s0 = 0, c0 = 0, s1 = 0, c1 = 0, s2 = 0, c2 = 0;
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+    const double wi = w[i];
+    const double wf = wi * F[i];
+    wF[i] = wf;
+    neumaier_add(s0, c0, wi);
+    neumaier_add(s1, c1, wf);
+    neumaier_add(s2, c2, wf * F[i]);
+  }
+  s_part[threadIdx.x][0] = s0;
+  s_part[threadIdx.x][1] = c0;
+  s_part[threadIdx.x][2] = s1;
+  s_part[threadIdx.x][3] = c1;
+  s_part[threadIdx.x][4] = s2;
+  s_part[threadIdx.x][5] = c2;
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int q = threadIdx.x;
+    double s = 0, c = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      neumaier_add(s, c, s_part[k][2 * q]);
+      neumaier_add(s, c, s_part[k][2 * q + 1]);
+    }
+    sums[3 * e + q] = s + c;
+  }
+}
+
+// Per-trajectory constants: FP64 trigonometry, rounded once to binary32.
+__device__ __forceinline__ TrajC make_traj(double t0, double u0, double tE, double al) {
+  double s, c;
+  sincos(al, &s, &c);
+  TrajC r;
+  r.t0 = t0;
+  r.iE = (float)(1.0 / tE);
+  r.ca = (float)c;
+  r.sa = (float)s;
+  r.bx = (float)(-u0 * s);
+  r.by = (float)(u0 * c);
+  r.pad = 0.0f;
+  return r;
+}
+
+__global__ void k_traj_prep_list(const double* __restrict__ params, int64_t n, TrajC* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double* p = params + 4 * i;
+    out[i] = make_traj(p[0], p[1], p[2], p[3]);
+  }
+}
+
+// axes = [u0 (nu) | alpha (na) | t0 (nt) | tE (ne)]; index ((iu*na + ia)*nt + it)*ne + ie
+__global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, int32_t na, int32_t nt,
+                                 int32_t ne, TrajC* __restrict__ out) {
+  const int64_t n = (int64_t)nu * na * nt * ne;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = i;
+    const int ie = (int)(r % ne);
+    r /= ne;
+    const int it = (int)(r % nt);
+    r /= nt;
+    const int ia = (int)(r % na);
+    const int iu = (int)(r / na);
+    out[i] = make_traj(axes[nu + na + it], axes[iu], axes[nu + na + nt + ie], axes[nu + ia]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Score one trajectory with one wavefront.  All lanes return the same values.
+__device__ __forceinline__ void score_traj(const MapC& m, const float* __restrict__ t,
+                                           const double* __restrict__ w,
+                                           const double* __restrict__ wF, int32_t np, double Sw,
+                                           double SF, double SFF, float t0p, const TrajC& c,
+                                           int lane, double& chi2, double& Fs, double& Fb) {
+  double sA = 0.0, sAA = 0.0, sAF = 0.0;
+  for (int32_t i = lane; i < np; i += kWave) {
+    const float A = sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
+    const double a = (double)A;
+    const double wa = w[i] * a;
+    sA += wa;
+    sAA = fma(wa, a, sAA);
+    sAF = fma(a, wF[i], sAF);
+  }
+  sA = wave_sum(sA);
+  sAA = wave_sum(sAA);
+  sAF = wave_sum(sAF);
+  profiled_fit(Sw, sA, sAA, SF, sAF, Fs, Fb);
+  chi2 = ((SFF - 2.0 * Fs * sAF) - 2.0 * Fb * SF) + ((Fs * Fs) * sAA + 2.0 * Fs * Fb * sA) +
+         (Fb * Fb) * Sw;
+}
+
+__global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ tc, int64_t n_traj,
+                                                      LcView lc, int32_t e, MapC m, SearchOut out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wpb = blockDim.x / kWave;
+  const int64_t nw = (int64_t)gridDim.x * wpb;
+  const int64_t p0 = lc.off[e];
+  const int32_t np = (int32_t)(lc.off[e + 1] - p0);
+  const float* t = lc.t + p0;
+  const double* w = lc.w + p0;
+  const double* wF = lc.wF + p0;
+  const double Sw = lc.sums[3 * e], SF = lc.sums[3 * e + 1], SFF = lc.sums[3 * e + 2];
+  const double tref = lc.t_ref[e];
+  for (int64_t k = (int64_t)blockIdx.x * wpb + (threadIdx.x / kWave); k < n_traj; k += nw) {
+    const TrajC c = tc[k];
+    const float t0p = (float)(c.t0 - tref);
+    double chi2, Fs, Fb;
+    score_traj(m, t, w, wF, np, Sw, SF, SFF, t0p, c, lane, chi2, Fs, Fb);
+    if (lane == 0) {
+      if (out.chi2) out.chi2[k] = chi2;
+      if (out.fs) out.fs[k] = Fs;
+      if (out.fb) out.fb[k] = Fb;
+    }
+  }
+}
+
+// Persistent batched search.  Item = (map * n_events + event) * n_blocks + block:
+// consecutive items share the map and the light curve, so concurrently running
+// workgroups hit the same map lines in L2.
+__global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
+  __shared__ int64_t s_item;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int wpb = blockDim.x / kWave;
+  const int64_t nb = (a.n_traj + a.traj_per_item - 1) / a.traj_per_item;
+  const int64_t total = nb * a.n_events * a.n_maps;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    const int64_t b = item % nb;
+    const int64_t me = item / nb;
+    const int32_t e = (int32_t)(me % a.n_events);
+    const int32_t mi = (int32_t)(me / a.n_events);
+    const MapC m = a.maps[mi];
+    const int64_t p0 = a.lc.off[e];
+    const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
+    const double Sw = a.lc.sums[3 * e], SF = a.lc.sums[3 * e + 1], SFF = a.lc.sums[3 * e + 2];
+    const double tref = a.lc.t_ref[e];
+    const TrajC* tc = a.tc + (a.shared ? 0 : (int64_t)e * a.n_traj);
+    const int64_t k1 = min((b + 1) * (int64_t)a.traj_per_item, a.n_traj);
+    const int64_t obase = ((int64_t)e * a.n_maps + mi) * a.n_traj;
+    for (int64_t k = b * a.traj_per_item + wave; k < k1; k += wpb) {
+      const TrajC c = tc[k];
+      const float t0p = (float)(c.t0 - tref);
+      double chi2, Fs, Fb;
+      score_traj(m, a.lc.t + p0, a.lc.w + p0, a.lc.wF + p0, np, Sw, SF, SFF, t0p, c, lane, chi2,
+                 Fs, Fb);
+      if (lane == 0) {
+        if (a.out.chi2) a.out.chi2[obase + k] = chi2;
+        if (a.out.fs) a.out.fs[obase + k] = Fs;
+        if (a.out.fb) a.out.fb[obase + k] = Fb;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Selection.  Keys order doubles totally: -0 is taken as +0, NaN after everything;
+// ties broken by the index.
+__device__ __forceinline__ uint64_t order_key(double x) {
+  if (x != x) return ~0ull;
+  if (x == 0.0) x = 0.0;
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(256) void k_best(const double* __restrict__ chi2, int64_t seg_len,
+                                              double* __restrict__ best_chi2,
+                                              int64_t* __restrict__ best_idx) {
+  __shared__ uint64_t s_key[4];
+  __shared__ int64_t s_idx[4];
+  const double* base = chi2 + (int64_t)blockIdx.x * seg_len;
+  uint64_t bk = ~0ull;
+  int64_t bi = INT64_MAX;
+  for (int64_t i = threadIdx.x; i < seg_len; i += blockDim.x) {
+    const uint64_t k = order_key(base[i]);
+    if (k < bk || (k == bk && i < bi)) {
+      bk = k;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t ok = __shfl_xor(bk, o, kWave);
+    const int64_t oi = __shfl_xor(bi, o, kWave);
+    if (ok < bk || (ok == bk && oi < bi)) {
+      bk = ok;
+      bi = oi;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_key[threadIdx.x >> 6] = bk;
+    s_idx[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q)
+      if (s_key[q] < bk || (s_key[q] == bk && s_idx[q] < bi)) {
+        bk = s_key[q];
+        bi = s_idx[q];
+      }
+    if (seg_len == 0) bi = -1;
+    if (best_chi2) best_chi2[blockIdx.x] = (bi >= 0) ? base[bi] : __longlong_as_double(0x7ff8000000000000ll);
+    if (best_idx) best_idx[blockIdx.x] = bi;
+  }
+}
+
+constexpr int TK_THREADS = 1024;
+constexpr int TK_WAVES = TK_THREADS / kWave;
+constexpr int TK_MAXK = 4096;
+
+// Block-wide exclusive prefix of a flag in index order (ballot within a wave, then
+// the wave totals).  Returns the position; *total receives the block total.
+__device__ __forceinline__ int block_scan_flag(bool f, int* s_wave, int* total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t m = __ballot(f);
+  const int inwave = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int q = 0; q < TK_WAVES; ++q) {
+    const int v = s_wave[q];
+    before += (q < wave) ? v : 0;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inwave;
+}
+
+// Radix select of the k-th smallest key (8 passes of 8-bit digits over the segment),
+// ordered compaction of the keys below it plus the first ties in index order, then a
+// bitonic sort of the k survivors by (key, position) in LDS.
+__global__ __launch_bounds__(TK_THREADS) void k_topk(const double* __restrict__ chi2,
+                                                     int64_t seg_len, int32_t k,
+                                                     double* __restrict__ out_chi2,
+                                                     int64_t* __restrict__ out_idx,
+                                                     uint64_t* __restrict__ skeys,
+                                                     int64_t* __restrict__ sidx) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int64_t s_krem;
+  __shared__ int s_wave[TK_WAVES];
+  __shared__ uint64_t lkey[TK_MAXK];
+  __shared__ int32_t lpos[TK_MAXK];
+
+  const int tid = threadIdx.x;
+  const int64_t seg = blockIdx.x;
+  const double* base = chi2 + seg * seg_len;
+  uint64_t* kk = skeys + seg * (int64_t)k;
+  int64_t* ki = sidx + seg * (int64_t)k;
+  const int64_t keff = min((int64_t)k, seg_len);
+
+  uint64_t prefix = 0, pmask = 0;
+  int64_t krem = keff;
+  if (keff > 0) {
+    for (int pass = 0; pass < 8; ++pass) {
+      const int shift = 56 - 8 * pass;
+      for (int q = tid; q < 256; q += TK_THREADS) hist[q] = 0u;
+      __syncthreads();
+      for (int64_t i = tid; i < seg_len; i += TK_THREADS) {
+        const uint64_t key = order_key(base[i]);
+        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t cum = 0;
+        int d = 255;
+        for (int q = 0; q < 256; ++q) {
+          if (cum + hist[q] >= krem) {
+            d = q;
+            break;
+          }
+          cum += hist[q];
+        }
+        s_prefix = prefix | ((uint64_t)d << shift);
+        s_krem = krem - cum;
+      }
+      __syncthreads();
+      prefix = s_prefix;
+      krem = s_krem;
+      pmask |= 255ull << shift;
+      __syncthreads();
+    }
+  }
+  const uint64_t T = prefix;
+  const int64_t nless = keff - krem;
+
+  // ordered compaction
+  int64_t less_base = 0, eq_base = 0;
+  for (int64_t start = 0; start < seg_len && keff > 0; start += TK_THREADS) {
+    const int64_t i = start + tid;
+    const uint64_t key = (i < seg_len) ? order_key(base[i]) : ~0ull;
+    const bool isless = (i < seg_len) && key < T;
+    const bool iseq = (i < seg_len) && key == T;
+    int tl, te;
+    const int pl = block_scan_flag(isless, s_wave, &tl);
+    const int pe = block_scan_flag(iseq, s_wave, &te);
+    if (isless) {
+      kk[less_base + pl] = key;
+      ki[less_base + pl] = i;
+    }
+    if (iseq && eq_base + pe < krem) {
+      kk[nless + eq_base + pe] = key;
+      ki[nless + eq_base + pe] = i;
+    }
+    less_base += tl;
+    eq_base += te;
+  }
+  __syncthreads();
+
+  // bitonic sort of (key, position) for the keff survivors
+  int n2 = 1;
+  while (n2 < keff) n2 <<= 1;
+  for (int q = tid; q < n2; q += TK_THREADS) {
+    lkey[q] = (q < keff) ? kk[q] : ~0ull;
+    lpos[q] = (q < keff) ? q : 0x7fffffff;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = tid; q < n2; q += TK_THREADS) {
+        const int r = q ^ stride;
+        if (r > q) {
+          const bool up = (q & size) == 0;
+          const uint64_t ka = lkey[q], kb = lkey[r];
+          const int32_t pa = lpos[q], pb = lpos[r];
+          const bool a_gt_b = (ka > kb) || (ka == kb && pa > pb);
+          if (a_gt_b == up) {
+            lkey[q] = kb;
+            lkey[r] = ka;
+            lpos[q] = pb;
+            lpos[r] = pa;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < k; q += TK_THREADS) {
+    if (q < keff) {
+      const int64_t idx = ki[lpos[q]];
+      out_idx[seg * k + q] = idx;
+      out_chi2[seg * k + q] = base[idx];
+    } else {
+      out_idx[seg * k + q] = -1;
+      out_chi2[seg * k + q] = __longlong_as_double(0x7ff8000000000000ll);
+    }
+  }
+}
+
+// Top-k flat index -> (t0, u0, tE, alpha), event and map index.  axes != nullptr:
+// product grid [u0 | alpha | t0 | tE]; else list rows (per event unless shared).
+__global__ void k_candidates(const double* __restrict__ axes, int32_t nu, int32_t na, int32_t nt,
+                             int32_t ne, const double* __restrict__ list, int32_t shared,
+                             int64_t n_traj, int32_t n_events, int32_t n_maps, int32_t k,
+                             const int64_t* __restrict__ idx, double* __restrict__ params,
+                             int32_t* __restrict__ event, int32_t* __restrict__ mapidx) {
+  const int64_t n = (int64_t)n_events * k;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = (int32_t)(i / k);
+    int64_t f = idx[i];
+    if (f < 0 || f >= (int64_t)n_maps * n_traj) f = 0;
+    const int32_t m = (int32_t)(f / n_traj);
+    const int64_t tj = f - (int64_t)m * n_traj;
+    double* out = params + 4 * i;
+    if (axes) {
+      int64_t r = tj;
+      const int ie = (int)(r % ne);
+      r /= ne;
+      const int it = (int)(r % nt);
+      r /= nt;
+      const int ia = (int)(r % na);
+      const int iu = (int)(r / na);
+      out[0] = axes[nu + na + it];
+      out[1] = axes[iu];
+      out[2] = axes[nu + na + nt + ie];
+      out[3] = axes[nu + ia];
+    } else {
+      const double* p = list + 4 * ((shared ? 0 : (int64_t)e * n_traj) + tj);
+      out[0] = p[0];
+      out[1] = p[1];
+      out[2] = p[2];
+      out[3] = p[3];
+    }
+    event[i] = e;
+    mapidx[i] = m;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_candidates(const double* axes, int32_t nu, int32_t na, int32_t nt, int32_t ne,
+                             const double* list, int32_t shared, int64_t n_traj, int32_t n_events,
+                             int32_t n_maps, int32_t k, const int64_t* idx, double* params,
+                             int32_t* event, int32_t* mapidx, hipStream_t st) {
+  const int64_t n = (int64_t)n_events * k;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_candidates, dim3((unsigned)blocks), dim3(256), 0, st, axes, nu, na, nt, ne,
+                     list, shared, n_traj, n_events, n_maps, k, idx, params, event, mapidx);
+  return hipGetLastError();
+}
+
+hipError_t launch_lc_prep(const float* /*t*/, const double* F, const double* w, const int64_t* off,
+                          int32_t n_events, double* wF, double* sums, hipStream_t st) {
+  if (n_events <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lc_prep, dim3(n_events), dim3(256), 0, st, F, w, off, wF, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_prep_list(const double* params, int64_t n, TrajC* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_traj_prep_list, dim3((unsigned)blocks), dim3(256), 0, st, params, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_prep_grid(const double* axes, int32_t nu, int32_t na, int32_t nt,
+                                 int32_t ne, TrajC* out, hipStream_t st) {
+  const int64_t n = (int64_t)nu * na * nt * ne;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_traj_prep_grid, dim3((unsigned)blocks), dim3(256), 0, st, axes, nu, na, nt,
+                     ne, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_plain(const TrajC* tc, int64_t n_traj, LcView lc, int32_t event,
+                               MapC map, SearchOut out, int waves_per_block, hipStream_t st) {
+  if (n_traj <= 0) return hipSuccess;
+  const int threads = waves_per_block * kWave;
+  int64_t blocks = (n_traj + waves_per_block - 1) / waves_per_block;
+  if (blocks > 1 << 20) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_search_plain, dim3((unsigned)blocks), dim3(threads), 0, st, tc, n_traj, lc,
+                     event, map, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_search_batched, dim3(a.grid_blocks), dim3(a.waves_per_block * kWave), 0, st,
+                     a);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(const double* chi2, int64_t n_seg, int64_t seg_len, double* best_chi2,
+                       int64_t* best_idx, hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_best, dim3((unsigned)n_seg), dim3(256), 0, st, chi2, seg_len, best_chi2,
+                     best_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32_t k,
+                       double* out_chi2, int64_t* out_idx, uint64_t* scratch_keys,
+                       int64_t* scratch_idx, hipStream_t st) {
+  if (n_seg <= 0 || k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_topk, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, chi2, seg_len, k,
+                     out_chi2, out_idx, scratch_keys, scratch_idx);
+  return hipGetLastError();
+}
+
+}  // namespace morse

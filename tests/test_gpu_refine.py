@@ -1,0 +1,131 @@
+"""GPU parity of the chi-square gradient and the L-BFGS refinement: chi2 within 1e-6,
+gradient components within 1e-4 max(|g_k|, 1e-3 |g|_inf) of the FP64 oracle adjoint
+(binary32 samples) and of central differences of the FP64 objective; refinement
+endpoints against the oracle state machine."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_01157_amd as M
+import workloads as W
+from oracle.adjoint import chi2_grad as oracle_grad, fd_gradient
+from oracle.lbfgs import LbfgsOptions, refine as oracle_refine
+from tests.helpers import note, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def dmap(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+
+
+def candidates(n, seed, truth, spread=(1.0, 0.02, 1.5, 0.05)):
+    rng = np.random.default_rng(seed)
+    base = np.array([truth["t0"], truth["u0"], truth["tE"], truth["alpha"]])
+    return base + rng.normal(0, 1, (n, 4)) * np.array(spread)
+
+
+def grad_ok(g, ref):
+    gmax = np.abs(ref).max(axis=1, keepdims=True)
+    tol = 1e-4 * np.maximum(np.abs(ref), 1e-3 * gmax)
+    return np.abs(g - ref) <= tol
+
+
+def test_chi2_grad_vs_oracle_adjoint(tiny_oracle_map):
+    c = W.config("tiny")
+    amap = tiny_oracle_map[2]
+    ev = W.load_lightcurve("tiny")
+    P = candidates(64, 1, ev["truth"])
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    note("chi2_grad tiny 64 candidates")
+    chi2, g, fs, fb = M.chi2_grad([(dmap(amap), c["window"])], lcs, torch.from_numpy(P).to(DEV),
+                                  torch.zeros(64, dtype=torch.int32, device=DEV),
+                                  torch.zeros(64, dtype=torch.int32, device=DEV))
+    oc, og, ofs, ofb = oracle_grad(amap, c["window"], ev["tt"], ev["F"], ev["w"], P, ev["t_ref"])
+    assert rel_err(chi2.cpu().numpy(), oc).max() < 1e-6
+    assert rel_err(chi2.cpu().numpy(), oc).max() < 1e-10
+    assert grad_ok(g.cpu().numpy(), og).all()
+    assert rel_err(fs.cpu().numpy(), ofs, 1e-3).max() < 1e-8
+
+
+def test_gradient_vs_central_differences(tiny_oracle_map):
+    """16 candidates, central differences of the FP64 objective with step 1e-5
+    relative; components where a sample changes bilinear cell between the two
+    evaluations are excluded (the interpolant has kinks there)."""
+    c = W.config("tiny")
+    amap = tiny_oracle_map[2]
+    ev = W.load_lightcurve("tiny")
+    P = candidates(16, 2, ev["truth"])
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    note("chi2_grad tiny 16 candidates vs FD")
+    _, g, _, _ = M.chi2_grad([(dmap(amap), c["window"])], lcs, torch.from_numpy(P).to(DEV),
+                             torch.zeros(16, dtype=torch.int32, device=DEV),
+                             torch.zeros(16, dtype=torch.int32, device=DEV))
+    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
+    g = g.cpu().numpy()
+    assert elig.sum() >= 8
+    assert grad_ok(g, fd)[elig].all()
+
+
+def test_multi_event_multi_map_gradients():
+    maps = []
+    for s, q in [(0.9, 0.02), (1.2, 3e-3)]:
+        from tests.helpers import oracle_map
+        win = (0.0, 0.0, 1.6, 1.6, 256, 256)
+        maps.append((oracle_map(s, q, (0.0, 0.0, 4.0, 4.0, 2048, 2048), win, 0.0)[2], win))
+    evs = [W.load_lightcurve("batched", e) for e in (3, 7, 11)]
+    rng = np.random.default_rng(3)
+    ev_idx = rng.integers(0, 3, 48).astype(np.int32)
+    mi = rng.integers(0, 2, 48).astype(np.int32)
+    P = np.stack([candidates(1, 10 + k, evs[ev_idx[k]]["truth"])[0] for k in range(48)])
+    lcs = M.LightCurveBatch.from_events(evs, DEV)
+    note("chi2_grad multi-event")
+    chi2, g, _, _ = M.chi2_grad([(dmap(a), w) for a, w in maps], lcs, torch.from_numpy(P).to(DEV),
+                                torch.from_numpy(ev_idx).to(DEV), torch.from_numpy(mi).to(DEV))
+    chi2, g = chi2.cpu().numpy(), g.cpu().numpy()
+    for k in range(48):
+        ev = evs[ev_idx[k]]
+        amap, win = maps[mi[k]]
+        oc, og, _, _ = oracle_grad(amap, win, ev["tt"], ev["F"], ev["w"], P[k:k + 1], ev["t_ref"])
+        assert rel_err(chi2[k], oc[0]) < 1e-6
+        assert grad_ok(g[k:k + 1], og).all(), k
+
+
+def test_refine_vs_oracle_state_machine(tiny_oracle_map):
+    c = W.config("tiny")
+    amap = tiny_oracle_map[2]
+    ev = W.load_lightcurve("tiny")
+    n = 32
+    P = candidates(n, 4, ev["truth"], spread=(0.5, 0.01, 1.0, 0.02))
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    note("refine tiny 32 candidates x 50 rounds")
+    out, chi2, chi2_0 = M.refine([(dmap(amap), c["window"])], lcs, torch.from_numpy(P).to(DEV),
+                                 torch.zeros(n, dtype=torch.int32, device=DEV),
+                                 torch.zeros(n, dtype=torch.int32, device=DEV), steps=50)
+    out, chi2, chi2_0 = out.cpu().numpy(), chi2.cpu().numpy(), chi2_0.cpu().numpy()
+    op, oc, o0 = oracle_refine(amap, c["window"], ev["tt"], ev["F"], ev["w"], ev["t_ref"], P,
+                               LbfgsOptions(steps=50))
+    assert rel_err(chi2_0, o0).max() < 1e-10
+    assert np.all(chi2 <= chi2_0)
+    # identical state machines: endpoints agree unless an FP64 rounding difference in
+    # a sum flipped one binary32 rounding of a trial point somewhere along the path
+    same = rel_err(chi2, oc) < 1e-6
+    assert same.mean() >= 0.9
+    assert np.median(chi2 / chi2_0) < 0.9
+
+
+def test_chi2fn_autograd(tiny_oracle_map):
+    c = W.config("tiny")
+    amap = tiny_oracle_map[2]
+    ev = W.load_lightcurve("tiny")
+    P = torch.from_numpy(candidates(8, 5, ev["truth"])).to(DEV).requires_grad_(True)
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    maps = [(dmap(amap), c["window"])]
+    z = torch.zeros(8, dtype=torch.int32, device=DEV)
+    note("Chi2Fn backward")
+    chi2 = M.Chi2Fn.apply(P, maps, lcs, z, z)
+    w = torch.linspace(0.5, 2.0, 8, dtype=torch.float64, device=DEV)
+    (chi2 * w).sum().backward()
+    _, g, _, _ = M.chi2_grad(maps, lcs, P.detach(), z, z)
+    assert torch.allclose(P.grad, w[:, None] * g, rtol=0, atol=0)

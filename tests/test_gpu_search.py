@@ -1,0 +1,182 @@
+"""GPU parity of the trajectory search: chi2 / Fs / Fb per trajectory against the
+oracle (same oracle-built map, same light curves), gate relative 1e-6 (expected
+~1e-12); best / top-k selection; plain == batched bitwise; determinism; edge cases."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_01157_amd as M
+import workloads as W
+from oracle.fit import topk as oracle_topk
+from oracle.search import grid_params, search_mirror32
+from tests.helpers import events, note, oracle_map, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GATE = 1e-6
+
+
+def dmap(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(DEV)
+
+
+def oracle_search(amap, window, ev, params):
+    return search_mirror32(amap, window, ev["tt"], ev["F"], ev["w"], params, ev["t_ref"])
+
+
+def test_tiny_grid_plain_vs_oracle(tiny_oracle_map):
+    c = W.config("tiny")
+    _, _, amap = tiny_oracle_map
+    ev = W.load_lightcurve("tiny")
+    axes = W.grid_axes("tiny")
+    note("search tiny grid plain")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    r = M.search([(dmap(amap), c["window"])], lcs, M.grid_trajectories(*axes), "plain",
+                 fs=True, fb=True, best=True, top_k=16)
+    chi2, fs, fb, _ = oracle_search(amap, c["window"], ev, grid_params(*axes))
+    g = r["chi2"].cpu().numpy()[0, 0]
+    assert rel_err(g, chi2).max() < GATE
+    assert rel_err(g, chi2).max() < 1e-9
+    assert rel_err(r["fs"].cpu().numpy()[0, 0], fs, 1e-3).max() < 1e-8
+    assert rel_err(r["fb"].cpu().numpy()[0, 0], fb, 1e-3).max() < 1e-8
+    bi = int(r["best_idx"][0, 0])
+    assert chi2[bi] <= chi2.min() * (1 + GATE)
+    ti, tv = oracle_topk(chi2, 16)
+    assert rel_err(r["topk_chi2"].cpu().numpy()[0], tv).max() < GATE
+    # indices agree wherever neighbouring values are not within the gate
+    gi = r["topk_idx"].cpu().numpy()[0]
+    sep = np.diff(np.sort(chi2))[:17] > 1e-8 * chi2.min()
+    for k in range(16):
+        if sep[max(k - 1, 0)] and sep[k]:
+            assert gi[k] == ti[k]
+
+
+def test_plain_equals_batched_and_deterministic(tiny_oracle_map):
+    c = W.config("tiny")
+    _, _, amap = tiny_oracle_map
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    tr = M.grid_trajectories(*W.grid_axes("tiny"))
+    maps = [(dmap(amap), c["window"])]
+    note("search tiny plain/batched x2")
+    a = M.search(maps, lcs, tr, "plain", best=True, top_k=8)
+    b = M.search(maps, lcs, tr, "batched", best=True, top_k=8)
+    b2 = M.search(maps, lcs, tr, "batched", best=True, top_k=8)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(b[k], b2[k]), k
+
+
+def small_maps():
+    out = []
+    for s, q in [(0.9, 0.02), (1.2, 3e-3), (0.7, 0.2)]:
+        rays = (0.0, 0.0, 4.0, 4.0, 2048, 2048)
+        win = (0.05, -0.02, 1.6, 1.6, 256, 256)
+        out.append((oracle_map(s, q, rays, win, 0.0)[2], win))
+    return out
+
+
+def test_multi_event_multi_map_lists_vs_oracle():
+    """Ragged events (incl. 3, 64, 65 points), three maps, per-event trajectory lists,
+    both modes, against the oracle for every (event, map, trajectory)."""
+    maps = small_maps()
+    evs = events("batched", [0, 1, 2, 3])
+    evs.append({k: (v[:3] if k in ("tt", "F", "w", "t") else v) for k, v in evs[0].items()})
+    evs.append({k: (v[:64] if k in ("tt", "F", "w", "t") else v) for k, v in evs[1].items()})
+    evs.append({k: (v[:65] if k in ("tt", "F", "w", "t") else v) for k, v in evs[2].items()})
+    n = 150
+    params = np.stack([W.random_trajectories("batched", e % 4, n) for e in range(len(evs))])
+    lcs = M.LightCurveBatch.from_events(evs, DEV)
+    tr = M.list_trajectories(torch.from_numpy(params).to(DEV), shared=False)
+    dm = [(dmap(a), w) for a, w in maps]
+    note("search multi-event lists plain + batched")
+    rp = M.search(dm, lcs, tr, "plain", fs=True, best=True, top_k=20)
+    rb = M.search(dm, lcs, tr, "batched", fs=True, best=True, top_k=20)
+    for k in rp:
+        assert torch.equal(rp[k], rb[k]), k
+    g = rp["chi2"].cpu().numpy()
+    for e, ev in enumerate(evs):
+        allc = []
+        for m, (amap, win) in enumerate(maps):
+            chi2, fs, _, _ = oracle_search(amap, win, ev, params[e])
+            # 3-point events fit exactly (chi2 ~ 0): compare on the data scale
+            floor = 1e-9 * float(np.sum(ev["w"] * ev["F"] ** 2))
+            assert rel_err(g[e, m], chi2, floor).max() < GATE, (e, m)
+            allc.append(chi2)
+        allc = np.concatenate(allc)
+        tv = np.sort(allc)[:20]
+        gt = rp["topk_chi2"].cpu().numpy()[e]
+        assert rel_err(gt, tv, 1e-9 * float(np.sum(ev["w"] * ev["F"] ** 2))).max() < GATE
+        gi = rp["topk_idx"].cpu().numpy()[e]
+        assert np.array_equal(np.sort(gt), gt)
+        assert len(set(gi.tolist())) == 20
+
+
+def test_degenerate_and_off_map_cases():
+    """A constant map makes A constant on the map (degenerate fit); a window far from
+    every trajectory puts every sample off the map (single-lens magnification)."""
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    flat = np.full((64, 64), 2.5, np.float32)
+    win_on = (0.0, 0.0, 100.0, 100.0, 64, 64)     # covers every trajectory: A = 2.5
+    win_off = (50.0, 50.0, 1.0, 1.0, 64, 64)      # covers none
+    params = W.random_trajectories("tiny", 0, 64)
+    params[:, 2] = np.abs(params[:, 2])
+    tr = M.list_trajectories(torch.from_numpy(params).to(DEV))
+    note("search degenerate / off-map")
+    r = M.search([(dmap(flat), win_on), (dmap(flat), win_off)], lcs, tr, "plain", fs=True, fb=True)
+    for m, win in enumerate((win_on, win_off)):
+        chi2, fs, fb, deg = oracle_search(flat, win, ev, params)
+        if m == 0:
+            assert deg.all()
+            assert np.all(r["fs"].cpu().numpy()[0, 0] == 0.0)
+        assert rel_err(r["chi2"].cpu().numpy()[0, m], chi2).max() < GATE
+        assert rel_err(r["fb"].cpu().numpy()[0, m], fb, 1e-3).max() < 1e-8
+
+
+def test_large_full_grid_sampled_vs_oracle(large_oracle_map):
+    """Full size of the large workload: 524288 grid trajectories x 3000 points on the
+    2048^2 map in the batched launch the bench times; 384 sampled trajectories and the
+    whole top-64 checked one by one against the oracle; plain == batched."""
+    c = W.config("large")
+    _, _, amap = large_oracle_map
+    ev = W.load_lightcurve("large")
+    axes = W.grid_axes("large")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    tr = M.grid_trajectories(*axes)
+    maps = [(dmap(amap), c["window"])]
+    note("search large grid batched")
+    rb = M.search(maps, lcs, tr, "batched", best=True, top_k=64)
+    note("search large grid plain")
+    rp = M.search(maps, lcs, tr, "plain", best=True, top_k=64)
+    for k in rb:
+        assert torch.equal(rb[k], rp[k]), k
+    g = rb["chi2"].cpu().numpy()[0, 0]
+    P = grid_params(*axes)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.choice(len(P), 384, replace=False),
+                                    rb["topk_idx"].cpu().numpy()[0]]))
+    chi2, _, _, _ = oracle_search(amap, c["window"], ev, P[idx])
+    assert rel_err(g[idx], chi2).max() < GATE
+    # selection is consistent with the full chi2 array
+    order = np.lexsort((np.arange(len(g)), g))[:64]
+    assert np.array_equal(rb["topk_idx"].cpu().numpy()[0], order)
+    assert int(rb["best_idx"][0, 0]) == order[0]
+
+
+def test_search_rejects_bad_arguments(tiny_oracle_map):
+    c = W.config("tiny")
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    m = [(dmap(tiny_oracle_map[2]), c["window"])]
+    note("search argument errors")
+    with pytest.raises(M.MorseError) as e:
+        M.search(m, lcs, M.grid_trajectories([0.1], [0.0], [0.0], [-1.0]))
+    assert e.value.code == -1
+    with pytest.raises(M.MorseError) as e:
+        M.search(m, lcs, M.grid_trajectories([0.1], [0.0], [0.0], [10.0]), top_k=5000)
+    assert e.value.code == -5
+    short = dict(ev, tt=ev["tt"][:2], F=ev["F"][:2], w=ev["w"][:2])
+    with pytest.raises(M.MorseError) as e:
+        M.search(m, M.LightCurveBatch.from_events([short], DEV), M.grid_trajectories([0.1], [0.0], [0.0], [10.0]))
+    assert e.value.code == -1
