@@ -40,7 +40,7 @@ def sample_derivatives(amap, window, params, tt=None, t=None, t_ref=0.0, mode="m
         ca = np.cos(params[:, 3])[:, None]
         sa = np.sin(params[:, 3])[:, None]
     d = {n: np.asarray(v, dtype=np.float64) if isinstance(v, np.ndarray) else float(v)
-         for n, v in P.items() if n != "onmap"}
+         for n, v in P.items() if n not in ("onmap", "i0", "j0")}
     on = P["onmap"]
     dgx = d["e0"] + d["fy"] * (d["e1"] - d["e0"])
     dgy = d["ax1"] - d["ax0"]
@@ -106,15 +106,23 @@ def chi2_exact64(amap, window, t, F, w, params, t_ref=0.0):
     return fit_and_chi2(A, F, w)[0]
 
 
-def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5):
-    """Central differences of the FP64 objective (reading X20).
+def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5, mode="exact64", tt=None):
+    """Central differences of the chi-square objective (reading X20).
 
-    Step h = rel * max(|theta|, s_theta), s = (tE, 1e-2, tE, 1).  A component is
-    eligible only when no sample changes bilinear cell or on/off-map state between
-    theta - h and theta + h (the bilinear interpolant has kinks at cell edges).
-    Returns (fd [n, 4], eligible [n, 4]).
+    mode "exact64": FP64 sampling from absolute times t; mode "mirror32": the
+    binary32 sampling of the search (times tt = fl32(t - t_ref)), i.e. the objective
+    the refinement minimises.  Step h = rel * max(|theta|, s_theta),
+    s = (tE, 1e-2, tE, 1).  A component is eligible only when no sample changes
+    bilinear cell or on/off-map state between theta - h and theta + h (the bilinear
+    interpolant has kinks at cell edges).  Returns (fd [n, 4], eligible [n, 4]).
     """
     params = np.asarray(params, dtype=np.float64).reshape(-1, 4)
+
+    def evaluate(p):
+        if mode == "exact64":
+            return sample_exact64(amap, window, p, t, t_ref, parts=True)
+        return sample_mirror32(amap, window, traj_constants32(p, t_ref), tt, parts=True)
+
     n = len(params)
     fd = np.zeros((n, 4))
     elig = np.zeros((n, 4), dtype=bool)
@@ -125,10 +133,10 @@ def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5):
         pm = params.copy()
         pp[:, k] += h
         pm[:, k] -= h
-        Ap, Pp = sample_exact64(amap, window, pp, t, t_ref, parts=True)
-        Am, Pm = sample_exact64(amap, window, pm, t, t_ref, parts=True)
-        cp = fit_and_chi2(Ap, F, w)[0]
-        cm = fit_and_chi2(Am, F, w)[0]
+        Ap, Pp = evaluate(pp)
+        Am, Pm = evaluate(pm)
+        cp = fit_and_chi2(np.asarray(Ap, np.float64), F, w)[0]
+        cm = fit_and_chi2(np.asarray(Am, np.float64), F, w)[0]
         fd[:, k] = (cp - cm) / (2.0 * h)
         same = (Pp["onmap"] == Pm["onmap"]) & (Pp["i0"] == Pm["i0"]) & (Pp["j0"] == Pm["j0"])
         elig[:, k] = same.all(axis=1)

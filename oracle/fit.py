@@ -2,14 +2,17 @@
 
 Eq. 5: F_i = F_S A(t_i) + F_B; Eq. 6: the (difference) flux is linear in A, so for a
 given trajectory the two flux parameters have a closed-form weighted least-squares
-solution.  With weights w_i = 1/sigma_i^2 and a_i = A(t_i) promoted to FP64:
-    S_w = sum w, S_A = sum w a, S_AA = sum w a^2, S_F = sum w F, S_AF = sum w a F,
-    det = S_AA S_w - S_A^2,
-    F_s = (S_AF S_w - S_A S_F)/det,  F_b = (S_AA S_F - S_A S_AF)/det,
-which is the unconstrained minimiser (reading X15).  When det <= 1e-12 S_AA S_w the
-magnification is (numerically) constant and the fit degenerates (reading X16):
-F_s = 0, F_b = S_F/S_w.  Chi-square (sec. 4.2: sum of per-point contributions) is
-summed directly, chi2 = sum w (F - F_s a - F_b)^2, over the same a.
+solution, the unconstrained minimiser (reading X15).  With weights w_i = 1/sigma_i^2
+and a_i = A(t_i) promoted to FP64 it is computed from the centred normal equations:
+    S_w = sum w,  abar = sum w a / S_w,  Fbar = sum w F / S_w,
+    S_aa = sum w (a - abar)^2,  S_aF = sum w (a - abar)(F - Fbar),
+    F_s = S_aF / S_aa,  F_b = Fbar - F_s abar,
+the same minimiser as (S_AF S_w - S_A S_F)/det, (S_AA S_F - S_A S_AF)/det with
+det = S_AA S_w - S_A^2 = S_w S_aa, written without the cancellation of det when a is
+nearly constant.  When det <= 1e-12 S_AA S_w (i.e. S_aa <= 1e-12 S_AA, S_AA = sum w a^2)
+the magnification is numerically constant and the fit degenerates (reading X16):
+F_s = 0, F_b = Fbar.  Chi-square (sec. 4.2: sum of per-point contributions) is summed
+directly, chi2 = sum w (F - F_s a - F_b)^2, over the same a.
 
 All sums here use Neumaier-compensated FP64 summation over the points, vectorised
 across trajectories.  Selection (sec. 4.4, best solutions as seeds) orders by
@@ -40,20 +43,29 @@ def neumaier_sum(x, axis=-1):
 
 
 def normal_sums(a, F, w):
+    """Weighted sums of the fit (last axis = points): S_w, S_A, S_AA, S_F, S_AF and the
+    centred abar, Fbar, S_aa, S_aF."""
     a = np.asarray(a, dtype=np.float64)
     F = np.broadcast_to(np.asarray(F, dtype=np.float64), a.shape)
     w = np.broadcast_to(np.asarray(w, dtype=np.float64), a.shape)
-    return dict(Sw=neumaier_sum(w), SA=neumaier_sum(w * a), SAA=neumaier_sum(w * a * a),
-                SF=neumaier_sum(w * F), SAF=neumaier_sum(w * a * F))
+    Sw = neumaier_sum(w)
+    SA = neumaier_sum(w * a)
+    SF = neumaier_sum(w * F)
+    abar = SA / Sw
+    Fbar = SF / Sw
+    da = a - abar[..., None]
+    dF = F - Fbar[..., None]
+    return dict(Sw=Sw, SA=SA, SAA=neumaier_sum(w * a * a), SF=SF, SAF=neumaier_sum(w * a * F),
+                abar=abar, Fbar=Fbar, Saa=neumaier_sum(w * da * da), SaF=neumaier_sum(w * da * dF))
 
 
 def profiled_fit(sums):
-    Sw, SA, SAA, SF, SAF = (sums[k] for k in ("Sw", "SA", "SAA", "SF", "SAF"))
-    det = SAA * Sw - SA * SA
-    degenerate = ~(det > DEGENERATE_RTOL * SAA * Sw)
+    """(Fs, Fb, degenerate) from ``normal_sums`` (centred form, see the module doc)."""
+    Sw, SAA, Saa, SaF, abar, Fbar = (sums[k] for k in ("Sw", "SAA", "Saa", "SaF", "abar", "Fbar"))
+    degenerate = ~(Saa > DEGENERATE_RTOL * SAA)
     with np.errstate(divide="ignore", invalid="ignore"):
-        Fs = np.where(degenerate, 0.0, (SAF * Sw - SA * SF) / det)
-        Fb = np.where(degenerate, SF / Sw, (SAA * SF - SA * SAF) / det)
+        Fs = np.where(degenerate, 0.0, SaF / Saa)
+        Fb = np.where(degenerate, Fbar, Fbar - Fs * abar)
     return Fs, Fb, degenerate
 
 

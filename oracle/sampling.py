@@ -87,7 +87,8 @@ def sample_mirror32(amap, window, consts, tt, parts=False):
     A = np.where(on, A_on, A_off)
     if parts:
         return A, dict(tau=tau, zx=zx, zy=zy, onmap=on, fx=fx, fy=fy, e0=e0, e1=e1,
-                       ax0=ax0, ax1=ax1, kx=g["kx"], ky=g["ky"])
+                       ax0=ax0, ax1=ax1, kx=g["kx"], ky=g["ky"], i0=np.where(on, i0, -1),
+                       j0=np.where(on, j0, -1))
     return A
 
 

@@ -650,7 +650,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   sp.lc.t = lcs->d_t;
   sp.lc.w = lcs->d_weight;
   sp.lc.F = lcs->d_flux;
-  sp.lc.wF = d_wF;
+  sp.lc.wFc = d_wF;
   sp.lc.off = d_off;
   sp.lc.sums = d_sums;
   sp.lc.t_ref = d_tref;
@@ -660,7 +660,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
 // Preparation kernels (light-curve sums, trajectory constants).
 hipError_t enqueue_prep(const SearchPlan& sp, const morse_trajectories* trajs, hipStream_t st) {
   hipError_t e = launch_lc_prep(sp.lc.t, sp.lc.F, sp.lc.w, sp.lc.off, sp.n_events,
-                                (double*)sp.lc.wF, (double*)sp.lc.sums, st);
+                                (double*)sp.lc.wFc, (double*)sp.lc.sums, st);
   if (e != hipSuccess) return e;
   if (trajs->kind == MORSE_TRAJ_GRID)
     return launch_traj_prep_grid(sp.axes, trajs->n_u0, trajs->n_alpha, trajs->n_t0, trajs->n_tE,
@@ -959,11 +959,11 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   lc.t = lcs->d_t;
   lc.w = lcs->d_weight;
   lc.F = lcs->d_flux;
-  lc.wF = (double*)pl.ptr(ctx, i_wF);
+  lc.wFc = (double*)pl.ptr(ctx, i_wF);
   lc.off = d_off;
   lc.sums = (double*)pl.ptr(ctx, i_sums);
   lc.t_ref = d_tref;
-  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, lcs->n_events, (double*)lc.wF,
+  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, lcs->n_events, (double*)lc.wFc,
                               (double*)lc.sums, ctx->stream));
   return MORSE_OK;
 }

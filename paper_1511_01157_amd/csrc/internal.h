@@ -42,15 +42,16 @@ struct MapC {
   float lx, ly;                  // on-map bound: g < M - 1
 };
 
-// Light curves after preparation: per point binary32 time offset, w and w*F;
-// per event the constant sums S_w, S_F, S_FF.
+// Light curves after preparation: per point binary32 time offset, w and the
+// centred weighted flux w (F - Fbar); per event S_w, the weighted mean Fbar and
+// V = sum w (F - Fbar)^2.
 struct LcView {
   const float* t;
   const double* w;
-  const double* wF;
+  const double* wFc;
   const double* F;
   const int64_t* off;   // device CSR offsets [n_events + 1]
-  const double* sums;   // [n_events][3]: S_w, S_F, S_FF
+  const double* sums;   // [n_events][3]: S_w, Fbar, V
   const double* t_ref;  // [n_events]
 };
 
@@ -129,19 +130,38 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Profiled fit (Eqs. 5-6) from the five sums; degenerate when
-// det <= 1e-12 S_AA S_w.  Returns true when degenerate.
-__device__ __forceinline__ bool profiled_fit(double Sw, double SA, double SAA, double SF,
-                                             double SAF, double& Fs, double& Fb) {
-  double det = SAA * Sw - SA * SA;
-  if (!(det > 1e-12 * SAA * Sw)) {
-    Fs = 0.0;
-    Fb = SF / Sw;
-    return true;
+// Profiled fit (Eqs. 5-6) in centred form.  With b = A - 1 and per-point
+// wFc = w (F - Fbar), one pass gives B1 = sum w b, B2 = sum w b^2, C = sum b wFc.
+// Then S_bb = B2 - B1^2/S_w equals det/S_w of the normal equations
+// (det = S_AA S_w - S_A^2, S_AA = B2 + 2 B1 + S_w), and
+//   F_s = C / S_bb,  F_b = Fbar - F_s (1 + B1/S_w),  chi2 = V - F_s C.
+// Degenerate (det <= 1e-12 S_AA S_w, i.e. S_bb <= 1e-12 S_AA): F_s = 0, F_b = Fbar,
+// chi2 = V.  The one-pass chi2 loses about eps * (S_AA/S_bb) * (V/chi2) relative
+// accuracy; `recheck` is set when that bound exceeds 1e-9 (an ill-conditioned or
+// near-perfect fit), and the caller then sums w r^2 directly in a second pass.
+struct Fit {
+  double Fs, Fb, chi2;
+  bool degenerate, recheck;
+};
+
+__device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, double B1, double B2,
+                                           double C) {
+  Fit f;
+  const double SAA = (B2 + 2.0 * B1) + Sw;
+  const double Sbb = B2 - (B1 * B1) / Sw;
+  f.degenerate = !(Sbb > 1e-12 * SAA);
+  f.recheck = false;
+  if (f.degenerate) {
+    f.Fs = 0.0;
+    f.Fb = Fbar;
+    f.chi2 = V;
+    return f;
   }
-  Fs = (SAF * Sw - SA * SF) / det;
-  Fb = (SAA * SF - SA * SAF) / det;
-  return false;
+  f.Fs = C / Sbb;
+  f.Fb = Fbar - f.Fs * (1.0 + B1 / Sw);
+  f.chi2 = V - f.Fs * C;
+  f.recheck = !(f.chi2 > 0.0) || (SAA * V > 1e7 * Sbb * f.chi2);
+  return f;
 }
 
 // ---------------------------------------------------------------------------

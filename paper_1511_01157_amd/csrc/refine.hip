@@ -4,7 +4,8 @@
 // sec. 4.2 bilinear map sampling) has (F_s, F_b) at their exact minimisers, so by the
 // envelope theorem d chi2/d theta = -2 F_s sum w r dA/d theta with r = F - F_s A - F_b.
 // One wavefront per candidate: pass 1 accumulates the normal-equation sums and solves
-// for (F_s, F_b); pass 2 re-samples each point, forms r, and accumulates in FP64
+// for (F_s, F_b) as the search does; pass 2 re-samples each point, forms r, and
+// accumulates in FP64
 //   chi2 = sum w r^2,  Gx = sum w r dA/dzx,  Gy = sum w r dA/dzy,
 //   Gxt = sum w r tau dA/dzx,  Gyt = sum w r tau dA/dzy,
 //   Ga = sum w r (zx dA/dzy - zy dA/dzx),
@@ -77,24 +78,24 @@ __global__ __launch_bounds__(256) void k_chi2_grad(GradArgs a) {
     const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
     const float* t = a.lc.t + p0;
     const double* w = a.lc.w + p0;
-    const double* wF = a.lc.wF + p0;
+    const double* wFc = a.lc.wFc + p0;
     const double* F = a.lc.F + p0;
-    const double Sw = a.lc.sums[3 * e], SF = a.lc.sums[3 * e + 1];
+    const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
 
-    // pass 1: normal-equation sums
-    double sA = 0.0, sAA = 0.0, sAF = 0.0;
+    // pass 1: normal-equation sums (centred form) and the profiled fit
+    double B1 = 0.0, B2 = 0.0, C = 0.0;
     for (int32_t i = lane; i < np; i += kWave) {
-      const double A = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by);
-      const double wa = w[i] * A;
-      sA += wa;
-      sAA = fma(wa, A, sAA);
-      sAF = fma(A, wF[i], sAF);
+      const double b = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by) - 1.0;
+      const double wb = w[i] * b;
+      B1 += wb;
+      B2 = fma(wb, b, B2);
+      C = fma(b, wFc[i], C);
     }
-    sA = wave_sum(sA);
-    sAA = wave_sum(sAA);
-    sAF = wave_sum(sAF);
-    double Fs, Fb;
-    profiled_fit(Sw, sA, sAA, SF, sAF, Fs, Fb);
+    B1 = wave_sum(B1);
+    B2 = wave_sum(B2);
+    C = wave_sum(C);
+    const Fit fit = centred_fit(Sw, Fbar, V, B1, B2, C);
+    const double Fs = fit.Fs, Fb = fit.Fb;
 
     // pass 2: residuals, direct chi-square and gradient sums
     const double kx = (double)m.kx, ky = (double)m.ky;

@@ -5,12 +5,13 @@
 //
 // Layout.  One wavefront scores one trajectory at a time: its 64 lanes stride over the
 // light-curve points (time-ordered, so a wave's lanes sample neighbouring map cells and
-// leave the map together), each lane keeps FP64 partial sums S_A, S_AA, S_AF, and a
-// butterfly shuffle reduces them in a fixed order.  S_w, S_F and S_FF depend only on
-// the light curve and are computed once per event.  The 2x2 solve and the chi-square
-//   chi2 = S_FF - 2 F_s S_AF - 2 F_b S_F + F_s^2 S_AA + 2 F_s F_b S_A + F_b^2 S_w
-// (the expansion of sum w (F - F_s a - F_b)^2) are FP64; this is one pass over the
-// points instead of two.
+// leave the map together), each lane keeps FP64 partial sums of the normal equations
+// in centred form (b = A - 1 against the mean-centred weighted flux), and a butterfly
+// shuffle reduces them in a fixed order.  S_w, the weighted mean flux and
+// V = sum w (F - Fbar)^2 depend only on the light curve and are computed once per
+// event.  The 2x2 solve gives chi2 = V - F_s C in the same pass; when the rounding
+// bound of that form exceeds 1e-9 relative (ill-conditioned or near-perfect fits) the
+// wave re-samples and sums w (F - F_s A - F_b)^2 directly.
 //
 // Plain mode launches one grid per (event, map).  Batched mode launches one persistent
 // grid whose workgroups pull (map, event, trajectory block) items from an atomic
@@ -25,8 +26,9 @@ namespace morse {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Light-curve preparation: wF = w F per point and, per event, S_w, S_F, S_FF with
-// Neumaier-compensated partial sums combined in a fixed order.
+// Light-curve preparation, one workgroup per event: S_w and S_F with
+// Neumaier-compensated partial sums combined in a fixed order, Fbar = S_F/S_w, then
+// wFc = w (F - Fbar) per point and V = sum w (F - Fbar)^2 the same way.
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
   double t = s + v;
   if (fabs(s) >= fabs(v))
@@ -39,34 +41,54 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
 __global__ __launch_bounds__(256) void k_lc_prep(const double* __restrict__ F,
                                                  const double* __restrict__ w,
                                                  const int64_t* __restrict__ off,
-                                                 double* __restrict__ wF, double* __restrict__ sums) {
-  __shared__ double s_part[256][6];
+                                                 double* __restrict__ wFc, double* __restrict__ sums) {
+  __shared__ double s_part[256][4];
+  __shared__ double s_res[3];
   const int e = blockIdx.x;
   const int64_t a = off[e], b = off[e + 1];
-  double s0 = 0, c0 = 0, s1 = 0, c1 = 0, s2 = 0, c2 = 0;
+  double s0 = 0, c0 = 0, s1 = 0, c1 = 0;
   for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
     const double wi = w[i];
-    const double wf = wi * F[i];
-    wF[i] = wf;
     neumaier_add(s0, c0, wi);
-    neumaier_add(s1, c1, wf);
-    neumaier_add(s2, c2, wf * F[i]);
+    neumaier_add(s1, c1, wi * F[i]);
   }
   s_part[threadIdx.x][0] = s0;
   s_part[threadIdx.x][1] = c0;
   s_part[threadIdx.x][2] = s1;
   s_part[threadIdx.x][3] = c1;
-  s_part[threadIdx.x][4] = s2;
-  s_part[threadIdx.x][5] = c2;
   __syncthreads();
-  if (threadIdx.x < 3) {
+  if (threadIdx.x < 2) {
     const int q = threadIdx.x;
     double s = 0, c = 0;
     for (int k = 0; k < (int)blockDim.x; ++k) {
       neumaier_add(s, c, s_part[k][2 * q]);
       neumaier_add(s, c, s_part[k][2 * q + 1]);
     }
-    sums[3 * e + q] = s + c;
+    s_res[q] = s + c;
+  }
+  __syncthreads();
+  const double Sw = s_res[0];
+  const double Fbar = s_res[1] / Sw;
+  double s2 = 0, c2 = 0;
+  for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
+    const double d = F[i] - Fbar;
+    const double wd = w[i] * d;
+    wFc[i] = wd;
+    neumaier_add(s2, c2, wd * d);
+  }
+  __syncthreads();
+  s_part[threadIdx.x][0] = s2;
+  s_part[threadIdx.x][1] = c2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0, c = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      neumaier_add(s, c, s_part[k][0]);
+      neumaier_add(s, c, s_part[k][1]);
+    }
+    sums[3 * e] = Sw;
+    sums[3 * e + 1] = Fbar;
+    sums[3 * e + 2] = s + c;
   }
 }
 
@@ -114,24 +136,34 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 // Score one trajectory with one wavefront.  All lanes return the same values.
 __device__ __forceinline__ void score_traj(const MapC& m, const float* __restrict__ t,
                                            const double* __restrict__ w,
-                                           const double* __restrict__ wF, int32_t np, double Sw,
-                                           double SF, double SFF, float t0p, const TrajC& c,
+                                           const double* __restrict__ wFc,
+                                           const double* __restrict__ F, int32_t np, double Sw,
+                                           double Fbar, double V, float t0p, const TrajC& c,
                                            int lane, double& chi2, double& Fs, double& Fb) {
-  double sA = 0.0, sAA = 0.0, sAF = 0.0;
+  double B1 = 0.0, B2 = 0.0, C = 0.0;
   for (int32_t i = lane; i < np; i += kWave) {
-    const float A = sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
-    const double a = (double)A;
-    const double wa = w[i] * a;
-    sA += wa;
-    sAA = fma(wa, a, sAA);
-    sAF = fma(a, wF[i], sAF);
+    const double b = (double)sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by) - 1.0;
+    const double wb = w[i] * b;
+    B1 += wb;
+    B2 = fma(wb, b, B2);
+    C = fma(b, wFc[i], C);
   }
-  sA = wave_sum(sA);
-  sAA = wave_sum(sAA);
-  sAF = wave_sum(sAF);
-  profiled_fit(Sw, sA, sAA, SF, sAF, Fs, Fb);
-  chi2 = ((SFF - 2.0 * Fs * sAF) - 2.0 * Fb * SF) + ((Fs * Fs) * sAA + 2.0 * Fs * Fb * sA) +
-         (Fb * Fb) * Sw;
+  B1 = wave_sum(B1);
+  B2 = wave_sum(B2);
+  C = wave_sum(C);
+  const Fit f = centred_fit(Sw, Fbar, V, B1, B2, C);
+  Fs = f.Fs;
+  Fb = f.Fb;
+  chi2 = f.chi2;
+  if (f.recheck) {  // wave-uniform: the sums are identical on every lane
+    double q = 0.0;
+    for (int32_t i = lane; i < np; i += kWave) {
+      const double a = (double)sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
+      const double r = F[i] - Fs * a - Fb;
+      q = fma(w[i] * r, r, q);
+    }
+    chi2 = wave_sum(q);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ tc, int64_t n_traj,
@@ -143,14 +175,15 @@ __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ 
   const int32_t np = (int32_t)(lc.off[e + 1] - p0);
   const float* t = lc.t + p0;
   const double* w = lc.w + p0;
-  const double* wF = lc.wF + p0;
-  const double Sw = lc.sums[3 * e], SF = lc.sums[3 * e + 1], SFF = lc.sums[3 * e + 2];
+  const double* wFc = lc.wFc + p0;
+  const double* F = lc.F + p0;
+  const double Sw = lc.sums[3 * e], Fbar = lc.sums[3 * e + 1], V = lc.sums[3 * e + 2];
   const double tref = lc.t_ref[e];
   for (int64_t k = (int64_t)blockIdx.x * wpb + (threadIdx.x / kWave); k < n_traj; k += nw) {
     const TrajC c = tc[k];
     const float t0p = (float)(c.t0 - tref);
     double chi2, Fs, Fb;
-    score_traj(m, t, w, wF, np, Sw, SF, SFF, t0p, c, lane, chi2, Fs, Fb);
+    score_traj(m, t, w, wFc, F, np, Sw, Fbar, V, t0p, c, lane, chi2, Fs, Fb);
     if (lane == 0) {
       if (out.chi2) out.chi2[k] = chi2;
       if (out.fs) out.fs[k] = Fs;
@@ -182,7 +215,7 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
     const MapC m = a.maps[mi];
     const int64_t p0 = a.lc.off[e];
     const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
-    const double Sw = a.lc.sums[3 * e], SF = a.lc.sums[3 * e + 1], SFF = a.lc.sums[3 * e + 2];
+    const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
     const double tref = a.lc.t_ref[e];
     const TrajC* tc = a.tc + (a.shared ? 0 : (int64_t)e * a.n_traj);
     const int64_t k1 = min((b + 1) * (int64_t)a.traj_per_item, a.n_traj);
@@ -191,8 +224,8 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
       const TrajC c = tc[k];
       const float t0p = (float)(c.t0 - tref);
       double chi2, Fs, Fb;
-      score_traj(m, a.lc.t + p0, a.lc.w + p0, a.lc.wF + p0, np, Sw, SF, SFF, t0p, c, lane, chi2,
-                 Fs, Fb);
+      score_traj(m, a.lc.t + p0, a.lc.w + p0, a.lc.wFc + p0, a.lc.F + p0, np, Sw, Fbar, V, t0p, c,
+                 lane, chi2, Fs, Fb);
       if (lane == 0) {
         if (a.out.chi2) a.out.chi2[obase + k] = chi2;
         if (a.out.fs) a.out.fs[obase + k] = Fs;
@@ -454,9 +487,9 @@ hipError_t launch_candidates(const double* axes, int32_t nu, int32_t na, int32_t
 }
 
 hipError_t launch_lc_prep(const float* /*t*/, const double* F, const double* w, const int64_t* off,
-                          int32_t n_events, double* wF, double* sums, hipStream_t st) {
+                          int32_t n_events, double* wFc, double* sums, hipStream_t st) {
   if (n_events <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lc_prep, dim3(n_events), dim3(256), 0, st, F, w, off, wF, sums);
+  hipLaunchKernelGGL(k_lc_prep, dim3(n_events), dim3(256), 0, st, F, w, off, wFc, sums);
   return hipGetLastError();
 }
 

@@ -127,5 +127,6 @@ def test_build_map_rejects_bad_arguments():
         M.build_map(1.0, 0.1, (0, 0, 4, 4, 64, 64), (0, 0, 2, 2, 16, 16), rho=-1.0, device=DEV)
     assert e.value.code == -1
     with pytest.raises(M.MorseError) as e:
-        M.build_map(1.0, 0.1, (0, 0, 4, 4, 64, 64), (0, 0, 2, 2, 16, 16), rho=1.0, device=DEV)
+        # rho / pixel = 16 > 15: the stencil would exceed 31 x 31
+        M.build_map(1.0, 0.1, (0, 0, 4, 4, 64, 64), (0, 0, 2, 2, 16, 16), rho=2.0, device=DEV)
     assert e.value.code == -4

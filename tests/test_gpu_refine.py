@@ -10,6 +10,7 @@ import paper_1511_01157_amd as M
 import workloads as W
 from oracle.adjoint import chi2_grad as oracle_grad, fd_gradient
 from oracle.lbfgs import LbfgsOptions, refine as oracle_refine
+from oracle.sampling import sample_exact64, sample_mirror32, traj_constants32
 from tests.helpers import note, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -50,9 +51,12 @@ def test_chi2_grad_vs_oracle_adjoint(tiny_oracle_map):
 
 
 def test_gradient_vs_central_differences(tiny_oracle_map):
-    """16 candidates, central differences of the FP64 objective with step 1e-5
-    relative; components where a sample changes bilinear cell between the two
-    evaluations are excluded (the interpolant has kinks there)."""
+    """16 candidates, central differences with step 1e-5 relative of the objective the
+    refinement minimises (binary32 samples, FP64 fit), gate 1e-4; components where a
+    sample changes bilinear cell between the two evaluations are excluded (the
+    interpolant has kinks there).  Against central differences of the FP64-sampled
+    objective the binary32 positions (about 3e-5 pixel) move the 1%-noise residuals by
+    up to ~1e-4 of their size, so that comparison is held to 1e-3."""
     c = W.config("tiny")
     amap = tiny_oracle_map[2]
     ev = W.load_lightcurve("tiny")
@@ -62,10 +66,17 @@ def test_gradient_vs_central_differences(tiny_oracle_map):
     _, g, _, _ = M.chi2_grad([(dmap(amap), c["window"])], lcs, torch.from_numpy(P).to(DEV),
                              torch.zeros(16, dtype=torch.int32, device=DEV),
                              torch.zeros(16, dtype=torch.int32, device=DEV))
-    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
     g = g.cpu().numpy()
+    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5,
+                           mode="mirror32", tt=ev["tt"])
     assert elig.sum() >= 8
-    assert grad_ok(g, fd)[elig].all()
+    ok = grad_ok(g, fd)
+    assert ok[elig].all(), (g[elig & ~ok], fd[elig & ~ok])
+    fd64, elig64 = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
+    gmax = np.abs(fd64).max(axis=1, keepdims=True)
+    tol = 1e-3 * np.maximum(np.abs(fd64), 1e-3 * gmax)
+    assert elig64.sum() >= 8
+    assert (np.abs(g - fd64) <= tol)[elig64].all()
 
 
 def test_multi_event_multi_map_gradients():
