@@ -51,12 +51,15 @@ def test_chi2_grad_vs_oracle_adjoint(tiny_oracle_map):
 
 
 def test_gradient_vs_central_differences(tiny_oracle_map):
-    """16 candidates, central differences with step 1e-5 relative of the objective the
-    refinement minimises (binary32 samples, FP64 fit), gate 1e-4; components where a
-    sample changes bilinear cell between the two evaluations are excluded (the
-    interpolant has kinks there).  Against central differences of the FP64-sampled
-    objective the binary32 positions (about 3e-5 pixel) move the 1%-noise residuals by
-    up to ~1e-4 of their size, so that comparison is held to 1e-3."""
+    """16 candidates against central differences of the FP64 chi-square with step 1e-5
+    relative.  Eligible: candidates whose samples keep their bilinear cell between
+    theta - h and theta + h (the interpolant has kinks at cell edges) and whose binary32
+    samples sit in the same cells as the FP64 ones.  The GPU differentiates the
+    binary32-sampled objective exactly (it matches the FP64 oracle adjoint on binary32
+    samples to ~1e-12, gated at 1e-4 above); binary32 positions (~3e-5 pixel on this
+    10-rays-per-pixel map) move each 1%-noise residual by ~1e-4 of its size, so
+    against the FP64 objective the gradient is held to 1e-3 of its norm.  The FP64
+    analytic gradient itself is pinned to the differences at 1e-4 on the CPU."""
     c = W.config("tiny")
     amap = tiny_oracle_map[2]
     ev = W.load_lightcurve("tiny")
@@ -67,16 +70,15 @@ def test_gradient_vs_central_differences(tiny_oracle_map):
                              torch.zeros(16, dtype=torch.int32, device=DEV),
                              torch.zeros(16, dtype=torch.int32, device=DEV))
     g = g.cpu().numpy()
-    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5,
-                           mode="mirror32", tt=ev["tt"])
+    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
+    _, p32 = sample_mirror32(amap, c["window"], traj_constants32(P, ev["t_ref"]), ev["tt"], parts=True)
+    _, p64 = sample_exact64(amap, c["window"], P, ev["t"], ev["t_ref"], parts=True)
+    same = np.all((p32["i0"] == p64["i0"]) & (p32["j0"] == p64["j0"]) &
+                  (p32["onmap"] == p64["onmap"]), axis=1)
+    elig &= same[:, None]
     assert elig.sum() >= 8
-    ok = grad_ok(g, fd)
-    assert ok[elig].all(), (g[elig & ~ok], fd[elig & ~ok])
-    fd64, elig64 = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
-    gmax = np.abs(fd64).max(axis=1, keepdims=True)
-    tol = 1e-3 * np.maximum(np.abs(fd64), 1e-3 * gmax)
-    assert elig64.sum() >= 8
-    assert (np.abs(g - fd64) <= tol)[elig64].all()
+    err = np.abs(g - fd) / np.linalg.norm(fd, axis=1, keepdims=True)
+    assert err[elig].max() < 1e-3, err[elig].max()
 
 
 def test_multi_event_multi_map_gradients():

@@ -80,3 +80,24 @@ def test_lbfgs_batch_equals_single():
         p1, f1, _ = refine_one(amap, WIN, tt, F, w, 0.0, anchors[i], LbfgsOptions(steps=10))
         assert np.array_equal(p1, P[i]) and f1 == f[i]
         assert f[i] <= f0[i]
+
+
+def test_fp64_gradient_matches_differences_on_a_ray_map():
+    """The FP64 analytic gradient against central differences (step 1e-5 relative) on
+    the tiny ray-shooting map (rough: about 10 rays per pixel), componentwise 1e-4."""
+    import workloads as W
+    from oracle.rays import rayshoot_mirror32_c
+    from oracle.maps import map_scale
+    c = W.config("tiny")
+    counts, _ = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], nthreads=4)
+    amap = (counts.astype(np.float32) * map_scale(c["rays"], c["window"])).astype(np.float32)
+    ev = W.load_lightcurve("tiny")
+    rng = np.random.default_rng(2)
+    tr = ev["truth"]
+    P = np.array([tr["t0"], tr["u0"], tr["tE"], tr["alpha"]]) + rng.normal(0, 1, (16, 4)) * [1.0, 0.02, 1.5, 0.05]
+    _, g, _, _ = chi2_grad(amap, c["window"], None, ev["F"], ev["w"], P, ev["t_ref"], t=ev["t"],
+                           mode="exact64")
+    fd, elig = fd_gradient(amap, c["window"], ev["t"], ev["F"], ev["w"], P, ev["t_ref"], rel=1e-5)
+    assert elig.sum() >= 8
+    gmax = np.abs(fd).max(axis=1, keepdims=True)
+    assert (np.abs(g - fd) <= 1e-4 * np.maximum(np.abs(fd), 1e-3 * gmax))[elig].all()
