@@ -33,8 +33,9 @@ struct TuneCfg {
 // Candidate shapes of the batched search tried by the autotuner; index 0 is the
 // default before tuning.
 const TuneCfg kTune[] = {
-    {128, 4, 4}, {64, 4, 4}, {256, 4, 4}, {64, 8, 2},
-    {128, 8, 2}, {256, 8, 4}, {32, 4, 8}, {512, 8, 2},
+    {128, 8, 8}, {64, 4, 16}, {128, 4, 16}, {256, 8, 8},
+    {64, 8, 8},  {32, 4, 16}, {256, 4, 8},  {512, 8, 4},
+    {128, 8, 4}, {64, 2, 32},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 
@@ -513,8 +514,8 @@ struct SearchPlan {
   std::vector<MapC> h_maps;
   LcView lc{};
   double* chi2 = nullptr;  // output or workspace
-  uint64_t* tk_keys = nullptr;
-  int64_t* tk_idx = nullptr;
+  void* tk_scratch = nullptr;
+  int num_cu = 256;
   uint32_t* counter = nullptr;
   double* axes = nullptr;
 };
@@ -614,8 +615,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(256),
                i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
-               i_tkk = pl.add(k > 0 ? 8 * (size_t)k * sp.n_events : 0),
-               i_tki = pl.add(k > 0 ? 8 * (size_t)k * sp.n_events : 0);
+               i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
   double* d_tref = (double*)pl.ptr(ctx, i_tref);
@@ -626,8 +626,8 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   double* d_wF = (double*)pl.ptr(ctx, i_wF);
   sp.tc = (TrajC*)pl.ptr(ctx, i_tc);
   sp.chi2 = out->d_chi2 ? out->d_chi2 : (double*)pl.ptr(ctx, i_chi);
-  sp.tk_keys = (uint64_t*)pl.ptr(ctx, i_tkk);
-  sp.tk_idx = (int64_t*)pl.ptr(ctx, i_tki);
+  sp.tk_scratch = pl.ptr(ctx, i_tk);
+  sp.num_cu = ctx->num_cu;
   sp.h_maps.resize(n_maps);
   for (int i = 0; i < n_maps; ++i) sp.h_maps[i] = make_mapc(maps[i].d_map, maps[i].window);
   const uint64_t key = metadata_key(maps, n_maps, lcs, trajs);
@@ -676,7 +676,7 @@ hipError_t enqueue_select(const SearchPlan& sp, const morse_search_out* out, hip
                     out->d_best_idx, st);
   if (e == hipSuccess && out->top_k > 0)
     e = launch_topk(sp.chi2, sp.n_events, (int64_t)sp.n_maps * sp.n_traj, out->top_k,
-                    out->d_topk_chi2, out->d_topk_idx, sp.tk_keys, sp.tk_idx, st);
+                    out->d_topk_chi2, out->d_topk_idx, sp.tk_scratch, sp.num_cu, st);
   return e;
 }
 
@@ -729,6 +729,9 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     return fail(ctx, out->top_k < 0 ? MORSE_EINVAL : MORSE_EUNSUPPORTED, "top_k must be in [0, 4096]");
   if (out->top_k > 0 && (!out->d_topk_chi2 || !out->d_topk_idx))
     return fail(ctx, MORSE_EINVAL, "top_k > 0 needs d_topk_chi2 and d_topk_idx");
+  if (out->top_k > 0 && ((double)n_maps * (double)traj_count(trajs) >= 4294967295.0 ||
+                         lcs->n_events > 65535))
+    return fail(ctx, MORSE_ERANGE, "top-k needs n_maps * n_traj < 2^32 and at most 65535 events");
   {
     const int64_t nt = traj_count(trajs);
     if ((double)nt * lcs->n_events * n_maps >= 9.0e18 ||

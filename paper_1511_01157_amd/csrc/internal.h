@@ -209,10 +209,11 @@ hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st);
 // Best (chi2, index) per segment of length seg_len; n_seg segments.
 hipError_t launch_best(const double* chi2, int64_t n_seg, int64_t seg_len, double* best_chi2,
                        int64_t* best_idx, hipStream_t st);
-// Top-k per segment (k <= 4096).
+// Top-k per segment (k <= 4096); scratch of topk_scratch_bytes(n_seg, k) bytes.
+size_t topk_scratch_bytes(int64_t n_seg, int32_t k);
 hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32_t k,
-                       double* out_chi2, int64_t* out_idx, uint64_t* scratch_keys,
-                       int64_t* scratch_idx, hipStream_t st);
+                       double* out_chi2, int64_t* out_idx, void* scratch, int num_cu,
+                       hipStream_t st);
 
 // Expand top-k flat indices (map * n_traj + traj) into parameter rows.
 hipError_t launch_candidates(const double* axes, int32_t nu, int32_t na, int32_t nt, int32_t ne,

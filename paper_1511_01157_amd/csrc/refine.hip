@@ -3,9 +3,10 @@
 // Chi-square gradient.  The profiled chi-square (Eqs. 5-6 of McDougall & Albrow 2015;
 // sec. 4.2 bilinear map sampling) has (F_s, F_b) at their exact minimisers, so by the
 // envelope theorem d chi2/d theta = -2 F_s sum w r dA/d theta with r = F - F_s A - F_b.
-// One wavefront per candidate: pass 1 accumulates the normal-equation sums and solves
-// for (F_s, F_b) as the search does; pass 2 re-samples each point, forms r, and
-// accumulates in FP64
+// One 256-lane workgroup per candidate (four wavefronts over the points, so a few
+// thousand candidates still fill the chip): pass 1 accumulates the normal-equation
+// sums and solves for (F_s, F_b) as the search does; pass 2 re-samples each point,
+// forms r, and accumulates in FP64
 //   chi2 = sum w r^2,  Gx = sum w r dA/dzx,  Gy = sum w r dA/dzy,
 //   Gxt = sum w r tau dA/dzx,  Gyt = sum w r tau dA/dzy,
 //   Ga = sum w r (zx dA/dzy - zy dA/dzx),
@@ -29,16 +30,41 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
   return ((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3];
 }
 
-__global__ __launch_bounds__(256) void k_chi2_grad(GradArgs a) {
+// Sum of one FP64 value over the workgroup in a fixed order (wave butterflies, then
+// the wave partials in wave order); every thread returns the same value.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV]) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wpb = blockDim.x / kWave;
-  const int64_t nw = (int64_t)gridDim.x * wpb;
-  for (int64_t c = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; c < a.n; c += nw) {
+  const int wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s_part[wave][q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = s_part[0][q];
+    for (int k = 1; k < nw; ++k) t += s_part[k][q];
+    v[q] = t;
+  }
+  __syncthreads();
+}
+
+// One workgroup (GRAD_THREADS lanes over the points) per candidate.
+constexpr int GRAD_THREADS = 256;
+
+__global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
+  __shared__ double s3[GRAD_THREADS / kWave][3];
+  __shared__ double s6[GRAD_THREADS / kWave][6];
+  const int tid = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
     if (a.active && !a.active[c]) continue;
     const int32_t e = a.event[c];
     const int32_t mi = a.mapidx[c];
     if (e < 0 || e >= a.n_events || mi < 0 || mi >= a.n_maps) {
-      if (lane == 0) {
+      if (tid == 0) {
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
         if (a.chi2) a.chi2[c] = nan;
         if (a.grad)
@@ -83,24 +109,22 @@ __global__ __launch_bounds__(256) void k_chi2_grad(GradArgs a) {
     const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
 
     // pass 1: normal-equation sums (centred form) and the profiled fit
-    double B1 = 0.0, B2 = 0.0, C = 0.0;
-    for (int32_t i = lane; i < np; i += kWave) {
+    double n1[3] = {0.0, 0.0, 0.0};
+    for (int32_t i = tid; i < np; i += GRAD_THREADS) {
       const double b = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by) - 1.0;
       const double wb = w[i] * b;
-      B1 += wb;
-      B2 = fma(wb, b, B2);
-      C = fma(b, wFc[i], C);
+      n1[0] += wb;
+      n1[1] = fma(wb, b, n1[1]);
+      n1[2] = fma(b, wFc[i], n1[2]);
     }
-    B1 = wave_sum(B1);
-    B2 = wave_sum(B2);
-    C = wave_sum(C);
-    const Fit fit = centred_fit(Sw, Fbar, V, B1, B2, C);
+    block_sum<3>(n1, s3);
+    const Fit fit = centred_fit(Sw, Fbar, V, n1[0], n1[1], n1[2]);
     const double Fs = fit.Fs, Fb = fit.Fb;
 
     // pass 2: residuals, direct chi-square and gradient sums
     const double kx = (double)m.kx, ky = (double)m.ky;
-    double chi = 0.0, Gx = 0.0, Gy = 0.0, Gxt = 0.0, Gyt = 0.0, Ga = 0.0;
-    for (int32_t i = lane; i < np; i += kWave) {
+    double n2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // chi, Gx, Gy, Gxt, Gyt, Ga
+    for (int32_t i = tid; i < np; i += GRAD_THREADS) {
       const Sample s = sample_full(m, t[i], t0p, iE, ca, sa, bx, by);
       const double A = (double)s.A;
       const double r = F[i] - Fs * A - Fb;
@@ -119,32 +143,27 @@ __global__ __launch_bounds__(256) void k_chi2_grad(GradArgs a) {
         dAx = dAdu * zx / u;
         dAy = dAdu * zy / u;
       }
-      chi = fma(wr, r, chi);
-      Gx = fma(wr, dAx, Gx);
-      Gy = fma(wr, dAy, Gy);
-      Gxt = fma(wr * dAx, tau, Gxt);
-      Gyt = fma(wr * dAy, tau, Gyt);
-      Ga = fma(wr, zx * dAy - zy * dAx, Ga);
+      n2[0] = fma(wr, r, n2[0]);
+      n2[1] = fma(wr, dAx, n2[1]);
+      n2[2] = fma(wr, dAy, n2[2]);
+      n2[3] = fma(wr * dAx, tau, n2[3]);
+      n2[4] = fma(wr * dAy, tau, n2[4]);
+      n2[5] = fma(wr, zx * dAy - zy * dAx, n2[5]);
     }
-    chi = wave_sum(chi);
-    Gx = wave_sum(Gx);
-    Gy = wave_sum(Gy);
-    Gxt = wave_sum(Gxt);
-    Gyt = wave_sum(Gyt);
-    Ga = wave_sum(Ga);
-    if (lane == 0) {
+    block_sum<6>(n2, s6);
+    if (tid == 0) {
       const double c64 = (double)ca, s64 = (double)sa;
       const double k2 = -2.0 * Fs;
       double g[4];
-      g[0] = k2 * (-(c64 * Gx + s64 * Gy) / tE);
-      g[1] = k2 * (-s64 * Gx + c64 * Gy);
-      g[2] = k2 * (-(c64 * Gxt + s64 * Gyt) / tE);
-      g[3] = k2 * Ga;
+      g[0] = k2 * (-(c64 * n2[1] + s64 * n2[2]) / tE);
+      g[1] = k2 * (-s64 * n2[1] + c64 * n2[2]);
+      g[2] = k2 * (-(c64 * n2[3] + s64 * n2[4]) / tE);
+      g[3] = k2 * n2[5];
       if (a.anchor) {  // gradient with respect to the scaled variables
         g[0] = g[0] * tE_anchor;
         g[2] = g[2] * tE;
       }
-      if (a.chi2) a.chi2[c] = chi;
+      if (a.chi2) a.chi2[c] = n2[0];
       if (a.grad)
         for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = g[q];
       if (a.fs) a.fs[c] = Fs;
@@ -295,9 +314,9 @@ __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
 
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  int64_t blocks = (a.n + 3) / 4;
-  if (blocks > 1 << 18) blocks = 1 << 18;
-  hipLaunchKernelGGL(k_chi2_grad, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  int64_t blocks = a.n;
+  if (blocks > 1 << 20) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_chi2_grad, dim3((unsigned)blocks), dim3(GRAD_THREADS), 0, st, a);
   return hipGetLastError();
 }
 

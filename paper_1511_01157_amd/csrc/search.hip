@@ -21,6 +21,8 @@
 
 #include "internal.h"
 
+#include <algorithm>
+
 namespace morse {
 
 namespace {
@@ -286,144 +288,211 @@ __global__ __launch_bounds__(256) void k_best(const double* __restrict__ chi2, i
   }
 }
 
-constexpr int TK_THREADS = 1024;
-constexpr int TK_WAVES = TK_THREADS / kWave;
+// Top-k per segment by radix select over the composite key (order_key(chi2), index):
+// 6 passes of 11-bit digits over the 64-bit key, then (only when the k-th key is shared
+// by more items than remain to take) 3 passes over the 32-bit index among those ties.
+// Each pass: every workgroup histograms its slice of the segment in LDS and merges it
+// into the segment's global histogram with atomics; one workgroup per segment then
+// scans the 2048 bins, fixes the next digit of the threshold and clears the histogram.
+// A collect pass writes exactly k survivors (order-free atomic slots) and one
+// workgroup per segment sorts them by (key, index) in LDS.
+constexpr int TK_BINS = 2048;
+constexpr int TK_THREADS = 256;
 constexpr int TK_MAXK = 4096;
+constexpr int TK_PASSES = 9;
 
-// Block-wide exclusive prefix of a flag in index order (ballot within a wave, then
-// the wave totals).  Returns the position; *total receives the block total.
-__device__ __forceinline__ int block_scan_flag(bool f, int* s_wave, int* total) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint64_t m = __ballot(f);
-  const int inwave = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) s_wave[wave] = __popcll(m);
-  __syncthreads();
-  int before = 0, tot = 0;
-  for (int q = 0; q < TK_WAVES; ++q) {
-    const int v = s_wave[q];
-    before += (q < wave) ? v : 0;
-    tot += v;
-  }
-  __syncthreads();
-  *total = tot;
-  return before + inwave;
+struct TkState {
+  uint64_t prefix;  // fixed high digits of the threshold key
+  uint64_t mask;
+  int64_t krem;     // rank still to place within the current bin
+  int64_t bincount; // items in the chosen bin of the last pass
+  uint32_t iprefix, imask;  // index digits (tie passes)
+  int32_t need_idx;
+  int32_t taken;    // collect counter
+};
+
+__device__ __forceinline__ void tk_digit(int pass, int& shift, int& width) {
+  // key passes: bits 63..53, 52..42, 41..31, 30..20, 19..9, 8..0; index: 31..21, 20..10, 9..0
+  const int sh[TK_PASSES] = {53, 42, 31, 20, 9, 0, 21, 10, 0};
+  const int wd[TK_PASSES] = {11, 11, 11, 11, 11, 9, 11, 11, 10};
+  shift = sh[pass];
+  width = wd[pass];
 }
 
-// Radix select of the k-th smallest key (8 passes of 8-bit digits over the segment),
-// ordered compaction of the keys below it plus the first ties in index order, then a
-// bitonic sort of the k survivors by (key, position) in LDS.
-__global__ __launch_bounds__(TK_THREADS) void k_topk(const double* __restrict__ chi2,
-                                                     int64_t seg_len, int32_t k,
-                                                     double* __restrict__ out_chi2,
-                                                     int64_t* __restrict__ out_idx,
-                                                     uint64_t* __restrict__ skeys,
-                                                     int64_t* __restrict__ sidx) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint64_t s_prefix;
-  __shared__ int64_t s_krem;
-  __shared__ int s_wave[TK_WAVES];
-  __shared__ uint64_t lkey[TK_MAXK];
-  __shared__ int32_t lpos[TK_MAXK];
-
-  const int tid = threadIdx.x;
+__global__ void k_tk_init(TkState* st, uint32_t* hist, uint64_t* keys, uint32_t* idx,
+                          int64_t n_seg, int64_t seg_len, int32_t k) {
   const int64_t seg = blockIdx.x;
-  const double* base = chi2 + seg * seg_len;
-  uint64_t* kk = skeys + seg * (int64_t)k;
-  int64_t* ki = sidx + seg * (int64_t)k;
-  const int64_t keff = min((int64_t)k, seg_len);
-
-  uint64_t prefix = 0, pmask = 0;
-  int64_t krem = keff;
-  if (keff > 0) {
-    for (int pass = 0; pass < 8; ++pass) {
-      const int shift = 56 - 8 * pass;
-      for (int q = tid; q < 256; q += TK_THREADS) hist[q] = 0u;
-      __syncthreads();
-      for (int64_t i = tid; i < seg_len; i += TK_THREADS) {
-        const uint64_t key = order_key(base[i]);
-        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int64_t cum = 0;
-        int d = 255;
-        for (int q = 0; q < 256; ++q) {
-          if (cum + hist[q] >= krem) {
-            d = q;
-            break;
-          }
-          cum += hist[q];
-        }
-        s_prefix = prefix | ((uint64_t)d << shift);
-        s_krem = krem - cum;
-      }
-      __syncthreads();
-      prefix = s_prefix;
-      krem = s_krem;
-      pmask |= 255ull << shift;
-      __syncthreads();
-    }
+  if (seg >= n_seg) return;
+  for (int b = threadIdx.x; b < TK_BINS; b += blockDim.x) hist[seg * TK_BINS + b] = 0u;
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {  // unfilled slots read as invalid
+    keys[seg * k + b] = ~0ull;
+    idx[seg * k + b] = 0xffffffffu;
   }
-  const uint64_t T = prefix;
-  const int64_t nless = keff - krem;
+  if (threadIdx.x == 0) {
+    TkState s;
+    s.prefix = 0;
+    s.mask = 0;
+    s.krem = min((int64_t)k, seg_len);
+    s.bincount = 0;
+    s.iprefix = 0;
+    s.imask = 0;
+    s.need_idx = 0;
+    s.taken = 0;
+    st[seg] = s;
+  }
+}
 
-  // ordered compaction
-  int64_t less_base = 0, eq_base = 0;
-  for (int64_t start = 0; start < seg_len && keff > 0; start += TK_THREADS) {
-    const int64_t i = start + tid;
-    const uint64_t key = (i < seg_len) ? order_key(base[i]) : ~0ull;
-    const bool isless = (i < seg_len) && key < T;
-    const bool iseq = (i < seg_len) && key == T;
-    int tl, te;
-    const int pl = block_scan_flag(isless, s_wave, &tl);
-    const int pe = block_scan_flag(iseq, s_wave, &te);
-    if (isless) {
-      kk[less_base + pl] = key;
-      ki[less_base + pl] = i;
+__global__ __launch_bounds__(TK_THREADS) void k_tk_hist(const double* __restrict__ chi2,
+                                                        int64_t seg_len,
+                                                        const TkState* __restrict__ st,
+                                                        uint32_t* __restrict__ hist, int pass) {
+  __shared__ uint32_t h[TK_BINS];
+  const int64_t seg = blockIdx.y;
+  const TkState s = st[seg];
+  if (s.krem <= 0 || (pass >= 6 && !s.need_idx)) return;  // uniform per workgroup
+  for (int b = threadIdx.x; b < TK_BINS; b += TK_THREADS) h[b] = 0u;
+  __syncthreads();
+  int shift, width;
+  tk_digit(pass, shift, width);
+  const uint32_t dmask = (1u << width) - 1u;
+  const double* base = chi2 + seg * seg_len;
+  for (int64_t i = blockIdx.x * (int64_t)TK_THREADS + threadIdx.x; i < seg_len;
+       i += (int64_t)gridDim.x * TK_THREADS) {
+    const uint64_t key = order_key(base[i]);
+    if (pass < 6) {
+      if ((key & s.mask) == s.prefix) atomicAdd(&h[(uint32_t)(key >> shift) & dmask], 1u);
+    } else if (key == s.prefix && (((uint32_t)i) & s.imask) == s.iprefix) {
+      atomicAdd(&h[((uint32_t)i >> shift) & dmask], 1u);
     }
-    if (iseq && eq_base + pe < krem) {
-      kk[nless + eq_base + pe] = key;
-      ki[nless + eq_base + pe] = i;
-    }
-    less_base += tl;
-    eq_base += te;
   }
   __syncthreads();
+  uint32_t* g = hist + seg * TK_BINS;
+  for (int b = threadIdx.x; b < TK_BINS; b += TK_THREADS)
+    if (h[b]) atomicAdd(&g[b], h[b]);
+}
 
-  // bitonic sort of (key, position) for the keff survivors
+__global__ __launch_bounds__(TK_THREADS) void k_tk_pick(TkState* __restrict__ st,
+                                                        uint32_t* __restrict__ hist, int pass) {
+  __shared__ int64_t incl[TK_THREADS];
+  const int64_t seg = blockIdx.x;
+  TkState s = st[seg];
+  if (s.krem <= 0 || (pass >= 6 && !s.need_idx)) return;
+  uint32_t* g = hist + seg * TK_BINS;
+  constexpr int PER = TK_BINS / TK_THREADS;
+  const int t = threadIdx.x;
+  uint32_t c[PER];
+  int64_t part = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    c[q] = g[t * PER + q];
+    part += c[q];
+  }
+  incl[t] = part;
+  __syncthreads();
+  for (int o = 1; o < TK_THREADS; o <<= 1) {
+    const int64_t v = (t >= o) ? incl[t - o] : 0;
+    __syncthreads();
+    incl[t] += v;
+    __syncthreads();
+  }
+  const int64_t before = incl[t] - part;
+  int shift, width;
+  tk_digit(pass, shift, width);
+  if (before < s.krem && s.krem <= incl[t]) {
+    int64_t cum = before;
+    int d = t * PER;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (cum + c[q] >= s.krem) {
+        d = t * PER + q;
+        break;
+      }
+      cum += c[q];
+    }
+    const int64_t cnt = g[d];
+    s.krem -= cum;
+    s.bincount = cnt;
+    const uint64_t wm = (1ull << width) - 1ull;
+    if (pass < 6) {
+      s.prefix |= (uint64_t)d << shift;
+      s.mask |= wm << shift;
+      if (pass == 5) s.need_idx = (s.bincount != s.krem) ? 1 : 0;
+    } else {
+      s.iprefix |= (uint32_t)d << shift;
+      s.imask |= (uint32_t)wm << shift;
+    }
+    st[seg] = s;
+  }
+  __syncthreads();
+  for (int b = t; b < TK_BINS; b += TK_THREADS) g[b] = 0u;
+}
+
+// Survivors: key < T, or key == T and (all ties taken, or index <= the chosen index).
+__global__ __launch_bounds__(TK_THREADS) void k_tk_collect(const double* __restrict__ chi2,
+                                                           int64_t seg_len, int32_t k,
+                                                           TkState* __restrict__ st,
+                                                           uint64_t* __restrict__ keys,
+                                                           uint32_t* __restrict__ idx) {
+  const int64_t seg = blockIdx.y;
+  const TkState s = st[seg];
+  const double* base = chi2 + seg * seg_len;
+  for (int64_t i = blockIdx.x * (int64_t)TK_THREADS + threadIdx.x; i < seg_len;
+       i += (int64_t)gridDim.x * TK_THREADS) {
+    const uint64_t key = order_key(base[i]);
+    bool take = key < s.prefix;
+    if (key == s.prefix) take = !s.need_idx || ((uint32_t)i <= s.iprefix);
+    if (take) {
+      const int pos = atomicAdd(&st[seg].taken, 1);
+      if (pos < k) {
+        keys[seg * k + pos] = key;
+        idx[seg * k + pos] = (uint32_t)i;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_tk_sort(const double* __restrict__ chi2, int64_t seg_len,
+                                                  int32_t k, const uint64_t* __restrict__ keys,
+                                                  const uint32_t* __restrict__ idx,
+                                                  double* __restrict__ out_chi2,
+                                                  int64_t* __restrict__ out_idx) {
+  __shared__ uint64_t lk[TK_MAXK];
+  __shared__ uint32_t li[TK_MAXK];
+  const int64_t seg = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t keff = min((int64_t)k, seg_len);
   int n2 = 1;
   while (n2 < keff) n2 <<= 1;
-  for (int q = tid; q < n2; q += TK_THREADS) {
-    lkey[q] = (q < keff) ? kk[q] : ~0ull;
-    lpos[q] = (q < keff) ? q : 0x7fffffff;
+  for (int q = tid; q < n2; q += blockDim.x) {
+    lk[q] = (q < keff) ? keys[seg * k + q] : ~0ull;
+    li[q] = (q < keff) ? idx[seg * k + q] : 0xffffffffu;
   }
   __syncthreads();
   for (int size = 2; size <= n2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int q = tid; q < n2; q += TK_THREADS) {
+      for (int q = tid; q < n2; q += blockDim.x) {
         const int r = q ^ stride;
         if (r > q) {
           const bool up = (q & size) == 0;
-          const uint64_t ka = lkey[q], kb = lkey[r];
-          const int32_t pa = lpos[q], pb = lpos[r];
-          const bool a_gt_b = (ka > kb) || (ka == kb && pa > pb);
+          const uint64_t ka = lk[q], kb = lk[r];
+          const uint32_t ia = li[q], ib = li[r];
+          const bool a_gt_b = (ka > kb) || (ka == kb && ia > ib);
           if (a_gt_b == up) {
-            lkey[q] = kb;
-            lkey[r] = ka;
-            lpos[q] = pb;
-            lpos[r] = pa;
+            lk[q] = kb;
+            lk[r] = ka;
+            li[q] = ib;
+            li[r] = ia;
           }
         }
       }
       __syncthreads();
     }
   }
-  for (int q = tid; q < k; q += TK_THREADS) {
-    if (q < keff) {
-      const int64_t idx = ki[lpos[q]];
-      out_idx[seg * k + q] = idx;
-      out_chi2[seg * k + q] = base[idx];
+  const double* base = chi2 + seg * seg_len;
+  for (int q = tid; q < k; q += blockDim.x) {
+    if (q < keff && (int64_t)li[q] < seg_len) {
+      out_idx[seg * k + q] = (int64_t)li[q];
+      out_chi2[seg * k + q] = base[li[q]];
     } else {
       out_idx[seg * k + q] = -1;
       out_chi2[seg * k + q] = __longlong_as_double(0x7ff8000000000000ll);
@@ -537,12 +606,39 @@ hipError_t launch_best(const double* chi2, int64_t n_seg, int64_t seg_len, doubl
   return hipGetLastError();
 }
 
+size_t topk_scratch_bytes(int64_t n_seg, int32_t k) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(TkState) * n_seg) + al(4 * (size_t)TK_BINS * n_seg) + al(8 * (size_t)k * n_seg) +
+         al(4 * (size_t)k * n_seg);
+}
+
 hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32_t k,
-                       double* out_chi2, int64_t* out_idx, uint64_t* scratch_keys,
-                       int64_t* scratch_idx, hipStream_t st) {
+                       double* out_chi2, int64_t* out_idx, void* scratch, int num_cu,
+                       hipStream_t st) {
   if (n_seg <= 0 || k <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_topk, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, chi2, seg_len, k,
-                     out_chi2, out_idx, scratch_keys, scratch_idx);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* p = (char*)scratch;
+  TkState* state = (TkState*)p;
+  p += al(sizeof(TkState) * n_seg);
+  uint32_t* hist = (uint32_t*)p;
+  p += al(4 * (size_t)TK_BINS * n_seg);
+  uint64_t* keys = (uint64_t*)p;
+  p += al(8 * (size_t)k * n_seg);
+  uint32_t* idx = (uint32_t*)p;
+  // enough workgroups to cover the chip about four times over all segments
+  int64_t per_seg = (seg_len + 16 * TK_THREADS - 1) / (16 * TK_THREADS);
+  const int64_t cap = std::max<int64_t>(1, (4 * (int64_t)num_cu * 4) / n_seg);
+  per_seg = std::max<int64_t>(1, std::min(per_seg, cap));
+  const dim3 grid((unsigned)per_seg, (unsigned)n_seg);
+  hipLaunchKernelGGL(k_tk_init, dim3((unsigned)n_seg), dim3(256), 0, st, state, hist, keys, idx, n_seg,
+                     seg_len, k);
+  for (int pass = 0; pass < TK_PASSES; ++pass) {
+    hipLaunchKernelGGL(k_tk_hist, grid, dim3(TK_THREADS), 0, st, chi2, seg_len, state, hist, pass);
+    hipLaunchKernelGGL(k_tk_pick, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, state, hist, pass);
+  }
+  hipLaunchKernelGGL(k_tk_collect, grid, dim3(TK_THREADS), 0, st, chi2, seg_len, k, state, keys, idx);
+  hipLaunchKernelGGL(k_tk_sort, dim3((unsigned)n_seg), dim3(1024), 0, st, chi2, seg_len, k, keys, idx,
+                     out_chi2, out_idx);
   return hipGetLastError();
 }
 

@@ -134,6 +134,24 @@ def test_degenerate_and_off_map_cases():
         assert rel_err(r["fb"].cpu().numpy()[0, m], fb, 1e-3).max() < 1e-8
 
 
+def test_topk_with_ties_takes_smallest_indices():
+    """A constant map makes every trajectory degenerate with chi2 = V exactly, so the
+    k-th key is shared by all items and the selection must fall back to the index."""
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev, ev], DEV)
+    flat = np.full((64, 64), 2.5, np.float32)
+    win = (0.0, 0.0, 100.0, 100.0, 64, 64)
+    tr = M.grid_trajectories(np.linspace(0.01, 0.5, 40), np.linspace(0, 6, 50), [0.0, 1.0], [10.0, 20.0])
+    note("search ties top-k")
+    for mode in ("plain", "batched"):
+        r = M.search([(dmap(flat), win), (dmap(flat), win)], lcs, tr, mode, best=True, top_k=300)
+        c = r["chi2"].cpu().numpy()
+        assert np.all(c == c.flat[0])
+        for e in range(2):
+            assert np.array_equal(r["topk_idx"].cpu().numpy()[e], np.arange(300))
+            assert np.all(r["best_idx"].cpu().numpy()[e] == 0)
+
+
 def test_large_full_grid_sampled_vs_oracle(large_oracle_map):
     """Full size of the large workload: 524288 grid trajectories x 3000 points on the
     2048^2 map in the batched launch the bench times; 384 sampled trajectories and the
