@@ -32,10 +32,11 @@ struct TuneCfg {
 };
 // Candidate shapes of the batched search tried by the autotuner; index 0 is the
 // default before tuning.
+// traj_per_item = trajectories per wavefront work item.
 const TuneCfg kTune[] = {
-    {128, 8, 8}, {64, 4, 16}, {128, 4, 16}, {256, 8, 8},
-    {64, 8, 8},  {32, 4, 16}, {256, 4, 8},  {512, 8, 4},
-    {128, 8, 4}, {64, 2, 32},
+    {8, 4, 16}, {4, 4, 16}, {16, 4, 16}, {8, 8, 8},
+    {32, 8, 8}, {2, 4, 16}, {16, 8, 4},  {8, 2, 32},
+    {64, 4, 8}, {4, 8, 8},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 
@@ -699,7 +700,8 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
   const int64_t nb = (sp.n_traj + cfg.traj_per_item - 1) / cfg.traj_per_item;
   const int64_t items = nb * sp.n_events * sp.n_maps;
   int64_t blocks = (int64_t)ctx->num_cu * cfg.blocks_per_cu;
-  if (blocks > items) blocks = items;
+  const int64_t need = (items + cfg.waves_per_block - 1) / cfg.waves_per_block;
+  if (blocks > need) blocks = need;
   a.grid_blocks = (int32_t)std::max<int64_t>(blocks, 1);
   return a;
 }
@@ -735,7 +737,7 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   {
     const int64_t nt = traj_count(trajs);
     if ((double)nt * lcs->n_events * n_maps >= 9.0e18 ||
-        (double)((nt + 31) / 32) * lcs->n_events * n_maps >= 2147483647.0)
+        (double)nt * lcs->n_events * n_maps >= 2147483647.0)
       return fail(ctx, MORSE_ERANGE, "too many (event, map, trajectory) items");
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));

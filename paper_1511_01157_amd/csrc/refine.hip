@@ -136,12 +136,12 @@ __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
         dAx = kx * (e0 + (double)s.fy * (e1 - e0));
         dAy = ky * ((double)s.ax1 - (double)s.ax0);
       } else {
+        // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
         const double u2 = zx * zx + zy * zy;
-        const double u = sqrt(u2);
-        const double q = u2 + 4.0;
-        const double dAdu = -8.0 / (u2 * (q * sqrt(q)));
-        dAx = dAdu * zx / u;
-        dAy = dAdu * zy / u;
+        const double p = u2 * (u2 + 4.0);
+        const double f = -8.0 / (p * sqrt(p));
+        dAx = f * zx;
+        dAy = f * zy;
       }
       n2[0] = fma(wr, r, n2[0]);
       n2[1] = fma(wr, dAx, n2[1]);

@@ -14,7 +14,7 @@
 // wave re-samples and sums w (F - F_s A - F_b)^2 directly.
 //
 // Plain mode launches one grid per (event, map).  Batched mode launches one persistent
-// grid whose workgroups pull (map, event, trajectory block) items from an atomic
+// grid whose wavefronts pull (map, event, trajectory block) items from an atomic
 // counter, so thousands of (event, map) pairs of uneven length share one launch; the
 // per-trajectory arithmetic and reduction order are the same, so results are
 // bitwise identical between the modes.
@@ -136,6 +136,17 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 
 // ---------------------------------------------------------------------------
 // Score one trajectory with one wavefront.  All lanes return the same values.
+// Each lane takes SU points per iteration (i, i + 64, ...): every load of the
+// iteration (times, weights, both map rows of every cell) is issued before the
+// arithmetic that needs it, so one memory latency covers SU points.  Map rows are
+// read at the clamped cell even for points off the map (always in bounds); the
+// bilinear value is then discarded for them and only the single-lens branch is
+// conditional.  The arithmetic of each point is exactly that of sample_A.
+#ifndef MORSE_SU
+#define MORSE_SU 1
+#endif
+constexpr int SU = MORSE_SU;  // points per lane per iteration (tuning knob)
+
 __device__ __forceinline__ void score_traj(const MapC& m, const float* __restrict__ t,
                                            const double* __restrict__ w,
                                            const double* __restrict__ wFc,
@@ -143,12 +154,54 @@ __device__ __forceinline__ void score_traj(const MapC& m, const float* __restric
                                            double Fbar, double V, float t0p, const TrajC& c,
                                            int lane, double& chi2, double& Fs, double& Fb) {
   double B1 = 0.0, B2 = 0.0, C = 0.0;
-  for (int32_t i = lane; i < np; i += kWave) {
-    const double b = (double)sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by) - 1.0;
-    const double wb = w[i] * b;
-    B1 += wb;
-    B2 = fma(wb, b, B2);
-    C = fma(b, wFc[i], C);
+  for (int32_t i0 = lane; i0 < np; i0 += SU * kWave) {
+    float tt[SU];
+    double wv[SU], fv[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int32_t i = min(i0 + u * kWave, np - 1);
+      tt[u] = t[i];
+      wv[u] = w[i];
+      fv[u] = wFc[i];
+    }
+    float zx[SU], zy[SU], gx[SU], gy[SU];
+    float2 r0[SU], r1[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const float tau = (tt[u] - t0p) * c.iE;
+      zx[u] = tau * c.ca + c.bx;
+      zy[u] = tau * c.sa + c.by;
+      gx[u] = ((zx[u] - m.sx) * m.kx) + m.ox;
+      gy[u] = ((zy[u] - m.sy) * m.ky) + m.oy;
+      // clamped cell (NaN -> 0): always a valid 2x2 block
+      const int ic = (int)floorf(fminf(fmaxf(gx[u], 0.0f), m.lx - 1.0f));
+      const int jc = (int)floorf(fminf(fmaxf(gy[u], 0.0f), m.ly - 1.0f));
+      const float* p = m.map + (size_t)jc * (size_t)m.mx + ic;
+      r0[u] = make_float2(p[0], p[1]);
+      r1[u] = make_float2(p[m.mx], p[m.mx + 1]);
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const bool on = gx[u] >= 0.0f && gx[u] < m.lx && gy[u] >= 0.0f && gy[u] < m.ly;
+      const float fx = gx[u] - floorf(gx[u]);
+      const float fy = gy[u] - floorf(gy[u]);
+      const float e0 = r0[u].y - r0[u].x;
+      const float e1 = r1[u].y - r1[u].x;
+      const float ax0 = r0[u].x + fx * e0;
+      const float ax1 = r1[u].x + fx * e1;
+      float A = ax0 + fy * (ax1 - ax0);
+      if (!on) {
+        const float uu = zx[u] * zx[u] + zy[u] * zy[u];
+        A = (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
+      }
+      if (i0 + u * kWave < np) {
+        const double b = (double)A - 1.0;
+        const double wb = wv[u] * b;
+        B1 += wb;
+        B2 = fma(wb, b, B2);
+        C = fma(b, fv[u], C);
+      }
+    }
   }
   B1 = wave_sum(B1);
   B2 = wave_sum(B2);
@@ -194,21 +247,19 @@ __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ 
   }
 }
 
-// Persistent batched search.  Item = (map * n_events + event) * n_blocks + block:
-// consecutive items share the map and the light curve, so concurrently running
-// workgroups hit the same map lines in L2.
+// Persistent batched search.  Every wavefront pulls its own work items from the
+// counter (no workgroup barrier, so a slow trajectory never holds up other waves).
+// Item = (map * n_events + event) * n_blocks + block of traj_per_item trajectories:
+// consecutive items share the map and the light curve, so concurrently running waves
+// hit the same map lines in L2.
 __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
-  __shared__ int64_t s_item;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int wpb = blockDim.x / kWave;
   const int64_t nb = (a.n_traj + a.traj_per_item - 1) / a.traj_per_item;
   const int64_t total = nb * a.n_events * a.n_maps;
   for (;;) {
-    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
-    __syncthreads();
-    const int64_t item = s_item;
-    __syncthreads();
+    int item32 = 0;
+    if (lane == 0) item32 = (int)atomicAdd(a.counter, 1u);
+    const int64_t item = (int64_t)(uint32_t)__shfl(item32, 0, kWave);
     if (item >= total) break;
     const int64_t b = item % nb;
     const int64_t me = item / nb;
@@ -222,7 +273,7 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
     const TrajC* tc = a.tc + (a.shared ? 0 : (int64_t)e * a.n_traj);
     const int64_t k1 = min((b + 1) * (int64_t)a.traj_per_item, a.n_traj);
     const int64_t obase = ((int64_t)e * a.n_maps + mi) * a.n_traj;
-    for (int64_t k = b * a.traj_per_item + wave; k < k1; k += wpb) {
+    for (int64_t k = b * a.traj_per_item; k < k1; ++k) {
       const TrajC c = tc[k];
       const float t0p = (float)(c.t0 - tref);
       double chi2, Fs, Fb;
