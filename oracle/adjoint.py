@@ -107,7 +107,7 @@ def chi2_exact64(amap, window, t, F, w, params, t_ref=0.0):
 
 
 def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5, mode="exact64", tt=None):
-    """Central differences of the chi-square objective (reading X20).
+    """Central differences of the chi-square objective.
 
     mode "exact64": FP64 sampling from absolute times t; mode "mirror32": the
     binary32 sampling of the search (times tt = fl32(t - t_ref)), i.e. the objective

@@ -2,7 +2,7 @@
 
 Test infrastructure only.  The paper's map comparisons and the map tolerance are
 stated outside caustic pixels; the paper never defines the term, so this module fixes
-the reading used here (X12): a pixel is a caustic pixel when it lies within
+the reading used here: a pixel is a caustic pixel when it lies within
 ``margin`` pixels (Chebyshev distance, in pixel-centre units) of a point of the
 point-source caustic, plus the finite-source radius in pixels for convolved maps.
 
@@ -41,7 +41,7 @@ def caustic_points(s: float, q: float, nphi: int):
 def caustic_mask(s: float, q: float, cx: float, cy: float, wx: float, wy: float,
                  nx: int, ny: int, margin_px: int = 2, rho: float = 0.0,
                  max_step_px: float = 0.25, nphi0: int = 4096, nphi_max: int = 1 << 21):
-    """Boolean [ny, nx] mask of caustic pixels of a map window (reading X12).
+    """Boolean [ny, nx] mask of caustic pixels of a map window.
 
     Pixel (j, i) has centre (cx - wx/2 + (i + 0.5) dx, cy - wy/2 + (j + 0.5) dy).  The
     caustic is sampled until every sample has a sample of the next phase within

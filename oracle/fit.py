@@ -2,7 +2,7 @@
 
 Eq. 5: F_i = F_S A(t_i) + F_B; Eq. 6: the (difference) flux is linear in A, so for a
 given trajectory the two flux parameters have a closed-form weighted least-squares
-solution, the unconstrained minimiser (reading X15).  With weights w_i = 1/sigma_i^2
+solution, the unconstrained minimiser (no sign constraint).  With weights w_i = 1/sigma_i^2
 and a_i = A(t_i) promoted to FP64 it is computed from the centred normal equations:
     S_w = sum w,  abar = sum w a / S_w,  Fbar = sum w F / S_w,
     S_aa = sum w (a - abar)^2,  S_aF = sum w (a - abar)(F - Fbar),
@@ -10,7 +10,7 @@ and a_i = A(t_i) promoted to FP64 it is computed from the centred normal equatio
 the same minimiser as (S_AF S_w - S_A S_F)/det, (S_AA S_F - S_A S_AF)/det with
 det = S_AA S_w - S_A^2 = S_w S_aa, written without the cancellation of det when a is
 nearly constant.  When det <= 1e-12 S_AA S_w (i.e. S_aa <= 1e-12 S_AA, S_AA = sum w a^2)
-the magnification is numerically constant and the fit degenerates (reading X16):
+the magnification is numerically constant and the fit degenerates:
 F_s = 0, F_b = Fbar.  Chi-square (sec. 4.2: sum of per-point contributions) is summed
 directly, chi2 = sum w (F - F_s a - F_b)^2, over the same a.
 

@@ -10,7 +10,7 @@ Sources in the paper (McDougall & Albrow 2015):
   * sec. 3, text after Eq. 2: inverting Eq. 2 gives a fifth-order complex polynomial
     with 3 or 5 physical solutions.
   * sec. 3, Eqs. 3-4: image magnification 1/det J with J = d zeta / d z; total
-    magnification is the sum over images (absolute values, reading X3 in the design doc).
+    magnification is the sum over images (absolute values of 1/det J).
 """
 from __future__ import annotations
 
@@ -23,7 +23,7 @@ __all__ = [
 
 
 def lens_setup(s: float, q: float):
-    """Mass fractions and positions (sec. 4.1; reading X1).
+    """Mass fractions and positions (sec. 4.1; the text's centre-of-mass origin).
 
     m1 = 1/(1+q) at x1 = -s q/(1+q); m2 = q/(1+q) at x2 = +s/(1+q).  The centre of
     mass m1 x1 + m2 x2 is the origin and x2 - x1 = s.
@@ -215,7 +215,7 @@ def paczynski(u):
 
 
 def disk_magnification(zeta_c, rho: float, s: float, q: float, nr: int = 16, nphi: int = 64):
-    """Uniform-disk finite-source magnification (sec. 3, finite source; reading X7).
+    """Uniform-disk finite-source magnification (sec. 3, finite source).
 
     Mean of the point-source magnification over the disk |zeta - zeta_c| <= rho:
     (1/2pi) int dphi int_0^1 2x A(rho x, phi) dx, Gauss-Legendre in x = r/rho (the

@@ -3,7 +3,7 @@
 Sec. 4.1 of the paper convolves each point-source map with radially symmetric source
 profiles of radius rho to obtain finite-source maps.  Here the profile is the uniform
 disk (no limb darkening) and the map is the piecewise-constant ray-count density of
-``rays``; reading X11: the finite-source value at a pixel centre is the average of the
+``rays``; the finite-source value at a pixel centre is the average of the
 count density over the disk of radius rho about that centre, i.e. a weighted sum of
 the neighbouring pixels with weights w = area(disk ∩ pixel) / (pi rho^2).
 
@@ -11,7 +11,7 @@ Normalisation: with lattice spacing (hx, hy) the unlensed ray density is 1/(hx h
 rays per unit area, so a pixel of area dx*dy holds dx*dy/(hx*hy) rays at magnification
 1 and A = count * (hx*hy)/(dx*dy).
 
-FP32 mirror (C-spec reading): scale = fl32(hx32*hy32/(dx*dy)) computed in FP64 from
+FP32 mirror: scale = fl32(hx32*hy32/(dx*dy)) computed in FP64 from
 the binary32 lattice spacings; weights computed in FP64, renormalised to sum 1,
 rounded once; taps visited row-major (dy outer, dx inner) over the (2Ry+1)x(2Rx+1)
 stencil, R = ceil(rho/d + 1/2), zero taps skipped; acc = ((w0*c0) + (w1*c1)) + ...

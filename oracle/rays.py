@@ -15,7 +15,7 @@ Three implementations:
     separately; the two must agree bit for bit (pin).
   * ``rayshoot_exact64``: the same formulas in FP64 from unrounded constants.
 
-FP32 mirror, step by step (readings X1, X4):
+FP32 mirror, step by step:
   lens constants m1, m2, x1, x2 from ``lens.lens_setup`` in FP64, rounded once;
   lattice spacing h = fl32(W/N), pixel scale k = fl32(M/V), centres fl32(c);
   ray i: g = (i - N/2) + 0.5 (exact), x = cx + g*h (two rounded ops);

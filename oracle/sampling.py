@@ -5,14 +5,14 @@ here) the trajectory angle from the positive lens axis, t0 the time of closest a
 tE the Einstein time.  Sec. 4.2: a time t_i maps to a point on the linear trajectory,
 and the magnification there is read from the map by bilinear interpolation.
 
-Reading X2 (orientation): zeta(t) = tau (cos a, sin a) + u0 (-sin a, cos a),
-tau = (t - t0)/tE.  Reading X8: map values sit at pixel centres, pixel i of M spanning
+Orientation (the paper does not fix it): zeta(t) = tau (cos a, sin a) + u0 (-sin a, cos a),
+tau = (t - t0)/tE.  Map values sit at pixel centres, pixel i of M spanning
 [c - V/2 + i V/M, c - V/2 + (i+1) V/M), so the continuous grid coordinate of a source
-position is g = (zeta - c) M/V + (M/2 - 1/2) and value i sits at g = i.  Reading X9:
-points whose 2x2 bilinear cell is not inside the map take the single-lens
+position is g = (zeta - c) M/V + (M/2 - 1/2) and value i sits at g = i.  Points
+whose 2x2 bilinear cell is not inside the map take the single-lens
 (Paczynski) magnification about the barycentre.
 
-FP32 mirror (S-spec).  Per trajectory, in FP64 then rounded once to binary32:
+FP32 mirror, operation by operation.  Per trajectory, in FP64 then rounded once to binary32:
   t0' = t0 - t_ref, iE = 1/tE, ca = cos a, sa = sin a, bx = -u0 sin a, by = u0 cos a.
 Per point (tt = fl32(t - t_ref), given as input), binary32 ops:
   tau = (tt - t0')*iE;  zx = tau*ca + bx;  zy = tau*sa + by;

@@ -5,7 +5,7 @@ curve; sec. 4.4: the best solutions seed the next stage.  The oracle evaluates t
 plain definition for every trajectory: sample the map along the trajectory
 (``sampling``), profile (F_s, F_b) and sum chi-square (``fit``).
 
-Trajectory order for a product grid (reading X19): row-major over
+Trajectory order for a product grid: row-major over
 (u0, alpha, t0, tE), i.e. index = ((iu0 * n_alpha + ia) * n_t0 + it0) * n_tE + itE.
 Parameters are rows (t0, u0, tE, alpha) in FP64.
 """

@@ -1,10 +1,10 @@
 """Write the true magnifications of the synthetic light curves (calls only the oracle).
 
 For every event of the tiny / large / sqgrid / batched workloads: source positions
-along the truth trajectory (sec. 4.1 parameters, reading X2), then the point-source
+along the truth trajectory (sec. 4.1 parameters), then the point-source
 binary-lens magnification from the quintic images (Eqs. 2-4).  For a finite source
 (rho > 0) points within 10 rho of the caustic (the proximity rule the paper uses for
-its finite-source refinement, sec. 5) take the uniform-disk average (reading X7).
+its finite-source refinement, sec. 5) take the uniform-disk average .
 Output: tests/golden/lc_amag_<name>.npz with one array e<event> per event.
 
 Run:  python tests/golden/make_lightcurves.py [name ...]

@@ -123,7 +123,7 @@ def truths(name: str):
 
 
 def lightcurve_times(name: str, event: int = 0) -> np.ndarray:
-    """Sorted FP64 observation times of one event (reading X5)."""
+    """Sorted FP64 observation times of one event (i.i.d. uniform, two 1-day gaps; 2-5 gaps of 0.3-3 d for batched)."""
     key = "batched" if name == "refine" else name
     tr = truths(key)[event]
     lo, hi = tr["t0"] - 2 * tr["tE"], tr["t0"] + 2 * tr["tE"]
@@ -153,7 +153,7 @@ def noise_deviates(name: str, n: int, event: int = 0) -> np.ndarray:
 
 
 def grid_axes(name: str):
-    """(u0s, alphas, t0s, tEs) of a product-grid workload (reading X19)."""
+    """(u0s, alphas, t0s, tEs) of a product-grid workload (u0 log-spaced, alpha = 2 pi k / n, t0 linear over t0 +- tE/2, tE log-spaced 5..100)."""
     tr = truths(name)[0]
     if name == "tiny":
         return (np.logspace(-3, np.log10(0.5), 32), 2 * np.pi * np.arange(32) / 32,
@@ -187,7 +187,7 @@ def load_lightcurve(name: str, event: int = 0):
     """Observed light curve of one event: dict(t, tt, t_ref, F, sigma, w, truth).
 
     F_true = Fs A_true + Fb (Eq. 5 as the observation model), sigma = 1% of F_true,
-    F = F_true + sigma * N(0, 1) (reading X6), w = 1/sigma^2, t_ref the mid-time, and
+    F = F_true + sigma * N(0, 1), w = 1/sigma^2, t_ref the mid-time, and
     tt = fl32(t - t_ref) the FP32 time offsets the search consumes.
     """
     key = "batched" if name == "refine" else name
