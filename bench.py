@@ -27,10 +27,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic lane-operations per unit (one FP32/FP64 add, mul, compare, floor,
-# convert, divide or square root = 1; derivation in the design notes):
-OPS_PER_RAY = 31          # lattice point, Eq. 2 with two divisions, bin rule, count
-OPS_PER_POINT_EVAL = 37   # tau, zeta, grid coordinate, cell, bilinear, 3 FP64 sums
-OPS_PER_ADJOINT_EVAL = 87  # pass 1 as the search + pass 2 (sample, residual, 6 sums)
+# convert, divide, square root or fused multiply-add = 1):
+#   ray: lattice point 2, d 2, r 4, two divisions 2, zeta_x 4, zeta_y 4, scaled
+#        offsets 4, floors 2, bin compares/selects 4, index 2, count 1        = 31
+#   point-evaluation: tau 2, zeta 4, grid coordinate 6, on-map test 4,
+#        floor/fraction 4, cell index 3, bilinear 9, FP64 sums 5              = 37
+#   adjoint point-evaluation: pass 1 (37) + pass 2: sample 32, residual 3,
+#        derivative 9, six FP64 sums 6                                        = 87
+OPS_PER_RAY = 31
+OPS_PER_POINT_EVAL = 37
+OPS_PER_ADJOINT_EVAL = 87
 # 256 CUs x 64 lanes x 2.4 GHz: one lane-operation per lane per clock (FP32 or FP64).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
@@ -104,7 +110,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the path shards per map or per ray row, see the design notes)", file=sys.stderr)
+              "(on several GPUs the path would deal maps or ray rows to GPUs and gather "
+              "the per-GPU top-k lists)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
