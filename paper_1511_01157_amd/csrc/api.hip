@@ -58,6 +58,9 @@ struct morse_ctx {
   // batched-search graph
   hipGraphExec_t gexec = nullptr;
   uint64_t graph_key = 0;
+  // refinement graph
+  hipGraphExec_t refine_gexec = nullptr;
+  uint64_t refine_key = 0;
   // autotune choices per shape class
   std::map<std::string, int> tune;
   // small auxiliary device buffer, separate from the workspace
@@ -127,6 +130,11 @@ int reserve(morse_ctx* ctx, size_t bytes) {
     (void)hipGraphExecDestroy(ctx->gexec);
     ctx->gexec = nullptr;
     ctx->graph_key = 0;
+  }
+  if (ctx->refine_gexec) {
+    (void)hipGraphExecDestroy(ctx->refine_gexec);
+    ctx->refine_gexec = nullptr;
+    ctx->refine_key = 0;
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
@@ -354,6 +362,7 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->refine_gexec) (void)hipGraphExecDestroy(ctx->refine_gexec);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
   (void)hipStreamDestroy(ctx->capture_stream);
@@ -1011,8 +1020,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                  const morse_lbfgs_opts* opts, double* d_chi2_out, double* d_chi2_init) {
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
-  if (opts->steps < 0 || opts->history < 1 || opts->history > 16 || opts->max_ls < 1 ||
-      !(opts->c1 > 0 && opts->c1 < 1) || !(opts->shrink > 0 && opts->shrink < 1))
+  if (opts->steps < 0 || opts->steps > 100000 || opts->history < 1 || opts->history > 16 ||
+      opts->max_ls < 1 || !(opts->c1 > 0 && opts->c1 < 1) || !(opts->shrink > 0 && opts->shrink < 1))
     return fail(ctx, MORSE_EINVAL, "invalid L-BFGS options");
   int rc;
   Plan pl;
@@ -1026,8 +1035,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   const size_t i_anchor = pl.add(32 * n), i_p = pl.add(16 * n), i_pt = pl.add(16 * n),
                i_f = pl.add(8 * n), i_g = pl.add(32 * n), i_d = pl.add(32 * n), i_step = pl.add(8 * n),
                i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
-               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n), i_ft = pl.add(8 * n),
-               i_gt = pl.add(32 * n);
+               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
   MapC* d_maps;
@@ -1054,14 +1062,6 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   s.start = ints + n;
   s.nls = ints + 2 * n;
   s.active = ints + 3 * n;
-  double* ft = (double*)pl.ptr(ctx, i_ft);
-  double* gt = (double*)pl.ptr(ctx, i_gt);
-  s.ft = ft;
-  s.gt = gt;
-  HIP_TRY(ctx, hipMemcpyAsync(anchor, d_params, 32 * n, hipMemcpyDeviceToDevice, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32((uint32_t*)s.pt, 4 * n, 0u, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32((uint32_t*)ints, 3 * n, 0u, ctx->stream));
-  HIP_TRY(ctx, launch_fill_u32((uint32_t*)s.active, n, 1u, ctx->stream));
   a.n = n;
   a.anchor = anchor;
   a.pt = s.pt;
@@ -1071,15 +1071,53 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.maps = d_maps;
   a.n_events = lcs->n_events;
   a.n_maps = n_maps;
-  a.chi2 = ft;
-  a.grad = gt;
-  for (int r = 0; r <= opts->steps; ++r) {
-    HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
-    if (r == 0 && d_chi2_init)
-      HIP_TRY(ctx, hipMemcpyAsync(d_chi2_init, ft, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
-    HIP_TRY(ctx, launch_lbfgs_update(s, r, ctx->stream));
+  // The rounds are captured once per argument set and replayed: copy of the start
+  // parameters, clears (fill kernels), steps + 1 fused rounds, write-back.
+  Hasher h;
+  h.pod(ctx->ws_epoch);
+  h.pod(n);
+  h.pod(n_maps);
+  h.pod(lcs->n_events);
+  h.pod(*opts);
+  h.pod(d_params);
+  h.pod(d_event);
+  h.pod(d_map_index);
+  h.pod(d_chi2_out);
+  h.pod(d_chi2_init);
+  h.pod(lcs->d_t);
+  h.pod(lcs->d_flux);
+  h.pod(lcs->d_weight);
+  if (!ctx->refine_gexec || ctx->refine_key != h.h) {
+    if (ctx->refine_gexec) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipGraphExecDestroy(ctx->refine_gexec);
+      ctx->refine_gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipStream_t cs = ctx->capture_stream;
+    HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_copy_f64(anchor, d_params, 4 * n, cs);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.pt, 4 * n, 0u, cs);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)ints, 3 * n, 0u, cs);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.active, n, 1u, cs);
+    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r)
+      e = launch_refine_round(a, s, r, d_chi2_init, cs);
+    if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ctx, MORSE_EHIP, "refine graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&ctx->refine_gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ctx->refine_gexec = nullptr;
+      return fail(ctx, MORSE_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->refine_key = h.h;
   }
-  HIP_TRY(ctx, launch_lbfgs_finish(s, d_params, d_chi2_out, ctx->stream));
+  HIP_TRY(ctx, hipGraphLaunch(ctx->refine_gexec, ctx->stream));
   return MORSE_OK;
 }
 

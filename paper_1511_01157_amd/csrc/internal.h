@@ -68,28 +68,50 @@ struct Sample {
   bool on;
 };
 
+// Two adjacent floats at any dword-aligned address (one 8-byte load).
+struct __attribute__((packed, aligned(4))) Pair {
+  float a, b;
+};
+
+// Load base[i] through a uniform base pointer and a 32-bit element offset, so the
+// backend can address with a scalar base plus one 32-bit VGPR offset.
+template <class T>
+__device__ __forceinline__ T ldg(const T* __restrict__ base, uint32_t i) {
+  return *(const T*)((const char*)base + (size_t)(i * (uint32_t)sizeof(T)));
+}
+
+__device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, float& v00, float& v10,
+                                         float& v01, float& v11) {
+  const uint32_t o = (uint32_t)(int)fj * (uint32_t)m.mx + (uint32_t)(int)fi;
+  const Pair r0 = *(const Pair*)((const char*)m.map + (size_t)(o * 4u));
+  const Pair r1 = *(const Pair*)((const char*)m.map + (size_t)((o + (uint32_t)m.mx) * 4u));
+  v00 = r0.a;
+  v10 = r0.b;
+  v01 = r1.a;
+  v11 = r1.b;
+}
+
 __device__ __forceinline__ float sample_A(const MapC& m, float tt, float t0p, float iE, float ca,
                                           float sa, float bx, float by) {
-  float tau = (tt - t0p) * iE;
-  float zx = tau * ca + bx;
-  float zy = tau * sa + by;
-  float gx = ((zx - m.sx) * m.kx) + m.ox;
-  float gy = ((zy - m.sy) * m.ky) + m.oy;
+  const float tau = (tt - t0p) * iE;
+  const float zx = tau * ca + bx;
+  const float zy = tau * sa + by;
+  const float gx = ((zx - m.sx) * m.kx) + m.ox;
+  const float gy = ((zy - m.sy) * m.ky) + m.oy;
   if (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly) {
-    float fi = floorf(gx);
-    float fj = floorf(gy);
-    float fx = gx - fi;
-    float fy = gy - fj;
-    const float* p = m.map + (size_t)(int)fj * (size_t)m.mx + (int)fi;
-    float v00 = p[0], v10 = p[1];
-    float v01 = p[m.mx], v11 = p[m.mx + 1];
-    float e0 = v10 - v00;
-    float e1 = v11 - v01;
-    float ax0 = v00 + fx * e0;
-    float ax1 = v01 + fx * e1;
+    const float fi = floorf(gx);
+    const float fj = floorf(gy);
+    const float fx = gx - fi;
+    const float fy = gy - fj;
+    float v00, v10, v01, v11;
+    map_cell(m, fi, fj, v00, v10, v01, v11);
+    const float e0 = v10 - v00;
+    const float e1 = v11 - v01;
+    const float ax0 = v00 + fx * e0;
+    const float ax1 = v01 + fx * e1;
     return ax0 + fy * (ax1 - ax0);
   }
-  float uu = zx * zx + zy * zy;
+  const float uu = zx * zx + zy * zy;
   return (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
 }
 
@@ -99,24 +121,23 @@ __device__ __forceinline__ Sample sample_full(const MapC& m, float tt, float t0p
   s.tau = (tt - t0p) * iE;
   s.zx = s.tau * ca + bx;
   s.zy = s.tau * sa + by;
-  float gx = ((s.zx - m.sx) * m.kx) + m.ox;
-  float gy = ((s.zy - m.sy) * m.ky) + m.oy;
+  const float gx = ((s.zx - m.sx) * m.kx) + m.ox;
+  const float gy = ((s.zy - m.sy) * m.ky) + m.oy;
   s.on = (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly);
   if (s.on) {
-    float fi = floorf(gx);
-    float fj = floorf(gy);
+    const float fi = floorf(gx);
+    const float fj = floorf(gy);
     s.fx = gx - fi;
     s.fy = gy - fj;
-    const float* p = m.map + (size_t)(int)fj * (size_t)m.mx + (int)fi;
-    float v00 = p[0], v10 = p[1];
-    float v01 = p[m.mx], v11 = p[m.mx + 1];
+    float v00, v10, v01, v11;
+    map_cell(m, fi, fj, v00, v10, v01, v11);
     s.e0 = v10 - v00;
     s.e1 = v11 - v01;
     s.ax0 = v00 + s.fx * s.e0;
     s.ax1 = v01 + s.fx * s.e1;
     s.A = s.ax0 + s.fy * (s.ax1 - s.ax0);
   } else {
-    float uu = s.zx * s.zx + s.zy * s.zy;
+    const float uu = s.zx * s.zx + s.zy * s.zy;
     s.A = (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
     s.fx = s.fy = s.e0 = s.e1 = s.ax0 = s.ax1 = 0.0f;
   }
@@ -169,6 +190,7 @@ __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, dou
 // first HIP error.
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
+hipError_t launch_copy_f64(double* dst, const double* src, size_t n, hipStream_t st);
 hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
                            hipStream_t st);
 hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
@@ -261,10 +283,11 @@ struct LbfgsState {
   int32_t* start;        // [n]
   int32_t* nls;          // [n]
   int32_t* active;       // [n]
-  const double* ft;      // [n] evaluation at pt
-  const double* gt;      // [n][4]
 };
-hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, hipStream_t st);
+// One round (evaluation + update) of every active candidate; chi2_init (nullable)
+// receives the round-0 chi2.
+hipError_t launch_refine_round(const GradArgs& a, const LbfgsState& s, int32_t round,
+                               double* chi2_init, hipStream_t st);
 hipError_t launch_lbfgs_finish(const LbfgsState& s, double* params, double* chi2_out,
                                hipStream_t st);
 

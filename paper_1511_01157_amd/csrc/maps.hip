@@ -44,6 +44,12 @@ __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
     p[i] = v;
 }
 
+__global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // Symmetric bin rule: v >= 0 (also -0) -> m/2 + floor(v) if v < m/2;
 // v < 0 -> m/2 - 1 - floor(-v) if -v < m/2.  floor(|v|) serves both branches.
 __device__ __forceinline__ bool bin1(float v, int32_t m, int32_t& out) {
@@ -256,6 +262,14 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(double* dst, const double* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

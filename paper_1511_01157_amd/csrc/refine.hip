@@ -16,9 +16,10 @@
 // dA/dzeta: on the map, k (e0 + fy (e1 - e0), ax1 - ax0) from the bilinear cell;
 // off the map, A(u) = (u^2+2)/(u sqrt(u^2+4)) gives dA/du = -8/(u^2 (u^2+4)^(3/2)).
 //
-// L-BFGS.  One thread per candidate runs the update of the state machine (accept on
-// the Armijo test or backtrack; two-loop recursion for the next direction), keeping
-// the binary32 variables p and the FP64 history in structure-of-arrays form.
+// L-BFGS.  After its evaluation, the first thread of a candidate's workgroup runs the
+// update of the state machine (accept on the Armijo test or backtrack; two-loop
+// recursion for the next direction), so one launch serves one round; the state (binary32
+// variables p, FP64 history) is kept in structure-of-arrays form.
 
 #include "internal.h"
 
@@ -55,119 +56,133 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV])
 // One workgroup (GRAD_THREADS lanes over the points) per candidate.
 constexpr int GRAD_THREADS = 256;
 
+struct Eval {
+  double chi2, Fs, Fb;
+  double g[4];
+  bool valid;
+};
+
+// chi2, (F_s, F_b) and the gradient of candidate c (every thread returns the same).
+// With an anchor the parameters are the L-BFGS variables and the gradient is with
+// respect to them.
+__device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s3)[3], double (*s6)[6]) {
+  Eval out;
+  const int tid = threadIdx.x;
+  const int32_t e = a.event[c];
+  const int32_t mi = a.mapidx[c];
+  out.valid = !(e < 0 || e >= a.n_events || mi < 0 || mi >= a.n_maps);
+  if (!out.valid) {
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    out.chi2 = out.Fs = out.Fb = nan;
+    for (int q = 0; q < 4; ++q) out.g[q] = nan;
+    return out;
+  }
+  const MapC m = a.maps[mi];
+  double t0, u0, tE, al, tE_anchor = 0.0;
+  if (a.anchor) {
+    const double* an = a.anchor + 4 * c;
+    const float* p = a.pt + 4 * c;
+    tE_anchor = an[2];
+    t0 = an[0] + (double)p[0] * an[2];
+    u0 = an[1] + (double)p[1];
+    tE = an[2] * exp((double)p[2]);
+    al = an[3] + (double)p[3];
+  } else {
+    const double* p = a.params + 4 * c;
+    t0 = p[0];
+    u0 = p[1];
+    tE = p[2];
+    al = p[3];
+  }
+  double sn, cs;
+  sincos(al, &sn, &cs);
+  const float iE = (float)(1.0 / tE);
+  const float ca = (float)cs;
+  const float sa = (float)sn;
+  const float bx = (float)(-u0 * sn);
+  const float by = (float)(u0 * cs);
+  const float t0p = (float)(t0 - a.lc.t_ref[e]);
+
+  const int64_t p0 = a.lc.off[e];
+  const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
+  const float* t = a.lc.t + p0;
+  const double* w = a.lc.w + p0;
+  const double* wFc = a.lc.wFc + p0;
+  const double* F = a.lc.F + p0;
+  const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
+
+  // pass 1: normal-equation sums (centred form) and the profiled fit
+  double n1[3] = {0.0, 0.0, 0.0};
+  for (int32_t i = tid; i < np; i += GRAD_THREADS) {
+    const uint32_t u = (uint32_t)i;
+    const double b = (double)sample_A(m, ldg(t, u), t0p, iE, ca, sa, bx, by) - 1.0;
+    const double wb = ldg(w, u) * b;
+    n1[0] += wb;
+    n1[1] = fma(wb, b, n1[1]);
+    n1[2] = fma(b, ldg(wFc, u), n1[2]);
+  }
+  block_sum<3>(n1, s3);
+  const Fit fit = centred_fit(Sw, Fbar, V, n1[0], n1[1], n1[2]);
+  const double Fs = fit.Fs, Fb = fit.Fb;
+
+  // pass 2: residuals, direct chi-square and gradient sums
+  const double kx = (double)m.kx, ky = (double)m.ky;
+  double n2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // chi, Gx, Gy, Gxt, Gyt, Ga
+  for (int32_t i = tid; i < np; i += GRAD_THREADS) {
+    const uint32_t u = (uint32_t)i;
+    const Sample sm = sample_full(m, ldg(t, u), t0p, iE, ca, sa, bx, by);
+    const double A = (double)sm.A;
+    const double r = ldg(F, u) - Fs * A - Fb;
+    const double wr = ldg(w, u) * r;
+    const double zx = (double)sm.zx, zy = (double)sm.zy, tau = (double)sm.tau;
+    double dAx, dAy;
+    if (sm.on) {
+      const double e0 = (double)sm.e0, e1 = (double)sm.e1;
+      dAx = kx * (e0 + (double)sm.fy * (e1 - e0));
+      dAy = ky * ((double)sm.ax1 - (double)sm.ax0);
+    } else {
+      // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
+      const double u2 = zx * zx + zy * zy;
+      const double pp = u2 * (u2 + 4.0);
+      const double f = -8.0 / (pp * sqrt(pp));
+      dAx = f * zx;
+      dAy = f * zy;
+    }
+    n2[0] = fma(wr, r, n2[0]);
+    n2[1] = fma(wr, dAx, n2[1]);
+    n2[2] = fma(wr, dAy, n2[2]);
+    n2[3] = fma(wr * dAx, tau, n2[3]);
+    n2[4] = fma(wr * dAy, tau, n2[4]);
+    n2[5] = fma(wr, zx * dAy - zy * dAx, n2[5]);
+  }
+  block_sum<6>(n2, s6);
+  const double c64 = (double)ca, s64 = (double)sa;
+  const double k2 = -2.0 * Fs;
+  out.g[0] = k2 * (-(c64 * n2[1] + s64 * n2[2]) / tE);
+  out.g[1] = k2 * (-s64 * n2[1] + c64 * n2[2]);
+  out.g[2] = k2 * (-(c64 * n2[3] + s64 * n2[4]) / tE);
+  out.g[3] = k2 * n2[5];
+  if (a.anchor) {  // gradient with respect to the scaled variables
+    out.g[0] = out.g[0] * tE_anchor;
+    out.g[2] = out.g[2] * tE;
+  }
+  out.chi2 = n2[0];
+  out.Fs = Fs;
+  out.Fb = Fb;
+  return out;
+}
+
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   __shared__ double s3[GRAD_THREADS / kWave][3];
   __shared__ double s6[GRAD_THREADS / kWave][6];
-  const int tid = threadIdx.x;
   for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
-    if (a.active && !a.active[c]) continue;
-    const int32_t e = a.event[c];
-    const int32_t mi = a.mapidx[c];
-    if (e < 0 || e >= a.n_events || mi < 0 || mi >= a.n_maps) {
-      if (tid == 0) {
-        const double nan = __longlong_as_double(0x7ff8000000000000ll);
-        if (a.chi2) a.chi2[c] = nan;
-        if (a.grad)
-          for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = nan;
-        if (a.fs) a.fs[c] = nan;
-        if (a.fb) a.fb[c] = nan;
-      }
-      continue;
-    }
-    const MapC m = a.maps[mi];
-    double t0, u0, tE, al, tE_anchor = 0.0;
-    if (a.anchor) {
-      const double* an = a.anchor + 4 * c;
-      const float* p = a.pt + 4 * c;
-      tE_anchor = an[2];
-      t0 = an[0] + (double)p[0] * an[2];
-      u0 = an[1] + (double)p[1];
-      tE = an[2] * exp((double)p[2]);
-      al = an[3] + (double)p[3];
-    } else {
-      const double* p = a.params + 4 * c;
-      t0 = p[0];
-      u0 = p[1];
-      tE = p[2];
-      al = p[3];
-    }
-    double sn, cs;
-    sincos(al, &sn, &cs);
-    const float iE = (float)(1.0 / tE);
-    const float ca = (float)cs;
-    const float sa = (float)sn;
-    const float bx = (float)(-u0 * sn);
-    const float by = (float)(u0 * cs);
-    const float t0p = (float)(t0 - a.lc.t_ref[e]);
-
-    const int64_t p0 = a.lc.off[e];
-    const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
-    const float* t = a.lc.t + p0;
-    const double* w = a.lc.w + p0;
-    const double* wFc = a.lc.wFc + p0;
-    const double* F = a.lc.F + p0;
-    const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
-
-    // pass 1: normal-equation sums (centred form) and the profiled fit
-    double n1[3] = {0.0, 0.0, 0.0};
-    for (int32_t i = tid; i < np; i += GRAD_THREADS) {
-      const double b = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by) - 1.0;
-      const double wb = w[i] * b;
-      n1[0] += wb;
-      n1[1] = fma(wb, b, n1[1]);
-      n1[2] = fma(b, wFc[i], n1[2]);
-    }
-    block_sum<3>(n1, s3);
-    const Fit fit = centred_fit(Sw, Fbar, V, n1[0], n1[1], n1[2]);
-    const double Fs = fit.Fs, Fb = fit.Fb;
-
-    // pass 2: residuals, direct chi-square and gradient sums
-    const double kx = (double)m.kx, ky = (double)m.ky;
-    double n2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // chi, Gx, Gy, Gxt, Gyt, Ga
-    for (int32_t i = tid; i < np; i += GRAD_THREADS) {
-      const Sample s = sample_full(m, t[i], t0p, iE, ca, sa, bx, by);
-      const double A = (double)s.A;
-      const double r = F[i] - Fs * A - Fb;
-      const double wr = w[i] * r;
-      const double zx = (double)s.zx, zy = (double)s.zy, tau = (double)s.tau;
-      double dAx, dAy;
-      if (s.on) {
-        const double e0 = (double)s.e0, e1 = (double)s.e1;
-        dAx = kx * (e0 + (double)s.fy * (e1 - e0));
-        dAy = ky * ((double)s.ax1 - (double)s.ax0);
-      } else {
-        // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
-        const double u2 = zx * zx + zy * zy;
-        const double p = u2 * (u2 + 4.0);
-        const double f = -8.0 / (p * sqrt(p));
-        dAx = f * zx;
-        dAy = f * zy;
-      }
-      n2[0] = fma(wr, r, n2[0]);
-      n2[1] = fma(wr, dAx, n2[1]);
-      n2[2] = fma(wr, dAy, n2[2]);
-      n2[3] = fma(wr * dAx, tau, n2[3]);
-      n2[4] = fma(wr * dAy, tau, n2[4]);
-      n2[5] = fma(wr, zx * dAy - zy * dAx, n2[5]);
-    }
-    block_sum<6>(n2, s6);
-    if (tid == 0) {
-      const double c64 = (double)ca, s64 = (double)sa;
-      const double k2 = -2.0 * Fs;
-      double g[4];
-      g[0] = k2 * (-(c64 * n2[1] + s64 * n2[2]) / tE);
-      g[1] = k2 * (-s64 * n2[1] + c64 * n2[2]);
-      g[2] = k2 * (-(c64 * n2[3] + s64 * n2[4]) / tE);
-      g[3] = k2 * n2[5];
-      if (a.anchor) {  // gradient with respect to the scaled variables
-        g[0] = g[0] * tE_anchor;
-        g[2] = g[2] * tE;
-      }
-      if (a.chi2) a.chi2[c] = n2[0];
+    const Eval ev = grad_eval(a, c, s3, s6);
+    if (threadIdx.x == 0) {
+      if (a.chi2) a.chi2[c] = ev.chi2;
       if (a.grad)
-        for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = g[q];
-      if (a.fs) a.fs[c] = Fs;
-      if (a.fb) a.fb[c] = Fb;
+        for (int q = 0; q < 4; ++q) a.grad[4 * c + q] = ev.g[q];
+      if (a.fs) a.fs[c] = ev.Fs;
+      if (a.fb) a.fb[c] = ev.Fb;
     }
   }
 }
@@ -233,14 +248,14 @@ __device__ void new_direction(const LbfgsState& s, int64_t c) {
   if (!moved) s.active[c] = 0;
 }
 
-__global__ void k_lbfgs_update(LbfgsState s, int32_t round) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= s.n || !s.active[c]) return;
-  const double ft = s.ft[c];
+// One update of the state machine for candidate c given the evaluation (ft, gt) at
+// its trial point.
+__device__ void lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double ft,
+                           const double* gt) {
   if (round == 0) {
     for (int k = 0; k < 4; ++k) {
       s.p[4 * c + k] = s.pt[4 * c + k];
-      s.g[4 * c + k] = s.gt[4 * c + k];
+      s.g[4 * c + k] = gt[k];
     }
     s.f[c] = ft;
     new_direction(s, c);
@@ -257,12 +272,12 @@ __global__ void k_lbfgs_update(LbfgsState s, int32_t round) {
     double sv[4], yv[4];
     for (int k = 0; k < 4; ++k) {
       sv[k] = (double)s.pt[4 * c + k] - (double)s.p[4 * c + k];
-      yv[k] = s.gt[4 * c + k] - g[k];
+      yv[k] = gt[k] - g[k];
     }
     const double sy = dot4(sv, yv);
     if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
-      int nh = s.nhist[c];
-      int st = s.start[c];
+      const int nh = s.nhist[c];
+      const int st = s.start[c];
       int slot;
       if (nh < s.m) {
         slot = (st + nh) % s.m;
@@ -280,7 +295,7 @@ __global__ void k_lbfgs_update(LbfgsState s, int32_t round) {
     }
     for (int k = 0; k < 4; ++k) {
       s.p[4 * c + k] = s.pt[4 * c + k];
-      s.g[4 * c + k] = s.gt[4 * c + k];
+      s.g[4 * c + k] = gt[k];
     }
     s.f[c] = ft;
     new_direction(s, c);
@@ -295,6 +310,23 @@ __global__ void k_lbfgs_update(LbfgsState s, int32_t round) {
       for (int k = 0; k < 4; ++k)
         s.pt[4 * c + k] = (float)((double)s.p[4 * c + k] + tn * d[k]);
     }
+  }
+}
+
+// One refinement round: every active candidate's workgroup evaluates chi2 and the
+// gradient at its trial point, then its first thread runs the update.
+__global__ __launch_bounds__(GRAD_THREADS) void k_refine_round(GradArgs a, LbfgsState s,
+                                                               int32_t round, double* chi2_init) {
+  __shared__ double s3[GRAD_THREADS / kWave][3];
+  __shared__ double s6[GRAD_THREADS / kWave][6];
+  for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
+    if (!s.active[c]) continue;  // uniform per workgroup
+    const Eval ev = grad_eval(a, c, s3, s6);
+    if (threadIdx.x == 0) {
+      if (round == 0 && chi2_init) chi2_init[c] = ev.chi2;
+      lbfgs_step(s, c, round, ev.chi2, ev.g);
+    }
+    __syncthreads();  // the update's writes precede the next candidate's reads
   }
 }
 
@@ -320,10 +352,13 @@ hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, hipStream_t st) {
-  if (s.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s,
-                     round);
+hipError_t launch_refine_round(const GradArgs& a, const LbfgsState& s, int32_t round,
+                               double* chi2_init, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  int64_t blocks = a.n;
+  if (blocks > 1 << 20) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_refine_round, dim3((unsigned)blocks), dim3(GRAD_THREADS), 0, st, a, s, round,
+                     chi2_init);
   return hipGetLastError();
 }
 

@@ -136,14 +136,12 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 
 // ---------------------------------------------------------------------------
 // Score one trajectory with one wavefront.  All lanes return the same values.
-// Each lane takes SU points per iteration (i, i + 64, ...): every load of the
-// iteration (times, weights, both map rows of every cell) is issued before the
-// arithmetic that needs it, so one memory latency covers SU points.  Map rows are
-// read at the clamped cell even for points off the map (always in bounds); the
-// bilinear value is then discarded for them and only the single-lens branch is
-// conditional.  The arithmetic of each point is exactly that of sample_A.
+// Each lane takes SU points per iteration (i, i + 64, ...), with their light-curve
+// loads issued together; only lanes whose point is on the map read the map (a
+// wavefront's lanes hold neighbouring times, so they mostly agree), the others take
+// the single-lens branch.  Arrays are addressed by 32-bit offsets from uniform bases.
 #ifndef MORSE_SU
-#define MORSE_SU 1
+#define MORSE_SU 2
 #endif
 constexpr int SU = MORSE_SU;  // points per lane per iteration (tuning knob)
 
@@ -159,42 +157,15 @@ __device__ __forceinline__ void score_traj(const MapC& m, const float* __restric
     double wv[SU], fv[SU];
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
-      const int32_t i = min(i0 + u * kWave, np - 1);
-      tt[u] = t[i];
-      wv[u] = w[i];
-      fv[u] = wFc[i];
-    }
-    float zx[SU], zy[SU], gx[SU], gy[SU];
-    float2 r0[SU], r1[SU];
-#pragma unroll
-    for (int u = 0; u < SU; ++u) {
-      const float tau = (tt[u] - t0p) * c.iE;
-      zx[u] = tau * c.ca + c.bx;
-      zy[u] = tau * c.sa + c.by;
-      gx[u] = ((zx[u] - m.sx) * m.kx) + m.ox;
-      gy[u] = ((zy[u] - m.sy) * m.ky) + m.oy;
-      // clamped cell (NaN -> 0): always a valid 2x2 block
-      const int ic = (int)floorf(fminf(fmaxf(gx[u], 0.0f), m.lx - 1.0f));
-      const int jc = (int)floorf(fminf(fmaxf(gy[u], 0.0f), m.ly - 1.0f));
-      const float* p = m.map + (size_t)jc * (size_t)m.mx + ic;
-      r0[u] = make_float2(p[0], p[1]);
-      r1[u] = make_float2(p[m.mx], p[m.mx + 1]);
+      const uint32_t i = (uint32_t)min(i0 + u * kWave, np - 1);
+      tt[u] = ldg(t, i);
+      wv[u] = ldg(w, i);
+      fv[u] = ldg(wFc, i);
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
-      const bool on = gx[u] >= 0.0f && gx[u] < m.lx && gy[u] >= 0.0f && gy[u] < m.ly;
-      const float fx = gx[u] - floorf(gx[u]);
-      const float fy = gy[u] - floorf(gy[u]);
-      const float e0 = r0[u].y - r0[u].x;
-      const float e1 = r1[u].y - r1[u].x;
-      const float ax0 = r0[u].x + fx * e0;
-      const float ax1 = r1[u].x + fx * e1;
-      float A = ax0 + fy * (ax1 - ax0);
-      if (!on) {
-        const float uu = zx[u] * zx[u] + zy[u] * zy[u];
-        A = (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
-      }
-      if (i0 + u * kWave < np) {
+      const float A = sample_A(m, tt[u], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
+      if (SU == 1 || i0 + u * kWave < np) {
         const double b = (double)A - 1.0;
         const double wb = wv[u] * b;
         B1 += wb;
@@ -213,9 +184,9 @@ __device__ __forceinline__ void score_traj(const MapC& m, const float* __restric
   if (f.recheck) {  // wave-uniform: the sums are identical on every lane
     double q = 0.0;
     for (int32_t i = lane; i < np; i += kWave) {
-      const double a = (double)sample_A(m, t[i], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
-      const double r = F[i] - Fs * a - Fb;
-      q = fma(w[i] * r, r, q);
+      const double a = (double)sample_A(m, ldg(t, (uint32_t)i), t0p, c.iE, c.ca, c.sa, c.bx, c.by);
+      const double r = ldg(F, (uint32_t)i) - Fs * a - Fb;
+      q = fma(ldg(w, (uint32_t)i) * r, r, q);
     }
     chi2 = wave_sum(q);
   }
