@@ -145,6 +145,14 @@ def main():
         ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
                    for _ in range(args.steps)]
 
+        # step buffers, allocated once so the captured graphs replay every step
+        sbuf = {}
+        cand = (torch.empty((k, 4), dtype=torch.float64, device=dev),
+                torch.empty(k, dtype=torch.int32, device=dev),
+                torch.empty(k, dtype=torch.int32, device=dev))
+        rbuf = (torch.empty(k, dtype=torch.float64, device=dev),
+                torch.empty(k, dtype=torch.float64, device=dev))
+
         def step(evs=None):
             mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
             mark(0)
@@ -152,10 +160,12 @@ def main():
             mark(1)
             M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap)
             mark(2)
-            r = M.search(maps, lcs, trajs, "batched", chi2=False, top_k=k)
+            r = M.search(maps, lcs, trajs, "batched", chi2=False, top_k=k, out=sbuf)
+            sbuf.update(r)
             mark(3)
-            P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1)
-            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps)
+            P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1, out=cand)
+            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps,
+                                         inplace=True, chi2_out=rbuf)
             mark(4)
             return r, out, chi2, chi2_0
 
@@ -180,10 +190,10 @@ def main():
         if not args.no_plain:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
-            M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
+            pbuf = M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
             e0.record(stream)
             for _ in range(3):
-                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
+                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, out=pbuf)
             e1.record(stream)
             torch.cuda.synchronize()
             plain_ms = e0.elapsed_time(e1) / 3

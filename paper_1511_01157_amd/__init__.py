@@ -201,30 +201,34 @@ def _map_views(maps):
 
 
 def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,
-           best=False, top_k=0):
+           best=False, top_k=0, out=None):
     """Chi-square of every trajectory on every map for every event.
 
     maps: list of (map tensor, window).  Returns a dict with the requested outputs:
     chi2/fs/fb [n_events, n_maps, n_traj], best_chi2/best_idx [n_events, n_maps],
-    topk_chi2/topk_idx [n_events, top_k] (index = map * n_traj + traj).
+    topk_chi2/topk_idx [n_events, top_k] (index = map * n_traj + traj).  ``out`` (a
+    dict from an earlier call with the same arguments) is reused instead of allocating;
+    the batched mode replays its captured graph only when all buffers are the same.
     """
     dev = lcs.t.device
     ctx = Context.get(_device_of(lcs.t))
     ne, nm, nt = lcs.n_events, len(maps), trajs.n
+    want = {"chi2": ((ne, nm, nt), torch.float64) if chi2 else None,
+            "fs": ((ne, nm, nt), torch.float64) if fs else None,
+            "fb": ((ne, nm, nt), torch.float64) if fb else None,
+            "best_chi2": ((ne, nm), torch.float64) if best else None,
+            "best_idx": ((ne, nm), torch.int64) if best else None,
+            "topk_chi2": ((ne, top_k), torch.float64) if top_k else None,
+            "topk_idx": ((ne, top_k), torch.int64) if top_k else None}
     res = {}
-    f64 = lambda *s: torch.empty(s, dtype=torch.float64, device=dev)
-    if chi2:
-        res["chi2"] = f64(ne, nm, nt)
-    if fs:
-        res["fs"] = f64(ne, nm, nt)
-    if fb:
-        res["fb"] = f64(ne, nm, nt)
-    if best:
-        res["best_chi2"] = f64(ne, nm)
-        res["best_idx"] = torch.empty((ne, nm), dtype=torch.int64, device=dev)
-    if top_k:
-        res["topk_chi2"] = f64(ne, top_k)
-        res["topk_idx"] = torch.empty((ne, top_k), dtype=torch.int64, device=dev)
+    for k, spec in want.items():
+        if spec is None:
+            continue
+        shape, dt = spec
+        t = out.get(k) if out else None
+        if t is None or tuple(t.shape) != shape or t.dtype != dt or not t.is_contiguous():
+            t = torch.empty(shape, dtype=dt, device=dev)
+        res[k] = t
     out = SearchOut(*(res[k].data_ptr() if k in res else None
                       for k in ("chi2", "fs", "fb", "best_chi2", "best_idx")),
                     int(top_k), 0, res["topk_chi2"].data_ptr() if top_k else None,
@@ -249,15 +253,18 @@ def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None):
     return best.value
 
 
-def candidates_from_topk(trajs, topk_idx, n_maps):
+def candidates_from_topk(trajs, topk_idx, n_maps, out=None):
     """Refinement candidates from a search's top-k: params [n_events*k, 4] float64,
-    event and map index [n_events*k] int32."""
+    event and map index [n_events*k] int32 (written into ``out`` when given)."""
     ne, k = topk_idx.shape
     dev = topk_idx.device
     ctx = Context.get(_device_of(topk_idx))
-    params = torch.empty((ne * k, 4), dtype=torch.float64, device=dev)
-    event = torch.empty(ne * k, dtype=torch.int32, device=dev)
-    mapi = torch.empty(ne * k, dtype=torch.int32, device=dev)
+    if out is not None:
+        params, event, mapi = out
+    else:
+        params = torch.empty((ne * k, 4), dtype=torch.float64, device=dev)
+        event = torch.empty(ne * k, dtype=torch.int32, device=dev)
+        mapi = torch.empty(ne * k, dtype=torch.int32, device=dev)
     ta = trajs.abi()
     ctx.check(ctx.lib.morse_candidates_from_topk(ctx.handle, ctypes.byref(ta), int(ne), int(n_maps),
                                                  int(k), _ptr(topk_idx.contiguous()), _ptr(params),
@@ -294,13 +301,18 @@ def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True):
 
 
 def refine(maps, lcs: LightCurveBatch, params, event, map_index, steps=50, history=8, max_ls=10,
-           c1=1e-4, shrink=0.5):
-    """Refined params (new tensor), final chi2 and initial chi2."""
+           c1=1e-4, shrink=0.5, inplace=False, chi2_out=None):
+    """Refined params, final chi2 and initial chi2.  With ``inplace`` the refined
+    parameters overwrite ``params``; ``chi2_out`` = (chi2, chi2_init) buffers to reuse
+    (the captured rounds replay only when every buffer is the same)."""
     n = _cand_args(params, event, map_index)
     ctx = Context.get(_device_of(params))
-    out = params.clone()
-    chi2 = torch.empty(n, dtype=torch.float64, device=params.device)
-    chi2_0 = torch.empty(n, dtype=torch.float64, device=params.device)
+    out = params if inplace else params.clone()
+    if chi2_out is not None:
+        chi2, chi2_0 = chi2_out
+    else:
+        chi2 = torch.empty(n, dtype=torch.float64, device=params.device)
+        chi2_0 = torch.empty(n, dtype=torch.float64, device=params.device)
     opts = LbfgsOpts(int(steps), int(history), int(max_ls), 0, float(c1), float(shrink))
     views = _map_views(maps)
     lca = lcs.abi()

@@ -995,8 +995,11 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (n > 0 && (!d_params || !d_event || !d_map_index))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
+  a.tc = (TrajC*)pl.ptr(ctx, i_tc);
+  a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
   if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
   a.n = n;
@@ -1010,6 +1013,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.grad = d_grad;
   a.fs = d_fs;
   a.fb = d_fb;
+  HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
   HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
   return MORSE_OK;
 }
@@ -1035,9 +1039,13 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   const size_t i_anchor = pl.add(32 * n), i_p = pl.add(16 * n), i_pt = pl.add(16 * n),
                i_f = pl.add(8 * n), i_g = pl.add(32 * n), i_d = pl.add(32 * n), i_step = pl.add(8 * n),
                i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
-               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n);
+               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n), i_ft = pl.add(8 * n),
+               i_gt = pl.add(32 * n), i_tc = pl.add(sizeof(TrajC) * (size_t)n),
+               i_tE = pl.add(8 * (size_t)n);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
+  a.tc = (TrajC*)pl.ptr(ctx, i_tc);
+  a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
   if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
   LbfgsState s;
@@ -1071,8 +1079,13 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.maps = d_maps;
   a.n_events = lcs->n_events;
   a.n_maps = n_maps;
+  double* ft = (double*)pl.ptr(ctx, i_ft);
+  double* gt = (double*)pl.ptr(ctx, i_gt);
+  a.chi2 = ft;
+  a.grad = gt;
   // The rounds are captured once per argument set and replayed: copy of the start
-  // parameters, clears (fill kernels), steps + 1 fused rounds, write-back.
+  // parameters, clears (fill kernels), steps + 1 rounds of (evaluation, update),
+  // write-back.
   Hasher h;
   h.pod(ctx->ws_epoch);
   h.pod(n);
@@ -1100,8 +1113,12 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.pt, 4 * n, 0u, cs);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)ints, 3 * n, 0u, cs);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.active, n, 1u, cs);
-    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r)
-      e = launch_refine_round(a, s, r, d_chi2_init, cs);
+    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
+      e = launch_cand_prep(a, cs);
+      if (e == hipSuccess) e = launch_chi2_grad(a, cs);
+      if (e == hipSuccess && r == 0 && d_chi2_init) e = launch_copy_f64(d_chi2_init, ft, n, cs);
+      if (e == hipSuccess) e = launch_lbfgs_update(s, r, ft, gt, cs);
+    }
     if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

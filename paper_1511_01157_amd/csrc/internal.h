@@ -256,12 +256,17 @@ struct GradArgs {
   const int32_t* mapidx;
   const MapC* maps;
   int32_t n_events, n_maps;  // out-of-range event / map indices give NaN outputs
+  TrajC* tc;                 // [n] per-candidate constants (written by the prep kernel)
+  double* tEv;               // [n] FP64 tE of each candidate
   LcView lc;
   double* chi2;
   double* grad;             // [n][4] or nullptr
   double* fs;
   double* fb;
 };
+// Per-candidate constants (FP64 natural parameters -> binary32 TrajC), then the
+// evaluation kernel.
+hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st);
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st);
 
 struct LbfgsState {
@@ -284,10 +289,9 @@ struct LbfgsState {
   int32_t* nls;          // [n]
   int32_t* active;       // [n]
 };
-// One round (evaluation + update) of every active candidate; chi2_init (nullable)
-// receives the round-0 chi2.
-hipError_t launch_refine_round(const GradArgs& a, const LbfgsState& s, int32_t round,
-                               double* chi2_init, hipStream_t st);
+// One update of every active candidate from its evaluation ft [n], gt [n][4].
+hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, const double* ft,
+                               const double* gt, hipStream_t st);
 hipError_t launch_lbfgs_finish(const LbfgsState& s, double* params, double* chi2_out,
                                hipStream_t st);
 

@@ -16,10 +16,11 @@
 // dA/dzeta: on the map, k (e0 + fy (e1 - e0), ax1 - ax0) from the bilinear cell;
 // off the map, A(u) = (u^2+2)/(u sqrt(u^2+4)) gives dA/du = -8/(u^2 (u^2+4)^(3/2)).
 //
-// L-BFGS.  After its evaluation, the first thread of a candidate's workgroup runs the
-// update of the state machine (accept on the Armijo test or backtrack; two-loop
-// recursion for the next direction), so one launch serves one round; the state (binary32
-// variables p, FP64 history) is kept in structure-of-arrays form.
+// L-BFGS.  One thread per candidate runs the update of the state machine (accept on the
+// Armijo test or backtrack; two-loop recursion for the next direction) after the
+// evaluation kernel; the state (binary32 variables p, FP64 history) is kept in
+// structure-of-arrays form.  (Running the update inside the evaluation workgroup was
+// slower: it raised register use and idled the workgroup during the serial update.)
 
 #include "internal.h"
 
@@ -78,30 +79,11 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s3)[3], double 
     return out;
   }
   const MapC m = a.maps[mi];
-  double t0, u0, tE, al, tE_anchor = 0.0;
-  if (a.anchor) {
-    const double* an = a.anchor + 4 * c;
-    const float* p = a.pt + 4 * c;
-    tE_anchor = an[2];
-    t0 = an[0] + (double)p[0] * an[2];
-    u0 = an[1] + (double)p[1];
-    tE = an[2] * exp((double)p[2]);
-    al = an[3] + (double)p[3];
-  } else {
-    const double* p = a.params + 4 * c;
-    t0 = p[0];
-    u0 = p[1];
-    tE = p[2];
-    al = p[3];
-  }
-  double sn, cs;
-  sincos(al, &sn, &cs);
-  const float iE = (float)(1.0 / tE);
-  const float ca = (float)cs;
-  const float sa = (float)sn;
-  const float bx = (float)(-u0 * sn);
-  const float by = (float)(u0 * cs);
-  const float t0p = (float)(t0 - a.lc.t_ref[e]);
+  const TrajC tc = a.tc[c];
+  const double tE = a.tEv[c];
+  const double tE_anchor = a.anchor ? a.anchor[4 * c + 2] : 0.0;
+  const float iE = tc.iE, ca = tc.ca, sa = tc.sa, bx = tc.bx, by = tc.by;
+  const float t0p = (float)(tc.t0 - a.lc.t_ref[e]);
 
   const int64_t p0 = a.lc.off[e];
   const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
@@ -172,10 +154,46 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s3)[3], double 
   return out;
 }
 
+// Natural parameters of each candidate (from the FP64 rows, or from the L-BFGS anchor
+// and binary32 displacement) -> trajectory constants, FP64 trigonometry rounded once.
+__global__ void k_cand_prep(GradArgs a) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  if (a.active && !a.active[c]) return;
+  double t0, u0, tE, al;
+  if (a.anchor) {
+    const double* an = a.anchor + 4 * c;
+    const float* p = a.pt + 4 * c;
+    t0 = an[0] + (double)p[0] * an[2];
+    u0 = an[1] + (double)p[1];
+    tE = an[2] * exp((double)p[2]);
+    al = an[3] + (double)p[3];
+  } else {
+    const double* p = a.params + 4 * c;
+    t0 = p[0];
+    u0 = p[1];
+    tE = p[2];
+    al = p[3];
+  }
+  double sn, cs;
+  sincos(al, &sn, &cs);
+  TrajC r;
+  r.t0 = t0;
+  r.iE = (float)(1.0 / tE);
+  r.ca = (float)cs;
+  r.sa = (float)sn;
+  r.bx = (float)(-u0 * sn);
+  r.by = (float)(u0 * cs);
+  r.pad = 0.0f;
+  a.tc[c] = r;
+  a.tEv[c] = tE;
+}
+
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   __shared__ double s3[GRAD_THREADS / kWave][3];
   __shared__ double s6[GRAD_THREADS / kWave][6];
   for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
+    if (a.active && !a.active[c]) continue;  // uniform per workgroup
     const Eval ev = grad_eval(a, c, s3, s6);
     if (threadIdx.x == 0) {
       if (a.chi2) a.chi2[c] = ev.chi2;
@@ -313,21 +331,13 @@ __device__ void lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double
   }
 }
 
-// One refinement round: every active candidate's workgroup evaluates chi2 and the
-// gradient at its trial point, then its first thread runs the update.
-__global__ __launch_bounds__(GRAD_THREADS) void k_refine_round(GradArgs a, LbfgsState s,
-                                                               int32_t round, double* chi2_init) {
-  __shared__ double s3[GRAD_THREADS / kWave][3];
-  __shared__ double s6[GRAD_THREADS / kWave][6];
-  for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
-    if (!s.active[c]) continue;  // uniform per workgroup
-    const Eval ev = grad_eval(a, c, s3, s6);
-    if (threadIdx.x == 0) {
-      if (round == 0 && chi2_init) chi2_init[c] = ev.chi2;
-      lbfgs_step(s, c, round, ev.chi2, ev.g);
-    }
-    __syncthreads();  // the update's writes precede the next candidate's reads
-  }
+__global__ void k_lbfgs_update(LbfgsState s, int32_t round, const double* __restrict__ ft,
+                               const double* __restrict__ gt) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= s.n || !s.active[c]) return;
+  double g[4];
+  for (int k = 0; k < 4; ++k) g[k] = gt[4 * c + k];
+  lbfgs_step(s, c, round, ft[c], g);
 }
 
 __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
@@ -344,6 +354,12 @@ __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
 
 }  // namespace
 
+hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cand_prep, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   int64_t blocks = a.n;
@@ -352,13 +368,11 @@ hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_refine_round(const GradArgs& a, const LbfgsState& s, int32_t round,
-                               double* chi2_init, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
-  int64_t blocks = a.n;
-  if (blocks > 1 << 20) blocks = 1 << 20;
-  hipLaunchKernelGGL(k_refine_round, dim3((unsigned)blocks), dim3(GRAD_THREADS), 0, st, a, s, round,
-                     chi2_init);
+hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, const double* ft,
+                               const double* gt, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s,
+                     round, ft, gt);
   return hipGetLastError();
 }
 

@@ -142,3 +142,27 @@ def test_chi2fn_autograd(tiny_oracle_map):
     (chi2 * w).sum().backward()
     _, g, _, _ = M.chi2_grad(maps, lcs, P.detach(), z, z)
     assert torch.allclose(P.grad, w[:, None] * g, rtol=0, atol=0)
+
+
+def test_refine_graph_replays_match_fresh_capture(tiny_oracle_map):
+    """The captured rounds replay on reused buffers (with eager work and
+    synchronisations in between) and give the same results as a fresh capture."""
+    c = W.config("tiny")
+    amap = tiny_oracle_map[2]
+    ev = W.load_lightcurve("tiny")
+    n = 16
+    P0 = torch.from_numpy(candidates(n, 6, ev["truth"])).to(DEV)
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    maps = [(dmap(amap), c["window"])]
+    z = torch.zeros(n, dtype=torch.int32, device=DEV)
+    note("refine graph replays")
+    ref, ref_chi2, _ = M.refine(maps, lcs, P0.clone(), z, z, steps=20)
+    P = P0.clone()
+    bufs = (torch.empty(n, dtype=torch.float64, device=DEV), torch.empty(n, dtype=torch.float64, device=DEV))
+    for rep in range(3):
+        P.copy_(P0)
+        torch.cuda.synchronize()
+        out, chi2, _ = M.refine(maps, lcs, P, z, z, steps=20, inplace=True, chi2_out=bufs)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(chi2, ref_chi2), rep
+        _ = (P0 * 2.0).sum().item()  # eager work between replays
