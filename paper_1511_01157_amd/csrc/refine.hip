@@ -4,10 +4,10 @@
 // sec. 4.2 bilinear map sampling) has (F_s, F_b) at their exact minimisers, so by the
 // envelope theorem d chi2/d theta = -2 F_s sum w r dA/d theta with r = F - F_s A - F_b.
 // One 256-lane workgroup per candidate (four wavefronts over the points, so a few
-// thousand candidates still fill the chip): pass 1 accumulates the normal-equation
-// sums and solves for (F_s, F_b) as the search does; pass 2 re-samples each point,
-// forms r, and accumulates in FP64
-//   chi2 = sum w r^2,  Gx = sum w r dA/dzx,  Gy = sum w r dA/dzy,
+// thousand candidates still fill the chip) samples each point once and accumulates in
+// FP64 the normal-equation sums with, for the directions D below, sum w D, sum w b D
+// and sum w (F - Fbar) D; the fit then gives (F_s, F_b) and the sums
+//   Gx = sum w r dA/dzx,  Gy = sum w r dA/dzy,
 //   Gxt = sum w r tau dA/dzx,  Gyt = sum w r tau dA/dzy,
 //   Ga = sum w r (zx dA/dzy - zy dA/dzx),
 // from which, with zeta = tau (ca, sa) + u0 (-sa, ca) and tau = (t - t0)/tE,
@@ -32,18 +32,44 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
   return ((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3];
 }
 
-// Sum of one FP64 value over the workgroup in a fixed order (wave butterflies, then
-// the wave partials in wave order); every thread returns the same value.
+// Wavefront reduce-scatter of N FP64 values per lane.  Each halving step over lane
+// bit MASK keeps ceil(N/2) slots: lanes with the bit set keep the upper half (padded
+// with a zero), the others the lower half, each adding its partner's copy of the slots
+// it keeps; six steps (MASK = 32 .. 1) exchange about N values in all, against 6 N for
+// a butterfly per value.  On return v[0] holds the wavefront total of original value
+// `slot` when `valid`; every value appears on exactly one valid lane (one with bit 0
+// clear), and the summation order is fixed.
+template <int N, int MASK>
+__device__ __forceinline__ void reduce_scatter(double* v, int lane, int& slot, bool& valid) {
+  if constexpr (MASK >= 1) {
+    constexpr int H = (N + 1) / 2;
+    const bool up = (lane & MASK) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double lo = v[i];
+      const double hi = (i + H < N) ? v[i + H] : 0.0;
+      const double other = __shfl_xor(up ? lo : hi, MASK, kWave);
+      v[i] = (up ? hi : lo) + other;
+    }
+    reduce_scatter<H, MASK / 2>(v, lane, slot, valid);
+    slot += up ? H : 0;
+    valid = valid && slot < N;
+  }
+}
+
+// Sum of NV FP64 values over the workgroup in a fixed order (a wavefront
+// reduce-scatter, then the wave partials in wave order); every thread returns the
+// same values.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV]) {
+  static_assert(kWave == 64 && NV <= 64, "reduce-scatter assumes 64-lane wavefronts");
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < NV; ++q) s_part[wave][q] = v[q];
+  int slot = 0;
+  bool valid = true;
+  reduce_scatter<NV, 32>(v, lane, slot, valid);
+  if (valid) s_part[wave][slot] = v[0];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -63,10 +89,41 @@ struct Eval {
   bool valid;
 };
 
+// dA/dzeta of one sample: on the map from the bilinear cell, off the map from the
+// point-source magnification.
+__device__ __forceinline__ void sample_dA(const Sample& sm, double kx, double ky, double& dAx,
+                                          double& dAy) {
+  if (sm.on) {
+    const double e0 = (double)sm.e0, e1 = (double)sm.e1;
+    dAx = kx * (e0 + (double)sm.fy * (e1 - e0));
+    dAy = ky * ((double)sm.ax1 - (double)sm.ax0);
+  } else {
+    // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
+    const double zx = (double)sm.zx, zy = (double)sm.zy;
+    const double u2 = zx * zx + zy * zy;
+    const double pp = u2 * (u2 + 4.0);
+    const double f = -8.0 / (pp * sqrt(pp));
+    dAx = f * zx;
+    dAy = f * zy;
+  }
+}
+
+// Number of derivative directions D (dA/dzx, dA/dzy, tau dA/dzx, tau dA/dzy,
+// zx dA/dzy - zy dA/dzx) and of one-pass sums (3 fit sums + 3 per direction).
+constexpr int kDirs = 5;
+constexpr int kSums = 3 + 3 * kDirs;
+
 // chi2, (F_s, F_b) and the gradient of candidate c (every thread returns the same).
 // With an anchor the parameters are the L-BFGS variables and the gradient is with
 // respect to them.
-__device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s3)[3], double (*s6)[6]) {
+//
+// One pass: with b = A - 1, wFc = w (F - Fbar) and c0 = B1/S_w the residual is
+// r = (F - Fbar) - F_s (b - c0), so for every direction D
+//   sum w r D = P_D - F_s (Q_D - c0 R_D),  P_D = sum wFc D, Q_D = sum w b D, R_D = sum w D,
+// and chi2 = V - F_s C (the search's one-pass fit).  When the fit is degenerate or that
+// chi2 is flagged as cancellation-prone, a second pass sums w r^2 and w r D directly
+// with the residual formed point by point.
+__device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums]) {
   Eval out;
   const int tid = threadIdx.x;
   const int32_t e = a.event[c];
@@ -92,63 +149,82 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s3)[3], double 
   const double* wFc = a.lc.wFc + p0;
   const double* F = a.lc.F + p0;
   const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
-
-  // pass 1: normal-equation sums (centred form) and the profiled fit
-  double n1[3] = {0.0, 0.0, 0.0};
-  for (int32_t i = tid; i < np; i += GRAD_THREADS) {
-    const uint32_t u = (uint32_t)i;
-    const double b = (double)sample_A(m, ldg(t, u), t0p, iE, ca, sa, bx, by) - 1.0;
-    const double wb = ldg(w, u) * b;
-    n1[0] += wb;
-    n1[1] = fma(wb, b, n1[1]);
-    n1[2] = fma(b, ldg(wFc, u), n1[2]);
-  }
-  block_sum<3>(n1, s3);
-  const Fit fit = centred_fit(Sw, Fbar, V, n1[0], n1[1], n1[2]);
-  const double Fs = fit.Fs, Fb = fit.Fb;
-
-  // pass 2: residuals, direct chi-square and gradient sums
   const double kx = (double)m.kx, ky = (double)m.ky;
-  double n2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // chi, Gx, Gy, Gxt, Gyt, Ga
+
+  // acc: B1, B2, C, then (R_D, Q_D, P_D) per direction
+  double acc[kSums];
+#pragma unroll
+  for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
   for (int32_t i = tid; i < np; i += GRAD_THREADS) {
     const uint32_t u = (uint32_t)i;
     const Sample sm = sample_full(m, ldg(t, u), t0p, iE, ca, sa, bx, by);
-    const double A = (double)sm.A;
-    const double r = ldg(F, u) - Fs * A - Fb;
-    const double wr = ldg(w, u) * r;
-    const double zx = (double)sm.zx, zy = (double)sm.zy, tau = (double)sm.tau;
+    const double b = (double)sm.A - 1.0;
+    const double wi = ldg(w, u), wfc = ldg(wFc, u);
+    const double wb = wi * b;
+    acc[0] += wb;
+    acc[1] = fma(wb, b, acc[1]);
+    acc[2] = fma(b, wfc, acc[2]);
     double dAx, dAy;
-    if (sm.on) {
-      const double e0 = (double)sm.e0, e1 = (double)sm.e1;
-      dAx = kx * (e0 + (double)sm.fy * (e1 - e0));
-      dAy = ky * ((double)sm.ax1 - (double)sm.ax0);
-    } else {
-      // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
-      const double u2 = zx * zx + zy * zy;
-      const double pp = u2 * (u2 + 4.0);
-      const double f = -8.0 / (pp * sqrt(pp));
-      dAx = f * zx;
-      dAy = f * zy;
+    sample_dA(sm, kx, ky, dAx, dAy);
+    const double tau = (double)sm.tau;
+    const double D[kDirs] = {dAx, dAy, dAx * tau, dAy * tau,
+                             (double)sm.zx * dAy - (double)sm.zy * dAx};
+#pragma unroll
+    for (int k = 0; k < kDirs; ++k) {
+      const double wD = wi * D[k];
+      acc[3 + 3 * k] += wD;
+      acc[4 + 3 * k] = fma(wD, b, acc[4 + 3 * k]);
+      acc[5 + 3 * k] = fma(wfc, D[k], acc[5 + 3 * k]);
     }
-    n2[0] = fma(wr, r, n2[0]);
-    n2[1] = fma(wr, dAx, n2[1]);
-    n2[2] = fma(wr, dAy, n2[2]);
-    n2[3] = fma(wr * dAx, tau, n2[3]);
-    n2[4] = fma(wr * dAy, tau, n2[4]);
-    n2[5] = fma(wr, zx * dAy - zy * dAx, n2[5]);
   }
-  block_sum<6>(n2, s6);
+  block_sum<kSums>(acc, s_part);
+  const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2]);
+  const double Fs = fit.Fs, Fb = fit.Fb;
+  double G[kDirs];  // sum w r D
+  double chi2;
+  if (!fit.degenerate && !fit.recheck) {
+    const double c0 = acc[0] / Sw;
+#pragma unroll
+    for (int k = 0; k < kDirs; ++k)
+      G[k] = acc[5 + 3 * k] - Fs * (acc[4 + 3 * k] - c0 * acc[3 + 3 * k]);
+    chi2 = fit.chi2;
+  } else {  // uniform per workgroup: the sums are identical on every thread
+    double n2[1 + kDirs];
+#pragma unroll
+    for (int q = 0; q <= kDirs; ++q) n2[q] = 0.0;
+    for (int32_t i = tid; i < np; i += GRAD_THREADS) {
+      const uint32_t u = (uint32_t)i;
+      const Sample sm = sample_full(m, ldg(t, u), t0p, iE, ca, sa, bx, by);
+      const double A = (double)sm.A;
+      const double r = ldg(F, u) - Fs * A - Fb;
+      const double wr = ldg(w, u) * r;
+      double dAx, dAy;
+      sample_dA(sm, kx, ky, dAx, dAy);
+      const double tau = (double)sm.tau;
+      n2[0] = fma(wr, r, n2[0]);
+      n2[1] = fma(wr, dAx, n2[1]);
+      n2[2] = fma(wr, dAy, n2[2]);
+      n2[3] = fma(wr * dAx, tau, n2[3]);
+      n2[4] = fma(wr * dAy, tau, n2[4]);
+      n2[5] = fma(wr, (double)sm.zx * dAy - (double)sm.zy * dAx, n2[5]);
+    }
+    // reuse the first 1 + kDirs columns of the partial-sum buffer
+    block_sum<1 + kDirs>(n2, reinterpret_cast<double (*)[1 + kDirs]>(&s_part[0][0]));
+    chi2 = n2[0];
+#pragma unroll
+    for (int k = 0; k < kDirs; ++k) G[k] = n2[1 + k];
+  }
   const double c64 = (double)ca, s64 = (double)sa;
   const double k2 = -2.0 * Fs;
-  out.g[0] = k2 * (-(c64 * n2[1] + s64 * n2[2]) / tE);
-  out.g[1] = k2 * (-s64 * n2[1] + c64 * n2[2]);
-  out.g[2] = k2 * (-(c64 * n2[3] + s64 * n2[4]) / tE);
-  out.g[3] = k2 * n2[5];
+  out.g[0] = k2 * (-(c64 * G[0] + s64 * G[1]) / tE);
+  out.g[1] = k2 * (-s64 * G[0] + c64 * G[1]);
+  out.g[2] = k2 * (-(c64 * G[2] + s64 * G[3]) / tE);
+  out.g[3] = k2 * G[4];
   if (a.anchor) {  // gradient with respect to the scaled variables
     out.g[0] = out.g[0] * tE_anchor;
     out.g[2] = out.g[2] * tE;
   }
-  out.chi2 = n2[0];
+  out.chi2 = chi2;
   out.Fs = Fs;
   out.Fb = Fb;
   return out;
@@ -190,11 +266,10 @@ __global__ void k_cand_prep(GradArgs a) {
 }
 
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
-  __shared__ double s3[GRAD_THREADS / kWave][3];
-  __shared__ double s6[GRAD_THREADS / kWave][6];
+  __shared__ double s_part[GRAD_THREADS / kWave][kSums];
   for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
     if (a.active && !a.active[c]) continue;  // uniform per workgroup
-    const Eval ev = grad_eval(a, c, s3, s6);
+    const Eval ev = grad_eval(a, c, s_part);
     if (threadIdx.x == 0) {
       if (a.chi2) a.chi2[c] = ev.chi2;
       if (a.grad)
