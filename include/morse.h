@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 1
+#define MORSE_ABI_VERSION 2
 
 enum morse_status {
   MORSE_OK = 0,
@@ -64,6 +64,23 @@ int morse_ctx_set_stream(morse_ctx* ctx, void* stream);
 int morse_ctx_synchronize(morse_ctx* ctx);
 /* Message of the last failing call on ctx (ctx == NULL: on this host thread). */
 const char* morse_last_error(const morse_ctx* ctx);
+
+/* Kernel timing (a measurement aid, off by default).  Families of timed kernels: */
+#define MORSE_KERNEL_RAYSHOOT 0 /* the ray-shooting kernel of morse_rayshoot / morse_build_map */
+#define MORSE_KERNEL_SEARCH 1   /* the scoring kernel(s) of morse_search (batched: one launch) */
+#define MORSE_KERNEL_GRADIENT 2 /* the chi-square/gradient kernel of morse_chi2_grad and of
+                                   every round of morse_refine */
+/* Enable timing for the families whose bit (1 << MORSE_KERNEL_*) is set in
+ * kernel_mask (0 disables).  While a family is timed, each launch of its kernel is
+ * bracketed by two HIP events recorded on the context's stream, and the entry points
+ * that launch it enqueue their kernels one by one instead of replaying a captured
+ * graph (same kernels, same results).  EINVAL for unknown bits. */
+int morse_ctx_set_timing(morse_ctx* ctx, uint32_t kernel_mask);
+/* Total event-measured time (ms) and number of timed launches of one family since the
+ * last reset; waits for the pending events of every family.  reset != 0 zeroes the
+ * family's totals after reading them.  Either output may be NULL. */
+int morse_ctx_kernel_time(morse_ctx* ctx, int32_t kernel, double* h_total_ms,
+                          int64_t* h_launches, int32_t reset);
 
 /* ------------------------------------------------------------------------------
  * Map build (ray-shooting magnification maps, sec. 3; lens equation Eq. 2;

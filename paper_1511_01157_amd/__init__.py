@@ -28,7 +28,11 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
            "normalize_convolve", "search", "autotune", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
-           "grid_trajectories", "list_trajectories", "abi_version"]
+           "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
+           "KERNEL_SEARCH", "KERNEL_GRADIENT"]
+
+# kernel families of Context.set_timing / Context.kernel_time
+KERNEL_RAYSHOOT, KERNEL_SEARCH, KERNEL_GRADIENT = 0, 1, 2
 
 
 class MorseError(RuntimeError):
@@ -90,6 +94,22 @@ class Context:
 
     def synchronize(self):
         self.check(self.lib.morse_ctx_synchronize(self.handle))
+
+    def set_timing(self, kernels=()):
+        """Bracket every launch of the given kernel families with HIP events on the
+        context's stream (an empty set disables timing)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+        self.check(self.lib.morse_ctx_set_timing(self.handle, mask))
+
+    def kernel_time(self, kernel, reset=False):
+        """(total ms, launches) of one timed kernel family since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.check(self.lib.morse_ctx_kernel_time(self.handle, int(kernel), ctypes.byref(ms),
+                                                  ctypes.byref(n), int(bool(reset))))
+        return ms.value, n.value
 
 
 def _device_of(t):

@@ -29,14 +29,15 @@ struct TuneCfg {
   int traj_per_item;
   int waves_per_block;
   int blocks_per_cu;
+  int tu;
 };
 // Candidate shapes of the batched search tried by the autotuner; index 0 is the
-// default before tuning.
-// traj_per_item = trajectories per wavefront work item.
+// default before tuning.  traj_per_item = trajectories per wavefront work item,
+// tu = trajectories scored together by one wavefront (sharing light-curve loads).
 const TuneCfg kTune[] = {
-    {8, 4, 16}, {4, 4, 16}, {16, 4, 16}, {8, 8, 8},
-    {32, 8, 8}, {2, 4, 16}, {16, 8, 4},  {8, 2, 32},
-    {64, 4, 8}, {4, 8, 8},
+    {8, 4, 16, 2},  {8, 4, 16, 1},  {16, 4, 16, 2}, {8, 8, 8, 2},
+    {32, 8, 8, 2},  {4, 4, 16, 2},  {16, 8, 4, 4},  {8, 2, 32, 2},
+    {16, 4, 16, 4}, {32, 8, 8, 1},  {8, 2, 32, 1},  {64, 4, 8, 4},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 
@@ -66,6 +67,22 @@ struct morse_ctx {
   // small auxiliary device buffer, separate from the workspace
   char* aux = nullptr;
   size_t aux_size = 0;
+  // disk-convolution taps resident on the device (key of the taps they hold)
+  char* taps = nullptr;
+  size_t taps_size = 0;
+  uint64_t taps_key = 0;
+  int32_t taps_n = 0;
+  size_t taps_wbytes = 0;
+  // kernel timing: enabled families, pending event pairs, free events, totals
+  uint32_t timing_mask = 0;
+  struct Timed {
+    int32_t kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> free_events;
+  double time_ms[3] = {0.0, 0.0, 0.0};
+  int64_t launches[3] = {0, 0, 0};
 };
 
 namespace {
@@ -101,6 +118,56 @@ struct Hasher {
   template <class T>
   void pod(const T& v) {
     bytes(&v, sizeof(T));
+  }
+};
+
+// Folds the pending timing events into the totals (waits for them).
+hipError_t resolve_timers(morse_ctx* ctx) {
+  for (const auto& t : ctx->timed) {
+    hipError_t e = hipEventSynchronize(t.b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return e;
+    ctx->time_ms[t.kernel] += ms;
+    ctx->launches[t.kernel] += 1;
+    ctx->free_events.push_back(t.a);
+    ctx->free_events.push_back(t.b);
+  }
+  ctx->timed.clear();
+  return hipSuccess;
+}
+
+hipError_t take_event(morse_ctx* ctx, hipEvent_t* e) {
+  if (!ctx->free_events.empty()) {
+    *e = ctx->free_events.back();
+    ctx->free_events.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+bool timed(const morse_ctx* ctx, int32_t kernel) { return (ctx->timing_mask >> kernel) & 1u; }
+
+// Brackets one launch of a kernel family with events on `st` when the family is timed.
+struct LaunchTimer {
+  morse_ctx* ctx;
+  int32_t kernel;
+  hipEvent_t a = nullptr;
+  hipError_t begin(hipStream_t st) {
+    if (!timed(ctx, kernel)) return hipSuccess;
+    hipError_t e = take_event(ctx, &a);
+    return e == hipSuccess ? hipEventRecord(a, st) : e;
+  }
+  hipError_t end(hipStream_t st) {
+    if (!a) return hipSuccess;
+    hipEvent_t b = nullptr;
+    hipError_t e = take_event(ctx, &b);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    ctx->timed.push_back({kernel, a, b});
+    a = nullptr;
+    // bound the pending list for callers that never read the totals
+    return ctx->timed.size() >= 4096 ? resolve_timers(ctx) : hipSuccess;
   }
 };
 
@@ -203,7 +270,33 @@ MapC make_mapc(const float* map, const morse_grid2d& w) {
   m.oy = (float)(w.ny / 2) - 0.5f;
   m.lx = (float)(w.nx - 1);
   m.ly = (float)(w.ny - 1);
+  m.tiles_x = (uint32_t)((w.nx - 1 + 3) / 4);
+  m.tiles_y = (uint32_t)((w.ny - 1 + 1) / 2);
+  m.quad = nullptr;
   return m;
+}
+
+// Quad-packed maps live in one workspace region: per map quad_bytes rounded to 256.
+size_t quad_region_bytes(const morse_map_view* maps, int32_t n_maps) {
+  size_t t = 0;
+  for (int i = 0; i < n_maps; ++i)
+    t += (quad_bytes(maps[i].window.nx, maps[i].window.ny) + 255) & ~size_t(255);
+  return t;
+}
+
+void assign_quads(std::vector<MapC>& hm, char* region) {
+  for (auto& m : hm) {
+    m.quad = (const float4*)region;
+    region += (quad_bytes(m.mx, m.my) + 255) & ~size_t(255);
+  }
+}
+
+int check_quad_size(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps) {
+  for (int i = 0; i < n_maps; ++i)
+    if (quad_bytes(maps[i].window.nx, maps[i].window.ny) >= ((size_t)1 << 32))
+      return fail(ctx, MORSE_ERANGE, "map %d: %d x %d pixels exceed the 4 GiB packed-cell limit", i,
+                  maps[i].window.nx, maps[i].window.ny);
+  return MORSE_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -365,6 +458,12 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   if (ctx->refine_gexec) (void)hipGraphExecDestroy(ctx->refine_gexec);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
+  if (ctx->taps) (void)hipFree(ctx->taps);
+  for (const auto& t : ctx->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
   (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -384,6 +483,28 @@ int morse_ctx_set_stream(morse_ctx* ctx, void* stream) {
 int morse_ctx_synchronize(morse_ctx* ctx) {
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_ctx_set_timing(morse_ctx* ctx, uint32_t kernel_mask) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (kernel_mask >> 3) return fail(ctx, MORSE_EINVAL, "unknown kernel bits in mask 0x%x", kernel_mask);
+  ctx->timing_mask = kernel_mask;
+  return MORSE_OK;
+}
+
+int morse_ctx_kernel_time(morse_ctx* ctx, int32_t kernel, double* h_total_ms,
+                          int64_t* h_launches, int32_t reset) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (kernel < 0 || kernel > 2) return fail(ctx, MORSE_EINVAL, "unknown kernel family %d", kernel);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, resolve_timers(ctx));
+  if (h_total_ms) *h_total_ms = ctx->time_ms[kernel];
+  if (h_launches) *h_launches = ctx->launches[kernel];
+  if (reset) {
+    ctx->time_ms[kernel] = 0.0;
+    ctx->launches[kernel] = 0;
+  }
   return MORSE_OK;
 }
 
@@ -423,7 +544,10 @@ int morse_rayshoot(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
   p.row0 = row_begin;
   p.row1 = row_end;
   if (!accumulate) HIP_TRY(ctx, launch_fill_u32(d_counts, (size_t)window->nx * window->ny, 0u, ctx->stream));
+  LaunchTimer tm{ctx, MORSE_KERNEL_RAYSHOOT};
+  HIP_TRY(ctx, tm.begin(ctx->stream));
   HIP_TRY(ctx, launch_rayshoot(p, d_counts, (unsigned long long*)d_stats, ctx->stream));
+  HIP_TRY(ctx, tm.end(ctx->stream));
   return MORSE_OK;
 }
 
@@ -437,21 +561,43 @@ int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const mor
   if (!d_counts || !d_map) return fail(ctx, MORSE_EINVAL, "d_counts / d_map is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const double dx = window->wx / window->nx, dy = window->wy / window->ny;
-  std::vector<float> w;
-  std::vector<int32_t> off;
-  if ((rc = disk_taps(ctx, rho, dx, dy, w, off))) return rc;
   const double hx = (double)(float)(rays->wx / rays->nx), hy = (double)(float)(rays->wy / rays->ny);
   const float scale = (float)(hx * hy / (dx * dy));
-  Plan pl;
-  const size_t iw = pl.add(w.size() * sizeof(float)), io = pl.add(off.size() * sizeof(int32_t));
-  if ((rc = reserve(ctx, pl.total()))) return rc;
-  float* d_w = (float*)pl.ptr(ctx, iw);
-  int32_t* d_off = (int32_t*)pl.ptr(ctx, io);
-  if ((rc = upload(ctx, d_w, w.data(), w.size() * sizeof(float)))) return rc;
-  if ((rc = upload(ctx, d_off, off.data(), off.size() * sizeof(int32_t)))) return rc;
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
+  // the taps stay resident between calls with the same (rho, dx, dy): no host work,
+  // upload or synchronisation in the steady state
+  Hasher key;
+  key.pod(rho);
+  key.pod(dx);
+  key.pod(dy);
+  if (!ctx->taps || ctx->taps_key != key.h) {
+    std::vector<float> w;
+    std::vector<int32_t> off;
+    if ((rc = disk_taps(ctx, rho, dx, dy, w, off))) return rc;
+    const size_t w_bytes = (w.size() * sizeof(float) + 255) & ~size_t(255);
+    const size_t need = w_bytes + off.size() * sizeof(int32_t);
+    if (need > ctx->taps_size) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (ctx->taps) (void)hipFree(ctx->taps);
+      ctx->taps = nullptr;
+      ctx->taps_size = 0;
+      if (hipMalloc((void**)&ctx->taps, need) != hipSuccess) {
+        ctx->taps = nullptr;
+        return fail(ctx, MORSE_ENOMEM, "taps allocation of %zu bytes failed", need);
+      }
+      ctx->taps_size = need;
+    }
+    ctx->taps_key = 0;
+    if ((rc = upload(ctx, ctx->taps, w.data(), w.size() * sizeof(float)))) return rc;
+    if ((rc = upload(ctx, ctx->taps + w_bytes, off.data(), off.size() * sizeof(int32_t)))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
+    ctx->taps_key = key.h;
+    ctx->taps_n = (int32_t)w.size();
+    ctx->taps_wbytes = w_bytes;
+  }
+  const float* d_w = (const float*)ctx->taps;
+  const int32_t* d_off = (const int32_t*)(ctx->taps + ctx->taps_wbytes);
   HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_map, window->nx, window->ny, d_w, d_off,
-                                         (int32_t)w.size(), scale, nullptr, ctx->stream));
+                                         ctx->taps_n, scale, nullptr, ctx->stream));
   return MORSE_OK;
 }
 
@@ -620,9 +766,11 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                          : 0;
   Plan pl;
   // metadata first, so its offsets do not depend on the output sizes
+  if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
+  // the packed maps follow the metadata: their offsets depend only on the metadata key
   const size_t i_off = pl.add(8 * (sp.n_events + 1)), i_tref = pl.add(8 * sp.n_events),
                i_maps = pl.add(sizeof(MapC) * n_maps), i_axes = pl.add(8 * (size_t)n_axes),
-               i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(256),
+               i_quad = pl.add(quad_region_bytes(maps, n_maps)), i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(256),
                i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
                i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0);
@@ -640,6 +788,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   sp.num_cu = ctx->num_cu;
   sp.h_maps.resize(n_maps);
   for (int i = 0; i < n_maps; ++i) sp.h_maps[i] = make_mapc(maps[i].d_map, maps[i].window);
+  assign_quads(sp.h_maps, pl.ptr(ctx, i_quad));
   const uint64_t key = metadata_key(maps, n_maps, lcs, trajs);
   if (key != ctx->upload_key || ctx->upload_epoch != ctx->ws_epoch) {
     std::vector<double> axes;
@@ -667,9 +816,11 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   return MORSE_OK;
 }
 
-// Preparation kernels (light-curve sums, trajectory constants).
+// Preparation kernels (map packing, light-curve sums, trajectory constants).
 hipError_t enqueue_prep(const SearchPlan& sp, const morse_trajectories* trajs, hipStream_t st) {
-  hipError_t e = launch_lc_prep(sp.lc.t, sp.lc.F, sp.lc.w, sp.lc.off, sp.n_events,
+  hipError_t e = launch_quad_pack(sp.d_maps, sp.h_maps.data(), sp.n_maps, st);
+  if (e != hipSuccess) return e;
+  e = launch_lc_prep(sp.lc.t, sp.lc.F, sp.lc.w, sp.lc.off, sp.n_events,
                                 (double*)sp.lc.wFc, (double*)sp.lc.sums, st);
   if (e != hipSuccess) return e;
   if (trajs->kind == MORSE_TRAJ_GRID)
@@ -706,6 +857,7 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
   a.counter = sp.counter;
   a.traj_per_item = cfg.traj_per_item;
   a.waves_per_block = cfg.waves_per_block;
+  a.tu = cfg.tu;
   const int64_t nb = (sp.n_traj + cfg.traj_per_item - 1) / cfg.traj_per_item;
   const int64_t items = nb * sp.n_events * sp.n_maps;
   int64_t blocks = (int64_t)ctx->num_cu * cfg.blocks_per_cu;
@@ -718,7 +870,7 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
 std::string shape_class(const SearchPlan& sp) {
   auto bucket = [](double v) { return (int)std::floor(std::log2(std::max(v, 1.0))); };
   std::ostringstream s;
-  s << "gfx950|maps" << bucket(sp.n_maps) << "|pts" << bucket((double)sp.n_pts / sp.n_events)
+  s << "gfx950|v2|maps" << bucket(sp.n_maps) << "|pts" << bucket((double)sp.n_pts / sp.n_events)
     << "|traj" << bucket((double)sp.n_traj) << "|ev" << bucket(sp.n_events);
   return s.str();
 }
@@ -761,7 +913,10 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
         const int64_t base = ((int64_t)e * n_maps + m) * sp.n_traj;
         SearchOut so{sp.chi2 + base, out->d_fs ? out->d_fs + base : nullptr,
                      out->d_fb ? out->d_fb + base : nullptr};
+        LaunchTimer tm{ctx, MORSE_KERNEL_SEARCH};
+        HIP_TRY(ctx, tm.begin(ctx->stream));
         HIP_TRY(ctx, launch_search_plain(tc, sp.n_traj, sp.lc, e, sp.h_maps[m], so, 4, ctx->stream));
+        HIP_TRY(ctx, tm.end(ctx->stream));
       }
     }
     HIP_TRY(ctx, enqueue_select(sp, out, ctx->stream));
@@ -783,6 +938,17 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   h.pod(trajs->d_params);
   h.pod(trajs->shared);
   h.pod(trajs->n);
+  if (timed(ctx, MORSE_KERNEL_SEARCH)) {  // same kernels, launched one by one
+    const BatchedArgs a = batched_args(ctx, sp, trajs, out, cfg);
+    HIP_TRY(ctx, enqueue_prep(sp, trajs, ctx->stream));
+    HIP_TRY(ctx, launch_fill_u32(sp.counter, 1, 0u, ctx->stream));
+    LaunchTimer tm{ctx, MORSE_KERNEL_SEARCH};
+    HIP_TRY(ctx, tm.begin(ctx->stream));
+    HIP_TRY(ctx, launch_search_batched(a, ctx->stream));
+    HIP_TRY(ctx, tm.end(ctx->stream));
+    HIP_TRY(ctx, enqueue_select(sp, out, ctx->stream));
+    return MORSE_OK;
+  }
   if (!ctx->gexec || ctx->graph_key != h.h) {
     if (ctx->gexec) {
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -934,7 +1100,8 @@ int morse_candidates_from_topk(morse_ctx* ctx, const morse_trajectories* trajs, 
 namespace {
 int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                     const morse_lightcurves* lcs, int64_t n, Plan& pl, size_t& i_off,
-                    size_t& i_tref, size_t& i_maps, size_t& i_sums, size_t& i_wF) {
+                    size_t& i_tref, size_t& i_maps, size_t& i_sums, size_t& i_wF,
+                    size_t& i_quad) {
   if (!maps || n_maps <= 0) return fail(ctx, MORSE_EINVAL, "need n_maps >= 1 maps");
   int rc;
   for (int i = 0; i < n_maps; ++i) {
@@ -948,23 +1115,27 @@ int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     if (lcs->h_offsets[e + 1] - lcs->h_offsets[e] < 3)
       return fail(ctx, MORSE_EINVAL, "event %d has fewer than 3 points", e);
   if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
   i_off = pl.add(8 * (lcs->n_events + 1));
   i_tref = pl.add(8 * lcs->n_events);
   i_maps = pl.add(sizeof(MapC) * n_maps);
   i_sums = pl.add(24 * (size_t)lcs->n_events);
   i_wF = pl.add(8 * (size_t)lcs->h_offsets[lcs->n_events]);
+  i_quad = pl.add(quad_region_bytes(maps, n_maps));
   return MORSE_OK;
 }
 
 int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                      const morse_lightcurves* lcs, const Plan& pl, size_t i_off, size_t i_tref,
-                     size_t i_maps, size_t i_sums, size_t i_wF, LcView& lc, MapC*& d_maps) {
+                     size_t i_maps, size_t i_sums, size_t i_wF, size_t i_quad, LcView& lc,
+                     MapC*& d_maps) {
   int rc;
   int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
   double* d_tref = (double*)pl.ptr(ctx, i_tref);
   d_maps = (MapC*)pl.ptr(ctx, i_maps);
   std::vector<MapC> hm(n_maps);
   for (int i = 0; i < n_maps; ++i) hm[i] = make_mapc(maps[i].d_map, maps[i].window);
+  assign_quads(hm, pl.ptr(ctx, i_quad));
   if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (lcs->n_events + 1)))) return rc;
   if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * lcs->n_events))) return rc;
   if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
@@ -977,6 +1148,7 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   lc.off = d_off;
   lc.sums = (double*)pl.ptr(ctx, i_sums);
   lc.t_ref = d_tref;
+  HIP_TRY(ctx, launch_quad_pack(d_maps, hm.data(), n_maps, ctx->stream));
   HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, lcs->n_events, (double*)lc.wFc,
                               (double*)lc.sums, ctx->stream));
   return MORSE_OK;
@@ -990,8 +1162,8 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   int rc;
   Plan pl;
-  size_t i_off, i_tref, i_maps, i_sums, i_wF;
-  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF))) return rc;
+  size_t i_off, i_tref, i_maps, i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad))) return rc;
   if (n > 0 && (!d_params || !d_event || !d_map_index))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1001,7 +1173,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
   a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
-  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
   a.n = n;
   a.params = d_params;
   a.event = d_event;
@@ -1014,7 +1186,10 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.fs = d_fs;
   a.fb = d_fb;
   HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
+  LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
+  HIP_TRY(ctx, tm.begin(ctx->stream));
   HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
+  HIP_TRY(ctx, tm.end(ctx->stream));
   return MORSE_OK;
 }
 
@@ -1029,8 +1204,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     return fail(ctx, MORSE_EINVAL, "invalid L-BFGS options");
   int rc;
   Plan pl;
-  size_t i_off, i_tref, i_maps, i_sums, i_wF;
-  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF))) return rc;
+  size_t i_off, i_tref, i_maps, i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad))) return rc;
   if (n > 0 && (!d_params || !d_event || !d_map_index || !d_chi2_out))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index / d_chi2_out is NULL");
   if (n == 0) return MORSE_OK;
@@ -1047,7 +1222,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
   a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
-  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, a.lc, d_maps))) return rc;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
   LbfgsState s;
   s.n = n;
   s.m = m;
@@ -1083,9 +1258,9 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   double* gt = (double*)pl.ptr(ctx, i_gt);
   a.chi2 = ft;
   a.grad = gt;
-  // The rounds are captured once per argument set and replayed: copy of the start
-  // parameters, clears (fill kernels), steps + 1 rounds of (evaluation, update),
-  // write-back.
+  // The rounds are captured once per argument set and replayed: start (anchor copy,
+  // state reset, first-trial constants), steps + 1 rounds of (evaluation, update with
+  // the next trial's constants), write-back.
   Hasher h;
   h.pod(ctx->ws_epoch);
   h.pod(n);
@@ -1100,6 +1275,24 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   h.pod(lcs->d_t);
   h.pod(lcs->d_flux);
   h.pod(lcs->d_weight);
+  // start, steps + 1 rounds, write-back; with `timing`, events bracket each evaluation
+  auto enqueue = [&](hipStream_t cs, bool timing) -> hipError_t {
+    hipError_t e = launch_refine_init(s, a, d_params, anchor, cs);
+    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
+      LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
+      if (timing) e = tm.begin(cs);
+      if (e == hipSuccess) e = launch_chi2_grad(a, cs);
+      if (e == hipSuccess && timing) e = tm.end(cs);
+      if (e == hipSuccess)
+        e = launch_lbfgs_update(s, a, r, ft, gt, r == 0 ? d_chi2_init : nullptr, cs);
+    }
+    if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
+    return e;
+  };
+  if (timed(ctx, MORSE_KERNEL_GRADIENT)) {  // same kernels, launched one by one
+    HIP_TRY(ctx, enqueue(ctx->stream, true));
+    return MORSE_OK;
+  }
   if (!ctx->refine_gexec || ctx->refine_key != h.h) {
     if (ctx->refine_gexec) {
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1109,17 +1302,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     hipGraph_t g = nullptr;
     hipStream_t cs = ctx->capture_stream;
     HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_copy_f64(anchor, d_params, 4 * n, cs);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.pt, 4 * n, 0u, cs);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)ints, 3 * n, 0u, cs);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)s.active, n, 1u, cs);
-    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
-      e = launch_cand_prep(a, cs);
-      if (e == hipSuccess) e = launch_chi2_grad(a, cs);
-      if (e == hipSuccess && r == 0 && d_chi2_init) e = launch_copy_f64(d_chi2_init, ft, n, cs);
-      if (e == hipSuccess) e = launch_lbfgs_update(s, r, ft, gt, cs);
-    }
-    if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
+    hipError_t e = enqueue(cs, false);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);

@@ -34,13 +34,26 @@ struct TrajC {
 };
 static_assert(sizeof(TrajC) == 32, "TrajC layout");
 
-// A map as the sampling kernels see it.
+// A map as the sampling kernels see it.  The row-major pixel values `map` are packed
+// once per call into `quad`: cell (i, j), 0 <= i < mx - 1, 0 <= j < my - 1, holds the
+// four pixel-centre values (A[j][i], A[j][i+1], A[j+1][i], A[j+1][i+1]) as one 16-byte
+// float4, and the cells are grouped in tiles of 4 (x) by 2 (y) cells, one 128-byte
+// cache line each, tiles in row-major order:
+//   q(i, j) = ((j / 2) tiles_x + i / 4) 8 + (j % 2) 4 + i % 4.
+// A bilinear sample is then one aligned load, and the samples of a wavefront along a
+// trajectory touch about 2.5x fewer cache lines than two row-major row loads.
 struct MapC {
   const float* map;
+  const float4* quad;
+  uint32_t tiles_x, tiles_y;
   int32_t mx, my;
   float sx, sy, kx, ky, ox, oy;  // grid coordinate g = (zeta - s) k + o
   float lx, ly;                  // on-map bound: g < M - 1
 };
+// Packed size of a map with mx x my pixels (bytes).
+inline size_t quad_bytes(int32_t mx, int32_t my) {
+  return (size_t)((mx - 1 + 3) / 4) * (size_t)((my - 1 + 1) / 2) * 128;
+}
 
 // Light curves after preparation: per point binary32 time offset, w and the
 // centred weighted flux w (F - Fbar); per event S_w, the weighted mean Fbar and
@@ -82,13 +95,13 @@ __device__ __forceinline__ T ldg(const T* __restrict__ base, uint32_t i) {
 
 __device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, float& v00, float& v10,
                                          float& v01, float& v11) {
-  const uint32_t o = (uint32_t)(int)fj * (uint32_t)m.mx + (uint32_t)(int)fi;
-  const Pair r0 = *(const Pair*)((const char*)m.map + (size_t)(o * 4u));
-  const Pair r1 = *(const Pair*)((const char*)m.map + (size_t)((o + (uint32_t)m.mx) * 4u));
-  v00 = r0.a;
-  v10 = r0.b;
-  v01 = r1.a;
-  v11 = r1.b;
+  const uint32_t i = (uint32_t)(int)fi, j = (uint32_t)(int)fj;
+  const uint32_t q = ((((j >> 1) * m.tiles_x + (i >> 2)) << 3) | ((j & 1u) << 2)) | (i & 3u);
+  const float4 v = ldg(m.quad, q);
+  v00 = v.x;
+  v10 = v.y;
+  v01 = v.z;
+  v11 = v.w;
 }
 
 __device__ __forceinline__ float sample_A(const MapC& m, float tt, float t0p, float iE, float ca,
@@ -144,11 +157,84 @@ __device__ __forceinline__ Sample sample_full(const MapC& m, float tt, float t0p
   return s;
 }
 
+// A value known to be the same on every lane, moved to scalar registers word by word
+// (loads from memory the kernel also writes are vector loads, whose results the
+// compiler would otherwise keep in vector registers).
+template <class T>
+__device__ __forceinline__ T uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "uniform() moves 32-bit words");
+  T r;
+  const int* src = reinterpret_cast<const int*>(&v);
+  int* dst = reinterpret_cast<int*>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return r;
+}
+
 // Deterministic wavefront sum (butterfly over 64 lanes, same order on every lane).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
+}
+
+// Wavefront reduce-scatter of N FP64 values per lane.  Each halving step over lane
+// bit MASK keeps ceil(N/2) slots: lanes with the bit set keep the upper half (padded
+// with a zero), the others the lower half, each adding its partner's copy of the slots
+// it keeps; six steps (MASK = 32 .. 1) exchange about N values in all, against 6 N for
+// one butterfly per value.  Each value is summed over the same pairing tree as
+// wave_sum (IEEE addition commutes), so the totals are bitwise those of wave_sum.  On
+// return v[0] holds the total of original value `slot` when `valid`; every value
+// appears on exactly one valid lane, rs_lane<N>(q).
+template <int N, int MASK = 32>
+__device__ __forceinline__ void reduce_scatter(double* v, int lane, int& slot, bool& valid) {
+  if constexpr (MASK >= 1) {
+    constexpr int H = (N + 1) / 2;
+    const bool up = (lane & MASK) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double lo = v[i];
+      const double hi = (i + H < N) ? v[i + H] : 0.0;
+      const double other = __shfl_xor(up ? lo : hi, MASK, kWave);
+      v[i] = (up ? hi : lo) + other;
+    }
+    reduce_scatter<H, MASK / 2>(v, lane, slot, valid);
+    slot += up ? H : 0;
+    valid = valid && slot < N;
+  }
+}
+
+// Lane that holds value q after reduce_scatter<N>.
+template <int N>
+constexpr int rs_lane(int q) {
+  int lane = 0, n = N;
+  for (int mask = 32; mask >= 1; mask >>= 1) {
+    const int h = (n + 1) / 2;
+    if (q >= h) {
+      lane |= mask;
+      q -= h;
+    }
+    n = h;
+  }
+  return lane;
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wavefront totals of N values, on every lane (bitwise wave_sum of each value).
+template <int N>
+__device__ __forceinline__ void wave_sums(double (&v)[N]) {
+  int slot = 0;
+  bool valid = true;
+  reduce_scatter<N>(v, threadIdx.x & (kWave - 1), slot, valid);
+  const double mine = v[0];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = read_lane(mine, rs_lane<N>(q));
 }
 
 // Profiled fit (Eqs. 5-6) in centred form.  With b = A - 1 and per-point
@@ -191,6 +277,9 @@ __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, dou
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_copy_f64(double* dst, const double* src, size_t n, hipStream_t st);
+// Packs every map of the device table `maps` (n_maps entries; h_maps the same table on
+// the host, for the sizes) into its quad layout.
+hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st);
 hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
                            hipStream_t st);
 hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
@@ -225,6 +314,7 @@ struct BatchedArgs {
   int32_t traj_per_item;
   int32_t waves_per_block;
   int32_t grid_blocks;
+  int32_t tu;               // trajectories scored together per wavefront (1, 2 or 4)
 };
 hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st);
 
@@ -289,9 +379,15 @@ struct LbfgsState {
   int32_t* nls;          // [n]
   int32_t* active;       // [n]
 };
-// One update of every active candidate from its evaluation ft [n], gt [n][4].
-hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, const double* ft,
-                               const double* gt, hipStream_t st);
+// Anchor copy, state reset and first-trial trajectory constants (a.tc, a.tEv).
+hipError_t launch_refine_init(const LbfgsState& s, const GradArgs& a, const double* params,
+                              double* anchor, hipStream_t st);
+// One update of every active candidate from its evaluation ft [n], gt [n][4], then the
+// trajectory constants of its next trial; round 0 also copies ft to chi2_init (if set).
+// s.m must be at most 16.
+hipError_t launch_lbfgs_update(const LbfgsState& s, const GradArgs& a, int32_t round,
+                               const double* ft, const double* gt, double* chi2_init,
+                               hipStream_t st);
 hipError_t launch_lbfgs_finish(const LbfgsState& s, double* params, double* chi2_out,
                                hipStream_t st);
 

@@ -17,6 +17,8 @@
 // over the whole source plane) each ray goes to a global atomic directly.  Integer
 // addition is order-free, so the counts are bit-identical whatever the schedule.
 
+#include <algorithm>
+
 #include "internal.h"
 
 #include <climits>
@@ -42,6 +44,30 @@ __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// Quad packing of one map per blockIdx.y (layout in MapC); cells beyond the map
+// (tile padding) are zero and never sampled.
+__global__ void k_quad_pack(const MapC* __restrict__ maps) {
+  const MapC m = maps[blockIdx.y];
+  const uint64_t nq = (uint64_t)m.tiles_x * m.tiles_y * 8;
+  float4* out = const_cast<float4*>(m.quad);
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nq;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t tile = q >> 3;
+    const uint32_t r = (uint32_t)(q & 7);
+    const uint64_t i = (tile % m.tiles_x) * 4 + (r & 3u);
+    const uint64_t j = (tile / m.tiles_x) * 2 + (r >> 2);
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i + 1 < (uint64_t)m.mx && j + 1 < (uint64_t)m.my) {
+      const float* row = m.map + j * (uint64_t)m.mx + i;
+      v.x = row[0];
+      v.y = row[1];
+      v.z = row[m.mx];
+      v.w = row[m.mx + 1];
+    }
+    out[q] = v;
+  }
 }
 
 __global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
@@ -262,6 +288,17 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st) {
+  if (n_maps <= 0) return hipSuccess;
+  uint64_t most = 0;
+  for (int32_t k = 0; k < n_maps; ++k)
+    most = std::max<uint64_t>(most, (uint64_t)h_maps[k].tiles_x * h_maps[k].tiles_y * 8);
+  uint64_t blocks = (most + 255) / 256;
+  if (blocks > 65536) blocks = 65536;  // grid-stride beyond
+  hipLaunchKernelGGL(k_quad_pack, dim3((unsigned)blocks, (unsigned)n_maps), dim3(256), 0, st, maps);
   return hipGetLastError();
 }
 

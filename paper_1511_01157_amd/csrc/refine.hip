@@ -32,31 +32,6 @@ __device__ __forceinline__ double dot4(const double* a, const double* b) {
   return ((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) + a[3] * b[3];
 }
 
-// Wavefront reduce-scatter of N FP64 values per lane.  Each halving step over lane
-// bit MASK keeps ceil(N/2) slots: lanes with the bit set keep the upper half (padded
-// with a zero), the others the lower half, each adding its partner's copy of the slots
-// it keeps; six steps (MASK = 32 .. 1) exchange about N values in all, against 6 N for
-// a butterfly per value.  On return v[0] holds the wavefront total of original value
-// `slot` when `valid`; every value appears on exactly one valid lane (one with bit 0
-// clear), and the summation order is fixed.
-template <int N, int MASK>
-__device__ __forceinline__ void reduce_scatter(double* v, int lane, int& slot, bool& valid) {
-  if constexpr (MASK >= 1) {
-    constexpr int H = (N + 1) / 2;
-    const bool up = (lane & MASK) != 0;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const double lo = v[i];
-      const double hi = (i + H < N) ? v[i + H] : 0.0;
-      const double other = __shfl_xor(up ? lo : hi, MASK, kWave);
-      v[i] = (up ? hi : lo) + other;
-    }
-    reduce_scatter<H, MASK / 2>(v, lane, slot, valid);
-    slot += up ? H : 0;
-    valid = valid && slot < N;
-  }
-}
-
 // Sum of NV FP64 values over the workgroup in a fixed order (a wavefront
 // reduce-scatter, then the wave partials in wave order); every thread returns the
 // same values.
@@ -68,7 +43,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV])
   const int nw = blockDim.x / kWave;
   int slot = 0;
   bool valid = true;
-  reduce_scatter<NV, 32>(v, lane, slot, valid);
+  reduce_scatter<NV>(v, lane, slot, valid);
   if (valid) s_part[wave][slot] = v[0];
   __syncthreads();
 #pragma unroll
@@ -126,8 +101,8 @@ constexpr int kSums = 3 + 3 * kDirs;
 __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums]) {
   Eval out;
   const int tid = threadIdx.x;
-  const int32_t e = a.event[c];
-  const int32_t mi = a.mapidx[c];
+  const int32_t e = uniform(a.event[c]);
+  const int32_t mi = uniform(a.mapidx[c]);
   out.valid = !(e < 0 || e >= a.n_events || mi < 0 || mi >= a.n_maps);
   if (!out.valid) {
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
@@ -135,20 +110,21 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
     for (int q = 0; q < 4; ++q) out.g[q] = nan;
     return out;
   }
-  const MapC m = a.maps[mi];
-  const TrajC tc = a.tc[c];
-  const double tE = a.tEv[c];
-  const double tE_anchor = a.anchor ? a.anchor[4 * c + 2] : 0.0;
+  const MapC m = uniform(a.maps[mi]);
+  const TrajC tc = uniform(a.tc[c]);
+  const double tE = uniform(a.tEv[c]);
+  const double tE_anchor = a.anchor ? uniform(a.anchor[4 * c + 2]) : 0.0;
   const float iE = tc.iE, ca = tc.ca, sa = tc.sa, bx = tc.bx, by = tc.by;
-  const float t0p = (float)(tc.t0 - a.lc.t_ref[e]);
+  const float t0p = (float)(tc.t0 - uniform(a.lc.t_ref[e]));
 
-  const int64_t p0 = a.lc.off[e];
-  const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
+  const int64_t p0 = uniform(a.lc.off[e]);
+  const int32_t np = (int32_t)(uniform(a.lc.off[e + 1]) - p0);
   const float* t = a.lc.t + p0;
   const double* w = a.lc.w + p0;
   const double* wFc = a.lc.wFc + p0;
   const double* F = a.lc.F + p0;
-  const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
+  const double Sw = uniform(a.lc.sums[3 * e]), Fbar = uniform(a.lc.sums[3 * e + 1]),
+               V = uniform(a.lc.sums[3 * e + 2]);
   const double kx = (double)m.kx, ky = (double)m.ky;
 
   // acc: B1, B2, C, then (R_D, Q_D, P_D) per direction
@@ -230,12 +206,9 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   return out;
 }
 
-// Natural parameters of each candidate (from the FP64 rows, or from the L-BFGS anchor
-// and binary32 displacement) -> trajectory constants, FP64 trigonometry rounded once.
-__global__ void k_cand_prep(GradArgs a) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= a.n) return;
-  if (a.active && !a.active[c]) return;
+// Natural parameters of candidate c (from its FP64 row, or from the L-BFGS anchor and
+// binary32 displacement) -> trajectory constants, FP64 trigonometry rounded once.
+__device__ void prep_candidate(const GradArgs& a, int64_t c) {
   double t0, u0, tE, al;
   if (a.anchor) {
     const double* an = a.anchor + 4 * c;
@@ -265,6 +238,13 @@ __global__ void k_cand_prep(GradArgs a) {
   a.tEv[c] = tE;
 }
 
+__global__ void k_cand_prep(GradArgs a) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  if (a.active && !a.active[c]) return;
+  prep_candidate(a, c);
+}
+
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   __shared__ double s_part[GRAD_THREADS / kWave][kSums];
   for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
@@ -280,43 +260,51 @@ __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   }
 }
 
-constexpr int kMaxHist = 16;
-
-struct Cand {
-  const LbfgsState& s;
-  int64_t c;
-  __device__ double* S(int slot) const { return s.S + ((c * s.m + slot) * 4); }
-  __device__ double* Y(int slot) const { return s.Y + ((c * s.m + slot) * 4); }
-};
-
 // New search direction at the accepted point (p, g); sets d, step, nls, pt and may
-// stop the candidate when the trial would not move it.
+// stop the candidate when the trial would not move it.  M >= m bounds the history;
+// the pairs are loaded into registers up front (one memory latency instead of one per
+// pair) and the two loops run over compile-time slots in the same order as a loop
+// over the nh stored pairs.
+template <int M>
 __device__ void new_direction(const LbfgsState& s, int64_t c) {
-  Cand cd{s, c};
-  double g[4], q[4], r[4], d[4], alph[kMaxHist];
+  const int nh = s.nhist[c];
+  const int st = s.start[c];
+  double Sr[M][4], Yr[M][4], Rr[M];
+#pragma unroll
+  for (int h = 0; h < M; ++h) {
+    if (h < nh) {
+      const int64_t slot = c * s.m + (st + h) % s.m;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Sr[h][k] = s.S[slot * 4 + k];
+        Yr[h][k] = s.Y[slot * 4 + k];
+      }
+      Rr[h] = s.R[slot];
+    }
+  }
+  double g[4], q[4], r[4], d[4], alph[M];
   for (int k = 0; k < 4; ++k) g[k] = s.g[4 * c + k];
-  int nh = s.nhist[c];
-  int st = s.start[c];
   for (int k = 0; k < 4; ++k) q[k] = g[k];
-  for (int h = nh - 1; h >= 0; --h) {
-    const int slot = (st + h) % s.m;
-    const double a = s.R[c * s.m + slot] * dot4(cd.S(slot), q);
-    alph[h] = a;
-    for (int k = 0; k < 4; ++k) q[k] = q[k] - a * cd.Y(slot)[k];
+#pragma unroll
+  for (int h = M - 1; h >= 0; --h) {
+    if (h < nh) {
+      const double a = Rr[h] * dot4(Sr[h], q);
+      alph[h] = a;
+      for (int k = 0; k < 4; ++k) q[k] = q[k] - a * Yr[h][k];
+    }
   }
   const double gn = sqrt(dot4(g, g));
-  double gamma;
-  if (nh > 0) {
-    const int slot = (st + nh - 1) % s.m;
-    gamma = dot4(cd.S(slot), cd.Y(slot)) / dot4(cd.Y(slot), cd.Y(slot));
-  } else {
-    gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
-  }
+  double gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
+#pragma unroll
+  for (int h = 0; h < M; ++h)
+    if (h == nh - 1) gamma = dot4(Sr[h], Yr[h]) / dot4(Yr[h], Yr[h]);
   for (int k = 0; k < 4; ++k) r[k] = gamma * q[k];
-  for (int h = 0; h < nh; ++h) {
-    const int slot = (st + h) % s.m;
-    const double b = s.R[c * s.m + slot] * dot4(cd.Y(slot), r);
-    for (int k = 0; k < 4; ++k) r[k] = r[k] + cd.S(slot)[k] * (alph[h] - b);
+#pragma unroll
+  for (int h = 0; h < M; ++h) {
+    if (h < nh) {
+      const double b = Rr[h] * dot4(Yr[h], r);
+      for (int k = 0; k < 4; ++k) r[k] = r[k] + Sr[h][k] * (alph[h] - b);
+    }
   }
   for (int k = 0; k < 4; ++k) d[k] = -r[k];
   const double gd = dot4(g, d);
@@ -342,8 +330,9 @@ __device__ void new_direction(const LbfgsState& s, int64_t c) {
 }
 
 // One update of the state machine for candidate c given the evaluation (ft, gt) at
-// its trial point.
-__device__ void lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double ft,
+// its trial point; returns whether the candidate is still active.
+template <int M>
+__device__ bool lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double ft,
                            const double* gt) {
   if (round == 0) {
     for (int k = 0; k < 4; ++k) {
@@ -351,8 +340,8 @@ __device__ void lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double
       s.g[4 * c + k] = gt[k];
     }
     s.f[c] = ft;
-    new_direction(s, c);
-    return;
+    new_direction<M>(s, c);
+    return s.active[c] != 0;
   }
   double g[4], d[4];
   for (int k = 0; k < 4; ++k) {
@@ -379,40 +368,63 @@ __device__ void lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double
         slot = st;
         s.start[c] = (st + 1) % s.m;
       }
-      Cand cd{s, c};
+      const int64_t row = c * s.m + slot;
       for (int k = 0; k < 4; ++k) {
-        cd.S(slot)[k] = sv[k];
-        cd.Y(slot)[k] = yv[k];
+        s.S[row * 4 + k] = sv[k];
+        s.Y[row * 4 + k] = yv[k];
       }
-      s.R[c * s.m + slot] = 1.0 / sy;
+      s.R[row] = 1.0 / sy;
     }
     for (int k = 0; k < 4; ++k) {
       s.p[4 * c + k] = s.pt[4 * c + k];
       s.g[4 * c + k] = gt[k];
     }
     s.f[c] = ft;
-    new_direction(s, c);
-  } else {
-    const int n = s.nls[c] + 1;
-    s.nls[c] = n;
-    if (n >= s.max_ls) {
-      s.active[c] = 0;
-    } else {
-      const double tn = t * s.shrink;
-      s.step[c] = tn;
-      for (int k = 0; k < 4; ++k)
-        s.pt[4 * c + k] = (float)((double)s.p[4 * c + k] + tn * d[k]);
-    }
+    new_direction<M>(s, c);
+    return s.active[c] != 0;
   }
+  const int n = s.nls[c] + 1;
+  s.nls[c] = n;
+  if (n >= s.max_ls) {
+    s.active[c] = 0;
+    return false;
+  }
+  const double tn = t * s.shrink;
+  s.step[c] = tn;
+  for (int k = 0; k < 4; ++k) s.pt[4 * c + k] = (float)((double)s.p[4 * c + k] + tn * d[k]);
+  return true;
 }
 
-__global__ void k_lbfgs_update(LbfgsState s, int32_t round, const double* __restrict__ ft,
-                               const double* __restrict__ gt) {
+// Start of a refinement: anchor = the candidate's row, p_t = 0, empty history, every
+// candidate active, and the trajectory constants of the first trial point.
+__global__ void k_refine_init(LbfgsState s, GradArgs a, const double* params,
+                              double* anchor) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= s.n) return;
+  for (int k = 0; k < 4; ++k) {
+    anchor[4 * c + k] = params[4 * c + k];
+    s.pt[4 * c + k] = 0.0f;
+  }
+  s.nhist[c] = 0;
+  s.start[c] = 0;
+  s.nls[c] = 0;
+  s.active[c] = 1;
+  prep_candidate(a, c);
+}
+
+// Update of every active candidate from its evaluation (ft, gt), then the trajectory
+// constants of its next trial point; round 0 also records the starting chi-square.
+template <int M>
+__global__ __launch_bounds__(64) void k_lbfgs_update(LbfgsState s, GradArgs a, int32_t round,
+                               const double* __restrict__ ft, const double* __restrict__ gt,
+                               double* __restrict__ chi2_init) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= s.n || !s.active[c]) return;
   double g[4];
   for (int k = 0; k < 4; ++k) g[k] = gt[4 * c + k];
-  lbfgs_step(s, c, round, ft[c], g);
+  const double f = ft[c];
+  if (round == 0 && chi2_init) chi2_init[c] = f;
+  if (lbfgs_step<M>(s, c, round, f, g)) prep_candidate(a, c);
 }
 
 __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
@@ -443,11 +455,24 @@ hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_lbfgs_update(const LbfgsState& s, int32_t round, const double* ft,
-                               const double* gt, hipStream_t st) {
+hipError_t launch_refine_init(const LbfgsState& s, const GradArgs& a, const double* params,
+                              double* anchor, hipStream_t st) {
   if (s.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s,
-                     round, ft, gt);
+  hipLaunchKernelGGL(k_refine_init, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st, s, a,
+                     params, anchor);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_update(const LbfgsState& s, const GradArgs& a, int32_t round,
+                               const double* ft, const double* gt, double* chi2_init,
+                               hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  // 64-lane workgroups: one thread per candidate, spread over as many CUs as possible
+  const dim3 grid((unsigned)((s.n + 63) / 64)), block(64);
+  if (s.m <= 8)
+    hipLaunchKernelGGL(k_lbfgs_update<8>, grid, block, 0, st, s, a, round, ft, gt, chi2_init);
+  else
+    hipLaunchKernelGGL(k_lbfgs_update<16>, grid, block, 0, st, s, a, round, ft, gt, chi2_init);
   return hipGetLastError();
 }
 

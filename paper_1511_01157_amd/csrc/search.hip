@@ -135,23 +135,30 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 }
 
 // ---------------------------------------------------------------------------
-// Score one trajectory with one wavefront.  All lanes return the same values.
+// Score TU trajectories with one wavefront.  All lanes return the same values.
 // Each lane takes SU points per iteration (i, i + 64, ...), with their light-curve
-// loads issued together; only lanes whose point is on the map read the map (a
-// wavefront's lanes hold neighbouring times, so they mostly agree), the others take
-// the single-lens branch.  Arrays are addressed by 32-bit offsets from uniform bases.
+// loads issued together and shared by the TU trajectories; only lanes whose point is
+// on the map read the map (a wavefront's lanes hold neighbouring times, so they mostly
+// agree), the others take the single-lens branch.  Every trajectory's sums see the
+// points in the same order for any TU, and wave_sums reduces each over the butterfly
+// tree, so the results do not depend on TU.  Arrays are addressed by 32-bit offsets
+// from uniform bases.
 #ifndef MORSE_SU
 #define MORSE_SU 2
 #endif
 constexpr int SU = MORSE_SU;  // points per lane per iteration (tuning knob)
 
-__device__ __forceinline__ void score_traj(const MapC& m, const float* __restrict__ t,
-                                           const double* __restrict__ w,
-                                           const double* __restrict__ wFc,
-                                           const double* __restrict__ F, int32_t np, double Sw,
-                                           double Fbar, double V, float t0p, const TrajC& c,
-                                           int lane, double& chi2, double& Fs, double& Fb) {
-  double B1 = 0.0, B2 = 0.0, C = 0.0;
+template <int TU>
+__device__ __forceinline__ void score_group(const MapC& m, const float* __restrict__ t,
+                                            const double* __restrict__ w,
+                                            const double* __restrict__ wFc,
+                                            const double* __restrict__ F, int32_t np, double Sw,
+                                            double Fbar, double V, const float (&t0p)[TU],
+                                            const TrajC (&c)[TU], int lane, double (&chi2)[TU],
+                                            double (&Fs)[TU], double (&Fb)[TU]) {
+  double acc[3 * TU];  // (B1, B2, C) per trajectory
+#pragma unroll
+  for (int q = 0; q < 3 * TU; ++q) acc[q] = 0.0;
   for (int32_t i0 = lane; i0 < np; i0 += SU * kWave) {
     float tt[SU];
     double wv[SU], fv[SU];
@@ -164,31 +171,36 @@ __device__ __forceinline__ void score_traj(const MapC& m, const float* __restric
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
-      const float A = sample_A(m, tt[u], t0p, c.iE, c.ca, c.sa, c.bx, c.by);
-      if (SU == 1 || i0 + u * kWave < np) {
-        const double b = (double)A - 1.0;
-        const double wb = wv[u] * b;
-        B1 += wb;
-        B2 = fma(wb, b, B2);
-        C = fma(b, fv[u], C);
+#pragma unroll
+      for (int v = 0; v < TU; ++v) {
+        const float A = sample_A(m, tt[u], t0p[v], c[v].iE, c[v].ca, c[v].sa, c[v].bx, c[v].by);
+        if (SU == 1 || i0 + u * kWave < np) {
+          const double b = (double)A - 1.0;
+          const double wb = wv[u] * b;
+          acc[3 * v] += wb;
+          acc[3 * v + 1] = fma(wb, b, acc[3 * v + 1]);
+          acc[3 * v + 2] = fma(b, fv[u], acc[3 * v + 2]);
+        }
       }
     }
   }
-  B1 = wave_sum(B1);
-  B2 = wave_sum(B2);
-  C = wave_sum(C);
-  const Fit f = centred_fit(Sw, Fbar, V, B1, B2, C);
-  Fs = f.Fs;
-  Fb = f.Fb;
-  chi2 = f.chi2;
-  if (f.recheck) {  // wave-uniform: the sums are identical on every lane
-    double q = 0.0;
-    for (int32_t i = lane; i < np; i += kWave) {
-      const double a = (double)sample_A(m, ldg(t, (uint32_t)i), t0p, c.iE, c.ca, c.sa, c.bx, c.by);
-      const double r = ldg(F, (uint32_t)i) - Fs * a - Fb;
-      q = fma(ldg(w, (uint32_t)i) * r, r, q);
+  wave_sums<3 * TU>(acc);
+#pragma unroll
+  for (int v = 0; v < TU; ++v) {
+    const Fit f = centred_fit(Sw, Fbar, V, acc[3 * v], acc[3 * v + 1], acc[3 * v + 2]);
+    Fs[v] = f.Fs;
+    Fb[v] = f.Fb;
+    chi2[v] = f.chi2;
+    if (f.recheck) {  // wave-uniform: the sums are identical on every lane
+      double q = 0.0;
+      for (int32_t i = lane; i < np; i += kWave) {
+        const double a = (double)sample_A(m, ldg(t, (uint32_t)i), t0p[v], c[v].iE, c[v].ca,
+                                          c[v].sa, c[v].bx, c[v].by);
+        const double r = ldg(F, (uint32_t)i) - Fs[v] * a - Fb[v];
+        q = fma(ldg(w, (uint32_t)i) * r, r, q);
+      }
+      chi2[v] = wave_sum(q);
     }
-    chi2 = wave_sum(q);
   }
 }
 
@@ -206,54 +218,72 @@ __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ 
   const double Sw = lc.sums[3 * e], Fbar = lc.sums[3 * e + 1], V = lc.sums[3 * e + 2];
   const double tref = lc.t_ref[e];
   for (int64_t k = (int64_t)blockIdx.x * wpb + (threadIdx.x / kWave); k < n_traj; k += nw) {
-    const TrajC c = tc[k];
-    const float t0p = (float)(c.t0 - tref);
-    double chi2, Fs, Fb;
-    score_traj(m, t, w, wFc, F, np, Sw, Fbar, V, t0p, c, lane, chi2, Fs, Fb);
+    const TrajC c[1] = {tc[k]};
+    const float t0p[1] = {(float)(c[0].t0 - tref)};
+    double chi2[1], Fs[1], Fb[1];
+    score_group<1>(m, t, w, wFc, F, np, Sw, Fbar, V, t0p, c, lane, chi2, Fs, Fb);
     if (lane == 0) {
-      if (out.chi2) out.chi2[k] = chi2;
-      if (out.fs) out.fs[k] = Fs;
-      if (out.fb) out.fb[k] = Fb;
+      if (out.chi2) out.chi2[k] = chi2[0];
+      if (out.fs) out.fs[k] = Fs[0];
+      if (out.fb) out.fb[k] = Fb[0];
     }
   }
 }
 
 // Persistent batched search.  Every wavefront pulls its own work items from the
 // counter (no workgroup barrier, so a slow trajectory never holds up other waves).
-// Item = (map * n_events + event) * n_blocks + block of traj_per_item trajectories:
-// consecutive items share the map and the light curve, so concurrently running waves
-// hit the same map lines in L2.
+// Trajectories are taken in groups of TU neighbours, scored together.  Item =
+// (map * n_events + event) * n_blocks + b scores groups b, b + n_blocks, ...
+// (traj_per_item / TU of them): the waves running at the same time take neighbouring
+// items, so they score neighbouring trajectories of the same map and light curve (on
+// a product grid, mostly the same line through the map) and share its cache lines.
+template <int TU>
 __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t nb = (a.n_traj + a.traj_per_item - 1) / a.traj_per_item;
+  const int64_t ng = (a.n_traj + TU - 1) / TU;
+  const int64_t gpi = max(a.traj_per_item / TU, 1);
+  const int64_t nb = (ng + gpi - 1) / gpi;
   const int64_t total = nb * a.n_events * a.n_maps;
   for (;;) {
     int item32 = 0;
     if (lane == 0) item32 = (int)atomicAdd(a.counter, 1u);
-    const int64_t item = (int64_t)(uint32_t)__shfl(item32, 0, kWave);
+    // first-lane read: the item is provably wave-uniform, so everything derived from it
+    // (indices, map and trajectory constants) stays in scalar registers
+    const int64_t item = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(item32);
     if (item >= total) break;
     const int64_t b = item % nb;
     const int64_t me = item / nb;
     const int32_t e = (int32_t)(me % a.n_events);
     const int32_t mi = (int32_t)(me / a.n_events);
-    const MapC m = a.maps[mi];
-    const int64_t p0 = a.lc.off[e];
-    const int32_t np = (int32_t)(a.lc.off[e + 1] - p0);
-    const double Sw = a.lc.sums[3 * e], Fbar = a.lc.sums[3 * e + 1], V = a.lc.sums[3 * e + 2];
-    const double tref = a.lc.t_ref[e];
+    const MapC m = uniform(a.maps[mi]);
+    const int64_t p0 = uniform(a.lc.off[e]);
+    const int32_t np = (int32_t)(uniform(a.lc.off[e + 1]) - p0);
+    const double Sw = uniform(a.lc.sums[3 * e]), Fbar = uniform(a.lc.sums[3 * e + 1]),
+                 V = uniform(a.lc.sums[3 * e + 2]);
+    const double tref = uniform(a.lc.t_ref[e]);
     const TrajC* tc = a.tc + (a.shared ? 0 : (int64_t)e * a.n_traj);
-    const int64_t k1 = min((b + 1) * (int64_t)a.traj_per_item, a.n_traj);
     const int64_t obase = ((int64_t)e * a.n_maps + mi) * a.n_traj;
-    for (int64_t k = b * a.traj_per_item; k < k1; ++k) {
-      const TrajC c = tc[k];
-      const float t0p = (float)(c.t0 - tref);
-      double chi2, Fs, Fb;
-      score_traj(m, a.lc.t + p0, a.lc.w + p0, a.lc.wFc + p0, a.lc.F + p0, np, Sw, Fbar, V, t0p, c,
-                 lane, chi2, Fs, Fb);
+    for (int64_t g = b; g < ng; g += nb) {
+      TrajC c[TU];
+      float t0p[TU];
+#pragma unroll
+      for (int v = 0; v < TU; ++v) {  // a short last group repeats its last trajectory
+        c[v] = uniform(tc[min(g * TU + v, a.n_traj - 1)]);
+        t0p[v] = (float)(c[v].t0 - tref);
+      }
+      double chi2[TU], Fs[TU], Fb[TU];
+      score_group<TU>(m, a.lc.t + p0, a.lc.w + p0, a.lc.wFc + p0, a.lc.F + p0, np, Sw, Fbar, V,
+                      t0p, c, lane, chi2, Fs, Fb);
       if (lane == 0) {
-        if (a.out.chi2) a.out.chi2[obase + k] = chi2;
-        if (a.out.fs) a.out.fs[obase + k] = Fs;
-        if (a.out.fb) a.out.fb[obase + k] = Fb;
+#pragma unroll
+        for (int v = 0; v < TU; ++v) {
+          const int64_t k = g * TU + v;
+          if (k < a.n_traj) {
+            if (a.out.chi2) a.out.chi2[obase + k] = chi2[v];
+            if (a.out.fs) a.out.fs[obase + k] = Fs[v];
+            if (a.out.fb) a.out.fb[obase + k] = Fb[v];
+          }
+        }
       }
     }
   }
@@ -615,8 +645,13 @@ hipError_t launch_search_plain(const TrajC* tc, int64_t n_traj, LcView lc, int32
 }
 
 hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_search_batched, dim3(a.grid_blocks), dim3(a.waves_per_block * kWave), 0, st,
-                     a);
+  const dim3 grid(a.grid_blocks), block(a.waves_per_block * kWave);
+  switch (a.tu) {
+    case 1: hipLaunchKernelGGL(k_search_batched<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_search_batched<2>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_search_batched<4>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
