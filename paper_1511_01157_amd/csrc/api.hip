@@ -770,7 +770,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   // the packed maps follow the metadata: their offsets depend only on the metadata key
   const size_t i_off = pl.add(8 * (sp.n_events + 1)), i_tref = pl.add(8 * sp.n_events),
                i_maps = pl.add(sizeof(MapC) * n_maps), i_axes = pl.add(8 * (size_t)n_axes),
-               i_quad = pl.add(quad_region_bytes(maps, n_maps)), i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(256),
+               i_quad = pl.add(quad_region_bytes(maps, n_maps)), i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(4 * kQueueWords),
                i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
                i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0);
@@ -855,6 +855,13 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
   a.out.fs = out->d_fs;
   a.out.fb = out->d_fb;
   a.counter = sp.counter;
+  a.nu = a.na = a.nt = a.ne = 0;
+  if (trajs->kind == MORSE_TRAJ_GRID) {
+    a.nu = trajs->n_u0;
+    a.na = trajs->n_alpha;
+    a.nt = trajs->n_t0;
+    a.ne = trajs->n_tE;
+  }
   a.traj_per_item = cfg.traj_per_item;
   a.waves_per_block = cfg.waves_per_block;
   a.tu = cfg.tu;
@@ -941,7 +948,7 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (timed(ctx, MORSE_KERNEL_SEARCH)) {  // same kernels, launched one by one
     const BatchedArgs a = batched_args(ctx, sp, trajs, out, cfg);
     HIP_TRY(ctx, enqueue_prep(sp, trajs, ctx->stream));
-    HIP_TRY(ctx, launch_fill_u32(sp.counter, 1, 0u, ctx->stream));
+    HIP_TRY(ctx, launch_fill_u32(sp.counter, kQueueWords, 0u, ctx->stream));
     LaunchTimer tm{ctx, MORSE_KERNEL_SEARCH};
     HIP_TRY(ctx, tm.begin(ctx->stream));
     HIP_TRY(ctx, launch_search_batched(a, ctx->stream));
@@ -959,7 +966,7 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     hipGraph_t g = nullptr;
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_prep(sp, trajs, ctx->capture_stream);
-    if (e == hipSuccess) e = launch_fill_u32(sp.counter, 1, 0u, ctx->capture_stream);
+    if (e == hipSuccess) e = launch_fill_u32(sp.counter, kQueueWords, 0u, ctx->capture_stream);
     if (e == hipSuccess) e = launch_search_batched(a, ctx->capture_stream);
     if (e == hipSuccess) e = enqueue_select(sp, out, ctx->capture_stream);
     hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
@@ -1009,7 +1016,7 @@ int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     const BatchedArgs a = batched_args(ctx, sub, trajs, &out, kTune[c]);
     float ms = 0.0f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-      e = launch_fill_u32(sub.counter, 1, 0u, ctx->stream);
+      e = launch_fill_u32(sub.counter, kQueueWords, 0u, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
       if (e == hipSuccess) e = launch_search_batched(a, ctx->stream);
       if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);

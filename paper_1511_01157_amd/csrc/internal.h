@@ -310,12 +310,17 @@ struct BatchedArgs {
   const MapC* maps;         // device table [n_maps]
   LcView lc;
   SearchOut out;            // full [e][m][traj] arrays
-  uint32_t* counter;        // work-queue counter (cleared by a fill kernel)
+  uint32_t* counter;        // kQueues work-queue counters, 128 bytes apart (cleared by a fill kernel)
+  int32_t nu, na, nt, ne;   // product-grid axes (na = 0 for trajectory lists)
   int32_t traj_per_item;
   int32_t waves_per_block;
   int32_t grid_blocks;
   int32_t tu;               // trajectories scored together per wavefront (1, 2 or 4)
 };
+// Work queues of the batched search (one per XCD) and the words they occupy.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;
+constexpr int kQueueWords = kQueues * kQueueStride;
 hipError_t launch_search_batched(const BatchedArgs& a, hipStream_t st);
 
 // Best (chi2, index) per segment of length seg_len; n_seg segments.

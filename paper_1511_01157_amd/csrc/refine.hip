@@ -245,9 +245,16 @@ __global__ void k_cand_prep(GradArgs a) {
   prep_candidate(a, c);
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (the grid is a multiple of 8), so
+// slot s runs on XCD s % 8; that XCD takes the contiguous candidate range
+// [x per, (x + 1) per) and neighbouring candidates (similar trajectories after a
+// ranked selection) share its L2.
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   __shared__ double s_part[GRAD_THREADS / kWave][kSums];
-  for (int64_t c = blockIdx.x; c < a.n; c += gridDim.x) {
+  const int64_t per = (a.n + 7) / 8;
+  for (int64_t slot = blockIdx.x; slot < 8 * per; slot += gridDim.x) {
+    const int64_t c = (slot % 8) * per + slot / 8;
+    if (c >= a.n) continue;
     if (a.active && !a.active[c]) continue;  // uniform per workgroup
     const Eval ev = grad_eval(a, c, s_part);
     if (threadIdx.x == 0) {
@@ -449,7 +456,7 @@ hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st) {
 
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  int64_t blocks = a.n;
+  int64_t blocks = 8 * ((a.n + 7) / 8);
   if (blocks > 1 << 20) blocks = 1 << 20;
   hipLaunchKernelGGL(k_chi2_grad, dim3((unsigned)blocks), dim3(GRAD_THREADS), 0, st, a);
   return hipGetLastError();

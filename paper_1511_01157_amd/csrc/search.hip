@@ -230,13 +230,29 @@ __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ 
   }
 }
 
-// Persistent batched search.  Every wavefront pulls its own work items from the
-// counter (no workgroup barrier, so a slow trajectory never holds up other waves).
-// Trajectories are taken in groups of TU neighbours, scored together.  Item =
-// (map * n_events + event) * n_blocks + b scores groups b, b + n_blocks, ...
-// (traj_per_item / TU of them): the waves running at the same time take neighbouring
-// items, so they score neighbouring trajectories of the same map and light curve (on
-// a product grid, mostly the same line through the map) and share its cache lines.
+// Persistent batched search.  Every wavefront pulls its own work items (no workgroup
+// barrier, so a slow trajectory never holds up other waves).  The item space is cut
+// into kQueues contiguous ranges, one queue each; workgroups are dispatched to the 8
+// XCDs in turn, so blockIdx % 8 names the workgroup's XCD and its home queue: each
+// XCD's L2 serves one compact part of the work, and a wave whose queue is empty moves
+// on to the next queue until all are drained.  Trajectories are taken in groups of
+// TU neighbours, scored together.  Item = (map * n_events + event) * n_blocks + b
+// scores groups b, b + n_blocks, ... (traj_per_item / TU of them): the waves of an
+// XCD running at the same time take neighbouring items, so they score neighbouring
+// trajectories of the same map and light curve.  On a product grid the scoring order
+// runs over (alpha, u0, t0, tE), tE fastest, so neighbouring trajectories lie on
+// nearly the same line through the map (the (u0, alpha, t0, tE) index order of the
+// outputs is unchanged).
+// Trajectory index of scoring position p (see k_search_batched).
+__device__ __forceinline__ int64_t traj_of(const BatchedArgs& a, int64_t p) {
+  if (a.na <= 0) return p;
+  const uint32_t u = (uint32_t)p;  // n_traj < 2^31
+  const uint32_t ie = u % (uint32_t)a.ne, r1 = u / (uint32_t)a.ne;
+  const uint32_t it = r1 % (uint32_t)a.nt, r2 = r1 / (uint32_t)a.nt;
+  const uint32_t iu = r2 % (uint32_t)a.nu, ia = r2 / (uint32_t)a.nu;
+  return (((int64_t)iu * a.na + ia) * a.nt + it) * a.ne + ie;
+}
+
 template <int TU>
 __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -244,13 +260,20 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
   const int64_t gpi = max(a.traj_per_item / TU, 1);
   const int64_t nb = (ng + gpi - 1) / gpi;
   const int64_t total = nb * a.n_events * a.n_maps;
+  int q = blockIdx.x % kQueues;
+  int left = kQueues;
   for (;;) {
-    int item32 = 0;
-    if (lane == 0) item32 = (int)atomicAdd(a.counter, 1u);
+    const int64_t lo = total * q / kQueues, hi = total * (q + 1) / kQueues;
+    int rel32 = 0;
+    if (lane == 0) rel32 = (int)atomicAdd(a.counter + q * kQueueStride, 1u);
     // first-lane read: the item is provably wave-uniform, so everything derived from it
     // (indices, map and trajectory constants) stays in scalar registers
-    const int64_t item = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(item32);
-    if (item >= total) break;
+    const int64_t item = lo + (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(rel32);
+    if (item >= hi) {  // this queue is drained (and stays drained)
+      if (--left == 0) break;
+      q = (q + 1) % kQueues;
+      continue;
+    }
     const int64_t b = item % nb;
     const int64_t me = item / nb;
     const int32_t e = (int32_t)(me % a.n_events);
@@ -266,9 +289,11 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
     for (int64_t g = b; g < ng; g += nb) {
       TrajC c[TU];
       float t0p[TU];
+      int64_t kk[TU];
 #pragma unroll
       for (int v = 0; v < TU; ++v) {  // a short last group repeats its last trajectory
-        c[v] = uniform(tc[min(g * TU + v, a.n_traj - 1)]);
+        kk[v] = traj_of(a, min(g * TU + v, a.n_traj - 1));
+        c[v] = uniform(tc[kk[v]]);
         t0p[v] = (float)(c[v].t0 - tref);
       }
       double chi2[TU], Fs[TU], Fb[TU];
@@ -277,8 +302,8 @@ __global__ __launch_bounds__(512) void k_search_batched(BatchedArgs a) {
       if (lane == 0) {
 #pragma unroll
         for (int v = 0; v < TU; ++v) {
-          const int64_t k = g * TU + v;
-          if (k < a.n_traj) {
+          const int64_t k = kk[v];
+          if (g * TU + v < a.n_traj) {
             if (a.out.chi2) a.out.chi2[obase + k] = chi2[v];
             if (a.out.fs) a.out.fs[obase + k] = Fs[v];
             if (a.out.fb) a.out.fb[obase + k] = Fb[v];
