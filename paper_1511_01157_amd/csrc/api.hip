@@ -286,7 +286,7 @@ size_t quad_region_bytes(const morse_map_view* maps, int32_t n_maps) {
 
 void assign_quads(std::vector<MapC>& hm, char* region) {
   for (auto& m : hm) {
-    m.quad = (const float4*)region;
+    m.quad = (const Quad*)region;
     region += (quad_bytes(m.mx, m.my) + 255) & ~size_t(255);
   }
 }

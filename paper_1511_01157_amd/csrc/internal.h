@@ -37,14 +37,28 @@ static_assert(sizeof(TrajC) == 32, "TrajC layout");
 // A map as the sampling kernels see it.  The row-major pixel values `map` are packed
 // once per call into `quad`: cell (i, j), 0 <= i < mx - 1, 0 <= j < my - 1, holds the
 // four pixel-centre values (A[j][i], A[j][i+1], A[j+1][i], A[j+1][i+1]) as one 16-byte
-// float4, and the cells are grouped in tiles of 4 (x) by 2 (y) cells, one 128-byte
+// Quad, and the cells are grouped in tiles of 4 (x) by 2 (y) cells, one 128-byte
 // cache line each, tiles in row-major order:
 //   q(i, j) = ((j / 2) tiles_x + i / 4) 8 + (j % 2) 4 + i % 4.
 // A bilinear sample is then one aligned load, and the samples of a wavefront along a
 // trajectory touch about 2.5x fewer cache lines than two row-major row loads.
+// One packed cell: the four pixel-centre values around it.
+struct alignas(16) Quad {
+  float v00, v10, v01, v11;
+};
+
+// Load of cell q (one global_load_dwordx4; see ldg).
+__device__ __forceinline__ Quad ldq(const Quad* __restrict__ base, uint32_t q) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) f4 gf4;
+  const f4 v = *(gf4*)((gchar*)base + (size_t)(q * 16u));
+  return Quad{v.x, v.y, v.z, v.w};
+}
+
 struct MapC {
   const float* map;
-  const float4* quad;
+  const Quad* quad;
   uint32_t tiles_x, tiles_y;
   int32_t mx, my;
   float sx, sy, kx, ky, ox, oy;  // grid coordinate g = (zeta - s) k + o
@@ -87,21 +101,59 @@ struct __attribute__((packed, aligned(4))) Pair {
 };
 
 // Load base[i] through a uniform base pointer and a 32-bit element offset, so the
-// backend can address with a scalar base plus one 32-bit VGPR offset.
+// backend can address with a scalar base plus one 32-bit VGPR offset.  The pointer is
+// taken as global memory explicitly (a pointer rebuilt from scalar registers has lost
+// its address space, and a generic pointer would compile to a slower flat load).
 template <class T>
 __device__ __forceinline__ T ldg(const T* __restrict__ base, uint32_t i) {
-  return *(const T*)((const char*)base + (size_t)(i * (uint32_t)sizeof(T)));
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) T gT;
+  return *(gT*)((gchar*)base + (size_t)(i * (uint32_t)sizeof(T)));
 }
 
 __device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, float& v00, float& v10,
                                          float& v01, float& v11) {
   const uint32_t i = (uint32_t)(int)fi, j = (uint32_t)(int)fj;
   const uint32_t q = ((((j >> 1) * m.tiles_x + (i >> 2)) << 3) | ((j & 1u) << 2)) | (i & 3u);
-  const float4 v = ldg(m.quad, q);
-  v00 = v.x;
-  v10 = v.y;
-  v01 = v.z;
-  v11 = v.w;
+  const Quad v = ldq(m.quad, q);
+  v00 = v.v00;
+  v10 = v.v10;
+  v01 = v.v01;
+  v11 = v.v11;
+}
+
+// Sampling in steps, so that the loads of several points can all be issued before
+// any of them is used: locate (trajectory position, on-map test, cell), one 16-byte
+// fetch of the cell (an off-map lane reads cell 0, and ignores it), then the blend.
+// The arithmetic is that of sample_A / sample_full.
+struct Loc {
+  float tau, zx, zy, fx, fy;
+  uint32_t q;  // packed cell index (0 off the map)
+  bool on;
+};
+
+__device__ __forceinline__ Loc locate(const MapC& m, float tt, float t0p, float iE, float ca,
+                                      float sa, float bx, float by) {
+  Loc l;
+  l.tau = (tt - t0p) * iE;
+  l.zx = l.tau * ca + bx;
+  l.zy = l.tau * sa + by;
+  const float gx = ((l.zx - m.sx) * m.kx) + m.ox;
+  const float gy = ((l.zy - m.sy) * m.ky) + m.oy;
+  l.on = (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly);
+  const float fi = l.on ? floorf(gx) : 0.0f;
+  const float fj = l.on ? floorf(gy) : 0.0f;
+  l.fx = gx - fi;
+  l.fy = gy - fj;
+  const uint32_t i = (uint32_t)(int)fi, j = (uint32_t)(int)fj;
+  l.q = ((((j >> 1) * m.tiles_x + (i >> 2)) << 3) | ((j & 1u) << 2)) | (i & 3u);
+  return l;
+}
+
+// Single-lens magnification about the barycentre, (uu + 2)/sqrt(uu (uu + 4)).
+__device__ __forceinline__ float point_lens_A(float zx, float zy) {
+  const float uu = zx * zx + zy * zy;
+  return (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
 }
 
 __device__ __forceinline__ float sample_A(const MapC& m, float tt, float t0p, float iE, float ca,

@@ -51,20 +51,20 @@ __global__ void k_fill_u64(uint64_t* p, size_t n, uint64_t v) {
 __global__ void k_quad_pack(const MapC* __restrict__ maps) {
   const MapC m = maps[blockIdx.y];
   const uint64_t nq = (uint64_t)m.tiles_x * m.tiles_y * 8;
-  float4* out = const_cast<float4*>(m.quad);
+  Quad* out = const_cast<Quad*>(m.quad);
   for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nq;
        q += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t tile = q >> 3;
     const uint32_t r = (uint32_t)(q & 7);
     const uint64_t i = (tile % m.tiles_x) * 4 + (r & 3u);
     const uint64_t j = (tile / m.tiles_x) * 2 + (r >> 2);
-    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    Quad v = {0.0f, 0.0f, 0.0f, 0.0f};
     if (i + 1 < (uint64_t)m.mx && j + 1 < (uint64_t)m.my) {
       const float* row = m.map + j * (uint64_t)m.mx + i;
-      v.x = row[0];
-      v.y = row[1];
-      v.z = row[m.mx];
-      v.w = row[m.mx + 1];
+      v.v00 = row[0];
+      v.v10 = row[1];
+      v.v01 = row[m.mx];
+      v.v11 = row[m.mx + 1];
     }
     out[q] = v;
   }

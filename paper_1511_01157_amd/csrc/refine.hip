@@ -131,20 +131,32 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   double acc[kSums];
 #pragma unroll
   for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
-  for (int32_t i = tid; i < np; i += GRAD_THREADS) {
-    const uint32_t u = (uint32_t)i;
-    const Sample sm = sample_full(m, ldg(t, u), t0p, iE, ca, sa, bx, by);
-    const double b = (double)sm.A - 1.0;
-    const double wi = ldg(w, u), wfc = ldg(wFc, u);
+  // Two points per thread and iteration (i and i + GRAD_THREADS, so each thread still
+  // takes its points in increasing order): all their loads are issued before use.
+  auto add_point = [&](const Loc& l, const Quad& v, double wi, double wfc) {
+    const float e0 = v.v10 - v.v00, e1 = v.v11 - v.v01;
+    const float ax0 = v.v00 + l.fx * e0, ax1 = v.v01 + l.fx * e1;
+    float A = ax0 + l.fy * (ax1 - ax0);
+    double dAx = kx * ((double)e0 + (double)l.fy * ((double)e1 - (double)e0));
+    double dAy = ky * ((double)ax1 - (double)ax0);
+    if (!l.on) {
+      A = point_lens_A(l.zx, l.zy);
+      // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
+      const double zx = (double)l.zx, zy = (double)l.zy;
+      const double u2 = zx * zx + zy * zy;
+      const double pp = u2 * (u2 + 4.0);
+      const double f = -8.0 / (pp * sqrt(pp));
+      dAx = f * zx;
+      dAy = f * zy;
+    }
+    const double b = (double)A - 1.0;
     const double wb = wi * b;
     acc[0] += wb;
     acc[1] = fma(wb, b, acc[1]);
     acc[2] = fma(b, wfc, acc[2]);
-    double dAx, dAy;
-    sample_dA(sm, kx, ky, dAx, dAy);
-    const double tau = (double)sm.tau;
+    const double tau = (double)l.tau;
     const double D[kDirs] = {dAx, dAy, dAx * tau, dAy * tau,
-                             (double)sm.zx * dAy - (double)sm.zy * dAx};
+                             (double)l.zx * dAy - (double)l.zy * dAx};
 #pragma unroll
     for (int k = 0; k < kDirs; ++k) {
       const double wD = wi * D[k];
@@ -152,6 +164,16 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
       acc[4 + 3 * k] = fma(wD, b, acc[4 + 3 * k]);
       acc[5 + 3 * k] = fma(wfc, D[k], acc[5 + 3 * k]);
     }
+  };
+  for (int32_t i0 = tid; i0 < np; i0 += 2 * GRAD_THREADS) {
+    const bool has1 = i0 + GRAD_THREADS < np;
+    const uint32_t u0 = (uint32_t)i0, u1 = has1 ? (uint32_t)(i0 + GRAD_THREADS) : u0;
+    const Loc l0 = locate(m, ldg(t, u0), t0p, iE, ca, sa, bx, by);
+    const Loc l1 = locate(m, ldg(t, u1), t0p, iE, ca, sa, bx, by);
+    const Quad v0 = ldq(m.quad, l0.q), v1 = ldq(m.quad, l1.q);
+    const double w0 = ldg(w, u0), f0 = ldg(wFc, u0), w1 = ldg(w, u1), f1 = ldg(wFc, u1);
+    add_point(l0, v0, w0, f0);
+    if (has1) add_point(l1, v1, w1, f1);
   }
   block_sum<kSums>(acc, s_part);
   const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2]);
