@@ -40,15 +40,26 @@ OPS_PER_ADJOINT_EVAL = 67
 # 256 CUs x 64 lanes x 2.4 GHz: one lane-operation per lane per clock (FP32 or FP64).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (scaled by the
-# copy-kernel calibration), keyed by the SHA-256 of the kernel source it was taken on.
-TRAFFIC = {}
+# HBM-side traffic per launch (bytes) of the dominant kernel from two rocprofv3 --pmc
+# runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
+# dispatches of one warm-up and one timed step), each scaled by what the same counter
+# reads for a 1 GiB device-to-device copy (FETCH_SIZE 524301 KiB: factor 1.99995;
+# WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel and a hash of the sources
+# it is built from; a changed kernel reports null until it is measured again.
+TRAFFIC = {
+    ("k_chi2_grad", "18c3653233c7fe61"): 286.2e6,  # 139677 KiB fetched, 158 KiB written
+}
+KERNEL_SOURCES = {"k_rayshoot": ("maps.hip", "internal.h"),
+                  "k_search_batched": ("search.hip", "internal.h"),
+                  "k_chi2_grad": ("refine.hip", "internal.h")}
 
 
-def kernel_sha(name):
-    path = os.path.join(ROOT, "paper_1511_01157_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_sha(kernel):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1511_01157_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -281,10 +292,8 @@ def main():
     ops_per_launch = {"k_rayshoot": OPS_PER_RAY * rays_per_step,
                       "k_search_batched": OPS_PER_POINT_EVAL * evals_per_step,
                       "k_chi2_grad": OPS_PER_ADJOINT_EVAL * k * n_pts}
-    kfile = {"k_rayshoot": "maps.hip", "k_search_batched": "search.hip",
-             "k_chi2_grad": "refine.hip"}[dom]
     dom_ms = dom_total_ms / dom_launches
-    traffic = TRAFFIC.get((dom, kernel_sha(kfile)))
+    traffic = TRAFFIC.get((dom, kernel_sha(dom)))
     achieved = ops_per_launch[dom] / (dom_ms * 1e-3) / 1e12
     line = {
         "metric": "light-curve point-evals/s (chi2 search) + rays/s (map build); batched vs plain",

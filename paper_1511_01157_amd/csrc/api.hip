@@ -43,6 +43,13 @@ constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 
 }  // namespace
 
+// A device buffer of host metadata with the key of what it holds.
+struct MetaBuf {
+  char* p = nullptr;
+  size_t size = 0;
+  uint64_t key = 0;
+};
+
 struct morse_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -53,9 +60,10 @@ struct morse_ctx {
   size_t ws_size = 0;
   uint64_t ws_epoch = 0;  // bumps when the workspace moves
   std::string err;
-  // host metadata already resident in the workspace (skip re-uploads)
-  uint64_t upload_key = 0;
-  uint64_t upload_epoch = ~0ull;
+  // host metadata of the searches and of the candidate entry points, each in a device
+  // buffer of its own (never in the shared workspace, which the other entry points
+  // overwrite) and uploaded only when its key changes
+  MetaBuf smeta, cmeta;
   // batched-search graph
   hipGraphExec_t gexec = nullptr;
   uint64_t graph_key = 0;
@@ -229,6 +237,22 @@ int reserve_aux(morse_ctx* ctx, size_t bytes) {
     return fail(ctx, MORSE_ENOMEM, "auxiliary allocation of %zu bytes failed", want);
   }
   ctx->aux_size = want;
+  return MORSE_OK;
+}
+
+// Grows a metadata buffer to at least `bytes` (its contents are then invalid).
+int reserve_meta(morse_ctx* ctx, MetaBuf& mb, size_t bytes) {
+  if (bytes <= mb.size) return MORSE_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (mb.p) (void)hipFree(mb.p);
+  mb.p = nullptr;
+  mb.size = 0;
+  mb.key = 0;
+  if (hipMalloc((void**)&mb.p, bytes) != hipSuccess) {
+    mb.p = nullptr;
+    return fail(ctx, MORSE_ENOMEM, "metadata allocation of %zu bytes failed", bytes);
+  }
+  mb.size = bytes;
   return MORSE_OK;
 }
 
@@ -459,6 +483,8 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->taps) (void)hipFree(ctx->taps);
+  if (ctx->smeta.p) (void)hipFree(ctx->smeta.p);
+  if (ctx->cmeta.p) (void)hipFree(ctx->cmeta.p);
   for (const auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -745,8 +771,8 @@ uint64_t metadata_key(const morse_map_view* maps, int32_t n_maps, const morse_li
   return h.h;
 }
 
-// Reserve the workspace and upload the host metadata of a search (skipped when the
-// same metadata is already resident).  Enqueues nothing else.
+// Reserve the workspace and upload the host metadata of a search into its own buffer
+// (skipped when the same metadata is already resident).  Enqueues nothing else.
 int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                 const morse_lightcurves* lcs, const morse_trajectories* trajs,
                 const morse_search_out* out, SearchPlan& sp) {
@@ -764,21 +790,14 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   const int n_axes = trajs->kind == MORSE_TRAJ_GRID
                          ? trajs->n_u0 + trajs->n_alpha + trajs->n_t0 + trajs->n_tE
                          : 0;
-  Plan pl;
-  // metadata first, so its offsets do not depend on the output sizes
   if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
-  // the packed maps follow the metadata: their offsets depend only on the metadata key
-  const size_t i_off = pl.add(8 * (sp.n_events + 1)), i_tref = pl.add(8 * sp.n_events),
-               i_maps = pl.add(sizeof(MapC) * n_maps), i_axes = pl.add(8 * (size_t)n_axes),
-               i_quad = pl.add(quad_region_bytes(maps, n_maps)), i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(4 * kQueueWords),
+  Plan pl;
+  const size_t i_quad = pl.add(quad_region_bytes(maps, n_maps)),
+               i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(4 * kQueueWords),
                i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
                i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0);
   if ((rc = reserve(ctx, pl.total()))) return rc;
-  int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
-  double* d_tref = (double*)pl.ptr(ctx, i_tref);
-  sp.d_maps = (MapC*)pl.ptr(ctx, i_maps);
-  sp.axes = (double*)pl.ptr(ctx, i_axes);
   double* d_sums = (double*)pl.ptr(ctx, i_sums);
   sp.counter = (uint32_t*)pl.ptr(ctx, i_cnt);
   double* d_wF = (double*)pl.ptr(ctx, i_wF);
@@ -789,8 +808,21 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   sp.h_maps.resize(n_maps);
   for (int i = 0; i < n_maps; ++i) sp.h_maps[i] = make_mapc(maps[i].d_map, maps[i].window);
   assign_quads(sp.h_maps, pl.ptr(ctx, i_quad));
-  const uint64_t key = metadata_key(maps, n_maps, lcs, trajs);
-  if (key != ctx->upload_key || ctx->upload_epoch != ctx->ws_epoch) {
+  // metadata buffer: offsets | reference times | map table | grid axes
+  const size_t b_off = (8 * (size_t)(sp.n_events + 1) + 255) & ~size_t(255);
+  const size_t b_tref = (8 * (size_t)sp.n_events + 255) & ~size_t(255);
+  const size_t b_maps = (sizeof(MapC) * n_maps + 255) & ~size_t(255);
+  if ((rc = reserve_meta(ctx, ctx->smeta, b_off + b_tref + b_maps + 8 * (size_t)n_axes))) return rc;
+  int64_t* d_off = (int64_t*)ctx->smeta.p;
+  double* d_tref = (double*)(ctx->smeta.p + b_off);
+  sp.d_maps = (MapC*)(ctx->smeta.p + b_off + b_tref);
+  sp.axes = (double*)(ctx->smeta.p + b_off + b_tref + b_maps);
+  Hasher key;
+  key.pod(ctx->smeta.p);
+  key.pod(metadata_key(maps, n_maps, lcs, trajs));
+  key.bytes(sp.h_maps.data(), sizeof(MapC) * n_maps);  // includes the packed-cell addresses
+  if (key.h != ctx->smeta.key) {
+    ctx->smeta.key = 0;
     std::vector<double> axes;
     if (n_axes) {
       axes.insert(axes.end(), trajs->h_u0, trajs->h_u0 + trajs->n_u0);
@@ -802,9 +834,8 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * sp.n_events))) return rc;
     if ((rc = upload(ctx, sp.d_maps, sp.h_maps.data(), sizeof(MapC) * n_maps))) return rc;
     if ((rc = upload(ctx, sp.axes, axes.data(), 8 * axes.size()))) return rc;
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->upload_key = key;
-    ctx->upload_epoch = ctx->ws_epoch;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host arrays go out of scope
+    ctx->smeta.key = key.h;
   }
   sp.lc.t = lcs->d_t;
   sp.lc.w = lcs->d_weight;
@@ -936,6 +967,7 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   const TuneCfg& cfg = kTune[cfg_idx];
   Hasher h;
   h.pod(metadata_key(maps, n_maps, lcs, trajs));
+  h.pod(ctx->smeta.p);
   h.pod(ctx->ws_epoch);
   h.pod(cfg_idx);
   h.pod(*out);
@@ -1106,9 +1138,8 @@ int morse_candidates_from_topk(morse_ctx* ctx, const morse_trajectories* trajs, 
 // ---------------------------------------------------------------------------
 namespace {
 int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
-                    const morse_lightcurves* lcs, int64_t n, Plan& pl, size_t& i_off,
-                    size_t& i_tref, size_t& i_maps, size_t& i_sums, size_t& i_wF,
-                    size_t& i_quad) {
+                    const morse_lightcurves* lcs, int64_t n, Plan& pl, size_t& i_sums,
+                    size_t& i_wF, size_t& i_quad) {
   if (!maps || n_maps <= 0) return fail(ctx, MORSE_EINVAL, "need n_maps >= 1 maps");
   int rc;
   for (int i = 0; i < n_maps; ++i) {
@@ -1123,31 +1154,44 @@ int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
       return fail(ctx, MORSE_EINVAL, "event %d has fewer than 3 points", e);
   if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
   if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
-  i_off = pl.add(8 * (lcs->n_events + 1));
-  i_tref = pl.add(8 * lcs->n_events);
-  i_maps = pl.add(sizeof(MapC) * n_maps);
   i_sums = pl.add(24 * (size_t)lcs->n_events);
   i_wF = pl.add(8 * (size_t)lcs->h_offsets[lcs->n_events]);
   i_quad = pl.add(quad_region_bytes(maps, n_maps));
   return MORSE_OK;
 }
 
+// Host metadata of the candidate entry points (event offsets, reference times, map
+// table) lives in its own device buffer, uploaded only when it changes, so calls that
+// alternate with searches neither re-upload nor wait for the device.
 int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
-                     const morse_lightcurves* lcs, const Plan& pl, size_t i_off, size_t i_tref,
-                     size_t i_maps, size_t i_sums, size_t i_wF, size_t i_quad, LcView& lc,
-                     MapC*& d_maps) {
+                     const morse_lightcurves* lcs, const Plan& pl, size_t i_sums, size_t i_wF,
+                     size_t i_quad, LcView& lc, MapC*& d_maps) {
   int rc;
-  int64_t* d_off = (int64_t*)pl.ptr(ctx, i_off);
-  double* d_tref = (double*)pl.ptr(ctx, i_tref);
-  d_maps = (MapC*)pl.ptr(ctx, i_maps);
+  const int32_t ne = lcs->n_events;
   std::vector<MapC> hm(n_maps);
   for (int i = 0; i < n_maps; ++i) hm[i] = make_mapc(maps[i].d_map, maps[i].window);
   assign_quads(hm, pl.ptr(ctx, i_quad));
-  if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (lcs->n_events + 1)))) return rc;
-  if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * lcs->n_events))) return rc;
-  if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  ctx->upload_key = 0;  // the search metadata region was overwritten
+  const size_t b_off = (8 * (size_t)(ne + 1) + 255) & ~size_t(255);
+  const size_t b_tref = (8 * (size_t)ne + 255) & ~size_t(255);
+  if ((rc = reserve_meta(ctx, ctx->cmeta, b_off + b_tref + sizeof(MapC) * n_maps))) return rc;
+  int64_t* d_off = (int64_t*)ctx->cmeta.p;
+  double* d_tref = (double*)(ctx->cmeta.p + b_off);
+  d_maps = (MapC*)(ctx->cmeta.p + b_off + b_tref);
+  Hasher h;
+  h.pod(ctx->cmeta.p);
+  h.pod(ne);
+  h.pod(n_maps);
+  h.bytes(lcs->h_offsets, 8 * (size_t)(ne + 1));
+  h.bytes(lcs->h_t_ref, 8 * (size_t)ne);
+  h.bytes(hm.data(), sizeof(MapC) * n_maps);  // includes the packed-cell addresses
+  if (h.h != ctx->cmeta.key) {
+    ctx->cmeta.key = 0;
+    if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (size_t)(ne + 1)))) return rc;
+    if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * (size_t)ne))) return rc;
+    if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host arrays go out of scope
+    ctx->cmeta.key = h.h;
+  }
   lc.t = lcs->d_t;
   lc.w = lcs->d_weight;
   lc.F = lcs->d_flux;
@@ -1156,8 +1200,8 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   lc.sums = (double*)pl.ptr(ctx, i_sums);
   lc.t_ref = d_tref;
   HIP_TRY(ctx, launch_quad_pack(d_maps, hm.data(), n_maps, ctx->stream));
-  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, lcs->n_events, (double*)lc.wFc,
-                              (double*)lc.sums, ctx->stream));
+  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, ne, (double*)lc.wFc, (double*)lc.sums,
+                              ctx->stream));
   return MORSE_OK;
 }
 }  // namespace
@@ -1169,8 +1213,8 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   int rc;
   Plan pl;
-  size_t i_off, i_tref, i_maps, i_sums, i_wF, i_quad;
-  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad))) return rc;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_sums, i_wF, i_quad))) return rc;
   if (n > 0 && (!d_params || !d_event || !d_map_index))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1180,7 +1224,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
   a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
-  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
   a.n = n;
   a.params = d_params;
   a.event = d_event;
@@ -1211,8 +1255,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     return fail(ctx, MORSE_EINVAL, "invalid L-BFGS options");
   int rc;
   Plan pl;
-  size_t i_off, i_tref, i_maps, i_sums, i_wF, i_quad;
-  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad))) return rc;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_sums, i_wF, i_quad))) return rc;
   if (n > 0 && (!d_params || !d_event || !d_map_index || !d_chi2_out))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index / d_chi2_out is NULL");
   if (n == 0) return MORSE_OK;
@@ -1229,7 +1273,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
   a.tEv = (double*)pl.ptr(ctx, i_tE);
   MapC* d_maps;
-  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_off, i_tref, i_maps, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
   LbfgsState s;
   s.n = n;
   s.m = m;
@@ -1282,6 +1326,13 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   h.pod(lcs->d_t);
   h.pod(lcs->d_flux);
   h.pod(lcs->d_weight);
+  // everything the workspace layout and the metadata buffer depend on
+  h.bytes(lcs->h_offsets, 8 * (size_t)(lcs->n_events + 1));
+  for (int i = 0; i < n_maps; ++i) {
+    h.pod(maps[i].d_map);
+    h.pod(maps[i].window);
+  }
+  h.pod(ctx->cmeta.p);
   // start, steps + 1 rounds, write-back; with `timing`, events bracket each evaluation
   auto enqueue = [&](hipStream_t cs, bool timing) -> hipError_t {
     hipError_t e = launch_refine_init(s, a, d_params, anchor, cs);

@@ -166,3 +166,43 @@ def test_refine_graph_replays_match_fresh_capture(tiny_oracle_map):
         torch.cuda.synchronize()
         assert torch.equal(out, ref) and torch.equal(chi2, ref_chi2), rep
         _ = (P0 * 2.0).sum().item()  # eager work between replays
+
+
+def test_alternating_entry_points_reuse_metadata_consistently(tiny_oracle_map):
+    """Searches, gradients and refinements on two different light-curve batches,
+    interleaved: every call gives what the same call gives on its own (the cached
+    metadata of one entry point is never taken for the other's)."""
+    c = W.config("tiny")
+    maps = [(dmap(tiny_oracle_map[2]), c["window"])]
+    evA = W.load_lightcurve("tiny")
+    evB = dict(evA)
+    keep = np.arange(len(evA["tt"])) % 3 != 0  # a different length and content
+    for k in ("t", "tt", "F", "sigma", "w"):
+        evB[k] = evA[k][keep]
+    lcA = M.LightCurveBatch.from_events([evA], DEV)
+    lcB = M.LightCurveBatch.from_events([evB], DEV)
+    P = torch.from_numpy(candidates(16, 9, evA["truth"])).to(DEV)
+    z = torch.zeros(16, dtype=torch.int32, device=DEV)
+    trajs = M.grid_trajectories(*W.grid_axes("tiny"))
+    note("alternating entry points")
+    gA = M.chi2_grad(maps, lcA, P, z, z)
+    sB = M.search(maps, lcB, trajs, "batched", top_k=4)
+    gB = M.chi2_grad(maps, lcB, P, z, z)
+    rA = M.refine(maps, lcA, P, z, z, steps=5)
+    sA = M.search(maps, lcA, trajs, "batched", top_k=4)
+    gA2 = M.chi2_grad(maps, lcA, P, z, z)
+    sB2 = M.search(maps, lcB, trajs, "batched", top_k=4)
+    rA2 = M.refine(maps, lcA, P, z, z, steps=5)
+    gB2 = M.chi2_grad(maps, lcB, P, z, z)
+    # the same search again right after a candidate call (its metadata stays resident)
+    sB3 = M.search(maps, lcB, trajs, "batched", top_k=4)
+    assert torch.equal(sB["chi2"], sB3["chi2"]) and torch.equal(sB["topk_idx"], sB3["topk_idx"])
+    for x, y in zip(gA, gA2):
+        assert torch.equal(x, y)
+    for x, y in zip(gB, gB2):
+        assert torch.equal(x, y)
+    assert torch.equal(sB["chi2"], sB2["chi2"]) and torch.equal(sB["topk_idx"], sB2["topk_idx"])
+    for x, y in zip(rA, rA2):
+        assert torch.equal(x, y)
+    assert not torch.equal(gA[0], gB[0])
+    assert not torch.equal(sA["chi2"], sB["chi2"])
