@@ -3,21 +3,22 @@
 // is linear in the magnification, so (F_s, F_b) are profiled out by weighted least
 // squares).
 //
-// Layout.  One wavefront scores one trajectory at a time: its 64 lanes stride over the
-// light-curve points (time-ordered, so a wave's lanes sample neighbouring map cells and
-// leave the map together), each lane keeps FP64 partial sums of the normal equations
-// in centred form (b = A - 1 against the mean-centred weighted flux), and a butterfly
-// shuffle reduces them in a fixed order.  S_w, the weighted mean flux and
-// V = sum w (F - Fbar)^2 depend only on the light curve and are computed once per
-// event.  The 2x2 solve gives chi2 = V - F_s C in the same pass; when the rounding
-// bound of that form exceeds 1e-9 relative (ill-conditioned or near-perfect fits) the
-// wave re-samples and sums w (F - F_s A - F_b)^2 directly.
+// Layout.  One wavefront scores TU neighbouring trajectories at a time: its 64 lanes
+// stride over the light-curve points (time-ordered, so a wave's lanes sample
+// neighbouring map cells and leave the map together), each lane keeps FP64 partial
+// sums of the normal equations in centred form (b = A - 1 against the mean-centred
+// weighted flux) per trajectory, and a fixed-order reduction (bitwise the butterfly of
+// each value) totals them.  S_w, the weighted mean flux and V = sum w (F - Fbar)^2
+// depend only on the light curve and are computed once per event.  The 2x2 solve gives
+// chi2 = V - F_s C in the same pass; when the rounding bound of that form exceeds 1e-9
+// relative (ill-conditioned or near-perfect fits) the wave re-samples and sums
+// w (F - F_s A - F_b)^2 directly.
 //
-// Plain mode launches one grid per (event, map).  Batched mode launches one persistent
-// grid whose wavefronts pull (map, event, trajectory block) items from an atomic
-// counter, so thousands of (event, map) pairs of uneven length share one launch; the
-// per-trajectory arithmetic and reduction order are the same, so results are
-// bitwise identical between the modes.
+// Plain mode launches one grid per (event, map), one trajectory per wavefront.  Batched
+// mode launches one persistent grid whose wavefronts pull (map, event, trajectory
+// group) items from per-XCD work queues, so thousands of (event, map) pairs of uneven
+// length share one launch; the per-trajectory arithmetic and reduction order are the
+// same, so results are bitwise identical between the modes.
 
 #include "internal.h"
 
