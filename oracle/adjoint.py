@@ -112,7 +112,9 @@ def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5, mode="exact6
     mode "exact64": FP64 sampling from absolute times t; mode "mirror32": the
     binary32 sampling of the search (times tt = fl32(t - t_ref)), i.e. the objective
     the refinement minimises.  Step h = rel * max(|theta|, s_theta),
-    s = (tE, 1e-2, tE, 1).  A component is eligible only when no sample changes
+    s = (tE, 1e-2, tE, 1), except for t0: a position in time, whose step is rel * tE
+    whatever the calendar origin (with absolute dates |t0| ~ 2.5e6 d, a step relative
+    to |t0| would span weeks of the light curve).  A component is eligible only when no sample changes
     bilinear cell or on/off-map state between theta - h and theta + h (the bilinear
     interpolant has kinks at cell edges).  Returns (fd [n, 4], eligible [n, 4]).
     """
@@ -128,7 +130,7 @@ def fd_gradient(amap, window, t, F, w, params, t_ref=0.0, rel=1e-5, mode="exact6
     elig = np.zeros((n, 4), dtype=bool)
     for k in range(4):
         scale = np.stack([params[:, 2], np.full(n, 1e-2), params[:, 2], np.ones(n)], axis=1)[:, k]
-        h = rel * np.maximum(np.abs(params[:, k]), scale)
+        h = rel * (params[:, 2] if k == 0 else np.maximum(np.abs(params[:, k]), scale))
         pp = params.copy()
         pm = params.copy()
         pp[:, k] += h
