@@ -27,18 +27,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic lane-operations per unit (one FP32/FP64 add, mul, compare, floor,
-# convert, divide, square root or fused multiply-add = 1):
+# convert, divide, square root or fused multiply-add = 1), split by the unit that
+# executes them, (binary32 and integer, FP64):
 #   ray: lattice point 2, d 2, r 4, two divisions 2, zeta_x 4, zeta_y 4, scaled
-#        offsets 4, floors 2, bin compares/selects 4, index 2, count 1        = 31
+#        offsets 4, floors 2, bin compares/selects 4, index 2, count 1    = (31, 0)
 #   point-evaluation: tau 2, zeta 4, grid coordinate 6, on-map test 4,
-#        floor/fraction 4, cell index 3, bilinear 9, FP64 sums 5              = 37
-#   adjoint point-evaluation: sample 32, fit sums 5, dA/dzeta 5, tau and alpha
-#        directions 5, five directions x (w D and three FP64 sums) 20         = 67
-OPS_PER_RAY = 31
-OPS_PER_POINT_EVAL = 37
-OPS_PER_ADJOINT_EVAL = 67
-# 256 CUs x 64 lanes x 2.4 GHz: one lane-operation per lane per clock (FP32 or FP64).
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+#        floor/fraction 4, cell index 3, bilinear 9 (binary32) + FP64 sums 5 = (32, 5)
+#   adjoint point-evaluation: sample 32 (binary32) + fit sums 5, dA/dzeta 5, tau and
+#        alpha directions 5, five directions x (w D and three sums) 20 (FP64) = (32, 35)
+OPS_PER_RAY = (31, 0)
+OPS_PER_POINT_EVAL = (32, 5)
+OPS_PER_ADJOINT_EVAL = (32, 35)
+# Vector peaks of one MI355X in lane-operations per second (an FMA counts once, so
+# these are half the published 157.3 TFLOP/s binary32 and 78.6 TFLOP/s FP64):
+# 256 CUs x 2.4 GHz x 128 binary32 lanes / 64 FP64 lanes per clock.
+PEAK_F32 = 256 * 2.4e9 * 128
+PEAK_F64 = 256 * 2.4e9 * 64
+
+
+def peak_for(ops):
+    """Peak lane-op rate of a unit of work with (binary32, FP64) operation counts."""
+    n32, n64 = ops
+    return (n32 + n64) / (n32 / PEAK_F32 + n64 / PEAK_F64)
+
 
 # HBM-side traffic per launch (bytes) of the dominant kernel from two rocprofv3 --pmc
 # runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
@@ -288,10 +299,12 @@ def main():
 
     rays_ms, norm_ms, search_ms, refine_ms = stage
     adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
-    # algorithmic lane-operations of one launch of each kernel
-    ops_per_launch = {"k_rayshoot": OPS_PER_RAY * rays_per_step,
-                      "k_search_batched": OPS_PER_POINT_EVAL * evals_per_step,
-                      "k_chi2_grad": OPS_PER_ADJOINT_EVAL * k * n_pts}
+    # algorithmic lane-operations of one launch of each kernel, and their peak rate
+    unit_ops = {"k_rayshoot": (OPS_PER_RAY, rays_per_step),
+                "k_search_batched": (OPS_PER_POINT_EVAL, evals_per_step),
+                "k_chi2_grad": (OPS_PER_ADJOINT_EVAL, k * n_pts)}
+    ops_per_launch = {kn: sum(o) * units for kn, (o, units) in unit_ops.items()}
+    peak = peak_for(unit_ops[dom][0]) / 1e12
     dom_ms = dom_total_ms / dom_launches
     traffic = TRAFFIC.get((dom, kernel_sha(dom)))
     achieved = ops_per_launch[dom] / (dom_ms * 1e-3) / 1e12
@@ -319,15 +332,19 @@ def main():
         "refine_improved_fraction": improved,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
-                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / (PEAK_LANE_OPS / 1e12), "traffic": traffic,
+                     "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
                      "launch_ms": dom_ms, "launches": dom_launches,
                      "ops_per_launch": ops_per_launch[dom],
                      "ops_are_upper_bound": dom == "k_chi2_grad",
                      "kernel_ms_per_step_warmup": per_step,
-                     "op_note": "lane-ops: one FP32/FP64 add, mul, compare, floor, cvt, div "
-                                "or sqrt per lane; peak 256 CU x 64 lanes x 2.4 GHz; launch "
-                                "time from HIP events around each launch over the timed steps"},
+                     "ops_per_unit_f32_f64": unit_ops[dom][0],
+                     "op_note": "achieved and peak in tera lane-operations/s (one FP32/FP64 "
+                                "add, mul, compare, floor, cvt, div, sqrt or FMA per lane = 1); "
+                                "peak = the kernel's binary32/FP64 op mix at 256 CU x 2.4 GHz x "
+                                "128 binary32 or 64 FP64 lanes per clock (half the published "
+                                "157.3/78.6 TFLOP/s, which count an FMA twice); launch time from "
+                                "HIP events around each launch over the timed steps"},
     }
     if not args.no_cpu_baseline:
         cb = cpu_baseline(c, ev, axes)
