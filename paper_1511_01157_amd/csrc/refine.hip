@@ -3,7 +3,7 @@
 // Chi-square gradient.  The profiled chi-square (Eqs. 5-6 of McDougall & Albrow 2015;
 // sec. 4.2 bilinear map sampling) has (F_s, F_b) at their exact minimisers, so by the
 // envelope theorem d chi2/d theta = -2 F_s sum w r dA/d theta with r = F - F_s A - F_b.
-// One 256-lane workgroup per candidate (four wavefronts over the points, so a few
+// One 128-lane workgroup per candidate (two wavefronts over the points, so a few
 // thousand candidates still fill the chip) samples each point once and accumulates in
 // FP64 the normal-equation sums with, for the directions D below, sum w D, sum w b D
 // and sum w (F - Fbar) D; the fit then gives (F_s, F_b) and the sums
@@ -55,8 +55,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV])
   __syncthreads();
 }
 
-// One workgroup (GRAD_THREADS lanes over the points) per candidate.
-constexpr int GRAD_THREADS = 256;
+// One workgroup (GRAD_THREADS lanes over the points) per candidate; each thread takes
+// GSU points per iteration.
+#ifndef MORSE_GRAD_THREADS
+#define MORSE_GRAD_THREADS 128
+#endif
+#ifndef MORSE_GSU
+#define MORSE_GSU 2
+#endif
+constexpr int GRAD_THREADS = MORSE_GRAD_THREADS;
+constexpr int GSU = MORSE_GSU;
 
 struct Eval {
   double chi2, Fs, Fb;
@@ -131,7 +139,7 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   double acc[kSums];
 #pragma unroll
   for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
-  // Two points per thread and iteration (i and i + GRAD_THREADS, so each thread still
+  // GSU points per thread and iteration (i, i + GRAD_THREADS, ..., so each thread still
   // takes its points in increasing order): all their loads are issued before use.
   auto add_point = [&](const Loc& l, const Quad& v, double wi, double wfc) {
     const float e0 = v.v10 - v.v00, e1 = v.v11 - v.v01;
@@ -159,21 +167,30 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
                              (double)l.zx * dAy - (double)l.zy * dAx};
 #pragma unroll
     for (int k = 0; k < kDirs; ++k) {
-      const double wD = wi * D[k];
-      acc[3 + 3 * k] += wD;
-      acc[4 + 3 * k] = fma(wD, b, acc[4 + 3 * k]);
+      acc[3 + 3 * k] = fma(wi, D[k], acc[3 + 3 * k]);
+      acc[4 + 3 * k] = fma(wb, D[k], acc[4 + 3 * k]);
       acc[5 + 3 * k] = fma(wfc, D[k], acc[5 + 3 * k]);
     }
   };
-  for (int32_t i0 = tid; i0 < np; i0 += 2 * GRAD_THREADS) {
-    const bool has1 = i0 + GRAD_THREADS < np;
-    const uint32_t u0 = (uint32_t)i0, u1 = has1 ? (uint32_t)(i0 + GRAD_THREADS) : u0;
-    const Loc l0 = locate(m, ldg(t, u0), t0p, iE, ca, sa, bx, by);
-    const Loc l1 = locate(m, ldg(t, u1), t0p, iE, ca, sa, bx, by);
-    const Quad v0 = ldq(m.quad, l0.q), v1 = ldq(m.quad, l1.q);
-    const double w0 = ldg(w, u0), f0 = ldg(wFc, u0), w1 = ldg(w, u1), f1 = ldg(wFc, u1);
-    add_point(l0, v0, w0, f0);
-    if (has1) add_point(l1, v1, w1, f1);
+  for (int32_t i0 = tid; i0 < np; i0 += GSU * GRAD_THREADS) {
+    uint32_t u[GSU];
+    Loc l[GSU];
+    Quad v[GSU];
+    double wv[GSU], fv[GSU];
+#pragma unroll
+    for (int k = 0; k < GSU; ++k)  // a point past the end repeats i0 (and is not added)
+      u[k] = i0 + k * GRAD_THREADS < np ? (uint32_t)(i0 + k * GRAD_THREADS) : (uint32_t)i0;
+#pragma unroll
+    for (int k = 0; k < GSU; ++k) l[k] = locate(m, ldg(t, u[k]), t0p, iE, ca, sa, bx, by);
+#pragma unroll
+    for (int k = 0; k < GSU; ++k) {
+      v[k] = ldq(m.quad, l[k].q);
+      wv[k] = ldg(w, u[k]);
+      fv[k] = ldg(wFc, u[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < GSU; ++k)
+      if (k == 0 || i0 + k * GRAD_THREADS < np) add_point(l[k], v[k], wv[k], fv[k]);
   }
   block_sum<kSums>(acc, s_part);
   const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2]);
