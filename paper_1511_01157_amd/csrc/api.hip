@@ -1265,7 +1265,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   const size_t i_anchor = pl.add(32 * n), i_p = pl.add(16 * n), i_pt = pl.add(16 * n),
                i_f = pl.add(8 * n), i_g = pl.add(32 * n), i_d = pl.add(32 * n), i_step = pl.add(8 * n),
                i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
-               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(16 * n), i_ft = pl.add(8 * n),
+               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(12 * n), i_ft = pl.add(8 * n),
                i_gt = pl.add(32 * n), i_tc = pl.add(sizeof(TrajC) * (size_t)n),
                i_tE = pl.add(8 * (size_t)n);
   if ((rc = reserve(ctx, pl.total()))) return rc;
@@ -1293,9 +1293,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   s.R = (double*)pl.ptr(ctx, i_R);
   int32_t* ints = (int32_t*)pl.ptr(ctx, i_int);
   s.nhist = ints;
-  s.start = ints + n;
-  s.nls = ints + 2 * n;
-  s.active = ints + 3 * n;
+  s.nls = ints + n;
+  s.active = ints + 2 * n;
   a.n = n;
   a.anchor = anchor;
   a.pt = s.pt;

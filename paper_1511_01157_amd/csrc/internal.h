@@ -428,11 +428,10 @@ struct LbfgsState {
   double* g;             // [n][4]
   double* d;             // [n][4]
   double* step;          // [n]
-  double* S;             // [n][m][4]
+  double* S;             // [n][m][4] history pairs, oldest first
   double* Y;             // [n][m][4]
   double* R;             // [n][m]
   int32_t* nhist;        // [n]
-  int32_t* start;        // [n]
   int32_t* nls;          // [n]
   int32_t* active;       // [n]
 };

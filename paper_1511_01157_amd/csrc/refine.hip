@@ -245,24 +245,10 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   return out;
 }
 
-// Natural parameters of candidate c (from its FP64 row, or from the L-BFGS anchor and
-// binary32 displacement) -> trajectory constants, FP64 trigonometry rounded once.
-__device__ void prep_candidate(const GradArgs& a, int64_t c) {
-  double t0, u0, tE, al;
-  if (a.anchor) {
-    const double* an = a.anchor + 4 * c;
-    const float* p = a.pt + 4 * c;
-    t0 = an[0] + (double)p[0] * an[2];
-    u0 = an[1] + (double)p[1];
-    tE = an[2] * exp((double)p[2]);
-    al = an[3] + (double)p[3];
-  } else {
-    const double* p = a.params + 4 * c;
-    t0 = p[0];
-    u0 = p[1];
-    tE = p[2];
-    al = p[3];
-  }
+// Trajectory constants of natural parameters (t0, u0, tE, alpha), FP64 trigonometry
+// rounded once, written for candidate c.
+__device__ void write_natural(const GradArgs& a, int64_t c, double t0, double u0, double tE,
+                              double al) {
   double sn, cs;
   sincos(al, &sn, &cs);
   TrajC r;
@@ -275,6 +261,23 @@ __device__ void prep_candidate(const GradArgs& a, int64_t c) {
   r.pad = 0.0f;
   a.tc[c] = r;
   a.tEv[c] = tE;
+}
+
+// Natural parameters from the L-BFGS anchor and binary32 displacement p.
+__device__ void write_traj(const GradArgs& a, int64_t c, const double* an, const float* p) {
+  write_natural(a, c, an[0] + (double)p[0] * an[2], an[1] + (double)p[1],
+                an[2] * exp((double)p[2]), an[3] + (double)p[3]);
+}
+
+// Candidate c's trajectory constants: from its FP64 row, or from its anchor and trial
+// displacement.
+__device__ void prep_candidate(const GradArgs& a, int64_t c) {
+  if (a.anchor) {
+    write_traj(a, c, a.anchor + 4 * c, a.pt + 4 * c);
+  } else {
+    const double* p = a.params + 4 * c;
+    write_natural(a, c, p[0], p[1], p[2], p[3]);
+  }
 }
 
 __global__ void k_cand_prep(GradArgs a) {
@@ -306,130 +309,171 @@ __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   }
 }
 
-// New search direction at the accepted point (p, g); sets d, step, nls, pt and may
-// stop the candidate when the trial would not move it.  M >= m bounds the history;
-// the pairs are loaded into registers up front (one memory latency instead of one per
-// pair) and the two loops run over compile-time slots in the same order as a loop
-// over the nh stored pairs.
+// One candidate's L-BFGS state, held in registers for one update.  The history pairs
+// are stored oldest first (an accepted pair past m shifts the others down), so all of
+// them, like every other field, load at once at the start of the update, with no load
+// waiting on another or on a store.  M >= m bounds the history; loops run over
+// compile-time slots in the order of a loop over the nh stored pairs.
 template <int M>
-__device__ void new_direction(const LbfgsState& s, int64_t c) {
-  const int nh = s.nhist[c];
-  const int st = s.start[c];
-  double Sr[M][4], Yr[M][4], Rr[M];
+struct Regs {
+  double S[M][4], Y[M][4], R[M];
+  double g[4], d[4], f, step;
+  float p[4], pt[4];
+  int nh, nls;
+};
+
+template <int M>
+__device__ __forceinline__ void load_regs(const LbfgsState& s, int64_t c, Regs<M>& q) {
 #pragma unroll
-  for (int h = 0; h < M; ++h) {
-    if (h < nh) {
-      const int64_t slot = c * s.m + (st + h) % s.m;
+  for (int h = 0; h < M; ++h) {  // slots past nh hold stale values and are never used
+    const int64_t row = c * s.m + min(h, s.m - 1);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Sr[h][k] = s.S[slot * 4 + k];
-        Yr[h][k] = s.Y[slot * 4 + k];
-      }
-      Rr[h] = s.R[slot];
+    for (int k = 0; k < 4; ++k) {
+      q.S[h][k] = s.S[row * 4 + k];
+      q.Y[h][k] = s.Y[row * 4 + k];
     }
+    q.R[h] = s.R[row];
   }
-  double g[4], q[4], r[4], d[4], alph[M];
-  for (int k = 0; k < 4; ++k) g[k] = s.g[4 * c + k];
-  for (int k = 0; k < 4; ++k) q[k] = g[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    q.g[k] = s.g[4 * c + k];
+    q.d[k] = s.d[4 * c + k];
+    q.p[k] = s.p[4 * c + k];
+    q.pt[k] = s.pt[4 * c + k];
+  }
+  q.f = s.f[c];
+  q.step = s.step[c];
+  q.nh = s.nhist[c];
+  q.nls = s.nls[c];
+}
+
+// New search direction at the accepted point (q.p, q.g); stores d, step, nls, pt and
+// may stop the candidate when the trial would not move it.  Returns whether it moved.
+template <int M>
+__device__ bool new_direction(const LbfgsState& s, int64_t c, Regs<M>& q) {
+  const int nh = q.nh;
+  double r[4], d[4], qq[4], alph[M];
+  for (int k = 0; k < 4; ++k) qq[k] = q.g[k];
 #pragma unroll
   for (int h = M - 1; h >= 0; --h) {
     if (h < nh) {
-      const double a = Rr[h] * dot4(Sr[h], q);
+      const double a = q.R[h] * dot4(q.S[h], qq);
       alph[h] = a;
-      for (int k = 0; k < 4; ++k) q[k] = q[k] - a * Yr[h][k];
+      for (int k = 0; k < 4; ++k) qq[k] = qq[k] - a * q.Y[h][k];
     }
   }
-  const double gn = sqrt(dot4(g, g));
+  const double gn = sqrt(dot4(q.g, q.g));
   double gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
 #pragma unroll
   for (int h = 0; h < M; ++h)
-    if (h == nh - 1) gamma = dot4(Sr[h], Yr[h]) / dot4(Yr[h], Yr[h]);
-  for (int k = 0; k < 4; ++k) r[k] = gamma * q[k];
+    if (h == nh - 1) gamma = dot4(q.S[h], q.Y[h]) / dot4(q.Y[h], q.Y[h]);
+  for (int k = 0; k < 4; ++k) r[k] = gamma * qq[k];
 #pragma unroll
   for (int h = 0; h < M; ++h) {
     if (h < nh) {
-      const double b = Rr[h] * dot4(Yr[h], r);
-      for (int k = 0; k < 4; ++k) r[k] = r[k] + Sr[h][k] * (alph[h] - b);
+      const double b = q.R[h] * dot4(q.Y[h], r);
+      for (int k = 0; k < 4; ++k) r[k] = r[k] + q.S[h][k] * (alph[h] - b);
     }
   }
   for (int k = 0; k < 4; ++k) d[k] = -r[k];
-  const double gd = dot4(g, d);
+  const double gd = dot4(q.g, d);
   bool finite = true;
   for (int k = 0; k < 4; ++k) finite = finite && isfinite(d[k]);
   if (!(gd < 0.0) || !finite) {
+    q.nh = 0;
     s.nhist[c] = 0;
-    s.start[c] = 0;
     gamma = gn > 0.0 ? 1e-2 / gn : 0.0;
-    for (int k = 0; k < 4; ++k) d[k] = -(gamma * g[k]);
+    for (int k = 0; k < 4; ++k) d[k] = -(gamma * q.g[k]);
   }
   s.step[c] = 1.0;
   s.nls[c] = 0;
   bool moved = false;
   for (int k = 0; k < 4; ++k) {
     s.d[4 * c + k] = d[k];
-    const float pk = s.p[4 * c + k];
-    const float v = (float)((double)pk + 1.0 * d[k]);
+    const float v = (float)((double)q.p[k] + 1.0 * d[k]);
+    q.pt[k] = v;
     s.pt[4 * c + k] = v;
-    moved = moved || (v != pk);
+    moved = moved || (v != q.p[k]);
   }
   if (!moved) s.active[c] = 0;
+  return moved;
 }
 
 // One update of the state machine for candidate c given the evaluation (ft, gt) at
-// its trial point; returns whether the candidate is still active.
+// its trial point; returns whether the candidate is still active (its next trial
+// point is then q.pt).
 template <int M>
 __device__ bool lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double ft,
-                           const double* gt) {
+                           const double* gt, Regs<M>& q) {
   if (round == 0) {
     for (int k = 0; k < 4; ++k) {
-      s.p[4 * c + k] = s.pt[4 * c + k];
-      s.g[4 * c + k] = gt[k];
+      q.p[k] = q.pt[k];
+      q.g[k] = gt[k];
+      s.p[4 * c + k] = q.p[k];
+      s.g[4 * c + k] = q.g[k];
     }
+    q.f = ft;
     s.f[c] = ft;
-    new_direction<M>(s, c);
-    return s.active[c] != 0;
+    q.nh = 0;
+    return new_direction<M>(s, c, q);
   }
-  double g[4], d[4];
-  for (int k = 0; k < 4; ++k) {
-    g[k] = s.g[4 * c + k];
-    d[k] = s.d[4 * c + k];
-  }
-  const double gd = dot4(g, d);
-  const double t = s.step[c];
-  if (isfinite(ft) && ft <= s.f[c] + (s.c1 * t) * gd) {
+  const double gd = dot4(q.g, q.d);
+  const double t = q.step;
+  if (isfinite(ft) && ft <= q.f + (s.c1 * t) * gd) {
     double sv[4], yv[4];
     for (int k = 0; k < 4; ++k) {
-      sv[k] = (double)s.pt[4 * c + k] - (double)s.p[4 * c + k];
-      yv[k] = gt[k] - g[k];
+      sv[k] = (double)q.pt[k] - (double)q.p[k];
+      yv[k] = gt[k] - q.g[k];
     }
     const double sy = dot4(sv, yv);
     if (sy > 1e-12 * sqrt(dot4(sv, sv)) * sqrt(dot4(yv, yv))) {
-      const int nh = s.nhist[c];
-      const int st = s.start[c];
-      int slot;
-      if (nh < s.m) {
-        slot = (st + nh) % s.m;
-        s.nhist[c] = nh + 1;
-      } else {
-        slot = st;
-        s.start[c] = (st + 1) % s.m;
+      const double rho = 1.0 / sy;
+      const int m = s.m;
+      if (q.nh == m) {  // full: drop the oldest pair
+#pragma unroll
+        for (int h = 0; h + 1 < M; ++h)
+          if (h + 1 < m) {
+            for (int k = 0; k < 4; ++k) {
+              q.S[h][k] = q.S[h + 1][k];
+              q.Y[h][k] = q.Y[h + 1][k];
+            }
+            q.R[h] = q.R[h + 1];
+          }
+        q.nh = m - 1;
       }
-      const int64_t row = c * s.m + slot;
-      for (int k = 0; k < 4; ++k) {
-        s.S[row * 4 + k] = sv[k];
-        s.Y[row * 4 + k] = yv[k];
-      }
-      s.R[row] = 1.0 / sy;
+#pragma unroll
+      for (int h = 0; h < M; ++h)
+        if (h == q.nh) {
+          for (int k = 0; k < 4; ++k) {
+            q.S[h][k] = sv[k];
+            q.Y[h][k] = yv[k];
+          }
+          q.R[h] = rho;
+        }
+      q.nh += 1;
+#pragma unroll
+      for (int h = 0; h < M; ++h)  // write the history back, oldest first
+        if (h < q.nh) {
+          const int64_t row = c * s.m + h;
+          for (int k = 0; k < 4; ++k) {
+            s.S[row * 4 + k] = q.S[h][k];
+            s.Y[row * 4 + k] = q.Y[h][k];
+          }
+          s.R[row] = q.R[h];
+        }
+      s.nhist[c] = q.nh;
     }
     for (int k = 0; k < 4; ++k) {
-      s.p[4 * c + k] = s.pt[4 * c + k];
-      s.g[4 * c + k] = gt[k];
+      q.p[k] = q.pt[k];
+      q.g[k] = gt[k];
+      s.p[4 * c + k] = q.p[k];
+      s.g[4 * c + k] = q.g[k];
     }
+    q.f = ft;
     s.f[c] = ft;
-    new_direction<M>(s, c);
-    return s.active[c] != 0;
+    return new_direction<M>(s, c, q);
   }
-  const int n = s.nls[c] + 1;
+  const int n = q.nls + 1;
   s.nls[c] = n;
   if (n >= s.max_ls) {
     s.active[c] = 0;
@@ -437,7 +481,10 @@ __device__ bool lbfgs_step(const LbfgsState& s, int64_t c, int32_t round, double
   }
   const double tn = t * s.shrink;
   s.step[c] = tn;
-  for (int k = 0; k < 4; ++k) s.pt[4 * c + k] = (float)((double)s.p[4 * c + k] + tn * d[k]);
+  for (int k = 0; k < 4; ++k) {
+    q.pt[k] = (float)((double)q.p[k] + tn * q.d[k]);
+    s.pt[4 * c + k] = q.pt[k];
+  }
   return true;
 }
 
@@ -452,7 +499,6 @@ __global__ void k_refine_init(LbfgsState s, GradArgs a, const double* params,
     s.pt[4 * c + k] = 0.0f;
   }
   s.nhist[c] = 0;
-  s.start[c] = 0;
   s.nls[c] = 0;
   s.active[c] = 1;
   prep_candidate(a, c);
@@ -466,11 +512,16 @@ __global__ __launch_bounds__(64) void k_lbfgs_update(LbfgsState s, GradArgs a, i
                                double* __restrict__ chi2_init) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= s.n || !s.active[c]) return;
-  double g[4];
-  for (int k = 0; k < 4; ++k) g[k] = gt[4 * c + k];
+  double g[4], an[4];
+  for (int k = 0; k < 4; ++k) {
+    g[k] = gt[4 * c + k];
+    an[k] = s.anchor[4 * c + k];
+  }
   const double f = ft[c];
+  Regs<M> q;
+  load_regs<M>(s, c, q);
   if (round == 0 && chi2_init) chi2_init[c] = f;
-  if (lbfgs_step<M>(s, c, round, f, g)) prep_candidate(a, c);
+  if (lbfgs_step<M>(s, c, round, f, g, q)) write_traj(a, c, an, q.pt);
 }
 
 __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
