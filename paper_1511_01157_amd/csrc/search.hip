@@ -529,52 +529,54 @@ __global__ __launch_bounds__(TK_THREADS) void k_tk_collect(const double* __restr
   }
 }
 
-__global__ __launch_bounds__(1024) void k_tk_sort(const double* __restrict__ chi2, int64_t seg_len,
-                                                  int32_t k, const uint64_t* __restrict__ keys,
-                                                  const uint32_t* __restrict__ idx,
-                                                  double* __restrict__ out_chi2,
-                                                  int64_t* __restrict__ out_idx) {
+// Final order of the k selected (key, index) pairs of a segment by rank: element e
+// goes to position #{(key, index) < (key_e, index_e)} (the pairs are distinct, so the
+// ranks are a permutation).  A workgroup stages the segment's pairs in LDS and ranks
+// TKR_ELEMS of them, four threads per element each counting over a quarter of the
+// pairs (the same LDS word is read by a whole wavefront at once).  Positions past the
+// segment's length get index -1 and NaN.
+constexpr int TKR_ELEMS = 64;
+__global__ __launch_bounds__(256) void k_tk_rank(const double* __restrict__ chi2, int64_t seg_len,
+                                                 int32_t k, const uint64_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ idx,
+                                                 double* __restrict__ out_chi2,
+                                                 int64_t* __restrict__ out_idx) {
   __shared__ uint64_t lk[TK_MAXK];
   __shared__ uint32_t li[TK_MAXK];
-  const int64_t seg = blockIdx.x;
+  __shared__ uint32_t part[4][TKR_ELEMS];
+  const int64_t seg = blockIdx.y;
   const int tid = threadIdx.x;
-  const int64_t keff = min((int64_t)k, seg_len);
-  int n2 = 1;
-  while (n2 < keff) n2 <<= 1;
-  for (int q = tid; q < n2; q += blockDim.x) {
-    lk[q] = (q < keff) ? keys[seg * k + q] : ~0ull;
-    li[q] = (q < keff) ? idx[seg * k + q] : 0xffffffffu;
+  const int keff = (int)min((int64_t)k, seg_len);
+  for (int q = tid; q < keff; q += blockDim.x) {
+    lk[q] = keys[seg * k + q];
+    li[q] = idx[seg * k + q];
   }
   __syncthreads();
-  for (int size = 2; size <= n2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int q = tid; q < n2; q += blockDim.x) {
-        const int r = q ^ stride;
-        if (r > q) {
-          const bool up = (q & size) == 0;
-          const uint64_t ka = lk[q], kb = lk[r];
-          const uint32_t ia = li[q], ib = li[r];
-          const bool a_gt_b = (ka > kb) || (ka == kb && ia > ib);
-          if (a_gt_b == up) {
-            lk[q] = kb;
-            lk[r] = ka;
-            li[q] = ib;
-            li[r] = ia;
-          }
-        }
-      }
-      __syncthreads();
+  const int el = tid % TKR_ELEMS, quarter = tid / TKR_ELEMS;
+  const int e = blockIdx.x * TKR_ELEMS + el;
+  uint32_t count = 0;
+  if (e < keff) {
+    const uint64_t mk = lk[e];
+    const uint32_t mi = li[e];
+    const int j0 = (int)((int64_t)keff * quarter / 4), j1 = (int)((int64_t)keff * (quarter + 1) / 4);
+    for (int j = j0; j < j1; ++j) {
+      const uint64_t kj = lk[j];
+      count += (kj < mk || (kj == mk && li[j] < mi)) ? 1u : 0u;
     }
   }
-  const double* base = chi2 + seg * seg_len;
-  for (int q = tid; q < k; q += blockDim.x) {
-    if (q < keff && (int64_t)li[q] < seg_len) {
-      out_idx[seg * k + q] = (int64_t)li[q];
-      out_chi2[seg * k + q] = base[li[q]];
-    } else {
-      out_idx[seg * k + q] = -1;
-      out_chi2[seg * k + q] = __longlong_as_double(0x7ff8000000000000ll);
-    }
+  part[quarter][el] = count;
+  __syncthreads();
+  if (quarter != 0 || e >= k) return;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  if (e < keff) {
+    const uint32_t rank = part[0][el] + part[1][el] + part[2][el] + part[3][el];
+    const uint32_t ie = li[e];
+    const bool valid = (int64_t)ie < seg_len;
+    out_idx[seg * k + rank] = valid ? (int64_t)ie : -1;
+    out_chi2[seg * k + rank] = valid ? chi2[seg * seg_len + ie] : nan;
+  } else {
+    out_idx[seg * k + e] = -1;
+    out_chi2[seg * k + e] = nan;
   }
 }
 
@@ -720,8 +722,8 @@ hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32
     hipLaunchKernelGGL(k_tk_pick, dim3((unsigned)n_seg), dim3(TK_THREADS), 0, st, state, hist, pass);
   }
   hipLaunchKernelGGL(k_tk_collect, grid, dim3(TK_THREADS), 0, st, chi2, seg_len, k, state, keys, idx);
-  hipLaunchKernelGGL(k_tk_sort, dim3((unsigned)n_seg), dim3(1024), 0, st, chi2, seg_len, k, keys, idx,
-                     out_chi2, out_idx);
+  hipLaunchKernelGGL(k_tk_rank, dim3((unsigned)((k + TKR_ELEMS - 1) / TKR_ELEMS), (unsigned)n_seg),
+                     dim3(256), 0, st, chi2, seg_len, k, keys, idx, out_chi2, out_idx);
   return hipGetLastError();
 }
 
