@@ -8,9 +8,12 @@ search of the 64x64x16x8 = 524288-trajectory grid against a 3000-point light cur
 with a top-4096 selection, and 50 L-BFGS rounds on those 4096 candidates.
 
 value = grid-search light-curve point-evaluations per second of the whole step (the
-map build and the refinement are charged to the same clock).  The JSON line also
-carries rays/s of the ray kernel, the batched and plain search rates, the adjoint
-rate, the roofline of the dominant kernel and the CPU oracle timed on this host.
+map build and the refinement are charged to the same clock), steps one after another.
+The line also reports the step time with consecutive steps pipelined (the map of step
+i + 1 built on a second stream while step i is searched and refined; --pipelined makes
+that the timed mode), rays/s of the ray kernel, the batched and plain search rates,
+the adjoint rate, the roofline of the dominant kernel and the CPU oracle timed on this
+host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -82,6 +85,9 @@ def parse():
     ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--pipelined", action="store_true",
+                    help="time steps with the next step's map built on a second stream "
+                         "(default: each step's map build, search and refinement in turn)")
     # profiling aids: a plain device copy of known size (the reference for scaling
     # the FETCH_SIZE / WRITE_SIZE counters), and text summaries of rocprofv3 output
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -204,7 +210,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # stream_b runs the search and the refinement; stream_a builds maps, in the
+    # pipelined mode the map of step i + 1 while stream_b works on step i
     stream = torch.cuda.Stream(device=dev)
+    stream_a = torch.cuda.Stream(device=dev)
+    ctx_b = M.Context.bound(stream)
+    ctx_a = M.Context.bound(stream_a)
     c = W.config("large")
     ev = W.load_lightcurve("large")
     axes = W.grid_axes("large")
@@ -217,16 +228,16 @@ def main():
     with torch.cuda.stream(stream):
         lcs = M.LightCurveBatch.from_events([ev], dev)
         trajs = M.grid_trajectories(*axes)
-        counts = torch.empty((c["window"][5], c["window"][4]), dtype=torch.int32, device=dev)
-        amap = torch.empty((c["window"][5], c["window"][4]), dtype=torch.float32, device=dev)
+        shape = (c["window"][5], c["window"][4])
+        counts = torch.empty(shape, dtype=torch.int32, device=dev)
+        amap = torch.empty(shape, dtype=torch.float32, device=dev)        # read by the search
+        amap_build = torch.empty(shape, dtype=torch.float32, device=dev)  # written by stream_a
         maps = [(amap, c["window"])]
         # the batched search shape comes from the autotuner (setup, not timed); the
         # map it tunes on is built once here
-        M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts)
-        M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap)
-        tuned = M.autotune(maps, lcs, trajs)
-        ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(5)]
-                   for _ in range(args.steps)]
+        M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts, ctx=ctx_b)
+        M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap, ctx=ctx_b)
+        tuned = M.autotune(maps, lcs, trajs, ctx=ctx_b)
 
         # step buffers, allocated once so the captured graphs replay every step
         sbuf = {}
@@ -235,64 +246,122 @@ def main():
                 torch.empty(k, dtype=torch.int32, device=dev))
         rbuf = (torch.empty(k, dtype=torch.float64, device=dev),
                 torch.empty(k, dtype=torch.float64, device=dev))
+        e_built = torch.cuda.Event()
+        e_copied = torch.cuda.Event()
 
-        def step(evs=None):
-            mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
+        def build(pipelined, evs=None):
+            """Ray shooting + normalisation of one step's map (stream_a when pipelined:
+            into amap_build, after the search has copied out the previous map)."""
+            if not pipelined:
+                mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
+                mark(0)
+                M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts, ctx=ctx_b)
+                mark(1)
+                M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap, ctx=ctx_b)
+                mark(2)
+                return
+            mark = (lambda j: evs[j].record(stream_a)) if evs else (lambda j: None)
             mark(0)
-            M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts)
+            M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts, ctx=ctx_a)
+            stream_a.wait_event(e_copied)
             mark(1)
-            M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap)
+            M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap_build, ctx=ctx_a)
             mark(2)
-            r = M.search(maps, lcs, trajs, "batched", chi2=False, top_k=k, out=sbuf)
-            sbuf.update(r)
+            e_built.record(stream_a)
+
+        def take_map():
+            """Stream_b takes the built map (a 16 MiB device copy) and frees amap_build."""
+            stream.wait_event(e_built)
+            amap.copy_(amap_build)
+            e_copied.record(stream)
+
+        def solve(evs=None):
+            mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
             mark(3)
-            P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1, out=cand)
-            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps,
-                                         inplace=True, chi2_out=rbuf)
+            r = M.search(maps, lcs, trajs, "batched", chi2=False, top_k=k, out=sbuf, ctx=ctx_b)
+            sbuf.update(r)
             mark(4)
+            P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1, out=cand, ctx=ctx_b)
+            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps,
+                                         inplace=True, chi2_out=rbuf, ctx=ctx_b)
+            mark(5)
             return r, out, chi2, chi2_0
 
+        def run(n, pipelined, ev_sets=None):
+            """n whole steps; pipelined: the map of step i + 1 is built on stream_a
+            while stream_b searches and refines step i."""
+            evs = (lambda i: ev_sets[i]) if ev_sets else (lambda i: None)
+            res = None
+            if not pipelined:
+                for i in range(n):
+                    build(False, evs(i))
+                    res = solve(evs(i))
+                return res
+            build(True, evs(0))
+            for i in range(n):
+                take_map()
+                if i + 1 < n:
+                    build(True, evs(i + 1))
+                res = solve(evs(i))
+            return res
+
+        def timed(n, pipelined):
+            # per step: build start, rays done, map done (build stream); search start,
+            # search done, refinement done (search stream)
+            ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(n)]
+            t_start = torch.cuda.Event(enable_timing=True)
+            t_end = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t_start.record(stream_a if pipelined else stream)
+            wall0 = time.perf_counter()
+            res = run(n, pipelined, ev_sets)
+            t_end.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - wall0
+            ms = t_start.elapsed_time(t_end) / n
+            stage = np.mean([[e[j].elapsed_time(e[j + 1]) for j in (0, 1, 3, 4)] for e in ev_sets],
+                            axis=0)
+            return ms, stage, wall, res
+
+        pipelined = args.pipelined
         # Warm-up with every kernel family timed (HIP events around each launch on the
-        # library's stream) picks the kernel with the most time per step; the timed
+        # library's streams) picks the kernel with the most time per step; the timed
         # steps then time that kernel only.  One untimed step in between captures the
-        # graphs of the other entry points outside the timed region.
-        ctx = M.Context.get(0)
-        fams = {"k_rayshoot": M.KERNEL_RAYSHOOT, "k_search_batched": M.KERNEL_SEARCH,
-                "k_chi2_grad": M.KERNEL_GRADIENT}
-        ctx.set_timing(fams.values())
+        # graphs of the entry points outside the timed region.
+        fams = {"k_rayshoot": (M.KERNEL_RAYSHOOT, ctx_a if pipelined else ctx_b),
+                "k_search_batched": (M.KERNEL_SEARCH, ctx_b),
+                "k_chi2_grad": (M.KERNEL_GRADIENT, ctx_b)}
+        for fam, cx in fams.values():
+            cx.set_timing([f for f, x in fams.values() if x is cx])
         n_warm = max(1, args.warmup)
-        for _ in range(n_warm):
-            step()
-        per_step = {n: ctx.kernel_time(f, reset=True)[0] / n_warm for n, f in fams.items()}
+        run(n_warm, pipelined)
+        per_step = {n: cx.kernel_time(f, reset=True)[0] / n_warm for n, (f, cx) in fams.items()}
         dom = max(per_step, key=per_step.get)
-        ctx.set_timing([fams[dom]])
-        step()
+        dom_fam, dom_ctx = fams[dom]
+        ctx_a.set_timing([])
+        ctx_b.set_timing([])
+        dom_ctx.set_timing([dom_fam])
+        run(1, pipelined)
         torch.cuda.synchronize()
-        ctx.kernel_time(fams[dom], reset=True)
-        t_start = torch.cuda.Event(enable_timing=True)
-        t_end = torch.cuda.Event(enable_timing=True)
-        t_start.record(stream)
-        wall0 = time.perf_counter()
-        for i in range(args.steps):
-            res = step(ev_sets[i])
-        t_end.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
-        ms_step = t_start.elapsed_time(t_end) / args.steps
-        stage = np.mean([[e[j].elapsed_time(e[j + 1]) for j in range(4)] for e in ev_sets], axis=0)
-        dom_total_ms, dom_launches = ctx.kernel_time(fams[dom], reset=True)
-        ctx.set_timing([])
+        dom_ctx.kernel_time(dom_fam, reset=True)
+        ms_step, stage, wall, res = timed(args.steps, pipelined)
+        dom_total_ms, dom_launches = dom_ctx.kernel_time(dom_fam, reset=True)
+        dom_ctx.set_timing([])
         r, out, chi2, chi2_0 = res
         improved = float((chi2 <= chi2_0).float().mean())
+        # the other schedule of the same steps, for reference
+        run(1, not pipelined)
+        other_ms = timed(args.steps, not pipelined)[0]
+        serial_ms, pipe_ms = (other_ms, ms_step) if pipelined else (ms_step, other_ms)
 
         plain_ms = None
         if not args.no_plain:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
-            pbuf = M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k)
+            pbuf = M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, ctx=ctx_b)
             e0.record(stream)
             for _ in range(3):
-                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, out=pbuf)
+                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, out=pbuf, ctx=ctx_b)
             e1.record(stream)
             torch.cuda.synchronize()
             plain_ms = e0.elapsed_time(e1) / 3
@@ -314,6 +383,9 @@ def main():
         "unit": "point-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "pipelined": pipelined,
+        "serial_ms_per_step": serial_ms,
+        "pipelined_ms_per_step": pipe_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 samples, f64 sums",
         "data": "synthetic (seeded light curve, oracle-computed magnifications)",

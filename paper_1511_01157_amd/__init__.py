@@ -74,6 +74,7 @@ class Context:
 
     @classmethod
     def get(cls, device) -> "Context":
+        """The device's shared context, enqueuing on torch's current stream."""
         dev = torch.device(device).index if not isinstance(device, int) else device
         dev = torch.cuda.current_device() if dev is None else dev
         ctx = cls._by_device.get(dev)
@@ -82,7 +83,18 @@ class Context:
         ctx.follow_stream()
         return ctx
 
+    @classmethod
+    def bound(cls, stream: torch.cuda.Stream) -> "Context":
+        """A context of its own (workspace, graphs, metadata) that always enqueues on
+        `stream`: pass it as ``ctx=`` to run work concurrently with another context."""
+        with torch.cuda.stream(stream):
+            ctx = Context(stream.device.index)
+        ctx._bound = True
+        return ctx
+
     def follow_stream(self):
+        if getattr(self, "_bound", False):
+            return
         s = torch.cuda.current_stream(self.device).cuda_stream
         if s != self.stream:
             self.check(self.lib.morse_ctx_set_stream(self.handle, ctypes.c_void_p(s or None)))
@@ -119,9 +131,9 @@ def _device_of(t):
 
 
 # ----------------------------------------------------------------------------- maps
-def rayshoot(s, q, rays, window, counts, rows=None, accumulate=False, stats=None):
+def rayshoot(s, q, rays, window, counts, rows=None, accumulate=False, stats=None, ctx=None):
     """Ray counts of lattice rows ``rows`` (default all) into ``counts`` (uint32 as int32)."""
-    ctx = Context.get(_device_of(counts))
+    ctx = ctx or Context.get(_device_of(counts))
     r0, r1 = rows if rows is not None else (0, int(rays[5]))
     ctx.check(ctx.lib.morse_rayshoot(ctx.handle, float(s), float(q), ctypes.byref(_grid(rays)),
                                      ctypes.byref(_grid(window)), int(r0), int(r1), _ptr(counts),
@@ -129,8 +141,8 @@ def rayshoot(s, q, rays, window, counts, rows=None, accumulate=False, stats=None
     return counts
 
 
-def normalize_convolve(counts, rays, window, rho=0.0, out=None):
-    ctx = Context.get(_device_of(counts))
+def normalize_convolve(counts, rays, window, rho=0.0, out=None, ctx=None):
+    ctx = ctx or Context.get(_device_of(counts))
     if out is None:
         out = torch.empty((int(window[5]), int(window[4])), dtype=torch.float32, device=counts.device)
     ctx.check(ctx.lib.morse_normalize_convolve(ctx.handle, _ptr(counts), ctypes.byref(_grid(rays)),
@@ -138,12 +150,12 @@ def normalize_convolve(counts, rays, window, rho=0.0, out=None):
     return out
 
 
-def build_map(s, q, rays, window, rho=0.0, device="cuda", out=None, counts=None, stats=False):
+def build_map(s, q, rays, window, rho=0.0, device="cuda", out=None, counts=None, stats=False, ctx=None):
     """Magnification map float32[ny, nx]; with stats=True also a dict of ray statistics."""
     dev = torch.device(device)
     if out is None:
         out = torch.empty((int(window[5]), int(window[4])), dtype=torch.float32, device=dev)
-    ctx = Context.get(_device_of(out))
+    ctx = ctx or Context.get(_device_of(out))
     st = MapStats() if stats else None
     ctx.check(ctx.lib.morse_build_map(ctx.handle, float(s), float(q), ctypes.byref(_grid(rays)),
                                       ctypes.byref(_grid(window)), float(rho), _ptr(counts),
@@ -221,7 +233,7 @@ def _map_views(maps):
 
 
 def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,
-           best=False, top_k=0, out=None):
+           best=False, top_k=0, out=None, ctx=None):
     """Chi-square of every trajectory on every map for every event.
 
     maps: list of (map tensor, window).  Returns a dict with the requested outputs:
@@ -231,7 +243,7 @@ def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False,
     the batched mode replays its captured graph only when all buffers are the same.
     """
     dev = lcs.t.device
-    ctx = Context.get(_device_of(lcs.t))
+    ctx = ctx or Context.get(_device_of(lcs.t))
     ne, nm, nt = lcs.n_events, len(maps), trajs.n
     want = {"chi2": ((ne, nm, nt), torch.float64) if chi2 else None,
             "fs": ((ne, nm, nt), torch.float64) if fs else None,
@@ -262,8 +274,8 @@ def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False,
     return res
 
 
-def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None):
-    ctx = Context.get(_device_of(lcs.t))
+def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None, ctx=None):
+    ctx = ctx or Context.get(_device_of(lcs.t))
     best = ctypes.c_int32(-1)
     views = _map_views(maps)
     lca = lcs.abi()
@@ -273,12 +285,12 @@ def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None):
     return best.value
 
 
-def candidates_from_topk(trajs, topk_idx, n_maps, out=None):
+def candidates_from_topk(trajs, topk_idx, n_maps, out=None, ctx=None):
     """Refinement candidates from a search's top-k: params [n_events*k, 4] float64,
     event and map index [n_events*k] int32 (written into ``out`` when given)."""
     ne, k = topk_idx.shape
     dev = topk_idx.device
-    ctx = Context.get(_device_of(topk_idx))
+    ctx = ctx or Context.get(_device_of(topk_idx))
     if out is not None:
         params, event, mapi = out
     else:
@@ -303,10 +315,10 @@ def _cand_args(params, event, map_index):
     return n
 
 
-def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True):
+def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True, ctx=None):
     """chi2 [n], grad [n, 4] (d/d t0, u0, tE, alpha), Fs [n], Fb [n]."""
     n = _cand_args(params, event, map_index)
-    ctx = Context.get(_device_of(params))
+    ctx = ctx or Context.get(_device_of(params))
     dev = params.device
     chi2 = torch.empty(n, dtype=torch.float64, device=dev)
     g = torch.empty((n, 4), dtype=torch.float64, device=dev) if grad else None
@@ -321,12 +333,12 @@ def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True):
 
 
 def refine(maps, lcs: LightCurveBatch, params, event, map_index, steps=50, history=8, max_ls=10,
-           c1=1e-4, shrink=0.5, inplace=False, chi2_out=None):
+           c1=1e-4, shrink=0.5, inplace=False, chi2_out=None, ctx=None):
     """Refined params, final chi2 and initial chi2.  With ``inplace`` the refined
     parameters overwrite ``params``; ``chi2_out`` = (chi2, chi2_init) buffers to reuse
     (the captured rounds replay only when every buffer is the same)."""
     n = _cand_args(params, event, map_index)
-    ctx = Context.get(_device_of(params))
+    ctx = ctx or Context.get(_device_of(params))
     out = params if inplace else params.clone()
     if chi2_out is not None:
         chi2, chi2_0 = chi2_out

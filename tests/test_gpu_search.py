@@ -208,3 +208,29 @@ def test_search_rejects_bad_arguments(tiny_oracle_map):
     with pytest.raises(M.MorseError) as e:
         M.search(m, M.LightCurveBatch.from_events([short], DEV), M.grid_trajectories([0.1], [0.0], [0.0], [10.0]))
     assert e.value.code == -1
+
+
+def test_bound_contexts_on_two_streams_match_the_default(tiny_oracle_map):
+    """Two contexts of their own, each bound to its own stream, give the same bits as
+    the shared context, also with their work interleaved."""
+    c = W.config("tiny")
+    maps = [(dmap(tiny_oracle_map[2]), c["window"])]
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    tr = M.grid_trajectories(*W.grid_axes("tiny"))
+    note("bound contexts: reference on the shared context")
+    ref = M.search(maps, lcs, tr, "batched", top_k=8)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(device=DEV), torch.cuda.Stream(device=DEV)
+    c1, c2 = M.Context.bound(s1), M.Context.bound(s2)
+    note("bound contexts: interleaved searches on two streams")
+    with torch.cuda.stream(s1):
+        r1 = M.search(maps, lcs, tr, "batched", top_k=8, ctx=c1)
+    with torch.cuda.stream(s2):
+        r2 = M.search(maps, lcs, tr, "plain", top_k=8, ctx=c2)
+    with torch.cuda.stream(s1):
+        r3 = M.search(maps, lcs, tr, "batched", top_k=8, ctx=c1, out=r1)
+    torch.cuda.synchronize()
+    for r in (r1, r2, r3):
+        for k in ref:
+            assert torch.equal(r[k], ref[k]), k
