@@ -145,7 +145,7 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 // tree, so the results do not depend on TU.  Arrays are addressed by 32-bit offsets
 // from uniform bases.
 #ifndef MORSE_SU
-#define MORSE_SU 2
+#define MORSE_SU 1
 #endif
 constexpr int SU = MORSE_SU;  // points per lane per iteration (tuning knob)
 
