@@ -38,6 +38,7 @@ const TuneCfg kTune[] = {
     {8, 4, 16, 2},  {8, 4, 16, 1},  {16, 4, 16, 2}, {8, 8, 8, 2},
     {32, 8, 8, 2},  {4, 4, 16, 2},  {16, 8, 4, 4},  {8, 2, 32, 2},
     {16, 4, 16, 4}, {32, 8, 8, 1},  {8, 2, 32, 1},  {64, 4, 8, 4},
+    {32, 8, 4, 4},  {16, 4, 8, 4},  {8, 8, 4, 4},   {16, 8, 2, 4},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 
@@ -908,7 +909,7 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
 std::string shape_class(const SearchPlan& sp) {
   auto bucket = [](double v) { return (int)std::floor(std::log2(std::max(v, 1.0))); };
   std::ostringstream s;
-  s << "gfx950|v2|maps" << bucket(sp.n_maps) << "|pts" << bucket((double)sp.n_pts / sp.n_events)
+  s << "gfx950|v3|maps" << bucket(sp.n_maps) << "|pts" << bucket((double)sp.n_pts / sp.n_events)
     << "|traj" << bucket((double)sp.n_traj) << "|ev" << bucket(sp.n_events);
   return s.str();
 }

@@ -30,7 +30,7 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Light-curve preparation, one workgroup per event: S_w and S_F with
-// Neumaier-compensated partial sums combined in a fixed order, Fbar = S_F/S_w, then
+// Neumaier-compensated partial sums combined by a fixed pairwise tree, Fbar = S_F/S_w, then
 // wFc = w (F - Fbar) per point and V = sum w (F - Fbar)^2 the same way.
 __device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
   double t = s + v;
@@ -41,12 +41,34 @@ __device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
   s = t;
 }
 
+// Pairwise tree over the workgroup's Neumaier partials (sum, compensation) held in
+// columns (2q, 2q + 1) of s_part, q < NQ, in a fixed order; every thread returns the
+// totals.
+template <int NQ>
+__device__ __forceinline__ void tree_totals(double (*s_part)[4], double (&tot)[NQ]) {
+  const int tid = threadIdx.x;
+  for (int half = blockDim.x / 2; half >= 1; half >>= 1) {
+    if (tid < half) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        double sm = s_part[tid][2 * q], c = s_part[tid][2 * q + 1];
+        neumaier_add(sm, c, s_part[tid + half][2 * q]);
+        s_part[tid][2 * q] = sm;
+        s_part[tid][2 * q + 1] = c + s_part[tid + half][2 * q + 1];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) tot[q] = s_part[0][2 * q] + s_part[0][2 * q + 1];
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_lc_prep(const double* __restrict__ F,
                                                  const double* __restrict__ w,
                                                  const int64_t* __restrict__ off,
                                                  double* __restrict__ wFc, double* __restrict__ sums) {
   __shared__ double s_part[256][4];
-  __shared__ double s_res[3];
   const int e = blockIdx.x;
   const int64_t a = off[e], b = off[e + 1];
   double s0 = 0, c0 = 0, s1 = 0, c1 = 0;
@@ -60,18 +82,10 @@ __global__ __launch_bounds__(256) void k_lc_prep(const double* __restrict__ F,
   s_part[threadIdx.x][2] = s1;
   s_part[threadIdx.x][3] = c1;
   __syncthreads();
-  if (threadIdx.x < 2) {
-    const int q = threadIdx.x;
-    double s = 0, c = 0;
-    for (int k = 0; k < (int)blockDim.x; ++k) {
-      neumaier_add(s, c, s_part[k][2 * q]);
-      neumaier_add(s, c, s_part[k][2 * q + 1]);
-    }
-    s_res[q] = s + c;
-  }
-  __syncthreads();
-  const double Sw = s_res[0];
-  const double Fbar = s_res[1] / Sw;
+  double t01[2];
+  tree_totals<2>(s_part, t01);
+  const double Sw = t01[0];
+  const double Fbar = t01[1] / Sw;
   double s2 = 0, c2 = 0;
   for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
     const double d = F[i] - Fbar;
@@ -79,19 +93,15 @@ __global__ __launch_bounds__(256) void k_lc_prep(const double* __restrict__ F,
     wFc[i] = wd;
     neumaier_add(s2, c2, wd * d);
   }
-  __syncthreads();
   s_part[threadIdx.x][0] = s2;
   s_part[threadIdx.x][1] = c2;
   __syncthreads();
+  double t2[1];
+  tree_totals<1>(s_part, t2);
   if (threadIdx.x == 0) {
-    double s = 0, c = 0;
-    for (int k = 0; k < (int)blockDim.x; ++k) {
-      neumaier_add(s, c, s_part[k][0]);
-      neumaier_add(s, c, s_part[k][1]);
-    }
     sums[3 * e] = Sw;
     sums[3 * e + 1] = Fbar;
-    sums[3 * e + 2] = s + c;
+    sums[3 * e + 2] = t2[0];
   }
 }
 
@@ -532,18 +542,18 @@ __global__ __launch_bounds__(TK_THREADS) void k_tk_collect(const double* __restr
 // Final order of the k selected (key, index) pairs of a segment by rank: element e
 // goes to position #{(key, index) < (key_e, index_e)} (the pairs are distinct, so the
 // ranks are a permutation).  A workgroup stages the segment's pairs in LDS and ranks
-// TKR_ELEMS of them, four threads per element each counting over a quarter of the
-// pairs (the same LDS word is read by a whole wavefront at once).  Positions past the
-// segment's length get index -1 and NaN.
-constexpr int TKR_ELEMS = 64;
-__global__ __launch_bounds__(256) void k_tk_rank(const double* __restrict__ chi2, int64_t seg_len,
-                                                 int32_t k, const uint64_t* __restrict__ keys,
-                                                 const uint32_t* __restrict__ idx,
-                                                 double* __restrict__ out_chi2,
-                                                 int64_t* __restrict__ out_idx) {
+// TKR_ELEMS of them, TKR_SPLIT threads per element each counting over a slice of the
+// pairs (a whole wavefront reads the same LDS words at once; the loop is unrolled so
+// the reads overlap).  Positions past the segment's length get index -1 and NaN.
+constexpr int TKR_ELEMS = 16;
+constexpr int TKR_SPLIT = 16;
+__global__ __launch_bounds__(TKR_ELEMS * TKR_SPLIT) void k_tk_rank(
+    const double* __restrict__ chi2, int64_t seg_len, int32_t k,
+    const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
+    double* __restrict__ out_chi2, int64_t* __restrict__ out_idx) {
   __shared__ uint64_t lk[TK_MAXK];
   __shared__ uint32_t li[TK_MAXK];
-  __shared__ uint32_t part[4][TKR_ELEMS];
+  __shared__ uint32_t part[TKR_SPLIT][TKR_ELEMS];
   const int64_t seg = blockIdx.y;
   const int tid = threadIdx.x;
   const int keff = (int)min((int64_t)k, seg_len);
@@ -552,24 +562,29 @@ __global__ __launch_bounds__(256) void k_tk_rank(const double* __restrict__ chi2
     li[q] = idx[seg * k + q];
   }
   __syncthreads();
-  const int el = tid % TKR_ELEMS, quarter = tid / TKR_ELEMS;
+  const int el = tid % TKR_ELEMS, slice = tid / TKR_ELEMS;
   const int e = blockIdx.x * TKR_ELEMS + el;
   uint32_t count = 0;
   if (e < keff) {
     const uint64_t mk = lk[e];
     const uint32_t mi = li[e];
-    const int j0 = (int)((int64_t)keff * quarter / 4), j1 = (int)((int64_t)keff * (quarter + 1) / 4);
+    const int j0 = (int)((int64_t)keff * slice / TKR_SPLIT);
+    const int j1 = (int)((int64_t)keff * (slice + 1) / TKR_SPLIT);
+#pragma unroll 8
     for (int j = j0; j < j1; ++j) {
       const uint64_t kj = lk[j];
-      count += (kj < mk || (kj == mk && li[j] < mi)) ? 1u : 0u;
+      const uint32_t ij = li[j];
+      count += (kj < mk || (kj == mk && ij < mi)) ? 1u : 0u;
     }
   }
-  part[quarter][el] = count;
+  part[slice][el] = count;
   __syncthreads();
-  if (quarter != 0 || e >= k) return;
+  if (slice != 0 || e >= k) return;
   const double nan = __longlong_as_double(0x7ff8000000000000ll);
   if (e < keff) {
-    const uint32_t rank = part[0][el] + part[1][el] + part[2][el] + part[3][el];
+    uint32_t rank = 0;
+#pragma unroll
+    for (int q = 0; q < TKR_SPLIT; ++q) rank += part[q][el];
     const uint32_t ie = li[e];
     const bool valid = (int64_t)ie < seg_len;
     out_idx[seg * k + rank] = valid ? (int64_t)ie : -1;
@@ -723,7 +738,8 @@ hipError_t launch_topk(const double* chi2, int64_t n_seg, int64_t seg_len, int32
   }
   hipLaunchKernelGGL(k_tk_collect, grid, dim3(TK_THREADS), 0, st, chi2, seg_len, k, state, keys, idx);
   hipLaunchKernelGGL(k_tk_rank, dim3((unsigned)((k + TKR_ELEMS - 1) / TKR_ELEMS), (unsigned)n_seg),
-                     dim3(256), 0, st, chi2, seg_len, k, keys, idx, out_chi2, out_idx);
+                     dim3(TKR_ELEMS * TKR_SPLIT), 0, st, chi2, seg_len, k, keys, idx, out_chi2,
+                     out_idx);
   return hipGetLastError();
 }
 
