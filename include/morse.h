@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 2
+#define MORSE_ABI_VERSION 3
 
 enum morse_status {
   MORSE_OK = 0,
@@ -213,6 +213,11 @@ int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
 int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                    const morse_lightcurves* lcs, const morse_trajectories* trajs,
                    const char* cache_path, int32_t* h_best_config);
+/* Load the shape choices of an autotune cache file into the context (classes it
+ * already holds are replaced).  Entries naming an unknown shape index are skipped.
+ * h_loaded (nullable) receives the number of classes taken.  Errors: EINVAL (NULL
+ * path), EUNSUPPORTED (file missing or unreadable).  Host only. */
+int morse_autotune_load(morse_ctx* ctx, const char* cache_path, int32_t* h_loaded);
 
 /* Candidates from a top-k result (sec. 4.4: the best grid solutions seed the next
  * stage): for every event e and rank r, the trajectory d_topk_idx[e][r] =

@@ -27,7 +27,7 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
                    SEARCH_BATCHED, SEARCH_PLAIN, TRAJ_GRID, TRAJ_LIST)
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
-           "normalize_convolve", "search", "autotune", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "normalize_convolve", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -283,6 +283,14 @@ def autotune(maps, lcs: LightCurveBatch, trajs, cache_path=None, ctx=None):
     ctx.check(ctx.lib.morse_autotune(ctx.handle, views, len(maps), ctypes.byref(lca), ctypes.byref(ta),
                                      cache_path.encode() if cache_path else None, ctypes.byref(best)))
     return best.value
+
+
+def autotune_load(cache_path, device=0, ctx=None):
+    """Take the shapes of an autotune cache file; returns the number of classes loaded."""
+    ctx = ctx or Context.get(device)
+    n = ctypes.c_int32(0)
+    ctx.check(ctx.lib.morse_autotune_load(ctx.handle, str(cache_path).encode(), ctypes.byref(n)))
+    return n.value
 
 
 def candidates_from_topk(trajs, topk_idx, n_maps, out=None, ctx=None):

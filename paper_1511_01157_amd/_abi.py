@@ -59,6 +59,7 @@ SIGNATURES = {
     "morse_ctx_set_stream": (c_int32, [c_void_p, c_void_p]),
     "morse_ctx_synchronize": (c_int32, [c_void_p]),
     "morse_ctx_set_timing": (c_int32, [c_void_p, ctypes.c_uint32]),
+    "morse_autotune_load": (c_int32, [c_void_p, c_char_p, ctypes.POINTER(c_int32)]),
     "morse_ctx_kernel_time": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(c_int64), c_int32]),
     "morse_last_error": (c_char_p, [c_void_p]),

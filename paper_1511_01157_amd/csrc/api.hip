@@ -906,6 +906,25 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
   return a;
 }
 
+// Reads an autotune cache ({"class": index, ...}); false when the file cannot be read.
+bool read_tune_cache(const char* path, std::map<std::string, int>& all) {
+  std::ifstream in(path);
+  if (!in) return false;
+  std::string txt((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
+  size_t p = 0;
+  while ((p = txt.find('"', p)) != std::string::npos) {
+    size_t q = txt.find('"', p + 1);
+    if (q == std::string::npos) break;
+    std::string k = txt.substr(p + 1, q - p - 1);
+    size_t colon = txt.find(':', q);
+    if (colon == std::string::npos) break;
+    all[k] = std::atoi(txt.c_str() + colon + 1);
+    p = txt.find_first_of(",}", colon);
+    if (p == std::string::npos) break;
+  }
+  return true;
+}
+
 std::string shape_class(const SearchPlan& sp) {
   auto bucket = [](double v) { return (int)std::floor(std::log2(std::max(v, 1.0))); };
   std::ostringstream s;
@@ -1070,21 +1089,7 @@ int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (cache_path) {
     // JSON object {"class": index, ...}: merge with the existing file
     std::map<std::string, int> all;
-    std::ifstream in(cache_path);
-    if (in) {
-      std::string txt((std::istreambuf_iterator<char>(in)), std::istreambuf_iterator<char>());
-      size_t p = 0;
-      while ((p = txt.find('"', p)) != std::string::npos) {
-        size_t q = txt.find('"', p + 1);
-        if (q == std::string::npos) break;
-        std::string k = txt.substr(p + 1, q - p - 1);
-        size_t colon = txt.find(':', q);
-        if (colon == std::string::npos) break;
-        all[k] = std::atoi(txt.c_str() + colon + 1);
-        p = txt.find_first_of(",}", colon);
-        if (p == std::string::npos) break;
-      }
-    }
+    read_tune_cache(cache_path, all);
     all[cls] = best;
     std::ofstream o(cache_path);
     o << "{";
@@ -1095,6 +1100,22 @@ int morse_autotune(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     }
     o << "}\n";
   }
+  return MORSE_OK;
+}
+
+int morse_autotune_load(morse_ctx* ctx, const char* cache_path, int32_t* h_loaded) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!cache_path) return fail(ctx, MORSE_EINVAL, "cache_path is NULL");
+  std::map<std::string, int> all;
+  if (!read_tune_cache(cache_path, all))
+    return fail(ctx, MORSE_EUNSUPPORTED, "cannot read autotune cache %s", cache_path);
+  int32_t n = 0;
+  for (const auto& kv : all) {
+    if (kv.second < 0 || kv.second >= kNumTune) continue;
+    ctx->tune[kv.first] = kv.second;
+    ++n;
+  }
+  if (h_loaded) *h_loaded = n;
   return MORSE_OK;
 }
 

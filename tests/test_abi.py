@@ -54,5 +54,6 @@ def test_null_arguments_fail_without_device_work():
     assert lib.morse_build_map(None, 1.0, 0.1, None, None, 0.0, None, None, None) == _abi.MORSE_EINVAL
     assert lib.morse_search(None, None, 0, None, None, 0, None) == _abi.MORSE_EINVAL
     assert lib.morse_ctx_set_timing(None, 1) == _abi.MORSE_EINVAL
+    assert lib.morse_autotune_load(None, b"x.json", None) == _abi.MORSE_EINVAL
     assert lib.morse_ctx_kernel_time(None, 0, None, None, 0) == _abi.MORSE_EINVAL
     assert lib.morse_ctx_destroy(None) == _abi.MORSE_OK

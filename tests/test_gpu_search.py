@@ -234,3 +234,29 @@ def test_bound_contexts_on_two_streams_match_the_default(tiny_oracle_map):
     for r in (r1, r2, r3):
         for k in ref:
             assert torch.equal(r[k], ref[k]), k
+
+
+def test_autotune_cache_round_trip(tiny_oracle_map, tmp_path):
+    """The shape the autotuner writes to its cache is what another context loads, and
+    searches with it give the same bits."""
+    c = W.config("tiny")
+    maps = [(dmap(tiny_oracle_map[2]), c["window"])]
+    ev = W.load_lightcurve("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    tr = M.grid_trajectories(*W.grid_axes("tiny"))
+    path = tmp_path / "tune.json"
+    note("autotune with a cache file")
+    best = M.autotune(maps, lcs, tr, cache_path=str(path))
+    ref = M.search(maps, lcs, tr, "batched", top_k=8)
+    text = path.read_text()
+    assert f": {best}" in text
+    s2 = torch.cuda.Stream(device=DEV)
+    c2 = M.Context.bound(s2)
+    assert M.autotune_load(str(path), ctx=c2) == 1
+    with torch.cuda.stream(s2):
+        r2 = M.search(maps, lcs, tr, "batched", top_k=8, ctx=c2)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(r2[k], ref[k]), k
+    with pytest.raises(M.MorseError):
+        M.autotune_load(str(tmp_path / "missing.json"), ctx=c2)
