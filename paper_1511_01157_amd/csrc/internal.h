@@ -95,11 +95,6 @@ struct Sample {
   bool on;
 };
 
-// Two adjacent floats at any dword-aligned address (one 8-byte load).
-struct __attribute__((packed, aligned(4))) Pair {
-  float a, b;
-};
-
 // Load base[i] through a uniform base pointer and a 32-bit element offset, so the
 // backend can address with a scalar base plus one 32-bit VGPR offset.  The pointer is
 // taken as global memory explicitly (a pointer rebuilt from scalar registers has lost
@@ -328,7 +323,6 @@ __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, dou
 // first HIP error.
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
-hipError_t launch_copy_f64(double* dst, const double* src, size_t n, hipStream_t st);
 // Packs every map of the device table `maps` (n_maps entries; h_maps the same table on
 // the host, for the sizes) into its quad layout.
 hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st);

@@ -70,12 +70,6 @@ __global__ void k_quad_pack(const MapC* __restrict__ maps) {
   }
 }
 
-__global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
 // Symmetric bin rule: v >= 0 (also -0) -> m/2 + floor(v) if v < m/2;
 // v < 0 -> m/2 - 1 - floor(-v) if -v < m/2.  floor(|v|) serves both branches.
 __device__ __forceinline__ bool bin1(float v, int32_t m, int32_t& out) {
@@ -302,13 +296,6 @@ hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps
   return hipGetLastError();
 }
 
-hipError_t launch_copy_f64(double* dst, const double* src, size_t n, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
-  return hipGetLastError();
-}
 
 hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
                            hipStream_t st) {
