@@ -25,7 +25,7 @@ import math
 import numpy as np
 
 __all__ = ["disk_pixel_weights", "map_scale", "normalize_convolve_mirror32",
-           "normalize_convolve_exact64", "stencil_radius"]
+           "normalize_convolve_exact64", "normalize_convolve_exact64_at", "stencil_radius"]
 
 
 def _seg_area(x, y, R):
@@ -153,3 +153,20 @@ def normalize_convolve_exact64(counts, scale64, weights64):
             if w[b + Ry, a + Rx] != 0:
                 acc += w[b + Ry, a + Rx] * _shifted(c, b, a)
     return acc * scale64
+
+
+def normalize_convolve_exact64_at(counts, scale64, weights64, pixels):
+    """FP64 values at the listed (j, i) pixels only: sum over the stencil of
+    w[b, a] * c[clamp(j + b), clamp(i + a)], times the scale (for wide stencils, where
+    the whole-map version is too slow)."""
+    c = np.asarray(counts)
+    w = np.asarray(weights64, dtype=np.float64)
+    my, mx = c.shape
+    Ry = (w.shape[0] - 1) // 2
+    Rx = (w.shape[1] - 1) // 2
+    out = np.empty(len(pixels))
+    for n, (j, i) in enumerate(pixels):
+        jj = np.clip(np.arange(j - Ry, j + Ry + 1), 0, my - 1)
+        ii = np.clip(np.arange(i - Rx, i + Rx + 1), 0, mx - 1)
+        out[n] = float(np.sum(w * c[np.ix_(jj, ii)].astype(np.float64))) * scale64
+    return out

@@ -68,3 +68,16 @@ def test_constant_map_invariant_and_mirror_vs_exact():
     # edge clamp: corner pixel uses itself for outside neighbours
     ref = sum(w[b + 1, a + 1] * float(c[max(b, 0), max(a, 0)]) for b in (-1, 0, 1) for a in (-1, 0, 1)) / 64
     assert A64[0, 0] == pytest.approx(ref, rel=1e-14)
+
+
+def test_per_pixel_sum_equals_whole_map_sum():
+    from oracle.maps import normalize_convolve_exact64_at
+    rng = np.random.default_rng(3)
+    c = rng.integers(0, 5000, (40, 52)).astype(np.uint32)
+    w = disk_pixel_weights(0.01, 3 / 1024, 3 / 1024)
+    A = normalize_convolve_exact64(c, 1 / 64, w)
+    px = [(0, 0), (39, 51), (0, 51), (39, 0), (20, 26), (3, 49)] + [(int(j), int(i)) for j, i in
+                                                                   zip(rng.integers(0, 40, 30), rng.integers(0, 52, 30))]
+    got = normalize_convolve_exact64_at(c, 1 / 64, w, px)
+    ref = np.array([A[j, i] for j, i in px])
+    assert np.allclose(got, ref, rtol=1e-13, atol=0)
