@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -63,6 +64,8 @@ def peak_for(ops):
 TRAFFIC = {
     ("k_chi2_grad", "985209e294ab513e"): 2.814e+08,  # 137327 KiB fetched, 174 KiB written
 }
+STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
+STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
 KERNEL_SOURCES = {"k_rayshoot": ("maps.hip", "internal.h"),
                   "k_search_batched": ("search.hip", "internal.h"),
                   "k_chi2_grad": ("refine.hip", "internal.h")}
@@ -85,6 +88,8 @@ def parse():
     ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-stack", action="store_true",
+                    help="skip the (untimed-step) seven-radius finite-source stack measurement")
     ap.add_argument("--pipelined", action="store_true",
                     help="time steps with the next step's map built on a second stream "
                          "(default: each step's map build, search and refinement in turn)")
@@ -366,6 +371,30 @@ def main():
             torch.cuda.synchronize()
             plain_ms = e0.elapsed_time(e1) / 3
 
+        # Finite-source stack of this step's counts: seven radii log-spaced over
+        # [0.001, 1] with limb-darkening coefficient 0.53, timed apart from the step.
+        stack = None
+        if not args.no_stack:
+            rhos = np.logspace(-3.0, 0.0, 7)
+            sout = M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, ctx=ctx_b)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, out=sout, ctx=ctx_b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st_ms = e0.elapsed_time(e1) / 5
+            d = c["window"][2] / c["window"][4]
+            # the library's split: stencil half-width above 15 pixels or at least
+            # STACK_FFT_MIN_TAPS non-zero taps -> transforms
+            n_fft = sum(1 for r in rhos if math.ceil(r / d + 0.5) > 15 or
+                        np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS)
+            stack = {"radii": [float(r) for r in rhos], "gamma": STACK_GAMMA, "ms": st_ms,
+                     "maps_per_s": len(rhos) / (st_ms * 1e-3), "fft_radii": n_fft,
+                     "map": [c["window"][5], c["window"][4]]}
+
     rays_ms, norm_ms, search_ms, refine_ms = stage
     adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
     # algorithmic lane-operations of one launch of each kernel, and their peak rate
@@ -402,6 +431,7 @@ def main():
                                      "plain": evals_per_step / (plain_ms * 1e-3) if plain_ms else None},
         "adjoint_point_evals_per_s_upper": adjoint_evals / (refine_ms * 1e-3),
         "refine_improved_fraction": improved,
+        "rho_stack": stack,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s",

@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 3
+#define MORSE_ABI_VERSION 4
 
 enum morse_status {
   MORSE_OK = 0,
@@ -128,6 +128,45 @@ int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const mor
 int morse_build_map(morse_ctx* ctx, double s, double q, const morse_grid2d* rays,
                     const morse_grid2d* window, double rho, uint32_t* d_counts, float* d_map,
                     morse_map_stats* h_stats);
+
+/* Finite-source maps for several source radii from one count map (sec. 4.1: each
+ * point-source map is convolved with radially symmetric source profiles of several
+ * radii and one fixed limb-darkening coefficient, giving one map per radius).
+ * Profile: the linear limb-darkening law with unit mean brightness over the disk,
+ * I(r) = 1 - gamma (1 - 1.5 sqrt(1 - r^2/rho^2)) for r <= rho; gamma = 0 is the
+ * uniform disk.  Pixel weights w_k = (integral of I over pixel k ∩ disk)/(pi rho^2),
+ * the area part from the circle-rectangle overlap and the limb part from closed-form
+ * hemisphere volumes, renormalised to sum 1 in FP64.
+ * For each k, d_maps + k * ny * nx receives A = scale * sum_k w_k c_{p+k} with the
+ * scale and edge clamp of morse_normalize_convolve.  Two evaluations:
+ *  - direct (stencil at most 31 x 31 and fewer than fft_min_taps non-zero taps): the
+ *    binary32 sum of morse_normalize_convolve with binary32 weights, in the same tap
+ *    order; for gamma = 0 identical bits to morse_normalize_convolve;
+ *  - FFT otherwise: the counts, extended past the edges by their edge pixels, are
+ *    convolved with the FP64 weights through FP64 transforms of power-of-two size
+ *    (at least map + 2 R per side, at most 4096), the result rounded once to binary32
+ *    (scale in FP64): within one binary32 unit in the last place of the FP64 direct
+ *    sum, closer than the direct binary32 sum of a wide stencil.
+ * fft_min_taps <= 0 takes MORSE_STACK_FFT_MIN_TAPS.  h_rho[n_rho] is host memory read
+ * during the call.  The first call for a set of (radii, gamma, pixel size) computes
+ * and keeps the profile transforms in the context (a synchronising call); later calls
+ * enqueue kernels only.  Workspace: three transforms (16 B per padded pixel each) plus
+ * one kept transform per pair of FFT radii.
+ * Errors: EINVAL (gamma outside [0, 1], a radius negative or not finite, NULL
+ * pointers), ERANGE (an FFT side above 4096). */
+#define MORSE_STACK_FFT_MIN_TAPS 256
+int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_grid2d* rays,
+                         const morse_grid2d* window, const double* h_rho, int32_t n_rho,
+                         double gamma, int32_t fft_min_taps, float* d_maps);
+
+/* The FP64 weights morse_convolve_stack uses for one radius (host only, no device
+ * needed): stencil [2 ry + 1][2 rx + 1] (row = y offset) without all-zero outer
+ * rings, normalised to sum 1.  Always sets *h_rx, *h_ry; writes h_w when it is not
+ * NULL (capacity = its length in doubles).  Errors (message in morse_last_error(NULL)):
+ * EINVAL (bad rho, pixel sizes or gamma; NULL h_rx / h_ry), ERANGE (capacity too
+ * small, rho above 4096 pixels). */
+int morse_profile_weights(double rho, double dx, double dy, double gamma, double* h_w,
+                          int64_t capacity, int32_t* h_rx, int32_t* h_ry);
 
 /* ------------------------------------------------------------------------------
  * Trajectory search (sec. 4.2: chi-square of each trajectory through a map by

@@ -27,7 +27,7 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
                    SEARCH_BATCHED, SEARCH_PLAIN, TRAJ_GRID, TRAJ_LIST)
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
-           "normalize_convolve", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "normalize_convolve", "convolve_stack", "profile_weights", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -148,6 +148,36 @@ def normalize_convolve(counts, rays, window, rho=0.0, out=None, ctx=None):
     ctx.check(ctx.lib.morse_normalize_convolve(ctx.handle, _ptr(counts), ctypes.byref(_grid(rays)),
                                                ctypes.byref(_grid(window)), float(rho), _ptr(out)))
     return out
+
+
+def convolve_stack(counts, rays, window, rhos, gamma=0.53, fft_min_taps=0, out=None, ctx=None):
+    """Finite-source maps float32[len(rhos), ny, nx] of one count map for each source
+    radius, limb-darkened profile with coefficient gamma (0 = uniform disk)."""
+    ctx = ctx or Context.get(_device_of(counts))
+    rh = np.ascontiguousarray(np.asarray(rhos, dtype=np.float64).reshape(-1))
+    if out is None:
+        out = torch.empty((len(rh), int(window[5]), int(window[4])), dtype=torch.float32,
+                          device=counts.device)
+    ctx.check(ctx.lib.morse_convolve_stack(ctx.handle, _ptr(counts), ctypes.byref(_grid(rays)),
+                                           ctypes.byref(_grid(window)), rh.ctypes.data, len(rh),
+                                           float(gamma), int(fft_min_taps), _ptr(out)))
+    return out
+
+
+def profile_weights(rho, dx, dy, gamma=0.53):
+    """The library's FP64 pixel weights [2ry+1, 2rx+1] of one limb-darkened disk (host)."""
+    lib = _abi.load()
+    rx, ry = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib.morse_profile_weights(float(rho), float(dx), float(dy), float(gamma), None, 0,
+                                   ctypes.byref(rx), ctypes.byref(ry))
+    if rc != _abi.MORSE_OK:
+        raise MorseError(rc, lib.morse_last_error(None).decode())
+    w = np.empty((2 * ry.value + 1, 2 * rx.value + 1), dtype=np.float64)
+    rc = lib.morse_profile_weights(float(rho), float(dx), float(dy), float(gamma), w.ctypes.data,
+                                   w.size, ctypes.byref(rx), ctypes.byref(ry))
+    if rc != _abi.MORSE_OK:
+        raise MorseError(rc, lib.morse_last_error(None).decode())
+    return w
 
 
 def build_map(s, q, rays, window, rho=0.0, device="cuda", out=None, counts=None, stats=False, ctx=None):

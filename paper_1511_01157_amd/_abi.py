@@ -67,6 +67,10 @@ SIGNATURES = {
                                  c_int32, c_int32, c_void_p, c_int32, c_void_p]),
     "morse_normalize_convolve": (c_int32, [c_void_p, c_void_p, POINTER(Grid2D), POINTER(Grid2D),
                                            c_double, c_void_p]),
+    "morse_convolve_stack": (c_int32, [c_void_p, c_void_p, POINTER(Grid2D), POINTER(Grid2D),
+                                       c_void_p, c_int32, c_double, c_int32, c_void_p]),
+    "morse_profile_weights": (c_int32, [c_double, c_double, c_double, c_double, c_void_p, c_int64,
+                                        POINTER(c_int32), POINTER(c_int32)]),
     "morse_build_map": (c_int32, [c_void_p, c_double, c_double, POINTER(Grid2D), POINTER(Grid2D),
                                   c_double, c_void_p, c_void_p, POINTER(MapStats)]),
     "morse_search": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves),

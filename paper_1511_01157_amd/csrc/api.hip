@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "stack.h"
 
 using namespace morse;
 
@@ -65,6 +66,18 @@ struct morse_ctx {
   // buffer of its own (never in the shared workspace, which the other entry points
   // overwrite) and uploaded only when its key changes
   MetaBuf smeta, cmeta;
+  // source-radius stacks: direct-sum taps, FFT twiddle tables and the transforms of
+  // the profile pairs, each kept until a call needs different ones
+  MetaBuf stack_taps, fft_tw, fft_spec;
+  // split of the last stack call's radii (key of its arguments): direct radii with
+  // their tap counts (taps in stack_taps, in this order), FFT radii, widest FFT stencil
+  struct StackSplit {
+    uint64_t key = 0;
+    std::vector<int> direct_k, fft_k;
+    std::vector<int32_t> ntaps;
+    size_t w_bytes = 0;  // the tap offsets follow the weights at this byte offset
+    int rmx = 0, rmy = 0;
+  } stack_split;
   // batched-search graph
   hipGraphExec_t gexec = nullptr;
   uint64_t graph_key = 0;
@@ -392,19 +405,68 @@ double rect_disk_area(double R, double x1, double x2, double y1, double y2) {
   return area;
 }
 
+// Volume under the unit hemisphere z = sqrt(1 - X^2 - Y^2) over {X >= a, Y >= b}.
+// For a, b >= 0 inside the disk, integrating over Y in closed form and then by parts
+// over X gives
+//   (pi/2 - atan(a b / r))/3 + a b r/3 - b (3 - b^2)/6 acos(a / sqrt(1 - b^2))
+//     - a (3 - a^2)/6 acos(b / sqrt(1 - a^2)),   r = sqrt(1 - a^2 - b^2);
+// negative a or b follow by reflection from the half-space volume
+// H(t) = pi (2 - 3t + t^3)/6 over {X >= t}.
+double hemi_half(double t) {
+  if (t <= -1.0) return 2.0 * M_PI / 3.0;
+  if (t >= 1.0) return 0.0;
+  return M_PI / 6.0 * (2.0 - 3.0 * t + t * t * t);
+}
+
+double hemi_upper(double a, double b) {
+  if (a < 0.0) return hemi_half(b) - hemi_upper(-a, b);
+  if (b < 0.0) return hemi_half(a) - hemi_upper(a, -b);
+  const double s2 = a * a + b * b;
+  if (s2 >= 1.0) return 0.0;
+  const double r = std::sqrt(1.0 - s2);
+  const double ca = std::min(1.0, a / std::sqrt(1.0 - b * b));
+  const double cb = std::min(1.0, b / std::sqrt(1.0 - a * a));
+  return (0.5 * M_PI - std::atan2(a * b, r)) / 3.0 + a * b * r / 3.0 -
+         b * (3.0 - b * b) / 6.0 * std::acos(ca) - a * (3.0 - a * a) / 6.0 * std::acos(cb);
+}
+
+// Integral of sqrt(R^2 - x^2 - y^2) over disk(0, R) ∩ [x1,x2] x [y1,y2].
+double rect_hemi_volume(double R, double x1, double x2, double y1, double y2) {
+  const double u1 = x1 / R, u2 = x2 / R, v1 = y1 / R, v2 = y2 / R;
+  const double v = hemi_upper(u1, v1) - hemi_upper(u2, v1) - hemi_upper(u1, v2) + hemi_upper(u2, v2);
+  return std::max(0.0, v) * R * R * R;
+}
+
+// Unnormalised weight of the pixel at offset (a, b) for the limb-darkened disk of
+// radius rho: the integral over pixel ∩ disk of I(r) = 1 - gamma (1 - 1.5 sqrt(1 -
+// r^2/rho^2)), i.e. (1 - gamma) area + 1.5 gamma/rho volume.  gamma = 0 gives the area
+// term alone (the uniform disk).
+double profile_pixel(double rho, double dx, double dy, double gamma, int a, int b) {
+  const double nx = std::max(0.0, (std::abs(a) - 0.5) * dx), ny = std::max(0.0, (std::abs(b) - 0.5) * dy);
+  if (nx * nx + ny * ny >= rho * rho) return 0.0;  // the pixel does not meet the disk
+  const double fx = (std::abs(a) + 0.5) * dx, fy = (std::abs(b) + 0.5) * dy;
+  const double x1 = (a - 0.5) * dx, x2 = (a + 0.5) * dx, y1 = (b - 0.5) * dy, y2 = (b + 0.5) * dy;
+  const double area = (fx * fx + fy * fy <= rho * rho) ? dx * dy : rect_disk_area(rho, x1, x2, y1, y2);
+  if (gamma == 0.0) return area;
+  return (1.0 - gamma) * area + 1.5 * gamma / rho * rect_hemi_volume(rho, x1, x2, y1, y2);
+}
+
+int stencil_half(double rho, double d) { return rho > 0.0 ? (int)std::ceil(rho / d + 0.5) : 0; }
+
 // Taps (dx, dy offsets and binary32 weights), row-major over the stencil, zero taps
-// dropped; rho within half a pixel gives the single tap 1.
-int disk_taps(morse_ctx* ctx, double rho, double dx, double dy, std::vector<float>& w,
-              std::vector<int32_t>& off) {
+// dropped, weights normalised to sum 1 in FP64 and rounded once; rho within half a
+// pixel gives the single tap 1.  Limited to stencils of at most 31 x 31.
+int profile_taps(morse_ctx* ctx, double rho, double dx, double dy, double gamma,
+                 std::vector<float>& w, std::vector<int32_t>& off) {
   w.clear();
   off.clear();
-  const int Rx = (int)std::ceil(rho / dx + 0.5), Ry = (int)std::ceil(rho / dy + 0.5);
   if (rho <= 0.0) {
     w.push_back(1.0f);
     off.push_back(0);
     off.push_back(0);
     return MORSE_OK;
   }
+  const int Rx = stencil_half(rho, dx), Ry = stencil_half(rho, dy);
   if (Rx > 15 || Ry > 15)
     return fail(ctx, MORSE_ERANGE, "disk radius spans more than 15 pixels (stencil > 31)");
   std::vector<double> wd;
@@ -412,19 +474,11 @@ int disk_taps(morse_ctx* ctx, double rho, double dx, double dy, std::vector<floa
   double sum = 0.0;
   for (int b = -Ry; b <= Ry; ++b)
     for (int a = -Rx; a <= Rx; ++a) {
-      double nx = std::max(0.0, (std::abs(a) - 0.5) * dx), ny = std::max(0.0, (std::abs(b) - 0.5) * dy);
-      double fx = (std::abs(a) + 0.5) * dx, fy = (std::abs(b) + 0.5) * dy;
-      double area;
-      if (nx * nx + ny * ny >= rho * rho)
-        area = 0.0;
-      else if (fx * fx + fy * fy <= rho * rho)
-        area = dx * dy;
-      else
-        area = rect_disk_area(rho, (a - 0.5) * dx, (a + 0.5) * dx, (b - 0.5) * dy, (b + 0.5) * dy);
-      wd.push_back(area);
+      const double v = profile_pixel(rho, dx, dy, gamma, a, b);
+      wd.push_back(v);
       od.push_back(a);
       od.push_back(b);
-      sum += area;
+      sum += v;
     }
   for (size_t k = 0; k < wd.size(); ++k) {
     if (wd[k] == 0.0) continue;
@@ -433,6 +487,26 @@ int disk_taps(morse_ctx* ctx, double rho, double dx, double dy, std::vector<floa
     off.push_back(od[2 * k + 1]);
   }
   return MORSE_OK;
+}
+
+int disk_taps(morse_ctx* ctx, double rho, double dx, double dy, std::vector<float>& w,
+              std::vector<int32_t>& off) {
+  return profile_taps(ctx, rho, dx, dy, 0.0, w, off);
+}
+
+// FP64 quadrant q[b][a] (0 <= a <= Rx, 0 <= b <= Ry) of the weights normalised to sum
+// 1 over the whole stencil (the weights are even in a and in b).
+void profile_quadrant(double rho, double dx, double dy, double gamma, int Rx, int Ry,
+                      std::vector<double>& q) {
+  q.assign((size_t)(Rx + 1) * (Ry + 1), 0.0);
+  double sum = 0.0;
+  for (int b = 0; b <= Ry; ++b)
+    for (int a = 0; a <= Rx; ++a) {
+      const double v = profile_pixel(rho, dx, dy, gamma, a, b);
+      q[(size_t)b * (Rx + 1) + a] = v;
+      sum += v * (a ? 2.0 : 1.0) * (b ? 2.0 : 1.0);
+    }
+  for (double& v : q) v /= sum;
 }
 
 }  // namespace
@@ -486,6 +560,8 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   if (ctx->taps) (void)hipFree(ctx->taps);
   if (ctx->smeta.p) (void)hipFree(ctx->smeta.p);
   if (ctx->cmeta.p) (void)hipFree(ctx->cmeta.p);
+  for (MetaBuf* mb : {&ctx->stack_taps, &ctx->fft_tw, &ctx->fft_spec})
+    if (mb->p) (void)hipFree(mb->p);
   for (const auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -625,6 +701,225 @@ int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const mor
   const int32_t* d_off = (const int32_t*)(ctx->taps + ctx->taps_wbytes);
   HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_map, window->nx, window->ny, d_w, d_off,
                                          ctx->taps_n, scale, nullptr, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_profile_weights(double rho, double dx, double dy, double gamma, double* h_w,
+                          int64_t capacity, int32_t* h_rx, int32_t* h_ry) {
+  if (!(std::isfinite(rho) && rho >= 0.0)) return fail(nullptr, MORSE_EINVAL, "rho must be finite and >= 0");
+  if (!(std::isfinite(dx) && dx > 0.0 && std::isfinite(dy) && dy > 0.0))
+    return fail(nullptr, MORSE_EINVAL, "pixel sizes must be finite and > 0");
+  if (!(gamma >= 0.0 && gamma <= 1.0)) return fail(nullptr, MORSE_EINVAL, "gamma must lie in [0, 1]");
+  if (!h_rx || !h_ry) return fail(nullptr, MORSE_EINVAL, "h_rx / h_ry is NULL");
+  if (rho / std::min(dx, dy) > 4096.0) return fail(nullptr, MORSE_ERANGE, "rho spans more than 4096 pixels");
+  int Rx = stencil_half(rho, dx), Ry = stencil_half(rho, dy);
+  std::vector<double> q(1, 1.0);
+  if (rho > 0.0) profile_quadrant(rho, dx, dy, gamma, Rx, Ry, q);
+  // trim all-zero outer rings
+  auto qw = [&](int a, int b) { return q[(size_t)b * (Rx + 1) + a]; };
+  int tx = 0, ty = 0;
+  for (int b = 0; b <= Ry; ++b)
+    for (int a = 0; a <= Rx; ++a)
+      if (qw(a, b) != 0.0) {
+        tx = std::max(tx, a);
+        ty = std::max(ty, b);
+      }
+  *h_rx = tx;
+  *h_ry = ty;
+  if (!h_w) return MORSE_OK;
+  const int64_t need = (int64_t)(2 * tx + 1) * (2 * ty + 1);
+  if (capacity < need)
+    return fail(nullptr, MORSE_ERANGE, "capacity %lld < %lld weights", (long long)capacity, (long long)need);
+  for (int b = -ty; b <= ty; ++b)
+    for (int a = -tx; a <= tx; ++a) h_w[(int64_t)(b + ty) * (2 * tx + 1) + (a + tx)] = qw(std::abs(a), std::abs(b));
+  return MORSE_OK;
+}
+
+int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_grid2d* rays,
+                         const morse_grid2d* window, const double* h_rho, int32_t n_rho,
+                         double gamma, int32_t fft_min_taps, float* d_maps) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if (!grid_ok(rays)) return fail(ctx, MORSE_EINVAL, "rays: invalid grid");
+  if ((rc = check_window(ctx, window, "window"))) return rc;
+  if (n_rho < 0) return fail(ctx, MORSE_EINVAL, "n_rho < 0");
+  if (n_rho == 0) return MORSE_OK;
+  if (!h_rho || !d_counts || !d_maps) return fail(ctx, MORSE_EINVAL, "h_rho / d_counts / d_maps is NULL");
+  if (!(gamma >= 0.0 && gamma <= 1.0)) return fail(ctx, MORSE_EINVAL, "gamma must lie in [0, 1]");
+  for (int k = 0; k < n_rho; ++k)
+    if (!(std::isfinite(h_rho[k]) && h_rho[k] >= 0.0))
+      return fail(ctx, MORSE_EINVAL, "rho[%d] must be finite and >= 0", k);
+  for (int k = 0; k < n_rho; ++k)
+    if (h_rho[k] / std::min(window->wx / window->nx, window->wy / window->ny) > 4096.0)
+      return fail(ctx, MORSE_ERANGE, "rho[%d] spans more than 4096 pixels", k);
+  if (fft_min_taps <= 0) fft_min_taps = MORSE_STACK_FFT_MIN_TAPS;
+  const int mx = window->nx, my = window->ny;
+  const double dx = window->wx / mx, dy = window->wy / my;
+  const double hx = (double)(float)(rays->wx / rays->nx), hy = (double)(float)(rays->wy / rays->ny);
+  const size_t npx = (size_t)mx * my;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+  // Direct or FFT per radius; the direct taps of the whole call in one device table.
+  // Both are kept in the context for the next call with the same arguments.
+  Hasher skey;
+  skey.pod(dx);
+  skey.pod(dy);
+  skey.pod(gamma);
+  skey.pod(fft_min_taps);
+  for (int k = 0; k < n_rho; ++k) skey.pod(h_rho[k]);
+  auto& sp = ctx->stack_split;
+  if (sp.key != skey.h || !ctx->stack_taps.p) {
+    sp.key = 0;
+    sp.direct_k.clear();
+    sp.fft_k.clear();
+    sp.ntaps.clear();
+    sp.rmx = sp.rmy = 0;
+    std::vector<float> w32;
+    std::vector<int32_t> off;
+    for (int k = 0; k < n_rho; ++k) {
+      const int Rx = stencil_half(h_rho[k], dx), Ry = stencil_half(h_rho[k], dy);
+      std::vector<float> wk;
+      std::vector<int32_t> ok;
+      bool direct = Rx <= 15 && Ry <= 15;
+      if (direct) {
+        if ((rc = profile_taps(ctx, h_rho[k], dx, dy, gamma, wk, ok))) return rc;
+        direct = (int64_t)wk.size() < (int64_t)fft_min_taps || wk.size() == 1;
+      }
+      if (direct) {
+        sp.direct_k.push_back(k);
+        sp.ntaps.push_back((int32_t)wk.size());
+        w32.insert(w32.end(), wk.begin(), wk.end());
+        off.insert(off.end(), ok.begin(), ok.end());
+      } else {
+        sp.fft_k.push_back(k);
+        sp.rmx = std::max(sp.rmx, Rx);
+        sp.rmy = std::max(sp.rmy, Ry);
+      }
+    }
+    const size_t w_bytes = (w32.size() * sizeof(float) + 255) & ~size_t(255);
+    if ((rc = reserve_meta(ctx, ctx->stack_taps, std::max<size_t>(256, w_bytes + off.size() * sizeof(int32_t)))))
+      return rc;
+    if ((rc = upload(ctx, ctx->stack_taps.p, w32.data(), w32.size() * sizeof(float)))) return rc;
+    if ((rc = upload(ctx, ctx->stack_taps.p + w_bytes, off.data(), off.size() * sizeof(int32_t)))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // the host tables go out of scope
+    sp.w_bytes = w_bytes;
+    sp.key = skey.h;
+  }
+  const std::vector<int>& direct_k = sp.direct_k;
+  const std::vector<int>& fft_k = sp.fft_k;
+  // FFT sizes checked before any launch
+  auto pow2_at_least = [](int64_t v) {
+    int64_t n = 2;
+    while (n < v) n <<= 1;
+    return n;
+  };
+  const int64_t nx64 = pow2_at_least((int64_t)mx + 2 * sp.rmx), ny64 = pow2_at_least((int64_t)my + 2 * sp.rmy);
+  if (!fft_k.empty() && (nx64 > kFftMaxN || ny64 > kFftMaxN))
+    return fail(ctx, MORSE_ERANGE, "FFT convolution needs %lld x %lld > %d per side (map plus twice the stencil radius)",
+                (long long)nx64, (long long)ny64, kFftMaxN);
+  {
+    const float scale = (float)(hx * hy / (dx * dy));
+    const size_t w_bytes = sp.w_bytes;
+    size_t at = 0;
+    for (size_t u = 0; u < direct_k.size(); ++u) {
+      const float* d_w = (const float*)(ctx->stack_taps.p) + at;
+      const int32_t* d_off = (const int32_t*)(ctx->stack_taps.p + w_bytes) + 2 * at;
+      HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_maps + (size_t)direct_k[u] * npx, mx, my, d_w,
+                                             d_off, sp.ntaps[u], scale, nullptr, ctx->stream));
+      at += (size_t)sp.ntaps[u];
+    }
+  }
+  if (fft_k.empty()) return MORSE_OK;
+
+  // FFT path: twiddles, profile-pair transforms (kept in the context), then one
+  // forward transform of the counts and one inverse transform per pair.
+  FftGrid g;
+  g.nx = (int32_t)nx64;
+  g.ny = (int32_t)ny64;
+  {
+    Hasher key;
+    key.pod(g.nx);
+    key.pod(g.ny);
+    const size_t need = (size_t)(g.nx + g.ny) * sizeof(double2);
+    if (ctx->fft_tw.key != key.h || ctx->fft_tw.size < need) {
+      if ((rc = reserve_meta(ctx, ctx->fft_tw, need))) return rc;
+      ctx->fft_tw.key = 0;
+      std::vector<double2> t((size_t)g.nx + g.ny);
+      for (int m = 0; m < g.nx; ++m) {
+        const double th = 2.0 * M_PI * m / g.nx;
+        t[m] = make_double2(std::cos(th), -std::sin(th));
+      }
+      for (int m = 0; m < g.ny; ++m) {
+        const double th = 2.0 * M_PI * m / g.ny;
+        t[(size_t)g.nx + m] = make_double2(std::cos(th), -std::sin(th));
+      }
+      if ((rc = upload(ctx, ctx->fft_tw.p, t.data(), need))) return rc;
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      ctx->fft_tw.key = key.h;
+    }
+    g.tw_x = (const double2*)ctx->fft_tw.p;
+    g.tw_y = (const double2*)ctx->fft_tw.p + g.nx;
+  }
+  const size_t nf = (size_t)g.nx * g.ny;
+  const size_t fbytes = nf * sizeof(double2);
+  const int pairs = (int)(fft_k.size() + 1) / 2;
+  Plan pl;
+  const size_t i0 = pl.add(fbytes), i1 = pl.add(fbytes), i2 = pl.add(fbytes);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  double2* B[3] = {(double2*)pl.ptr(ctx, i0), (double2*)pl.ptr(ctx, i1), (double2*)pl.ptr(ctx, i2)};
+  {
+    Hasher key;
+    key.pod(g.nx);
+    key.pod(g.ny);
+    key.pod(dx);
+    key.pod(dy);
+    key.pod(gamma);
+    for (int k : fft_k) key.pod(h_rho[k]);
+    const size_t need = (size_t)pairs * fbytes;
+    if (ctx->fft_spec.key != key.h || ctx->fft_spec.size < need) {
+      if ((rc = reserve_meta(ctx, ctx->fft_spec, need))) return rc;
+      ctx->fft_spec.key = 0;
+      for (int p = 0; p < pairs; ++p) {
+        std::vector<double> q[2];
+        int rx[2] = {0, 0}, ry[2] = {0, 0};
+        const int nk = (2 * p + 1 < (int)fft_k.size()) ? 2 : 1;
+        for (int u = 0; u < nk; ++u) {
+          const double rho = h_rho[fft_k[2 * p + u]];
+          rx[u] = stencil_half(rho, dx);
+          ry[u] = stencil_half(rho, dy);
+          profile_quadrant(rho, dx, dy, gamma, rx[u], ry[u], q[u]);
+        }
+        // the quadrant tables go through B[2] (free until the counts transform)
+        double* dq0 = (double*)B[2];
+        double* dq1 = dq0 + q[0].size();
+        if ((q[0].size() + q[1].size()) * sizeof(double) > fbytes)
+          return fail(ctx, MORSE_ERANGE, "profile tables exceed the transform buffer");
+        if ((rc = upload(ctx, dq0, q[0].data(), q[0].size() * sizeof(double)))) return rc;
+        if (nk == 2 && (rc = upload(ctx, dq1, q[1].data(), q[1].size() * sizeof(double)))) return rc;
+        HIP_TRY(ctx, launch_fft_rows_taps(g, dq0, rx[0], ry[0], nk == 2 ? dq1 : nullptr, rx[1], ry[1],
+                                          B[0], ctx->stream));
+        double2* spec = (double2*)ctx->fft_spec.p + (size_t)p * nf;
+        double2* res = nullptr;
+        HIP_TRY(ctx, launch_fft_cols(g, -1, B[0], spec, B[1], nullptr, &res, ctx->stream));
+        if (res != spec) HIP_TRY(ctx, hipMemcpyAsync(spec, res, fbytes, hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // q goes out of scope
+      }
+      ctx->fft_spec.key = key.h;
+    }
+  }
+  double2* X = nullptr;
+  HIP_TRY(ctx, launch_fft_rows_counts(g, d_counts, mx, my, B[0], ctx->stream));
+  HIP_TRY(ctx, launch_fft_cols(g, -1, B[0], B[1], B[2], nullptr, &X, ctx->stream));
+  double2* other = (X == B[1]) ? B[2] : B[1];
+  const double scale = hx * hy / (dx * dy) / ((double)g.nx * (double)g.ny);
+  for (int p = 0; p < pairs; ++p) {
+    const double2* spec = (const double2*)ctx->fft_spec.p + (size_t)p * nf;
+    double2* Y = nullptr;
+    HIP_TRY(ctx, launch_fft_cols(g, 1, X, B[0], other, spec, &Y, ctx->stream));
+    float* m1 = d_maps + (size_t)fft_k[2 * p] * npx;
+    float* m2 = (2 * p + 1 < (int)fft_k.size()) ? d_maps + (size_t)fft_k[2 * p + 1] * npx : nullptr;
+    HIP_TRY(ctx, launch_fft_rows_store(g, Y, mx, my, scale, m1, m2, ctx->stream));
+  }
   return MORSE_OK;
 }
 

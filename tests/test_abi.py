@@ -56,4 +56,9 @@ def test_null_arguments_fail_without_device_work():
     assert lib.morse_ctx_set_timing(None, 1) == _abi.MORSE_EINVAL
     assert lib.morse_autotune_load(None, b"x.json", None) == _abi.MORSE_EINVAL
     assert lib.morse_ctx_kernel_time(None, 0, None, None, 0) == _abi.MORSE_EINVAL
+    assert lib.morse_convolve_stack(None, None, None, None, None, 0, 0.5, 0, None) == _abi.MORSE_EINVAL
+    rx, ry = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.morse_profile_weights(0.01, 1e-3, 1e-3, 0.5, None, 0, None, None) == _abi.MORSE_EINVAL
+    assert lib.morse_profile_weights(0.01, 1e-3, 1e-3, 1.5, None, 0, ctypes.byref(rx), ctypes.byref(ry)) == _abi.MORSE_EINVAL
+    assert lib.morse_profile_weights(-1.0, 1e-3, 1e-3, 0.5, None, 0, ctypes.byref(rx), ctypes.byref(ry)) == _abi.MORSE_EINVAL
     assert lib.morse_ctx_destroy(None) == _abi.MORSE_OK

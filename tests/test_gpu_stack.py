@@ -1,0 +1,159 @@
+"""GPU parity of the source-radius stack: finite-source maps of one count map for
+several radii of a limb-darkened source profile (sec. 4.1), through the C ABI
+(morse_convolve_stack).  Direct-sum radii are checked against the oracle's binary32
+mirror (whole maps), FFT radii against the oracle's FP64 definition (whole maps at small
+sizes, sampled pixels at wide stencils and full size).  Counts come from the GPU ray
+kernel and are first checked bit-exact against the oracle's own counts; the oracle then
+works from its own counts and its own (quadrature) weights."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_01157_amd as M
+import workloads as W
+from oracle.maps import (map_scale, normalize_convolve_exact64, normalize_convolve_exact64_at,
+                         normalize_convolve_mirror32)
+from oracle.profiles import ld_pixel_weights, stack_rhos
+from oracle.rays import rayshoot_mirror32_c
+from tests.helpers import note
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GAMMA = 0.53
+FORCE_DIRECT = 2**31 - 1
+FORCE_FFT = 1
+
+
+def counts_pair(s, q, rays, window):
+    """GPU counts (device int32 view) and the oracle's counts, checked equal."""
+    gc = torch.empty((window[5], window[4]), dtype=torch.int32, device=DEV)
+    M.rayshoot(s, q, rays, window, gc)
+    oc, _ = rayshoot_mirror32_c(s, q, rays, window, nthreads=16)
+    assert np.array_equal(gc.cpu().numpy().view(np.uint32), oc)
+    return gc, oc
+
+
+def sample_pixels(my, mx, n, seed):
+    rng = np.random.default_rng(seed)
+    fixed = [(0, 0), (0, mx - 1), (my - 1, 0), (my - 1, mx - 1), (my // 2, mx // 2),
+             (0, mx // 3), (my - 1, mx // 2), (my // 4, 0), (my // 3, mx - 1)]
+    rnd = [(int(j), int(i)) for j, i in zip(rng.integers(0, my, n), rng.integers(0, mx, n))]
+    return fixed + rnd
+
+
+def test_direct_radii_match_mirror32_and_uniform_disk_bits():
+    c = W.config("tiny")
+    win = c["window"]
+    d = win[2] / win[4]
+    gc, oc = counts_pair(c["s"], c["q"], c["rays"], win)
+    rhos = [0.0, 0.002, 0.006, 0.02, 0.05]  # from one tap to stencils of 29 x 29 pixels
+    note("stack: direct radii, gamma 0.53")
+    maps = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA, fft_min_taps=FORCE_DIRECT)
+    s32 = map_scale(c["rays"], win)
+    for k, rho in enumerate(rhos):
+        ref = normalize_convolve_mirror32(oc, s32, ld_pixel_weights(rho, d, d, GAMMA))
+        g = maps[k].cpu().numpy()
+        assert np.abs(g - ref).max() <= 2e-7 * max(1.0, float(ref.max())), rho
+    # gamma = 0: the same taps and kernel as the single-radius entry point, so the same bits
+    maps0 = M.convolve_stack(gc, c["rays"], win, rhos, 0.0, fft_min_taps=FORCE_DIRECT)
+    for k, rho in enumerate(rhos):
+        assert torch.equal(maps0[k], M.normalize_convolve(gc, c["rays"], win, rho)), rho
+    # limb darkening changes the convolved maps
+    assert not torch.equal(maps0[3], maps[3])
+
+
+def test_fft_radii_match_exact64_whole_maps():
+    c = W.config("tiny")
+    win = c["window"]
+    d = win[2] / win[4]
+    gc, oc = counts_pair(c["s"], c["q"], c["rays"], win)
+    rhos = [0.002, 0.006, 0.02, 0.05, 0.04]  # odd count: the last transform carries one map
+    note("stack: same radii through the FFT path")
+    fft = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA, fft_min_taps=FORCE_FFT)
+    direct = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA, fft_min_taps=FORCE_DIRECT)
+    s64 = float(np.float32(c["rays"][2] / c["rays"][4])) * float(np.float32(c["rays"][3] / c["rays"][5])) / (d * d)
+    for k, rho in enumerate(rhos):
+        w = ld_pixel_weights(rho, d, d, GAMMA)
+        ref = normalize_convolve_exact64(oc, s64, w)
+        g = fft[k].cpu().numpy().astype(np.float64)
+        den = np.maximum(ref, 1e-6 * ref.max())
+        assert (np.abs(g - ref) / den).max() < 1e-6, rho
+        # binary32 rounding of an FP64 result: within one unit in the last place
+        big = ref > 1e-6 * ref.max()
+        ulp = np.spacing(ref[big].astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(g[big] - ref[big]) <= ulp), rho
+        # the direct binary32 path errs by at most (n + 3) 2^-24 relative (rounded weights,
+        # products, the sequential sum of n positive terms, rounded scale, last product);
+        # the transform path, rounded once, is the closer of the two
+        n = np.count_nonzero(w)
+        dd = direct[k].cpu().numpy().astype(np.float64)
+        e_direct = np.abs(dd - ref) / den
+        assert e_direct.max() <= (n + 3) * 2.0**-24, rho
+        assert (np.abs(g - ref) / den).max() <= max(e_direct.max(), 2.0**-23), rho
+
+
+def test_wide_radii_sampled_pixels():
+    # 256^2 map over 3 units (d = 0.0117), radii up to 86 pixels: 512^2 transforms
+    rays = (0.0, 0.0, 6.0, 6.0, 4096, 4096)
+    win = (0.0, 0.0, 3.0, 3.0, 256, 256)
+    d = 3.0 / 256
+    gc, oc = counts_pair(0.8, 5e-3, rays, win)
+    rhos = [0.1, 0.3, 1.0]
+    note("stack: wide radii (9, 26, 86 pixels)")
+    maps = M.convolve_stack(gc, rays, win, rhos, GAMMA)
+    s64 = float(np.float32(6.0 / 4096)) ** 2 / (d * d)
+    px = sample_pixels(256, 256, 120, 21)
+    for k, rho in enumerate(rhos):
+        ref = normalize_convolve_exact64_at(oc, s64, ld_pixel_weights(rho, d, d, GAMMA), px)
+        g = np.array([float(maps[k, j, i]) for j, i in px])
+        assert (np.abs(g - ref) / ref).max() < 1e-6, rho
+
+
+def test_seven_radius_stack_full_size():
+    # the stack of seven radii log-spaced over [0.001, 1] of a 2048^2 map (32768^2 rays):
+    # direct sums for the narrow radii, 4096^2 transforms for the rest
+    c = W.config("large")
+    win = c["window"]
+    d = win[2] / win[4]
+    note("stack: 2^30 rays on the GPU and in the oracle")
+    gc, oc = counts_pair(c["s"], c["q"], c["rays"], win)
+    rhos = stack_rhos()
+    note("stack: seven radii, gamma 0.53")
+    maps = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA)
+    again = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA)  # kept transforms
+    assert torch.equal(maps, again)
+    s32 = map_scale(c["rays"], win)
+    s64 = float(np.float32(c["rays"][2] / c["rays"][4])) ** 2 / (d * d)
+    px = sample_pixels(win[5], win[4], 48, 22)
+    for k, rho in enumerate(rhos):
+        note(f"stack: oracle weights rho={rho:.4g}")
+        w = ld_pixel_weights(rho, d, d, GAMMA)
+        if w.size < 64:  # direct sum: whole map against the binary32 mirror
+            ref = normalize_convolve_mirror32(oc, s32, w)
+            assert np.abs(maps[k].cpu().numpy() - ref).max() <= 2e-7 * float(ref.max()), rho
+        else:
+            ref = normalize_convolve_exact64_at(oc, s64, w, px)
+            g = np.array([float(maps[k, j, i]) for j, i in px])
+            assert (np.abs(g - ref) / ref).max() < 1e-6, rho
+
+
+def test_stack_argument_errors():
+    c = W.config("tiny")
+    win = c["window"]
+    gc = torch.zeros((win[5], win[4]), dtype=torch.int32, device=DEV)
+    with pytest.raises(M.MorseError) as e:
+        M.convolve_stack(gc, c["rays"], win, [0.01], 1.5)
+    assert e.value.code == -1
+    with pytest.raises(M.MorseError) as e:
+        M.convolve_stack(gc, c["rays"], win, [0.01, -0.1], 0.5)
+    assert e.value.code == -1
+    # a 512-pixel map over 2 units with rho = 8: 512 + 2 * 2049 > 4096
+    with pytest.raises(M.MorseError) as e:
+        M.convolve_stack(gc, c["rays"], win, [0.01, 8.0], 0.5)
+    assert e.value.code == -4
+    # nothing is written when a call fails
+    out = torch.full((2, win[5], win[4]), 7.0, device=DEV)
+    with pytest.raises(M.MorseError):
+        M.convolve_stack(gc, c["rays"], win, [0.01, 8.0], 0.5, out=out)
+    torch.cuda.synchronize()
+    assert bool(torch.all(out == 7.0))
