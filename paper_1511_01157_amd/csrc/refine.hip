@@ -55,16 +55,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*s_part)[NV])
   __syncthreads();
 }
 
-// One workgroup (GRAD_THREADS lanes over the points) per candidate; each thread takes
-// GSU points per iteration.
+// One workgroup (GRAD_THREADS lanes over the points) per candidate; thread k takes the
+// points k, k + GRAD_THREADS, k + 2 GRAD_THREADS, ... in increasing order.
 #ifndef MORSE_GRAD_THREADS
 #define MORSE_GRAD_THREADS 128
 #endif
-#ifndef MORSE_GSU
-#define MORSE_GSU 1
-#endif
 constexpr int GRAD_THREADS = MORSE_GRAD_THREADS;
-constexpr int GSU = MORSE_GSU;
 
 struct Eval {
   double chi2, Fs, Fb;
@@ -139,8 +135,6 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   double acc[kSums];
 #pragma unroll
   for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
-  // GSU points per thread and iteration (i, i + GRAD_THREADS, ..., so each thread
-  // takes its points in increasing order).
   auto add_point = [&](const Loc& l, const Quad& v, double wi, double wfc) {
     const float e0 = v.v10 - v.v00, e1 = v.v11 - v.v01;
     const float ax0 = v.v00 + l.fx * e0, ax1 = v.v01 + l.fx * e1;
@@ -172,49 +166,30 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
       acc[5 + 3 * k] = fma(wfc, D[k], acc[5 + 3 * k]);
     }
   };
-  // Software pipeline: the times of iteration n + 2 and the cells and weights of
-  // iteration n + 1 are in flight while iteration n is added.
-  constexpr int32_t STEP = GSU * GRAD_THREADS;
-  auto idx = [&](int32_t i, int k) -> uint32_t {  // past the end: clamped, never added
-    const int32_t j = i + k * GRAD_THREADS;
-    return (uint32_t)(j < np ? j : np - 1);
-  };
-  Loc l[GSU];
-  Quad v[GSU];
-  double wv[GSU], fv[GSU];
-  float tn[GSU];
-#pragma unroll
-  for (int k = 0; k < GSU; ++k) {
-    l[k] = locate(m, ldg(t, idx(tid, k)), t0p, iE, ca, sa, bx, by);
-    v[k] = ldq(m.quad, l[k].q);
-    wv[k] = ldg(w, idx(tid, k));
-    fv[k] = ldg(wFc, idx(tid, k));
-    tn[k] = ldg(t, idx(tid + STEP, k));
-  }
-  for (int32_t i0 = tid; i0 < np; i0 += STEP) {
-    float tnn[GSU];
-    Loc ln[GSU];
-    Quad vn[GSU];
-    double wn[GSU], fn[GSU];
-#pragma unroll
-    for (int k = 0; k < GSU; ++k) {
-      tnn[k] = ldg(t, idx(i0 + 2 * STEP, k));
-      ln[k] = locate(m, tn[k], t0p, iE, ca, sa, bx, by);
-      vn[k] = ldq(m.quad, ln[k].q);
-      wn[k] = ldg(w, idx(i0 + STEP, k));
-      fn[k] = ldg(wFc, idx(i0 + STEP, k));
-    }
-#pragma unroll
-    for (int k = 0; k < GSU; ++k)
-      if (i0 + k * GRAD_THREADS < np) add_point(l[k], v[k], wv[k], fv[k]);
-#pragma unroll
-    for (int k = 0; k < GSU; ++k) {
-      l[k] = ln[k];
-      v[k] = vn[k];
-      wv[k] = wn[k];
-      fv[k] = fn[k];
-      tn[k] = tnn[k];
-    }
+  // Software pipeline over two register sets (a, b), so that nothing is copied between
+  // iterations: while one point is added, the cell and weights of the next point and
+  // the time of the one after are in flight.  Loads past the end are clamped to the
+  // last point and never added.
+  constexpr int32_t STEP = GRAD_THREADS;
+  auto idx = [&](int32_t j) -> uint32_t { return (uint32_t)(j < np ? j : np - 1); };
+  Loc la = locate(m, ldg(t, idx(tid)), t0p, iE, ca, sa, bx, by);
+  Quad va = ldq(m.quad, la.q);
+  double wa = ldg(w, idx(tid)), fa = ldg(wFc, idx(tid));
+  float ta = ldg(t, idx(tid + STEP));
+  for (int32_t i0 = tid; i0 < np; i0 += 2 * STEP) {
+    // set b: point i0 + STEP (time ta); time of i0 + 2 STEP
+    const float tb = ldg(t, idx(i0 + 2 * STEP));
+    const Loc lb = locate(m, ta, t0p, iE, ca, sa, bx, by);
+    const Quad vb = ldq(m.quad, lb.q);
+    const double wb = ldg(w, idx(i0 + STEP)), fb = ldg(wFc, idx(i0 + STEP));
+    add_point(la, va, wa, fa);
+    // set a: point i0 + 2 STEP (time tb); time of i0 + 3 STEP
+    ta = ldg(t, idx(i0 + 3 * STEP));
+    la = locate(m, tb, t0p, iE, ca, sa, bx, by);
+    va = ldq(m.quad, la.q);
+    wa = ldg(w, idx(i0 + 2 * STEP));
+    fa = ldg(wFc, idx(i0 + 2 * STEP));
+    if (i0 + STEP < np) add_point(lb, vb, wb, fb);
   }
   block_sum<kSums>(acc, s_part);
   const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2]);
