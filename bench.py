@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-lines", action="store_true",
+                    help="skip the (untimed-step) caustic-line filter measurement")
     ap.add_argument("--no-stack", action="store_true",
                     help="skip the (untimed-step) seven-radius finite-source stack measurement")
     ap.add_argument("--pipelined", action="store_true",
@@ -395,6 +397,31 @@ def main():
                      "maps_per_s": len(rhos) / (st_ms * 1e-3), "fft_radii": n_fft,
                      "map": [c["window"][5], c["window"][4]]}
 
+        # Caustic-centred lines of this lens (sec. 4.2) through the minimum-magnification
+        # filter (sec. 4.3) on the step's map, timed apart from the step.
+        lines_rec = None
+        if not args.no_lines:
+            caus = M.caustics(c["s"], c["q"])
+            L = M.caustic_lines(caus, np.linspace(0.0, 4.0, 32), np.linspace(0.0, 2 * np.pi, 257)[:-1])
+            dl = torch.from_numpy(L).to(dev)
+            Fv = np.asarray(ev["F"])
+            a_min = 0.9 * float(Fv.max() / Fv.min())
+            best, keep, kept = M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            lf_ms = e0.elapsed_time(e1) / 5
+            w = c["window"]
+            ns = math.ceil(2.0 * 0.5 * math.hypot(w[2], w[3]) * max(w[4] / w[2], w[5] / w[3])) + 1
+            lines_rec = {"caustics": int(len(caus)), "lines": int(len(L)), "kept": int(len(kept)),
+                         "a_min": a_min, "samples_per_line": ns, "filter_ms": lf_ms,
+                         "samples_per_s": len(L) * ns / (lf_ms * 1e-3)}
+
     rays_ms, norm_ms, search_ms, refine_ms = stage
     adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
     # algorithmic lane-operations of one launch of each kernel, and their peak rate
@@ -432,6 +459,7 @@ def main():
         "adjoint_point_evals_per_s_upper": adjoint_evals / (refine_ms * 1e-3),
         "refine_improved_fraction": improved,
         "rho_stack": stack,
+        "caustic_lines": lines_rec,
         "wall_s_timed": wall,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s",

@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 4
+#define MORSE_ABI_VERSION 5
 
 enum morse_status {
   MORSE_OK = 0,
@@ -267,6 +267,58 @@ int morse_autotune_load(morse_ctx* ctx, const char* cache_path, int32_t* h_loade
 int morse_candidates_from_topk(morse_ctx* ctx, const morse_trajectories* trajs, int32_t n_events,
                                int32_t n_maps, int32_t top_k, const int64_t* d_topk_idx,
                                double* d_params, int32_t* d_event, int32_t* d_map_index);
+
+/* ------------------------------------------------------------------------------
+ * Caustic-centred trajectories (sec. 4.2: radial distances r from the centres of the
+ * caustics, scaled by their sizes, and angles phi, in place of u0 about the lens
+ * centre; Fig. 1) and the minimum-magnification filter (sec. 4.3, first optimisation:
+ * a trajectory whose magnification along its path, read from the point-source map,
+ * never reaches the minimum the light curve implies is discarded).
+ * ------------------------------------------------------------------------------ */
+
+/* The separate caustics of the binary lens (s, q) (host only, no device needed).
+ * Critical points at nphi equally spaced phases (the quartic m1 (z - x2)^2 +
+ * m2 (z - x1)^2 = e^{-i phi} (z - x1)^2 (z - x2)^2, roots by the Aberth-Ehrlich
+ * iteration); each is joined to the nearest critical point of the next phase and each
+ * connected set is one critical curve, mapped by Eq. 2 to one caustic.  Rows of
+ * h_out[n][5]: (cx, cy, half_w, half_h, size) of the caustic's bounding box, size =
+ * the larger half-side; ordered by (round(1e9 cy), cx).  *h_n = the number of
+ * caustics (1, 2 or 3); h_out may be NULL to ask for it.  Errors (morse_last_error(NULL)):
+ * EINVAL (s <= 0, q outside (0, 1], nphi outside [16, 2^20], h_n NULL), ERANGE
+ * (capacity < n). */
+int morse_caustics(double s, double q, int32_t nphi, double* h_out, int32_t capacity, int32_t* h_n);
+
+/* Lines (host only): for caustic k (rows of morse_caustics), r_j and phi_l,
+ * h_lines[(k n_r + j) n_phi + l] = (u0, alpha, shift) with alpha = phi,
+ * u0 = r S - cx sin phi + cy cos phi, shift = cx cos phi + cy sin phi: the path
+ * zeta = tau (cos a, sin a) + u0 (-sin a, cos a) passes at r S from the caustic centre,
+ * closest at tau = shift.  Errors: EINVAL (negative counts, NULL arrays). */
+int morse_caustic_lines(const double* h_caustics, int32_t n_caustics, const double* h_r, int32_t n_r,
+                        const double* h_phi, int32_t n_phi, double* h_lines);
+
+/* Minimum-magnification filter of n lines d_lines[n][3] (device FP64, as above) on one
+ * point-source map.  Each line is sampled across the map window: tau_k = fl32(tau_c -
+ * R) + k fl32(2R/(n_s - 1)) in binary32 for k < n_s = ceil(2 R kmax) + 1, with tau_c =
+ * cx cos a + cy sin a (window centre), R half the window diagonal and kmax the larger
+ * of nx/wx, ny/wy (samples at most a pixel apart); each sample is evaluated exactly as
+ * morse_search evaluates a point (t0' = 0, 1/tE = 1).  d_best[n] (float) = the largest
+ * sample (NaN if any is NaN), d_keep[n] (uint8) = d_best >= fl32(a_min).  Optional:
+ * d_kept[n] (int64) receives the kept line indices in ascending order, d_count (device
+ * int64) their number, h_count the same on the host (synchronises).  Workspace: the map
+ * packed into cells (16 B per pixel).  Errors: EINVAL (bad window, NULL arrays, a_min
+ * not finite), ERANGE (map too large to pack, more than 1e7 samples per line). */
+int morse_line_filter(morse_ctx* ctx, const morse_map_view* map, const double* d_lines, int64_t n,
+                      double a_min, float* d_best, uint8_t* d_keep, int64_t* d_kept,
+                      int64_t* d_count, int64_t* h_count);
+
+/* Trajectory list of the kept lines: d_params[(k n_t0 + a) n_tE + b][4] =
+ * (t0_a - shift tE_b, u0, tE_b, alpha) of line d_kept[k] (line k when d_kept is NULL),
+ * k < n_kept: t0 is the time of closest approach to the caustic centre.  The result is
+ * a morse_trajs list (kind MORSE_TRAJ_LIST).  h_t0, h_tE host arrays (read during the
+ * call; the call synchronises).  Errors: EINVAL (negative counts, NULL arrays, tE <= 0). */
+int morse_lines_to_trajectories(morse_ctx* ctx, const double* d_lines, const int64_t* d_kept,
+                                int64_t n_kept, const double* h_t0, int32_t n_t0, const double* h_tE,
+                                int32_t n_tE, double* d_params);
 
 /* ------------------------------------------------------------------------------
  * Gradient and refinement (candidates from the search refined on their maps).

@@ -27,7 +27,8 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
                    SEARCH_BATCHED, SEARCH_PLAIN, TRAJ_GRID, TRAJ_LIST)
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
-           "normalize_convolve", "convolve_stack", "profile_weights", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "normalize_convolve", "convolve_stack", "profile_weights", "caustics", "caustic_lines",
+           "line_filter", "lines_to_trajectories", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -260,6 +261,66 @@ def _map_views(maps):
             raise ValueError(f"map {i} must be contiguous float32 [ny, nx] matching its window")
         views[i] = MapView(m.data_ptr(), _grid(w))
     return views
+
+
+# ----------------------------------------------------- caustic-centred lines + filter
+def caustics(s, q, nphi=4096):
+    """Separate caustics of the lens (s, q): float64 [n, 5] rows (cx, cy, half_w, half_h, size)."""
+    lib = _abi.load()
+    n = ctypes.c_int32()
+    rc = lib.morse_caustics(float(s), float(q), int(nphi), None, 0, ctypes.byref(n))
+    if rc != _abi.MORSE_OK:
+        raise MorseError(rc, lib.morse_last_error(None).decode())
+    out = np.empty((n.value, 5), dtype=np.float64)
+    rc = lib.morse_caustics(float(s), float(q), int(nphi), out.ctypes.data, n.value, ctypes.byref(n))
+    if rc != _abi.MORSE_OK:
+        raise MorseError(rc, lib.morse_last_error(None).decode())
+    return out
+
+
+def caustic_lines(caus, r, phi):
+    """Lines float64 [n_caustics * n_r * n_phi, 3] (u0, alpha, shift), caustic-major."""
+    lib = _abi.load()
+    c = np.ascontiguousarray(np.asarray(caus, dtype=np.float64).reshape(-1, 5))
+    rr = np.ascontiguousarray(np.asarray(r, dtype=np.float64).reshape(-1))
+    pp = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+    out = np.empty((len(c) * len(rr) * len(pp), 3), dtype=np.float64)
+    rc = lib.morse_caustic_lines(c.ctypes.data, len(c), rr.ctypes.data, len(rr), pp.ctypes.data,
+                                 len(pp), out.ctypes.data)
+    if rc != _abi.MORSE_OK:
+        raise MorseError(rc, lib.morse_last_error(None).decode())
+    return out
+
+
+def line_filter(amap, window, lines, a_min, ctx=None):
+    """Minimum-magnification filter of device lines float64 [n, 3] on one map:
+    (best float32 [n], keep uint8 [n], kept int64 [count] ascending)."""
+    ctx = ctx or Context.get(_device_of(amap))
+    if lines.dtype != torch.float64 or not lines.is_contiguous() or lines.shape[-1] != 3:
+        raise ValueError("lines must be contiguous float64 [n, 3]")
+    n = lines.shape[0]
+    best = torch.empty(n, dtype=torch.float32, device=lines.device)
+    keep = torch.empty(n, dtype=torch.uint8, device=lines.device)
+    kept = torch.empty(max(n, 1), dtype=torch.int64, device=lines.device)
+    count = ctypes.c_int64()
+    view = MapView(amap.data_ptr(), _grid(window))
+    ctx.check(ctx.lib.morse_line_filter(ctx.handle, ctypes.byref(view), _ptr(lines), n, float(a_min),
+                                        _ptr(best), _ptr(keep), _ptr(kept), None, ctypes.byref(count)))
+    return best, keep, kept[:count.value]
+
+
+def lines_to_trajectories(lines, kept, t0, tE, ctx=None):
+    """Trajectory rows float64 [n_kept * n_t0 * n_tE, 4] (t0, u0, tE, alpha) of the kept
+    lines (all lines when kept is None); t0 = time of closest approach to the caustic centre."""
+    ctx = ctx or Context.get(_device_of(lines))
+    a = np.ascontiguousarray(np.asarray(t0, dtype=np.float64).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(tE, dtype=np.float64).reshape(-1))
+    nk = lines.shape[0] if kept is None else kept.shape[0]
+    out = torch.empty((nk * len(a) * len(b), 4), dtype=torch.float64, device=lines.device)
+    ctx.check(ctx.lib.morse_lines_to_trajectories(ctx.handle, _ptr(lines), _ptr(kept), nk,
+                                                  a.ctypes.data, len(a), b.ctypes.data, len(b),
+                                                  _ptr(out)))
+    return out
 
 
 def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,

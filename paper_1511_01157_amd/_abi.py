@@ -71,6 +71,12 @@ SIGNATURES = {
                                        c_void_p, c_int32, c_double, c_int32, c_void_p]),
     "morse_profile_weights": (c_int32, [c_double, c_double, c_double, c_double, c_void_p, c_int64,
                                         POINTER(c_int32), POINTER(c_int32)]),
+    "morse_caustics": (c_int32, [c_double, c_double, c_int32, c_void_p, c_int32, POINTER(c_int32)]),
+    "morse_caustic_lines": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
+    "morse_line_filter": (c_int32, [c_void_p, POINTER(MapView), c_void_p, c_int64, c_double, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "morse_lines_to_trajectories": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
+                                              c_void_p, c_int32, c_void_p]),
     "morse_build_map": (c_int32, [c_void_p, c_double, c_double, POINTER(Grid2D), POINTER(Grid2D),
                                   c_double, c_void_p, c_void_p, POINTER(MapStats)]),
     "morse_search": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves),

@@ -1,0 +1,184 @@
+// Caustic-centred trajectory lines on gfx950: the minimum-magnification filter and the
+// expansion of the kept lines into trajectory lists.
+//
+// Sec. 4.2 of McDougall & Albrow 2015 searches straight trajectories at radial distances
+// from the caustic centres; sec. 4.3 first discards every trajectory whose magnification
+// along its path, read from the point-source map, stays below the minimum that the
+// light curve implies.  A line here is (u0, alpha, shift): the path tau (cos a, sin a) +
+// u0 (-sin a, cos a), whose closest approach to its caustic centre is at tau = shift.
+//
+// Filter layout.  One wavefront per line, lanes over the samples: the line is sampled
+// across the map window at spacing h <= 1 pixel, each sample exactly as the search
+// samples a point (the same binary32 geometry and bilinear blend of the packed cells,
+// the single-lens value off the map), and the largest value (NaN if any sample is NaN)
+// decides.  The kept lines are then listed in ascending order by a three-step
+// stream compaction (counts per block, one scan, scatter), so the result does not
+// depend on the schedule.
+
+#include "lines.h"
+
+namespace morse {
+
+namespace {
+
+constexpr int kFilterThreads = 256;
+constexpr int kCompactThreads = 256;
+constexpr int kCompactPer = 4;  // flags per thread
+constexpr int kCompactBlock = kCompactThreads * kCompactPer;
+
+// max that propagates NaN (as a maximum over an array does)
+__device__ __forceinline__ float nanmax(float a, float b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
+__global__ __launch_bounds__(kFilterThreads) void k_line_filter(LineFilterArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (kFilterThreads / kWave);
+  for (int64_t l = blockIdx.x * (int64_t)(kFilterThreads / kWave) + threadIdx.x / kWave; l < a.n;
+       l += waves) {
+    const double u0 = a.lines[3 * l], al = a.lines[3 * l + 1];
+    double sn, cn;
+    sincos(al, &sn, &cn);
+    const float ca = (float)cn, sa = (float)sn;
+    const float bx = (float)(-u0 * sn), by = (float)(u0 * cn);
+    const double tau_c = a.cxw * cn + a.cyw * sn;
+    const float lo = (float)(tau_c - a.half_diag);
+    float best = -__builtin_inff();
+    for (int k = lane; k < a.ns; k += kWave) {
+      const float tau = lo + (float)k * a.h;
+      best = nanmax(best, sample_A(a.m, tau, 0.0f, 1.0f, ca, sa, bx, by));
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) best = nanmax(best, __shfl_xor(best, off));
+    if (lane == 0) {
+      a.best[l] = best;
+      a.keep[l] = best >= a.amin ? 1 : 0;
+    }
+  }
+}
+
+// Block b counts the set flags of keep[b B, (b + 1) B).
+__global__ __launch_bounds__(kCompactThreads) void k_compact_count(const uint8_t* keep, int64_t n,
+                                                                   int64_t* counts) {
+  __shared__ int s[kCompactThreads];
+  const int64_t base = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x * kCompactPer;
+  int c = 0;
+  for (int j = 0; j < kCompactPer; ++j)
+    if (base + j < n) c += keep[base + j] ? 1 : 0;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = kCompactThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = s[0];
+}
+
+// Exclusive scan of the nb block counts in place (one workgroup, chunk by chunk); the
+// total goes to *total.
+__global__ __launch_bounds__(kCompactThreads) void k_compact_scan(int64_t* counts, int64_t nb,
+                                                                  int64_t* total) {
+  __shared__ int64_t s[kCompactThreads];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kCompactThreads) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nb ? counts[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 1; w < kCompactThreads; w <<= 1) {  // inclusive Hillis-Steele scan
+      const int64_t add = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) counts[i] = carry + s[threadIdx.x] - v;
+    carry += s[kCompactThreads - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// Block b writes the indices of its set flags from position offsets[b] on.
+__global__ __launch_bounds__(kCompactThreads) void k_compact_scatter(const uint8_t* keep, int64_t n,
+                                                                     const int64_t* offsets,
+                                                                     int64_t* kept) {
+  __shared__ int s[kCompactThreads];
+  const int64_t base = blockIdx.x * (int64_t)kCompactBlock + threadIdx.x * kCompactPer;
+  int c = 0;
+  for (int j = 0; j < kCompactPer; ++j)
+    if (base + j < n) c += keep[base + j] ? 1 : 0;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 1; w < kCompactThreads; w <<= 1) {
+    const int add = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t pos = offsets[blockIdx.x] + s[threadIdx.x] - c;
+  for (int j = 0; j < kCompactPer; ++j)
+    if (base + j < n && keep[base + j]) kept[pos++] = base + j;
+}
+
+__global__ __launch_bounds__(256) void k_lines_traj(const double* lines, const int64_t* kept,
+                                                    int64_t n_kept, const double* t0, int32_t n_t0,
+                                                    const double* tE, int32_t n_tE,
+                                                    double* params) {
+  const int64_t per = (int64_t)n_t0 * n_tE;
+  const int64_t total = n_kept * per;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = j / per;
+    const int32_t a = (int32_t)((j / n_tE) % n_t0), b = (int32_t)(j % n_tE);
+    const int64_t l = kept ? kept[k] : k;
+    const double u0 = lines[3 * l], al = lines[3 * l + 1], shift = lines[3 * l + 2];
+    params[4 * j] = t0[a] - shift * tE[b];
+    params[4 * j + 1] = u0;
+    params[4 * j + 2] = tE[b];
+    params[4 * j + 3] = al;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_line_filter(const LineFilterArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (!a.lines || !a.best || !a.keep || a.ns < 2 || !a.m.quad) return hipErrorInvalidValue;
+  const int64_t per_block = kFilterThreads / kWave;
+  int64_t blocks = (a.n + per_block - 1) / per_block;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_line_filter, dim3((unsigned)blocks), dim3(kFilterThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t compact_scratch_elems(int64_t n) { return (size_t)((n + kCompactBlock - 1) / kCompactBlock) + 1; }
+
+hipError_t launch_compact(const uint8_t* keep, int64_t n, int64_t* scratch, int64_t* kept,
+                          int64_t* d_count, hipStream_t st) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const int64_t nb = (n + kCompactBlock - 1) / kCompactBlock;
+  if (nb > (int64_t)1 << 30) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_compact_count, dim3((unsigned)nb), dim3(kCompactThreads), 0, st, keep, n,
+                     scratch);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(kCompactThreads), 0, st, scratch, nb, d_count);
+  if (kept)
+    hipLaunchKernelGGL(k_compact_scatter, dim3((unsigned)nb), dim3(kCompactThreads), 0, st, keep,
+                       n, scratch, kept);
+  return hipGetLastError();
+}
+
+hipError_t launch_lines_to_traj(const double* lines, const int64_t* kept, int64_t n_kept,
+                                const double* t0, int32_t n_t0, const double* tE, int32_t n_tE,
+                                double* params, hipStream_t st) {
+  const int64_t total = n_kept * (int64_t)n_t0 * n_tE;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_lines_traj, dim3((unsigned)blocks), dim3(256), 0, st, lines, kept, n_kept,
+                     t0, n_t0, tE, n_tE, params);
+  return hipGetLastError();
+}
+
+}  // namespace morse

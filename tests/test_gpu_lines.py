@@ -1,0 +1,77 @@
+"""GPU parity of the caustic-centred (r, phi) trajectories (sec. 4.2) and the
+minimum-magnification line filter (sec. 4.3), through the C ABI.  The maps are the
+oracle's own (uploaded), so the filter's largest samples must equal the oracle's
+binary32 mirror bit for bit, and the keep flags, the kept-line list and the expanded
+trajectory lists exactly; a search over the kept trajectories is checked against the
+oracle's chi-square."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_01157_amd as M
+import workloads as W
+from oracle.lines import caustic_lines, line_filter_mirror32, lines_to_trajectories
+from oracle.search import search_mirror32
+from tests.helpers import note, oracle_map, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def filter_case(amap, win, lines, a_min):
+    dmap = torch.from_numpy(np.ascontiguousarray(amap)).to(DEV)
+    dl = torch.from_numpy(lines).to(DEV)
+    best, keep, kept = M.line_filter(dmap, win, dl, a_min)
+    ob, ok = line_filter_mirror32(amap, win, lines, a_min)
+    assert np.array_equal(best.cpu().numpy().view(np.uint32), ob.view(np.uint32))
+    assert np.array_equal(keep.cpu().numpy().astype(bool), ok)
+    assert np.array_equal(kept.cpu().numpy(), np.flatnonzero(ok))
+    return dmap, dl, kept, ok
+
+
+def test_filter_tiny_map_all_caustics():
+    c = W.config("tiny")
+    note("lines: tiny oracle map")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], c["window"], 0.0)
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.0, 0.25, 0.5, 1.0, 2.0, 4.0]),
+                          np.linspace(0.0, 2 * np.pi, 65)[:-1])
+    _, _, kept, ok = filter_case(amap, c["window"], lines, 3.0)
+    assert 0 < ok.sum() < len(ok)
+    # thresholds that keep everything or nothing, and lines that miss the window
+    filter_case(amap, c["window"], lines, 0.0)
+    _, _, kept, ok = filter_case(amap, c["window"], lines, 1e30)
+    assert len(kept) == 0
+    far = np.array([[5.0, 0.3, 0.0], [-7.5, 2.0, 1.0]])
+    filter_case(amap, c["window"], far, 1.0)
+
+
+def test_filter_and_search_large_map():
+    c = W.config("large")
+    win = c["window"]
+    note("lines: large oracle map (2^30 rays)")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, c["rho"])
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.linspace(0.0, 3.0, 16), np.linspace(0.0, 2 * np.pi, 129)[:-1])
+    ev = W.load_lightcurve("large")
+    F = np.asarray(ev["F"])
+    a_min = 0.9 * float(F.max() / F.min())  # peak over baseline flux bounds A from below
+    note(f"lines: filter {len(lines)} lines, A_min {a_min:.3f}")
+    dmap, dl, kept, ok = filter_case(amap, win, lines, a_min)
+    assert 0 < len(kept) < len(lines)
+    t0 = np.linspace(-10.0, 10.0, 8)  # around the event's peak time
+    tE = np.geomspace(5.0, 100.0, 6)
+    note(f"lines: {len(kept)} kept lines -> trajectories")
+    P = M.lines_to_trajectories(dl, kept, t0, tE)
+    oP = lines_to_trajectories(lines, np.flatnonzero(ok), t0, tE)
+    assert np.array_equal(P.cpu().numpy(), oP)
+    # the caustic-centred trajectories through the batched search
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    trajs = M.list_trajectories(P)
+    r = M.search([(dmap, win)], lcs, trajs, "batched", top_k=64)
+    g = r["chi2"][0, 0].cpu().numpy()
+    order = np.lexsort((np.arange(g.size), g))[:64]
+    assert np.array_equal(r["topk_idx"][0].cpu().numpy(), order)
+    idx = np.unique(np.concatenate([order[:8], np.random.default_rng(5).choice(len(oP), 40, replace=False)]))
+    oc = search_mirror32(amap, win, ev["tt"], ev["F"], ev["w"], oP[idx], ev["t_ref"])[0]
+    assert rel_err(g[idx], oc).max() < 1e-6
