@@ -18,8 +18,9 @@ a downhill simplex (Nelder & Mead 1965) for the chi-square minimum, with up to 5
     ones of equal value; NaN counts as +inf;
   * stop when f_worst - f_best <= ftol |f_best| or after max_iter iterations;
   * FP64 vertex arithmetic in the order written below; chi-square of a vertex is the
-    search's chi-square (binary32 samples, FP64 fit) of the trajectory
-    (t0' - shift tE, u0, tE, alpha).
+    search's chi-square (binary32 samples, profiled FP64 fit) of the trajectory
+    (t0' - shift tE, u0, tE, alpha), its sums taken exactly rounded (math.fsum), as
+    one trajectory at a time is evaluated.
 """
 from __future__ import annotations
 
@@ -27,7 +28,7 @@ import math
 
 import numpy as np
 
-from .search import search_mirror32
+from .sampling import sample_mirror32, traj_constants32
 
 __all__ = ["nelder_mead", "line_chi2", "line_simplex"]
 
@@ -87,12 +88,34 @@ def nelder_mead(func, x0, steps, max_iter=5000, ftol=1e-10):
     return x[0], f[0], it
 
 
+def _chi2_one(A, F, w):
+    """Profiled chi-square of one trajectory (Eqs. 5-6 in the centred form of the search,
+    degenerate when S_aa <= 1e-12 S_AA), every sum exactly rounded (math.fsum)."""
+    a = np.asarray(A, dtype=np.float64)
+    F = np.asarray(F, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    Sw = math.fsum(w)
+    abar = math.fsum(w * a) / Sw
+    Fbar = math.fsum(w * F) / Sw
+    SAA = math.fsum(w * a * a)
+    da = a - abar
+    Saa = math.fsum(w * da * da)
+    if Saa > 1e-12 * SAA:
+        Fs = math.fsum(w * da * (F - Fbar)) / Saa
+        Fb = Fbar - Fs * abar
+    else:
+        Fs, Fb = 0.0, Fbar
+    r = F - Fs * a - Fb
+    return math.fsum(w * r * r)
+
+
 def line_chi2(amap, window, tt, F, w, t_ref, line, x):
     """Chi-square of the line's trajectory at x = (t0', ln tE)."""
     u0, al, shift = (float(v) for v in line)
     tE = math.exp(x[1])
     p = np.array([[x[0] - shift * tE, u0, tE, al]])
-    return float(search_mirror32(amap, window, tt, F, w, p, t_ref)[0][0])
+    A = sample_mirror32(amap, window, traj_constants32(p, t_ref), tt)[0]
+    return _chi2_one(A, F, w)
 
 
 def line_simplex(amap, window, tt, F, w, t_ref, line, start, steps, max_iter=5000, ftol=1e-10):

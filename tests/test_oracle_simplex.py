@@ -57,3 +57,20 @@ def test_line_simplex_recovers_single_lens_truth():
     t0f, tEf, chi2, it = line_simplex(amap, win, tt, F, w, 0.0, line, (0.0, 15.0), (2.0, 0.2),
                                       max_iter=2000, ftol=1e-12)
     assert abs(t0f - t0) < 2e-3 and abs(tEf / tE - 1) < 1e-3 and chi2 < 1e-2
+
+
+def test_line_chi2_equals_the_search_chi2():
+    from oracle.search import search_mirror32
+    rng = np.random.default_rng(8)
+    nx = 256
+    win = (0.0, 0.0, 2.0, 2.0, nx, nx)
+    amap = (1.0 + rng.random((nx, nx))).astype(np.float32)
+    t = np.sort(rng.uniform(-30, 30, 300))
+    F = 1.0 + rng.random(300)
+    w = 1.0 / (0.01 + 0.01 * rng.random(300)) ** 2
+    tt = (t - 5.0).astype(np.float32)
+    for line, x in (((0.1, 0.4, 0.2), (1.0, math.log(18.0))), ((0.6, 2.5, -0.3), (-4.0, math.log(40.0)))):
+        u0, al, shift = line
+        tE = math.exp(x[1])
+        ref = search_mirror32(amap, win, tt, F, w, np.array([[x[0] - shift * tE, u0, tE, al]]), 5.0)[0][0]
+        assert line_chi2(amap, win, tt, F, w, 5.0, line, x) == pytest.approx(ref, rel=1e-12)
