@@ -421,6 +421,24 @@ def main():
             lines_rec = {"caustics": int(len(caus)), "lines": int(len(L)), "kept": int(len(kept)),
                          "a_min": a_min, "samples_per_line": ns, "filter_ms": lf_ms,
                          "samples_per_s": len(L) * ns / (lf_ms * 1e-3)}
+            # downhill simplex over (t0', ln tE) of every kept line (sec. 4.2), from the
+            # single-lens estimate (t0', tE) = (0, 20)
+            kl = dl[kept].contiguous()
+            st = torch.tensor([[0.0, 20.0]], dtype=torch.float64, device=dev).repeat(len(kl), 1)
+            sx_opts = dict(max_iter=5000, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
+            M.line_simplex(maps, lcs, kl, st, ctx=ctx_b, **sx_opts)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            sx = M.line_simplex(maps, lcs, kl, st, ctx=ctx_b, **sx_opts)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sx_ms = e0.elapsed_time(e1)
+            its = sx[3].double()
+            lines_rec["simplex"] = {"lines": int(len(kl)), "ms": sx_ms, "max_iter": 5000,
+                                    "iterations_mean": float(its.mean()),
+                                    "iterations_max": int(its.max()),
+                                    "best_chi2": float(sx[0].min()),
+                                    "simplex_iterations_per_s": float(its.sum()) / (sx_ms * 1e-3)}
 
     rays_ms, norm_ms, search_ms, refine_ms = stage
     adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active

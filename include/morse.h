@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 5
+#define MORSE_ABI_VERSION 6
 
 enum morse_status {
   MORSE_OK = 0,
@@ -319,6 +319,30 @@ int morse_line_filter(morse_ctx* ctx, const morse_map_view* map, const double* d
 int morse_lines_to_trajectories(morse_ctx* ctx, const double* d_lines, const int64_t* d_kept,
                                 int64_t n_kept, const double* h_t0, int32_t n_t0, const double* h_tE,
                                 int32_t n_tE, double* d_params);
+
+/* Downhill simplex along lines (sec. 4.2: each (r, phi) trajectory runs a simplex for
+ * the chi-square minimum over its times; sec. 5: up to 5000 steps).  One simplex per
+ * (line, map) over x = (t0', ln tE), t0' the time of closest approach to the caustic
+ * centre (the trajectory is (t0' - shift tE, u0, tE, alpha) of line (u0, alpha,
+ * shift)), from d_start[line] = (t0', tE) and the vertices x0 + (step_t0, 0),
+ * x0 + (0, step_ln_tE).  Reflection 1, expansion 2, contraction 1/2, shrink 1/2 with
+ * the acceptance rules of Lagarias et al. (1998); vertices in a stable chi-square order
+ * (a new vertex after old ones of equal value, NaN as +inf); stop when f_worst -
+ * f_best <= ftol |f_best| or after max_iter iterations.  Chi-square as morse_search
+ * computes it, for light curve `event`.  Outputs [n_lines][n_maps]: the best vertex's
+ * chi-square, t0', tE and the iterations taken.  d_lines [n_lines][3] and d_start
+ * [n_lines][2] are device FP64.  Several maps (a finite-source stack) give the source
+ * radius as a map index.  Errors: EINVAL (as morse_chi2_grad; bad event, opts, NULL
+ * arrays), ERANGE (maps too large to pack). */
+typedef struct {
+  int32_t max_iter; /* 5000 */
+  int32_t reserved;
+  double step_t0, step_ln_tE, ftol;
+} morse_simplex_opts;
+int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                       const morse_lightcurves* lcs, int32_t event, const double* d_lines,
+                       int64_t n_lines, const double* d_start, const morse_simplex_opts* opts,
+                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters);
 
 /* ------------------------------------------------------------------------------
  * Gradient and refinement (candidates from the search refined on their maps).

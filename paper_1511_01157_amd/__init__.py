@@ -28,7 +28,7 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
            "normalize_convolve", "convolve_stack", "profile_weights", "caustics", "caustic_lines",
-           "line_filter", "lines_to_trajectories", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "line_filter", "lines_to_trajectories", "line_simplex", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -321,6 +321,29 @@ def lines_to_trajectories(lines, kept, t0, tE, ctx=None):
                                                   a.ctypes.data, len(a), b.ctypes.data, len(b),
                                                   _ptr(out)))
     return out
+
+
+def line_simplex(maps, lcs: LightCurveBatch, lines, start, event=0, max_iter=5000, step_t0=2.0,
+                 step_ln_tE=0.2, ftol=1e-10, ctx=None):
+    """Downhill simplex over (t0', ln tE) of every device line [n, 3] on every map, from
+    start [n, 2] (t0', tE): (chi2, t0', tE, iterations), each [n, n_maps]."""
+    ctx = ctx or Context.get(_device_of(lines))
+    views = _map_views(maps)
+    for t, k in ((lines, 3), (start, 2)):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.shape[-1] != k:
+            raise ValueError("lines [n, 3] and start [n, 2] must be contiguous float64")
+    n = lines.shape[0]
+    shape = (n, len(maps))
+    chi2 = torch.empty(shape, dtype=torch.float64, device=lines.device)
+    t0 = torch.empty(shape, dtype=torch.float64, device=lines.device)
+    tE = torch.empty(shape, dtype=torch.float64, device=lines.device)
+    it = torch.empty(shape, dtype=torch.int32, device=lines.device)
+    opts = _abi.SimplexOpts(int(max_iter), 0, float(step_t0), float(step_ln_tE), float(ftol))
+    lc = lcs.abi()
+    ctx.check(ctx.lib.morse_line_simplex(ctx.handle, views, len(maps), ctypes.byref(lc), int(event),
+                                         _ptr(lines), n, _ptr(start), ctypes.byref(opts), _ptr(chi2),
+                                         _ptr(t0), _ptr(tE), _ptr(it)))
+    return chi2, t0, tE, it
 
 
 def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,

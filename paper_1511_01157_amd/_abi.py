@@ -46,6 +46,11 @@ class SearchOut(ctypes.Structure):
                 ("reserved", c_int32), ("d_topk_chi2", c_void_p), ("d_topk_idx", c_void_p)]
 
 
+class SimplexOpts(ctypes.Structure):
+    _fields_ = [("max_iter", c_int32), ("reserved", c_int32), ("step_t0", c_double),
+                ("step_ln_tE", c_double), ("ftol", c_double)]
+
+
 class LbfgsOpts(ctypes.Structure):
     _fields_ = [("steps", c_int32), ("history", c_int32), ("max_ls", c_int32),
                 ("reserved", c_int32), ("c1", c_double), ("shrink", c_double)]
@@ -77,6 +82,9 @@ SIGNATURES = {
                                     c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
     "morse_lines_to_trajectories": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                               c_void_p, c_int32, c_void_p]),
+    "morse_line_simplex": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves), c_int32,
+                                     c_void_p, c_int64, c_void_p, POINTER(SimplexOpts), c_void_p,
+                                     c_void_p, c_void_p, c_void_p]),
     "morse_build_map": (c_int32, [c_void_p, c_double, c_double, POINTER(Grid2D), POINTER(Grid2D),
                                   c_double, c_void_p, c_void_p, POINTER(MapStats)]),
     "morse_search": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves),

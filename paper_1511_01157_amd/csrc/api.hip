@@ -22,6 +22,7 @@
 #include "internal.h"
 #include "stack.h"
 #include "lines.h"
+#include "simplex.h"
 
 using namespace morse;
 
@@ -1773,6 +1774,47 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   return MORSE_OK;
 }
 }  // namespace
+
+int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                       const morse_lightcurves* lcs, int32_t event, const double* d_lines,
+                       int64_t n_lines, const double* d_start, const morse_simplex_opts* opts,
+                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  Plan pl;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n_lines, pl, i_sums, i_wF, i_quad))) return rc;
+  if (event < 0 || event >= lcs->n_events) return fail(ctx, MORSE_EINVAL, "event %d out of range", event);
+  if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
+  if (opts->max_iter < 0) return fail(ctx, MORSE_EINVAL, "max_iter < 0");
+  if (!(std::isfinite(opts->step_t0) && std::isfinite(opts->step_ln_tE) && std::isfinite(opts->ftol) &&
+        opts->ftol >= 0.0))
+    return fail(ctx, MORSE_EINVAL, "steps and ftol must be finite, ftol >= 0");
+  if (n_lines == 0) return MORSE_OK;
+  if (!d_lines || !d_start || !d_chi2 || !d_t0 || !d_tE || !d_iters)
+    return fail(ctx, MORSE_EINVAL, "NULL device array");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  SimplexArgs a{};
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  a.maps = d_maps;
+  a.n_maps = n_maps;
+  a.event = event;
+  a.lines = d_lines;
+  a.n_lines = n_lines;
+  a.start = d_start;
+  a.d_t0 = opts->step_t0;
+  a.d_ln_tE = opts->step_ln_tE;
+  a.ftol = opts->ftol;
+  a.max_iter = opts->max_iter;
+  a.chi2 = d_chi2;
+  a.t0 = d_t0;
+  a.tE = d_tE;
+  a.iters = d_iters;
+  HIP_TRY(ctx, launch_line_simplex(a, ctx->stream));
+  return MORSE_OK;
+}
 
 int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                     const morse_lightcurves* lcs, int64_t n, const double* d_params,

@@ -1,0 +1,77 @@
+"""GPU parity of the downhill simplex along caustic-centred lines (sec. 4.2) through the
+C ABI (morse_line_simplex).  A simplex path branches on chi-square comparisons, so the
+gate is per evaluation: the GPU's final chi-square equals the oracle's chi-square of
+the GPU's final vertex (1e-6), it never exceeds the start's, and most endpoints equal
+the oracle's own simplex run (same iterations, chi-square within 1e-9)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1511_01157_amd as M
+import workloads as W
+from oracle.lines import caustic_lines
+from oracle.maps import disk_pixel_weights, map_scale, normalize_convolve_mirror32
+from oracle.simplex import line_chi2, line_simplex
+from tests.helpers import note, oracle_map, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def run_case(amaps, win, ev, lines, start, opts, n_path):
+    dmaps = [(torch.from_numpy(np.ascontiguousarray(a)).to(DEV), win) for a in amaps]
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    chi2, t0, tE, it = M.line_simplex(dmaps, lcs, torch.from_numpy(lines).to(DEV),
+                                      torch.from_numpy(start).to(DEV), **opts)
+    chi2, t0, tE, it = (x.cpu().numpy() for x in (chi2, t0, tE, it))
+    args = (ev["tt"], ev["F"], ev["w"], ev["t_ref"])
+    same = []
+    for l in range(len(lines)):
+        for k, amap in enumerate(amaps):
+            x = (t0[l, k], math.log(tE[l, k]))
+            oc = line_chi2(amap, win, *args, lines[l], x)
+            assert rel_err(chi2[l, k], oc) < 1e-6, (l, k)
+            c_start = line_chi2(amap, win, *args, lines[l], (start[l, 0], math.log(start[l, 1])))
+            assert chi2[l, k] <= c_start * (1 + 1e-12), (l, k)
+            assert 0 <= it[l, k] <= opts["max_iter"]
+            if len(same) < n_path:
+                o = line_simplex(amap, win, *args, lines[l], start[l],
+                                 (opts["step_t0"], opts["step_ln_tE"]), opts["max_iter"], opts["ftol"])
+                same.append(o[3] == it[l, k] and rel_err(o[2], chi2[l, k]) < 1e-9)
+    return same, it
+
+
+def test_simplex_tiny_two_maps():
+    c = W.config("tiny")
+    win = c["window"]
+    note("simplex: tiny oracle maps")
+    counts, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, 0.0)
+    d = win[2] / win[4]
+    amap2 = normalize_convolve_mirror32(counts, map_scale(c["rays"], win), disk_pixel_weights(0.02, d, d))
+    ev = W.load_lightcurve("tiny")
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.0, 0.5, 1.5]), np.linspace(0.0, 2 * np.pi, 9)[:-1])
+    start = np.tile([2.0, 15.0], (len(lines), 1))
+    opts = dict(max_iter=300, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
+    note(f"simplex: {len(lines)} lines x 2 maps")
+    same, it = run_case([amap, amap2], win, ev, lines, start, opts, n_path=48)
+    assert np.mean(same) >= 0.75, same
+    assert it.max() > 10
+
+
+def test_simplex_large_map_kept_lines():
+    c = W.config("large")
+    win = c["window"]
+    note("simplex: large oracle map (2^30 rays)")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, c["rho"])
+    ev = W.load_lightcurve("large")
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.linspace(0.0, 2.0, 4), np.linspace(0.0, 2 * np.pi, 17)[:-1])
+    rng = np.random.default_rng(9)
+    start = np.stack([rng.uniform(-5, 5, len(lines)), rng.uniform(10, 40, len(lines))], axis=1)
+    opts = dict(max_iter=200, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
+    note(f"simplex: {len(lines)} lines on the 2048^2 map")
+    same, _ = run_case([amap], win, ev, lines, start, opts, n_path=12)
+    assert np.mean(same) >= 0.75, same
