@@ -1801,6 +1801,7 @@ int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_map
   a.maps = d_maps;
   a.n_maps = n_maps;
   a.event = event;
+  a.n_points = (int32_t)(lcs->h_offsets[event + 1] - lcs->h_offsets[event]);
   a.lines = d_lines;
   a.n_lines = n_lines;
   a.start = d_start;

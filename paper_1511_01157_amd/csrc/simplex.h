@@ -11,6 +11,7 @@ struct SimplexArgs {
   int32_t n_maps;
   LcView lc;             // prepared light curves (wFc and per-event sums)
   int32_t event;         // the event every line is fitted to
+  int32_t n_points;      // its number of points (host copy)
   const double* lines;   // [n_lines][3] (u0, alpha, shift)
   int64_t n_lines;
   const double* start;   // [n_lines][2] (t0', tE)

@@ -7,7 +7,7 @@
 // x = (t0', ln tE) (t0' the time of closest approach to the caustic centre) in
 // registers, identical on every lane, and evaluates each vertex's chi-square with the
 // lanes over the light-curve points (four per lane and pass, their loads in flight
-// together): binary32 samples as in the search, FP64 sums of the centred one-pass fit
+// together; light curves of up to 3072 points are first copied to LDS): binary32 samples as in the search, FP64 sums of the centred one-pass fit
 // (w b, w b^2, b w (F - Fbar) with b = A - 1) combined in a fixed order (wavefront
 // reduce-scatter, then the four wavefronts in order), and a direct second pass of
 // w r^2 when the fit is degenerate or flagged as cancellation-prone.  The simplex steps
@@ -27,6 +27,7 @@ namespace {
 constexpr int kItemThreads = 256;  // one workgroup (four wavefronts) per (line, map)
 constexpr int kItemWaves = kItemThreads / kWave;
 constexpr int kUnroll = 4;  // points per lane and iteration of a chi-square pass
+constexpr int kStagePoints = 3072;  // light curves up to this length go to LDS (60 KiB)
 
 struct Vertex {
   double x0, x1, f;
@@ -58,8 +59,13 @@ __device__ __forceinline__ void block_sums(double (&v)[N], double (*s_red)[4]) {
   __syncthreads();
 }
 
+// With kStaged the light curve's t, w and w (F - Fbar) are copied to LDS once per
+// workgroup (n_points <= kStagePoints) and every evaluation reads them from there.
+template <bool kStaged>
 __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
   __shared__ double s_red[kItemWaves][4];
+  __shared__ float s_t[kStaged ? kStagePoints : 1];
+  __shared__ double s_w[kStaged ? kStagePoints : 1], s_f[kStaged ? kStagePoints : 1];
   const int tid = threadIdx.x;
   const int64_t items = a.n_lines * a.n_maps;
   const int32_t e = a.event;
@@ -69,6 +75,14 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
   const double* w = a.lc.w + p0;
   const double* wFc = a.lc.wFc + p0;
   const double* F = a.lc.F + p0;
+  if (kStaged) {
+    for (int32_t i = tid; i < np; i += kItemThreads) {
+      s_t[i] = t[i];
+      s_w[i] = w[i];
+      s_f[i] = wFc[i];
+    }
+    __syncthreads();
+  }
   const double t_ref = uniform(a.lc.t_ref[e]);
   const double Sw = uniform(a.lc.sums[3 * e]), Fbar = uniform(a.lc.sums[3 * e + 1]),
                V = uniform(a.lc.sums[3 * e + 2]);
@@ -96,10 +110,10 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
         for (int k = 0; k < kUnroll; ++k) {
           const int32_t j = i0 + k * kItemThreads;
           const uint32_t jj = (uint32_t)(j < np ? j : np - 1);
-          lc[k] = locate(m, ldg(t, jj), t0p, iE, ca, sa, bx, by);
+          lc[k] = locate(m, kStaged ? s_t[jj] : ldg(t, jj), t0p, iE, ca, sa, bx, by);
           q[k] = ldq(m.quad, lc[k].q);
-          wv[k] = ldg(w, jj);
-          fv[k] = ldg(wFc, jj);
+          wv[k] = kStaged ? s_w[jj] : ldg(w, jj);
+          fv[k] = kStaged ? s_f[jj] : ldg(wFc, jj);
         }
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
@@ -240,7 +254,10 @@ hipError_t launch_line_simplex(const SimplexArgs& a, hipStream_t st) {
   if (items <= 0) return hipSuccess;
   int64_t blocks = items;
   if (blocks > (1 << 20)) blocks = 1 << 20;
-  hipLaunchKernelGGL(k_line_simplex, dim3((unsigned)blocks), dim3(kItemThreads), 0, st, a);
+  if (a.n_points <= kStagePoints)
+    hipLaunchKernelGGL(k_line_simplex<true>, dim3((unsigned)blocks), dim3(kItemThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_line_simplex<false>, dim3((unsigned)blocks), dim3(kItemThreads), 0, st, a);
   return hipGetLastError();
 }
 

@@ -75,3 +75,22 @@ def test_simplex_large_map_kept_lines():
     note(f"simplex: {len(lines)} lines on the 2048^2 map")
     same, _ = run_case([amap], win, ev, lines, start, opts, n_path=12)
     assert np.mean(same) >= 0.75, same
+
+
+def test_simplex_long_light_curve_unstaged():
+    # light curves longer than the LDS stage (3072 points) are read from global memory
+    c = W.config("tiny")
+    win = c["window"]
+    lens = [len(W.load_lightcurve("batched", e)["tt"]) for e in range(64)]
+    e = int(np.argmax(lens))
+    assert lens[e] > 3072
+    ev = W.load_lightcurve("batched", e)
+    note(f"simplex: batched event {e} ({lens[e]} points) on the tiny oracle map")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, 0.0)
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.3, 1.0]), np.linspace(0.0, 2 * np.pi, 5)[:-1])
+    tmid = float(np.median(np.asarray(ev["tt"], dtype=np.float64))) + float(ev["t_ref"])
+    start = np.tile([tmid, 30.0], (len(lines), 1))
+    opts = dict(max_iter=60, step_t0=3.0, step_ln_tE=0.3, ftol=1e-10)
+    same, _ = run_case([amap], win, ev, lines, start, opts, n_path=4)
+    assert np.mean(same) >= 0.75, same
