@@ -1022,22 +1022,27 @@ int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_g
                                           B[0], ctx->stream));
         double2* spec = (double2*)ctx->fft_spec.p + (size_t)p * nf;
         double2* res = nullptr;
-        HIP_TRY(ctx, launch_fft_cols(g, -1, B[0], spec, B[1], nullptr, &res, ctx->stream));
+        const ColTransform full{-1, g.nx, g.nx, g.nx, 0, 0, nullptr, g.ny};
+        HIP_TRY(ctx, launch_fft_cols(g, full, B[0], spec, B[1], &res, ctx->stream));
         if (res != spec) HIP_TRY(ctx, hipMemcpyAsync(spec, res, fbytes, hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // q goes out of scope
       }
       ctx->fft_spec.key = key.h;
     }
   }
+  // counts: half spectrum [ny][nx/2 + 1] (the padded image is real)
+  const int32_t h = g.nx / 2 + 1;
   double2* X = nullptr;
   HIP_TRY(ctx, launch_fft_rows_counts(g, d_counts, mx, my, B[0], ctx->stream));
-  HIP_TRY(ctx, launch_fft_cols(g, -1, B[0], B[1], B[2], nullptr, &X, ctx->stream));
+  const ColTransform fwd{-1, h, h, h, my, 0, nullptr, g.ny};
+  HIP_TRY(ctx, launch_fft_cols(g, fwd, B[0], B[1], B[2], &X, ctx->stream));
   double2* other = (X == B[1]) ? B[2] : B[1];
   const double scale = hx * hy / (dx * dy) / ((double)g.nx * (double)g.ny);
   for (int p = 0; p < pairs; ++p) {
     const double2* spec = (const double2*)ctx->fft_spec.p + (size_t)p * nf;
     double2* Y = nullptr;
-    HIP_TRY(ctx, launch_fft_cols(g, 1, X, B[0], other, spec, &Y, ctx->stream));
+    const ColTransform inv{1, g.nx, h, g.nx, 0, h, spec, my};
+    HIP_TRY(ctx, launch_fft_cols(g, inv, X, B[0], other, &Y, ctx->stream));
     float* m1 = d_maps + (size_t)fft_k[2 * p] * npx;
     float* m2 = (2 * p + 1 < (int)fft_k.size()) ? d_maps + (size_t)fft_k[2 * p + 1] * npx : nullptr;
     HIP_TRY(ctx, launch_fft_rows_store(g, Y, mx, my, scale, m1, m2, ctx->stream));

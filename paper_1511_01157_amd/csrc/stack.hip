@@ -15,9 +15,14 @@
 // Along x one workgroup holds a whole row in LDS and runs the Stockham passes there
 // (radix 16, then 8, 4 or 2 for the remainder); along y each pass runs in global memory
 // with consecutive lanes on consecutive columns, so every load and store of a wavefront
-// is one contiguous 1 KiB segment.  Forward: rows (fused with building the padded input),
-// then columns.  Inverse: columns (the first pass fused with the spectral product), then
-// rows (fused with the crop, the scale and the binary32 store).
+// is one contiguous 1 KiB segment.  Forward (counts): the rows of the map only (the
+// padded rows above and below repeat the edge rows), each padded in x and transformed,
+// keeping the columns 0 .. nx/2 (the input is real, so the other half is the conjugate
+// reflection); then the columns of that half spectrum, the first pass reading each
+// padded row from its map row.  Inverse (per pair of profiles): columns, the first pass
+// rebuilding the full spectrum by conjugate reflection and multiplying by the pair's
+// transform, the last writing only the map's rows; then those rows (fused with the
+// crop, the scale and the binary32 store).  The profile transforms use full arrays.
 
 #include "stack.h"
 
@@ -180,18 +185,21 @@ __device__ __forceinline__ int pad_index(int p, int n, int m) {
   return i < 0 ? 0 : (i > m - 1 ? m - 1 : i);
 }
 
+// Map row y (grid = my): transform of its padded row; columns 0 .. nx/2 stored (the
+// rest follow by Hermitian symmetry, the row being real), out[my][nx/2 + 1].
 __global__ __launch_bounds__(kRowThreads) void k_fft_rows_counts(FftGrid g, const uint32_t* counts,
                                                                  int32_t mx, int32_t my,
                                                                  double2* out) {
   __shared__ double2 s[kFftMaxN];
   const int y = blockIdx.x;
-  const uint32_t* row = counts + (size_t)pad_index(y, g.ny, my) * mx;
+  const uint32_t* row = counts + (size_t)y * mx;
   for (int x = threadIdx.x; x < g.nx; x += kRowThreads)
     s[x] = make_double2((double)row[pad_index(x, g.nx, mx)], 0.0);
   __syncthreads();
   lds_fft<-1>(s, g.nx, g.tw_x);
-  double2* o = out + (size_t)y * g.nx;
-  for (int x = threadIdx.x; x < g.nx; x += kRowThreads) o[x] = s[x];
+  const int h = g.nx / 2 + 1;
+  double2* o = out + (size_t)y * h;
+  for (int x = threadIdx.x; x < h; x += kRowThreads) o[x] = s[x];
 }
 
 __device__ __forceinline__ double quad_weight(const double* q, int rx, int ry, int a, int b) {
@@ -236,46 +244,64 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_store(FftGrid g, const
   }
 }
 
-// One Stockham pass along y for every column (the row pass's indexing with rows in
-// place of LDS slots); thread t takes column t mod nx and butterfly t / nx.
+// One Stockham pass along y for columns 0 .. ncols - 1 (the row pass's indexing with
+// rows in place of LDS slots); thread t takes column t mod ncols and butterfly t / ncols.
+// The first pass of a transform may read a compact padded input (row -> its map row)
+// or a Hermitian half spectrum (columns beyond herm_cols by conjugate reflection) and
+// multiply by a spectral product; the last may skip rows the caller does not read.
+struct ColPassArgs {
+  int32_t ncols, in_stride, out_stride, ns;
+  int32_t map_rows, herm_cols, out_rows;
+};
+
 template <int R, int SGN, bool MUL>
-__global__ __launch_bounds__(256) void k_fft_col_pass(FftGrid g, int ns, const double2* in,
+__global__ __launch_bounds__(256) void k_fft_col_pass(FftGrid g, ColPassArgs c, const double2* in,
                                                       double2* out, const double2* mul) {
-  const int n = g.ny, nx = g.nx;
+  const int n = g.ny;
   const int nb = n / R;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nb * nx) return;
-  const int x = (int)(t & (nx - 1));
-  const int j = (int)(t / nx);
+  if (t >= (int64_t)nb * c.ncols) return;
+  const int x = (int)(t % c.ncols);
+  const int j = (int)(t / c.ncols);
   Cx v[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const size_t idx = (size_t)(j + r * nb) * nx + x;
-    v[r] = ld(in[idx]);
-    if (MUL) v[r] = cmul(v[r], ld(mul[idx]));
+    const int row = j + r * nb;
+    if (c.map_rows > 0) {
+      v[r] = ld(in[(size_t)pad_index(row, n, c.map_rows) * c.in_stride + x]);
+    } else if (c.herm_cols > 0 && x >= c.herm_cols) {
+      const Cx e = ld(in[(size_t)((n - row) & (n - 1)) * c.in_stride + (g.nx - x)]);
+      v[r] = {e.re, -e.im};
+    } else {
+      v[r] = ld(in[(size_t)row * c.in_stride + x]);
+    }
+    if (MUL) v[r] = cmul(v[r], ld(mul[(size_t)row * g.nx + x]));
   }
-  const int k = j & (ns - 1);
-  if (ns > 1) {
-    const int step = n / (ns * R);
+  const int k = j & (c.ns - 1);
+  if (c.ns > 1) {
+    const int step = n / (c.ns * R);
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<SGN>(g.tw_y, r * k * step));
   }
   dft<R, SGN>(v);
-  const int base = (j / ns) * ns * R + k;
+  const int base = (j / c.ns) * c.ns * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) out[(size_t)(base + r * ns) * nx + x] = st(v[r]);
+  for (int r = 0; r < R; ++r) {
+    const int orow = base + r * c.ns;
+    if (orow < c.out_rows) out[(size_t)orow * c.out_stride + x] = st(v[r]);
+  }
 }
 
 template <int SGN, bool MUL>
-hipError_t col_pass(const FftGrid& g, int R, int ns, const double2* in, double2* out,
+hipError_t col_pass(const FftGrid& g, int R, const ColPassArgs& c, const double2* in, double2* out,
                     const double2* mul, hipStream_t st) {
-  const int64_t threads = (int64_t)(g.ny / R) * g.nx;
+  const int64_t threads = (int64_t)(g.ny / R) * c.ncols;
   const dim3 grid((unsigned)((threads + 255) / 256));
   switch (R) {
-    case 16: hipLaunchKernelGGL((k_fft_col_pass<16, SGN, MUL>), grid, dim3(256), 0, st, g, ns, in, out, mul); break;
-    case 8: hipLaunchKernelGGL((k_fft_col_pass<8, SGN, MUL>), grid, dim3(256), 0, st, g, ns, in, out, mul); break;
-    case 4: hipLaunchKernelGGL((k_fft_col_pass<4, SGN, MUL>), grid, dim3(256), 0, st, g, ns, in, out, mul); break;
-    default: hipLaunchKernelGGL((k_fft_col_pass<2, SGN, MUL>), grid, dim3(256), 0, st, g, ns, in, out, mul); break;
+    case 16: hipLaunchKernelGGL((k_fft_col_pass<16, SGN, MUL>), grid, dim3(256), 0, st, g, c, in, out, mul); break;
+    case 8: hipLaunchKernelGGL((k_fft_col_pass<8, SGN, MUL>), grid, dim3(256), 0, st, g, c, in, out, mul); break;
+    case 4: hipLaunchKernelGGL((k_fft_col_pass<4, SGN, MUL>), grid, dim3(256), 0, st, g, c, in, out, mul); break;
+    default: hipLaunchKernelGGL((k_fft_col_pass<2, SGN, MUL>), grid, dim3(256), 0, st, g, c, in, out, mul); break;
   }
   return hipGetLastError();
 }
@@ -287,17 +313,11 @@ bool valid(const FftGrid& g) {
 
 }  // namespace
 
-int fft_col_passes(int32_t n) {
-  int p = 0;
-  for (int ns = 1; ns < n; ++p) ns *= (n / ns >= 16) ? 16 : n / ns;
-  return p;
-}
-
 hipError_t launch_fft_rows_counts(const FftGrid& g, const uint32_t* counts, int32_t mx, int32_t my,
                                   double2* out, hipStream_t st) {
   if (!valid(g) || mx < 1 || my < 1 || mx > g.nx || my > g.ny) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fft_rows_counts, dim3((unsigned)g.ny), dim3(kRowThreads), 0, st, g, counts,
-                     mx, my, out);
+  hipLaunchKernelGGL(k_fft_rows_counts, dim3((unsigned)my), dim3(kRowThreads), 0, st, g, counts, mx,
+                     my, out);
   return hipGetLastError();
 }
 
@@ -312,26 +332,35 @@ hipError_t launch_fft_rows_taps(const FftGrid& g, const double* q1, int32_t r1x,
   return hipGetLastError();
 }
 
-hipError_t launch_fft_cols(const FftGrid& g, int sign, const double2* src, double2* a, double2* b,
-                           const double2* mul, double2** result, hipStream_t st) {
-  if (!valid(g) || !src || !a || !b || a == b || (sign != 1 && sign != -1)) return hipErrorInvalidValue;
+hipError_t launch_fft_cols(const FftGrid& g, const ColTransform& ct, const double2* src, double2* a,
+                           double2* b, double2** result, hipStream_t st) {
+  if (!valid(g) || !src || !a || !b || a == b || (ct.sign != 1 && ct.sign != -1) || ct.ncols < 1 ||
+      ct.ncols > g.nx || ct.src_stride < (ct.herm_cols > 0 ? ct.herm_cols : ct.ncols) ||
+      ct.stride < ct.ncols || ct.map_rows < 0 ||
+      ct.map_rows > g.ny || ct.herm_cols < 0 || ct.herm_cols > g.nx / 2 + 1 ||
+      (ct.herm_cols > 0 && ct.ncols != g.nx) || ct.last_rows < 1 || ct.last_rows > g.ny)
+    return hipErrorInvalidValue;
   const double2* cur = src;
   double2* dst = (src == a) ? b : a;
-  int ns = 1;
+  ColPassArgs c{ct.ncols, ct.src_stride, ct.stride, 1, ct.map_rows, ct.herm_cols, g.ny};
   bool first = true;
-  while (ns < g.ny) {
-    const int R = (g.ny / ns >= 16) ? 16 : g.ny / ns;
+  while (c.ns < g.ny) {
+    const int R = (g.ny / c.ns >= 16) ? 16 : g.ny / c.ns;
+    if (c.ns * R == g.ny) c.out_rows = ct.last_rows;  // the last pass
+    const double2* m = first ? ct.mul : nullptr;
     hipError_t e;
-    const double2* m = first ? mul : nullptr;
-    if (sign < 0)
-      e = m ? col_pass<-1, true>(g, R, ns, cur, dst, m, st) : col_pass<-1, false>(g, R, ns, cur, dst, m, st);
+    if (ct.sign < 0)
+      e = m ? col_pass<-1, true>(g, R, c, cur, dst, m, st) : col_pass<-1, false>(g, R, c, cur, dst, m, st);
     else
-      e = m ? col_pass<1, true>(g, R, ns, cur, dst, m, st) : col_pass<1, false>(g, R, ns, cur, dst, m, st);
+      e = m ? col_pass<1, true>(g, R, c, cur, dst, m, st) : col_pass<1, false>(g, R, c, cur, dst, m, st);
     if (e != hipSuccess) return e;
     cur = dst;
     dst = (dst == a) ? b : a;
-    ns *= R;
+    c.ns *= R;
     first = false;
+    c.in_stride = ct.stride;  // passes after the first read the work buffers
+    c.map_rows = 0;
+    c.herm_cols = 0;
   }
   *result = const_cast<double2*>(cur);
   return hipSuccess;

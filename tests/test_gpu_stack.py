@@ -157,3 +157,20 @@ def test_stack_argument_errors():
         M.convolve_stack(gc, c["rays"], win, [0.01, 8.0], 0.5, out=out)
     torch.cuda.synchronize()
     assert bool(torch.all(out == 7.0))
+
+
+def test_fft_non_square_window_and_pixels():
+    # 384 x 256 pixels of 6.25e-3 x 4.6875e-3, off-centre window: 512 x 512 transforms
+    rays = (0.0, 0.0, 4.0, 3.0, 3000, 2250)
+    win = (0.1, -0.05, 2.4, 1.2, 384, 256)
+    dx, dy = 2.4 / 384, 1.2 / 256
+    gc, oc = counts_pair(0.9, 0.02, rays, win)
+    rhos = [0.05, 0.03, 0.012]
+    note("stack: non-square window through the FFT path")
+    maps = M.convolve_stack(gc, rays, win, rhos, GAMMA, fft_min_taps=FORCE_FFT)
+    s64 = float(np.float32(4.0 / 3000)) * float(np.float32(3.0 / 2250)) / (dx * dy)
+    for k, rho in enumerate(rhos):
+        ref = normalize_convolve_exact64(oc, s64, ld_pixel_weights(rho, dx, dy, GAMMA))
+        g = maps[k].cpu().numpy().astype(np.float64)
+        den = np.maximum(ref, 1e-6 * ref.max())
+        assert (np.abs(g - ref) / den).max() < 1e-6, rho
