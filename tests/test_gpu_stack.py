@@ -174,3 +174,46 @@ def test_fft_non_square_window_and_pixels():
         g = maps[k].cpu().numpy().astype(np.float64)
         den = np.maximum(ref, 1e-6 * ref.max())
         assert (np.abs(g - ref) / den).max() < 1e-6, rho
+
+
+def test_search_over_the_radius_stack():
+    # the search over (u0, alpha, rho, t0, tE): the stack's maps are searched as a bank,
+    # rho being the map index; every map checked against the oracle's own stack maps
+    from oracle.search import grid_params, search_mirror32
+    from tests.helpers import rel_err
+    c = W.config("tiny")
+    win = c["window"]
+    d = win[2] / win[4]
+    gc, oc = counts_pair(c["s"], c["q"], c["rays"], win)
+    rhos = [0.002, 0.01, 0.05, 0.1]  # direct sums for the first two, transforms for the rest
+    maps = M.convolve_stack(gc, c["rays"], win, rhos, GAMMA)
+    s32 = map_scale(c["rays"], win)
+    s64 = float(np.float32(c["rays"][2] / c["rays"][4])) * float(np.float32(c["rays"][3] / c["rays"][5])) / (d * d)
+    omaps = []
+    for rho in rhos:
+        w = ld_pixel_weights(rho, d, d, GAMMA)
+        if np.count_nonzero(w) < 256:
+            omaps.append(normalize_convolve_mirror32(oc, s32, w))
+        else:
+            omaps.append(normalize_convolve_exact64(oc, s64, w).astype(np.float32))
+    for k in range(len(rhos)):  # the transform path rounds the same FP64 sum once
+        g = maps[k].cpu().numpy()
+        assert np.abs(g - omaps[k]).max() <= 2e-7 * float(omaps[k].max()), rhos[k]
+    ev = W.load_lightcurve("tiny")
+    axes = W.grid_axes("tiny")
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    views = [(maps[k], win) for k in range(len(rhos))]
+    note("stack: batched search over the four-radius bank")
+    r = M.search(views, lcs, M.grid_trajectories(*axes), "batched", best=True, top_k=16)
+    P = grid_params(*axes)
+    g = r["chi2"][0].cpu().numpy()  # [maps, trajectories]
+    idx = np.unique(np.concatenate([np.argsort(g.min(axis=0))[:8],
+                                    np.random.default_rng(3).choice(len(P), 24, replace=False)]))
+    # the transform maps may differ from the oracle's by one binary32 unit at some pixels,
+    # so the chi-square gate here is 1e-5 (1e-6 on identical samples elsewhere)
+    for k in range(len(rhos)):
+        o = search_mirror32(omaps[k], win, ev["tt"], ev["F"], ev["w"], P[idx], ev["t_ref"])[0]
+        assert rel_err(g[k, idx], o).max() < 1e-5, rhos[k]
+    flat = g.reshape(-1)
+    order = np.lexsort((np.arange(flat.size), flat))[:16]
+    assert np.array_equal(r["topk_idx"][0].cpu().numpy(), order)
