@@ -12,7 +12,21 @@ Entry points (same names as the C ABI):
   chi2_grad(maps, lcs, params, ev, mi)      chi-square and its gradient
   refine(maps, lcs, params, ev, mi)         batched L-BFGS refinement
   Chi2Fn                                    torch.autograd.Function over chi2_grad
+  convolve_stack(counts, rays, window, rhos, gamma)
+                                            finite-source maps of several radii
+                                            (limb-darkened profile) from one count map
+  profile_weights(rho, dx, dy, gamma)       the pixel weights it uses (host)
+  caustics(s, q) / caustic_lines(c, r, phi) caustic centres and sizes, (r, phi) lines (host)
+  line_filter(map, window, lines, a_min)    minimum-magnification filter of the lines
+  lines_to_trajectories(lines, kept, t0, tE) trajectory list of the kept lines
+  line_simplex(maps, lcs, lines, start)     downhill simplex over (t0', ln tE) per line and map
 Grids are tuples (cx, cy, wx, wy, nx, ny).
+
+A caustic-centred search, for example:
+  c = caustics(s, q); L = torch.from_numpy(caustic_lines(c, r, phi)).cuda()
+  best, keep, kept = line_filter(amap, window, L, a_min)
+  P = lines_to_trajectories(L, kept, t0, tE)
+  res = search([(amap, window)], lcs, list_trajectories(P), "batched", top_k=k)
 """
 from __future__ import annotations
 
