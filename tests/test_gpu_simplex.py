@@ -94,3 +94,33 @@ def test_simplex_long_light_curve_unstaged():
     opts = dict(max_iter=60, step_t0=3.0, step_ln_tE=0.3, ftol=1e-10)
     same, _ = run_case([amap], win, ev, lines, start, opts, n_path=4)
     assert np.mean(same) >= 0.75, same
+
+
+def test_simplex_edge_cases():
+    c = W.config("tiny")
+    win = c["window"]
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, 0.0)
+    ev = W.load_lightcurve("tiny")
+    dmaps = [(torch.from_numpy(np.ascontiguousarray(amap)).to(DEV), win)]
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    lines = caustic_lines(M.caustics(c["s"], c["q"]), np.array([0.5]), np.array([0.3, 1.9, 4.0]))
+    start = np.tile([1.0, 18.0], (len(lines), 1))
+    dl, ds = torch.from_numpy(lines).to(DEV), torch.from_numpy(start).to(DEV)
+    # no iterations: the best of the three initial vertices
+    chi2, t0, tE, it = (x.cpu().numpy() for x in M.line_simplex(dmaps, lcs, dl, ds, max_iter=0,
+                                                                 step_t0=2.0, step_ln_tE=0.2))
+    args = (ev["tt"], ev["F"], ev["w"], ev["t_ref"])
+    for l in range(len(lines)):
+        x0 = (1.0, math.log(18.0))
+        verts = [x0, (x0[0] + 2.0, x0[1]), (x0[0], x0[1] + 0.2)]
+        f = [line_chi2(amap, win, *args, lines[l], v) for v in verts]
+        b = int(np.argmin(f))
+        assert it[l, 0] == 0 and rel_err(chi2[l, 0], f[b]) < 1e-6
+        assert t0[l, 0] == verts[b][0] and abs(tE[l, 0] / math.exp(verts[b][1]) - 1) < 1e-15
+    # no lines: nothing to do
+    e = M.line_simplex(dmaps, lcs, dl[:0].contiguous(), ds[:0].contiguous())
+    assert e[0].shape == (0, 1)
+    # an event outside the batch is rejected before any launch
+    with pytest.raises(M.MorseError) as err:
+        M.line_simplex(dmaps, lcs, dl, ds, event=1)
+    assert err.value.code == -1
