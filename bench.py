@@ -196,6 +196,92 @@ def cpu_baseline(c, ev, axes, P_sample_every=128, rows=8192, n_refine=2):
     }
 
 
+# Algorithmic work of the rows measured beside the step (see the design doc for the counts):
+# one line-filter sample = tau 2, position 2, zeta 4, grid coordinates 4, on-map tests
+# 4, floor/fraction 4, cell index 3, bilinear blend 9, max 1 (binary32/integer); one
+# point of a simplex chi-square evaluation = the search's sample (32) + b, w b and the
+# three FP64 sums (6).
+OPS_PER_FILTER_SAMPLE = (33, 0)
+OPS_PER_SIMPLEX_POINT = (32, 6)
+HBM_PEAK_GBS = 8000.0
+
+
+def fft_passes(n):
+    p, ns = 0, 1
+    while ns < n:
+        ns *= 16 if n // ns >= 16 else n // ns
+        p += 1
+    return p
+
+
+def stack_bytes(mx, my, nx, ny, n_fft, n_direct):
+    """Algorithmic HBM bytes of one stack call: the counts' forward transform (map rows,
+    half spectrum), one inverse per pair of FFT radii, and the direct radii (4 B of
+    counts read and 4 B of map written per pixel each)."""
+    h = nx // 2 + 1
+    P = fft_passes(ny)
+    fwd = mx * my * 4 + my * h * 16 + (my * h * 16 + ny * h * 16) + (P - 1) * 2 * ny * h * 16
+    inv = (ny * h * 16 + 2 * ny * nx * 16) + (P - 2) * 2 * ny * nx * 16 + (ny * nx * 16 + my * nx * 16) \
+        + (my * nx * 16 + 2 * mx * my * 4)
+    pairs = (n_fft + 1) // 2
+    return (fwd + pairs * inv if n_fft else 0) + n_direct * 8 * mx * my
+
+
+def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
+    """The oracle timed on bounded samples of the stack, line-filter and simplex
+    measurements (single-threaded numpy; oracle counts of 64 central ray rows)."""
+    import numpy as np
+    from oracle.lines import caustic_components, caustic_lines, line_filter_mirror32
+    from oracle.simplex import line_chi2
+    from oracle.maps import (map_scale, normalize_convolve_exact64_at, normalize_convolve_mirror32)
+    from oracle.profiles import ld_pixel_weights
+    from oracle.rays import rayshoot_mirror32_c
+
+    win = c["window"]
+    ny_r = c["rays"][5]
+    counts, _ = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], win, rows=(ny_r // 2 - 32, ny_r // 2 + 32),
+                                    nthreads=max(1, min(16, os.cpu_count() or 1)))
+    mx, my = win[4], win[5]
+    d = win[2] / mx
+    s32 = map_scale(c["rays"], win)
+    t_stack, parts = 0.0, []
+    for rho in rhos:
+        w = ld_pixel_weights(rho, d, d, gamma)
+        if np.count_nonzero(w) < STACK_FFT_MIN_TAPS and w.shape[0] <= 31:
+            t = time.perf_counter()
+            normalize_convolve_mirror32(counts, s32, w)
+            dt = time.perf_counter() - t
+            parts.append(f"rho {rho:.3g}: whole map {dt:.2f} s")
+        else:
+            px = [(my // 2 + 3 * k, mx // 2 - 5 * k) for k in range(8)]
+            t = time.perf_counter()
+            normalize_convolve_exact64_at(counts, float(s32), w, px)
+            dt = (time.perf_counter() - t) * mx * my / len(px)
+            parts.append(f"rho {rho:.3g}: {len(px)} pixels, {dt:.0f} s scaled")
+        t_stack += dt
+    amap = normalize_convolve_mirror32(counts, s32, ld_pixel_weights(c["rho"], d, d, 0.0))
+    L = caustic_lines(caustic_components(c["s"], c["q"]), r, phi)
+    n_sub = 128
+    t = time.perf_counter()
+    line_filter_mirror32(amap, win, L[:n_sub], a_min)
+    t_filter = (time.perf_counter() - t) * len(L) / n_sub
+    n_sx = 20  # chi-square evaluations timed; the simplex makes n_eval of them
+    t = time.perf_counter()
+    for k in range(n_sx):
+        line_chi2(amap, win, ev["tt"], ev["F"], ev["w"], ev["t_ref"], L[k], (0.5 * k, math.log(20.0)))
+    t_sx = (time.perf_counter() - t) * n_eval / n_sx
+    return (
+        {"value": len(rhos) / t_stack, "unit": "maps/s", "cores": 1, "kind": "oracle",
+         "sample": "seven-radius stack of the oracle's counts (64 central ray rows), weights "
+                   "computed beforehand: " + "; ".join(parts)},
+        {"value": len(L) / t_filter, "unit": "lines/s", "cores": 1, "kind": "oracle",
+         "sample": f"binary32 line filter of {n_sub} of {len(L)} lines ({t_filter:.1f} s scaled)"},
+        {"value": n_kept / t_sx, "unit": "lines/s", "cores": 1, "kind": "oracle",
+         "sample": f"{n_sx} chi-square evaluations of the oracle's simplex, scaled to the "
+                   f"{n_eval} the GPU simplex made for {n_kept} lines ({t_sx:.0f} s scaled)"},
+    )
+
+
 def main():
     args = parse()
     if args.summarize_trace:
@@ -393,9 +479,23 @@ def main():
             # STACK_FFT_MIN_TAPS non-zero taps -> transforms
             n_fft = sum(1 for r in rhos if math.ceil(r / d + 0.5) > 15 or
                         np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS)
+            mx, my = c["window"][4], c["window"][5]
+            r_fft = max([math.ceil(r / d + 0.5) for r in rhos if math.ceil(r / d + 0.5) > 15 or
+                         np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS],
+                        default=0)
+            nfx = 1 << max(1, (mx + 2 * r_fft - 1).bit_length())
+            nfy = 1 << max(1, (my + 2 * r_fft - 1).bit_length())
+            sb = stack_bytes(mx, my, nfx, nfy, n_fft, len(rhos) - n_fft)
             stack = {"radii": [float(r) for r in rhos], "gamma": STACK_GAMMA, "ms": st_ms,
                      "maps_per_s": len(rhos) / (st_ms * 1e-3), "fft_radii": n_fft,
-                     "map": [c["window"][5], c["window"][4]]}
+                     "map": [my, mx], "fft_size": [nfy, nfx],
+                     "roofline": {"bound": "hbm", "achieved": sb / (st_ms * 1e-3) / 1e9,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": sb / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "bytes_per_call": sb, "traffic": None,
+                                  "note": "algorithmic bytes of the whole call (transform "
+                                          "passes, products, stores, direct radii) over the "
+                                          "call's time"}}
 
         # Caustic-centred lines of this lens (sec. 4.2) through the minimum-magnification
         # filter (sec. 4.3) on the step's map, timed apart from the step.
@@ -418,9 +518,18 @@ def main():
             lf_ms = e0.elapsed_time(e1) / 5
             w = c["window"]
             ns = math.ceil(2.0 * 0.5 * math.hypot(w[2], w[3]) * max(w[4] / w[2], w[5] / w[3])) + 1
+            f_ops = sum(OPS_PER_FILTER_SAMPLE) * len(L) * ns / (lf_ms * 1e-3) / 1e12
             lines_rec = {"caustics": int(len(caus)), "lines": int(len(L)), "kept": int(len(kept)),
                          "a_min": a_min, "samples_per_line": ns, "filter_ms": lf_ms,
-                         "samples_per_s": len(L) * ns / (lf_ms * 1e-3)}
+                         "samples_per_s": len(L) * ns / (lf_ms * 1e-3),
+                         "roofline": {"bound": "alu", "achieved": f_ops,
+                                      "peak": peak_for(OPS_PER_FILTER_SAMPLE) / 1e12,
+                                      "unit": "TFLOP/s",
+                                      "frac": f_ops / (peak_for(OPS_PER_FILTER_SAMPLE) / 1e12),
+                                      "ops_per_unit_f32_f64": OPS_PER_FILTER_SAMPLE,
+                                      "traffic": None,
+                                      "note": "tera lane-operations/s over the whole call "
+                                              "(packing the map and the compaction included)"}}
             # downhill simplex over (t0', ln tE) of every kept line (sec. 4.2), from the
             # single-lens estimate (t0', tE) = (0, 20)
             kl = dl[kept].contiguous()
@@ -434,11 +543,26 @@ def main():
             torch.cuda.synchronize()
             sx_ms = e0.elapsed_time(e1)
             its = sx[3].double()
+            n_eval = int(sx[4].long().sum())
+            s_ops = sum(OPS_PER_SIMPLEX_POINT) * n_eval * n_pts / (sx_ms * 1e-3) / 1e12
             lines_rec["simplex"] = {"lines": int(len(kl)), "ms": sx_ms, "max_iter": 5000,
                                     "iterations_mean": float(its.mean()),
                                     "iterations_max": int(its.max()),
+                                    "chi2_evaluations": n_eval,
                                     "best_chi2": float(sx[0].min()),
-                                    "simplex_iterations_per_s": float(its.sum()) / (sx_ms * 1e-3)}
+                                    "simplex_iterations_per_s": float(its.sum()) / (sx_ms * 1e-3),
+                                    "point_evals_per_s": n_eval * n_pts / (sx_ms * 1e-3),
+                                    "roofline": {"bound": "alu", "achieved": s_ops,
+                                                 "peak": peak_for(OPS_PER_SIMPLEX_POINT) / 1e12,
+                                                 "unit": "TFLOP/s",
+                                                 "frac": s_ops / (peak_for(OPS_PER_SIMPLEX_POINT) / 1e12),
+                                                 "ops_per_unit_f32_f64": OPS_PER_SIMPLEX_POINT,
+                                                 "traffic": None,
+                                                 "note": "the longest simplex (iterations_max) "
+                                                         "bounds the launch"}}
+            beside = dict(rhos=np.logspace(-3.0, 0.0, 7), r=np.linspace(0.0, 4.0, 32),
+                          phi=np.linspace(0.0, 2 * np.pi, 257)[:-1], a_min=a_min,
+                          n_kept=int(len(kl)), n_eval=n_eval)
 
     rays_ms, norm_ms, search_ms, refine_ms = stage
     adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
@@ -498,6 +622,13 @@ def main():
         cb = cpu_baseline(c, ev, axes)
         cb.pop("step_s")
         line["cpu_baseline"] = cb
+        if stack is not None and lines_rec is not None and "simplex" in lines_rec:
+            b_st, b_lf, b_sx = cpu_baseline_beside(c, ev, beside["rhos"], STACK_GAMMA, beside["r"],
+                                                  beside["phi"], beside["a_min"], beside["n_kept"],
+                                                  beside["n_eval"])
+            stack["cpu_baseline"] = b_st
+            lines_rec["cpu_baseline"] = b_lf
+            lines_rec["simplex"]["cpu_baseline"] = b_sx
     print(json.dumps(line), flush=True)
 
 

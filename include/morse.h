@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define MORSE_ABI_VERSION 6
+#define MORSE_ABI_VERSION 7
 
 enum morse_status {
   MORSE_OK = 0,
@@ -330,7 +330,8 @@ int morse_lines_to_trajectories(morse_ctx* ctx, const double* d_lines, const int
  * (a new vertex after old ones of equal value, NaN as +inf); stop when f_worst -
  * f_best <= ftol |f_best| or after max_iter iterations.  Chi-square as morse_search
  * computes it, for light curve `event`.  Outputs [n_lines][n_maps]: the best vertex's
- * chi-square, t0', tE and the iterations taken.  d_lines [n_lines][3] and d_start
+ * chi-square, t0', tE, the iterations taken and (d_evals, nullable) the chi-square
+ * evaluations made (3 initial, then 1 to 4 per iteration).  d_lines [n_lines][3] and d_start
  * [n_lines][2] are device FP64.  Several maps (a finite-source stack) give the source
  * radius as a map index.  Errors: EINVAL (as morse_chi2_grad; bad event, opts, NULL
  * arrays), ERANGE (maps too large to pack). */
@@ -342,7 +343,8 @@ typedef struct {
 int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                        const morse_lightcurves* lcs, int32_t event, const double* d_lines,
                        int64_t n_lines, const double* d_start, const morse_simplex_opts* opts,
-                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters);
+                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters,
+                       int32_t* d_evals);
 
 /* ------------------------------------------------------------------------------
  * Gradient and refinement (candidates from the search refined on their maps).

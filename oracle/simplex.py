@@ -38,10 +38,16 @@ def _key(f):
 
 
 def nelder_mead(func, x0, steps, max_iter=5000, ftol=1e-10):
-    """Minimise func over R^2 from x0; returns (x_best, f_best, iterations)."""
+    """Minimise func over R^2 from x0; returns (x_best, f_best, iterations, evaluations)."""
+    calls = [0]
+
+    def fn(v):
+        calls[0] += 1
+        return _key(func(v))
+
     x = [list(map(float, x0)), [float(x0[0]) + float(steps[0]), float(x0[1])],
          [float(x0[0]), float(x0[1]) + float(steps[1])]]
-    f = [_key(func(v)) for v in x]
+    f = [fn(v) for v in x]
 
     def order():
         idx = sorted(range(3), key=lambda i: f[i])  # stable: equal values keep their order
@@ -59,10 +65,10 @@ def nelder_mead(func, x0, steps, max_iter=5000, ftol=1e-10):
         it += 1
         xb = [(x[0][k] + x[1][k]) * 0.5 for k in range(2)]
         xr = [xb[k] + (xb[k] - x[2][k]) for k in range(2)]
-        fr = _key(func(xr))
+        fr = fn(xr)
         if fr < f[0]:
             xe = [xb[k] + 2.0 * (xb[k] - x[2][k]) for k in range(2)]
-            fe = _key(func(xe))
+            fe = fn(xe)
             if fe < fr:
                 replace(xe, fe)
             else:
@@ -72,20 +78,20 @@ def nelder_mead(func, x0, steps, max_iter=5000, ftol=1e-10):
         else:
             if fr < f[2]:
                 xc = [xb[k] + 0.5 * (xr[k] - xb[k]) for k in range(2)]
-                fc = _key(func(xc))
+                fc = fn(xc)
                 ok = fc <= fr
             else:
                 xc = [xb[k] + 0.5 * (x[2][k] - xb[k]) for k in range(2)]
-                fc = _key(func(xc))
+                fc = fn(xc)
                 ok = fc < f[2]
             if ok:
                 replace(xc, fc)
             else:
                 for i in (1, 2):
                     x[i] = [x[0][k] + 0.5 * (x[i][k] - x[0][k]) for k in range(2)]
-                    f[i] = _key(func(x[i]))
+                    f[i] = fn(x[i])
                 order()
-    return x[0], f[0], it
+    return x[0], f[0], it, calls[0]
 
 
 def _chi2_one(A, F, w):
@@ -119,7 +125,8 @@ def line_chi2(amap, window, tt, F, w, t_ref, line, x):
 
 
 def line_simplex(amap, window, tt, F, w, t_ref, line, start, steps, max_iter=5000, ftol=1e-10):
-    """Simplex endpoint of one line: (t0', tE, chi2, iterations) from start (t0', tE)."""
-    x, f, it = nelder_mead(lambda v: line_chi2(amap, window, tt, F, w, t_ref, line, v),
+    """Simplex endpoint of one line: (t0', tE, chi2, iterations, evaluations) from start
+    (t0', tE)."""
+    x, f, it, ne = nelder_mead(lambda v: line_chi2(amap, window, tt, F, w, t_ref, line, v),
                            (float(start[0]), math.log(float(start[1]))), steps, max_iter, ftol)
-    return x[0], math.exp(x[1]), f, it
+    return x[0], math.exp(x[1]), f, it, ne

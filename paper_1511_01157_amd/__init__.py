@@ -340,7 +340,7 @@ def lines_to_trajectories(lines, kept, t0, tE, ctx=None):
 def line_simplex(maps, lcs: LightCurveBatch, lines, start, event=0, max_iter=5000, step_t0=2.0,
                  step_ln_tE=0.2, ftol=1e-10, ctx=None):
     """Downhill simplex over (t0', ln tE) of every device line [n, 3] on every map, from
-    start [n, 2] (t0', tE): (chi2, t0', tE, iterations), each [n, n_maps]."""
+    start [n, 2] (t0', tE): (chi2, t0', tE, iterations, evaluations), each [n, n_maps]."""
     ctx = ctx or Context.get(_device_of(lines))
     views = _map_views(maps)
     for t, k in ((lines, 3), (start, 2)):
@@ -352,12 +352,13 @@ def line_simplex(maps, lcs: LightCurveBatch, lines, start, event=0, max_iter=500
     t0 = torch.empty(shape, dtype=torch.float64, device=lines.device)
     tE = torch.empty(shape, dtype=torch.float64, device=lines.device)
     it = torch.empty(shape, dtype=torch.int32, device=lines.device)
+    ev = torch.empty(shape, dtype=torch.int32, device=lines.device)
     opts = _abi.SimplexOpts(int(max_iter), 0, float(step_t0), float(step_ln_tE), float(ftol))
     lc = lcs.abi()
     ctx.check(ctx.lib.morse_line_simplex(ctx.handle, views, len(maps), ctypes.byref(lc), int(event),
                                          _ptr(lines), n, _ptr(start), ctypes.byref(opts), _ptr(chi2),
-                                         _ptr(t0), _ptr(tE), _ptr(it)))
-    return chi2, t0, tE, it
+                                         _ptr(t0), _ptr(tE), _ptr(it), _ptr(ev)))
+    return chi2, t0, tE, it, ev
 
 
 def search(maps, lcs: LightCurveBatch, trajs, mode="plain", chi2=True, fs=False, fb=False,

@@ -84,7 +84,7 @@ SIGNATURES = {
                                               c_void_p, c_int32, c_void_p]),
     "morse_line_simplex": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves), c_int32,
                                      c_void_p, c_int64, c_void_p, POINTER(SimplexOpts), c_void_p,
-                                     c_void_p, c_void_p, c_void_p]),
+                                     c_void_p, c_void_p, c_void_p, c_void_p]),
     "morse_build_map": (c_int32, [c_void_p, c_double, c_double, POINTER(Grid2D), POINTER(Grid2D),
                                   c_double, c_void_p, c_void_p, POINTER(MapStats)]),
     "morse_search": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves),

@@ -1783,7 +1783,8 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
 int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                        const morse_lightcurves* lcs, int32_t event, const double* d_lines,
                        int64_t n_lines, const double* d_start, const morse_simplex_opts* opts,
-                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters) {
+                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters,
+                       int32_t* d_evals) {
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   int rc;
   Plan pl;
@@ -1818,6 +1819,7 @@ int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_map
   a.t0 = d_t0;
   a.tE = d_tE;
   a.iters = d_iters;
+  a.evals = d_evals;
   HIP_TRY(ctx, launch_line_simplex(a, ctx->stream));
   return MORSE_OK;
 }

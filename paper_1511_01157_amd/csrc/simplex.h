@@ -22,6 +22,7 @@ struct SimplexArgs {
   double* t0;
   double* tE;
   int32_t* iters;
+  int32_t* evals;        // nullable: chi-square evaluations per item
 };
 
 hipError_t launch_line_simplex(const SimplexArgs& a, hipStream_t st);

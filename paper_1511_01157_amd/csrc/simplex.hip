@@ -150,9 +150,10 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
     Vertex v[3];
     double px0 = s0, px1 = s1, b0 = 0.0, b1 = 0.0, r0 = 0.0, r1 = 0.0, fr = 0.0;
     int state = kInit0;
-    int32_t it = 0;
+    int32_t it = 0, evals = 0;
     for (;;) {
       const double f = chi2_at(px0, px1);
+      ++evals;
       bool next = false;  // an iteration is complete: order, test, start the next
       bool shrink = false;
       switch (state) {
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
       a.t0[item] = v[0].x0;
       a.tE[item] = exp(v[0].x1);
       a.iters[item] = it;
+      if (a.evals) a.evals[item] = evals;
     }
   }
 }

@@ -23,9 +23,10 @@ DEV = "cuda:0"
 def run_case(amaps, win, ev, lines, start, opts, n_path):
     dmaps = [(torch.from_numpy(np.ascontiguousarray(a)).to(DEV), win) for a in amaps]
     lcs = M.LightCurveBatch.from_events([ev], DEV)
-    chi2, t0, tE, it = M.line_simplex(dmaps, lcs, torch.from_numpy(lines).to(DEV),
-                                      torch.from_numpy(start).to(DEV), **opts)
-    chi2, t0, tE, it = (x.cpu().numpy() for x in (chi2, t0, tE, it))
+    res = M.line_simplex(dmaps, lcs, torch.from_numpy(lines).to(DEV), torch.from_numpy(start).to(DEV),
+                         **opts)
+    chi2, t0, tE, it, ne = (x.cpu().numpy() for x in res)
+    assert np.all(ne >= 3 + it) and np.all(ne <= 3 + 4 * it)
     args = (ev["tt"], ev["F"], ev["w"], ev["t_ref"])
     same = []
     for l in range(len(lines)):
@@ -39,7 +40,7 @@ def run_case(amaps, win, ev, lines, start, opts, n_path):
             if len(same) < n_path:
                 o = line_simplex(amap, win, *args, lines[l], start[l],
                                  (opts["step_t0"], opts["step_ln_tE"]), opts["max_iter"], opts["ftol"])
-                same.append(o[3] == it[l, k] and rel_err(o[2], chi2[l, k]) < 1e-9)
+                same.append(o[3] == it[l, k] and o[4] == ne[l, k] and rel_err(o[2], chi2[l, k]) < 1e-9)
     return same, it
 
 
@@ -107,8 +108,9 @@ def test_simplex_edge_cases():
     start = np.tile([1.0, 18.0], (len(lines), 1))
     dl, ds = torch.from_numpy(lines).to(DEV), torch.from_numpy(start).to(DEV)
     # no iterations: the best of the three initial vertices
-    chi2, t0, tE, it = (x.cpu().numpy() for x in M.line_simplex(dmaps, lcs, dl, ds, max_iter=0,
-                                                                 step_t0=2.0, step_ln_tE=0.2))
+    chi2, t0, tE, it, ne = (x.cpu().numpy() for x in M.line_simplex(dmaps, lcs, dl, ds, max_iter=0,
+                                                                     step_t0=2.0, step_ln_tE=0.2))
+    assert np.all(ne == 3)
     args = (ev["tt"], ev["F"], ev["w"], ev["t_ref"])
     for l in range(len(lines)):
         x0 = (1.0, math.log(18.0))

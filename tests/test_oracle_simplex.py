@@ -12,13 +12,14 @@ from oracle.simplex import line_chi2, line_simplex, nelder_mead
 
 def test_quadratic_minimum():
     f = lambda v: (v[0] - 1.0) ** 2 + 10.0 * (v[1] + 2.0) ** 2
-    x, fx, it = nelder_mead(f, (4.0, 3.0), (0.5, 0.5), max_iter=2000, ftol=1e-14)
+    x, fx, it, ne = nelder_mead(f, (4.0, 3.0), (0.5, 0.5), max_iter=2000, ftol=1e-14)
+    assert 3 + it <= ne <= 3 + 4 * it
     assert abs(x[0] - 1.0) < 1e-5 and abs(x[1] + 2.0) < 1e-5 and fx < 1e-10 and it < 2000
 
 
 def test_rosenbrock_agrees_with_scipy():
     f = lambda v: 100.0 * (v[1] - v[0] ** 2) ** 2 + (1.0 - v[0]) ** 2
-    x, fx, it = nelder_mead(f, (-1.2, 1.0), (0.1, 0.1), max_iter=5000, ftol=1e-15)
+    x, fx, it, _ = nelder_mead(f, (-1.2, 1.0), (0.1, 0.1), max_iter=5000, ftol=1e-15)
     ref = optimize.minimize(f, (-1.2, 1.0), method="Nelder-Mead",
                             options=dict(xatol=1e-10, fatol=1e-15, maxiter=5000))
     assert abs(x[0] - 1.0) < 1e-4 and abs(x[1] - 1.0) < 1e-4
@@ -32,8 +33,9 @@ def test_iteration_cap_and_nan_as_infinity():
         calls.append(1)
         return float("nan") if v[0] > 2.0 else (v[0] - 1.0) ** 2 + v[1] ** 2
 
-    x, fx, it = nelder_mead(f, (0.0, 0.5), (1.5, 0.3), max_iter=7, ftol=0.0)
+    x, fx, it, ne = nelder_mead(f, (0.0, 0.5), (1.5, 0.3), max_iter=7, ftol=0.0)
     assert it == 7 and math.isfinite(fx) and fx <= (0.0 - 1.0) ** 2 + 0.25
+    assert ne == len(calls)
 
 
 def test_line_simplex_recovers_single_lens_truth():
@@ -54,7 +56,7 @@ def test_line_simplex_recovers_single_lens_truth():
     tt = t.astype(np.float32)
     line = (u0, al, 0.0)
     assert line_chi2(amap, win, tt, F, w, 0.0, line, (t0, math.log(tE))) < 1e-2
-    t0f, tEf, chi2, it = line_simplex(amap, win, tt, F, w, 0.0, line, (0.0, 15.0), (2.0, 0.2),
+    t0f, tEf, chi2, it, _ = line_simplex(amap, win, tt, F, w, 0.0, line, (0.0, 15.0), (2.0, 0.2),
                                       max_iter=2000, ftol=1e-12)
     assert abs(t0f - t0) < 2e-3 and abs(tEf / tE - 1) < 1e-3 and chi2 < 1e-2
 
