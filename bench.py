@@ -196,7 +196,7 @@ def cpu_baseline(c, ev, axes, P_sample_every=128, rows=8192, n_refine=2):
     }
 
 
-# Algorithmic work of the rows measured beside the step (see the design doc for the counts):
+# Algorithmic work of the rows measured beside the step:
 # one line-filter sample = tau 2, position 2, zeta 4, grid coordinates 4, on-map tests
 # 4, floor/fraction 4, cell index 3, bilinear blend 9, max 1 (binary32/integer); one
 # point of a simplex chi-square evaluation = the search's sample (32) + b, w b and the
