@@ -1,0 +1,299 @@
+// C ABI, candidates: chi-square and gradient, batched L-BFGS refinement, and the
+// downhill simplex along lines, all on candidates' own maps and light curves.
+
+#include "host.h"
+
+using namespace morse;
+using namespace morse::host;
+
+namespace {
+
+int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, int64_t n, Plan& pl, size_t& i_sums,
+                    size_t& i_wF, size_t& i_quad) {
+  if (!maps || n_maps <= 0) return fail(ctx, MORSE_EINVAL, "need n_maps >= 1 maps");
+  int rc;
+  for (int i = 0; i < n_maps; ++i) {
+    if (!maps[i].d_map) return fail(ctx, MORSE_EINVAL, "map %d: d_map is NULL", i);
+    if ((rc = check_window(ctx, &maps[i].window, "map window"))) return rc;
+  }
+  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
+      !lcs->d_weight)
+    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
+  for (int e = 0; e < lcs->n_events; ++e)
+    if (lcs->h_offsets[e + 1] - lcs->h_offsets[e] < 3)
+      return fail(ctx, MORSE_EINVAL, "event %d has fewer than 3 points", e);
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
+  i_sums = pl.add(24 * (size_t)lcs->n_events);
+  i_wF = pl.add(8 * (size_t)lcs->h_offsets[lcs->n_events]);
+  i_quad = pl.add(quad_region_bytes(maps, n_maps));
+  return MORSE_OK;
+}
+
+// Host metadata of the candidate entry points (event offsets, reference times, map
+// table) lives in its own device buffer, uploaded only when it changes, so calls that
+// alternate with searches neither re-upload nor wait for the device.
+int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                     const morse_lightcurves* lcs, const Plan& pl, size_t i_sums, size_t i_wF,
+                     size_t i_quad, LcView& lc, MapC*& d_maps) {
+  int rc;
+  const int32_t ne = lcs->n_events;
+  std::vector<MapC> hm(n_maps);
+  for (int i = 0; i < n_maps; ++i) hm[i] = make_mapc(maps[i].d_map, maps[i].window);
+  assign_quads(hm, pl.ptr(ctx, i_quad));
+  const size_t b_off = (8 * (size_t)(ne + 1) + 255) & ~size_t(255);
+  const size_t b_tref = (8 * (size_t)ne + 255) & ~size_t(255);
+  if ((rc = reserve_meta(ctx, ctx->cmeta, b_off + b_tref + sizeof(MapC) * n_maps))) return rc;
+  int64_t* d_off = (int64_t*)ctx->cmeta.p;
+  double* d_tref = (double*)(ctx->cmeta.p + b_off);
+  d_maps = (MapC*)(ctx->cmeta.p + b_off + b_tref);
+  Hasher h;
+  h.pod(ctx->cmeta.p);
+  h.pod(ne);
+  h.pod(n_maps);
+  h.bytes(lcs->h_offsets, 8 * (size_t)(ne + 1));
+  h.bytes(lcs->h_t_ref, 8 * (size_t)ne);
+  h.bytes(hm.data(), sizeof(MapC) * n_maps);  // includes the packed-cell addresses
+  if (h.h != ctx->cmeta.key) {
+    ctx->cmeta.key = 0;
+    if ((rc = upload(ctx, d_off, lcs->h_offsets, 8 * (size_t)(ne + 1)))) return rc;
+    if ((rc = upload(ctx, d_tref, lcs->h_t_ref, 8 * (size_t)ne))) return rc;
+    if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // host arrays go out of scope
+    ctx->cmeta.key = h.h;
+  }
+  lc.t = lcs->d_t;
+  lc.w = lcs->d_weight;
+  lc.F = lcs->d_flux;
+  lc.wFc = (double*)pl.ptr(ctx, i_wF);
+  lc.off = d_off;
+  lc.sums = (double*)pl.ptr(ctx, i_sums);
+  lc.t_ref = d_tref;
+  HIP_TRY(ctx, launch_quad_pack(d_maps, hm.data(), n_maps, ctx->stream));
+  HIP_TRY(ctx, launch_lc_prep(lc.t, lc.F, lc.w, lc.off, ne, (double*)lc.wFc, (double*)lc.sums,
+                              ctx->stream));
+  return MORSE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+
+int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                       const morse_lightcurves* lcs, int32_t event, const double* d_lines,
+                       int64_t n_lines, const double* d_start, const morse_simplex_opts* opts,
+                       double* d_chi2, double* d_t0, double* d_tE, int32_t* d_iters,
+                       int32_t* d_evals) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  Plan pl;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n_lines, pl, i_sums, i_wF, i_quad))) return rc;
+  if (event < 0 || event >= lcs->n_events) return fail(ctx, MORSE_EINVAL, "event %d out of range", event);
+  if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
+  if (opts->max_iter < 0) return fail(ctx, MORSE_EINVAL, "max_iter < 0");
+  if (!(std::isfinite(opts->step_t0) && std::isfinite(opts->step_ln_tE) && std::isfinite(opts->ftol) &&
+        opts->ftol >= 0.0))
+    return fail(ctx, MORSE_EINVAL, "steps and ftol must be finite, ftol >= 0");
+  if (n_lines == 0) return MORSE_OK;
+  if (!d_lines || !d_start || !d_chi2 || !d_t0 || !d_tE || !d_iters)
+    return fail(ctx, MORSE_EINVAL, "NULL device array");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  SimplexArgs a{};
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  a.maps = d_maps;
+  a.n_maps = n_maps;
+  a.event = event;
+  a.n_points = (int32_t)(lcs->h_offsets[event + 1] - lcs->h_offsets[event]);
+  a.lines = d_lines;
+  a.n_lines = n_lines;
+  a.start = d_start;
+  a.d_t0 = opts->step_t0;
+  a.d_ln_tE = opts->step_ln_tE;
+  a.ftol = opts->ftol;
+  a.max_iter = opts->max_iter;
+  a.chi2 = d_chi2;
+  a.t0 = d_t0;
+  a.tE = d_tE;
+  a.iters = d_iters;
+  a.evals = d_evals;
+  HIP_TRY(ctx, launch_line_simplex(a, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                    const morse_lightcurves* lcs, int64_t n, const double* d_params,
+                    const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
+                    double* d_grad, double* d_fs, double* d_fb) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  Plan pl;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_sums, i_wF, i_quad))) return rc;
+  if (n > 0 && (!d_params || !d_event || !d_map_index))
+    return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  GradArgs a{};
+  a.tc = (TrajC*)pl.ptr(ctx, i_tc);
+  a.tEv = (double*)pl.ptr(ctx, i_tE);
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  a.n = n;
+  a.params = d_params;
+  a.event = d_event;
+  a.mapidx = d_map_index;
+  a.maps = d_maps;
+  a.n_events = lcs->n_events;
+  a.n_maps = n_maps;
+  a.chi2 = d_chi2;
+  a.grad = d_grad;
+  a.fs = d_fs;
+  a.fb = d_fb;
+  HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
+  LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
+  HIP_TRY(ctx, tm.begin(ctx->stream));
+  HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
+  HIP_TRY(ctx, tm.end(ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                 const morse_lightcurves* lcs, int64_t n, double* d_params,
+                 const int32_t* d_event, const int32_t* d_map_index,
+                 const morse_lbfgs_opts* opts, double* d_chi2_out, double* d_chi2_init) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
+  if (opts->steps < 0 || opts->steps > 100000 || opts->history < 1 || opts->history > 16 ||
+      opts->max_ls < 1 || !(opts->c1 > 0 && opts->c1 < 1) || !(opts->shrink > 0 && opts->shrink < 1))
+    return fail(ctx, MORSE_EINVAL, "invalid L-BFGS options");
+  int rc;
+  Plan pl;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_sums, i_wF, i_quad))) return rc;
+  if (n > 0 && (!d_params || !d_event || !d_map_index || !d_chi2_out))
+    return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index / d_chi2_out is NULL");
+  if (n == 0) return MORSE_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const int m = opts->history;
+  const size_t i_anchor = pl.add(32 * n), i_p = pl.add(16 * n), i_pt = pl.add(16 * n),
+               i_f = pl.add(8 * n), i_g = pl.add(32 * n), i_d = pl.add(32 * n), i_step = pl.add(8 * n),
+               i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
+               i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(12 * n), i_ft = pl.add(8 * n),
+               i_gt = pl.add(32 * n), i_tc = pl.add(sizeof(TrajC) * (size_t)n),
+               i_tE = pl.add(8 * (size_t)n);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  GradArgs a{};
+  a.tc = (TrajC*)pl.ptr(ctx, i_tc);
+  a.tEv = (double*)pl.ptr(ctx, i_tE);
+  MapC* d_maps;
+  if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
+  LbfgsState s;
+  s.n = n;
+  s.m = m;
+  s.max_ls = opts->max_ls;
+  s.c1 = opts->c1;
+  s.shrink = opts->shrink;
+  double* anchor = (double*)pl.ptr(ctx, i_anchor);
+  s.anchor = anchor;
+  s.p = (float*)pl.ptr(ctx, i_p);
+  s.pt = (float*)pl.ptr(ctx, i_pt);
+  s.f = (double*)pl.ptr(ctx, i_f);
+  s.g = (double*)pl.ptr(ctx, i_g);
+  s.d = (double*)pl.ptr(ctx, i_d);
+  s.step = (double*)pl.ptr(ctx, i_step);
+  s.S = (double*)pl.ptr(ctx, i_S);
+  s.Y = (double*)pl.ptr(ctx, i_Y);
+  s.R = (double*)pl.ptr(ctx, i_R);
+  int32_t* ints = (int32_t*)pl.ptr(ctx, i_int);
+  s.nhist = ints;
+  s.nls = ints + n;
+  s.active = ints + 2 * n;
+  a.n = n;
+  a.anchor = anchor;
+  a.pt = s.pt;
+  a.active = s.active;
+  a.event = d_event;
+  a.mapidx = d_map_index;
+  a.maps = d_maps;
+  a.n_events = lcs->n_events;
+  a.n_maps = n_maps;
+  double* ft = (double*)pl.ptr(ctx, i_ft);
+  double* gt = (double*)pl.ptr(ctx, i_gt);
+  a.chi2 = ft;
+  a.grad = gt;
+  // The rounds are captured once per argument set and replayed: start (anchor copy,
+  // state reset, first-trial constants), steps + 1 rounds of (evaluation, update with
+  // the next trial's constants), write-back.
+  Hasher h;
+  h.pod(ctx->ws_epoch);
+  h.pod(n);
+  h.pod(n_maps);
+  h.pod(lcs->n_events);
+  h.pod(*opts);
+  h.pod(d_params);
+  h.pod(d_event);
+  h.pod(d_map_index);
+  h.pod(d_chi2_out);
+  h.pod(d_chi2_init);
+  h.pod(lcs->d_t);
+  h.pod(lcs->d_flux);
+  h.pod(lcs->d_weight);
+  // everything the workspace layout and the metadata buffer depend on
+  h.bytes(lcs->h_offsets, 8 * (size_t)(lcs->n_events + 1));
+  for (int i = 0; i < n_maps; ++i) {
+    h.pod(maps[i].d_map);
+    h.pod(maps[i].window);
+  }
+  h.pod(ctx->cmeta.p);
+  // start, steps + 1 rounds, write-back; with `timing`, events bracket each evaluation
+  auto enqueue = [&](hipStream_t cs, bool timing) -> hipError_t {
+    hipError_t e = launch_refine_init(s, a, d_params, anchor, cs);
+    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
+      LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
+      if (timing) e = tm.begin(cs);
+      if (e == hipSuccess) e = launch_chi2_grad(a, cs);
+      if (e == hipSuccess && timing) e = tm.end(cs);
+      if (e == hipSuccess)
+        e = launch_lbfgs_update(s, a, r, ft, gt, r == 0 ? d_chi2_init : nullptr, cs);
+    }
+    if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
+    return e;
+  };
+  if (timed(ctx, MORSE_KERNEL_GRADIENT)) {  // same kernels, launched one by one
+    HIP_TRY(ctx, enqueue(ctx->stream, true));
+    return MORSE_OK;
+  }
+  if (!ctx->refine_gexec || ctx->refine_key != h.h) {
+    if (ctx->refine_gexec) {
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      (void)hipGraphExecDestroy(ctx->refine_gexec);
+      ctx->refine_gexec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipStream_t cs = ctx->capture_stream;
+    HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue(cs, false);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ctx, MORSE_EHIP, "refine graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&ctx->refine_gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      ctx->refine_gexec = nullptr;
+      return fail(ctx, MORSE_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    ctx->refine_key = h.h;
+  }
+  HIP_TRY(ctx, hipGraphLaunch(ctx->refine_gexec, ctx->stream));
+  return MORSE_OK;
+}
+
+}  // extern "C"

@@ -1,6 +1,7 @@
 // Internal declarations of the gfx950 library: device-side data layouts, the
 // per-sample arithmetic shared by the search and gradient kernels, and the host
-// launchers each kernel file exports to api.hip.  Not part of the public ABI.
+// launchers each kernel file exports to the C ABI sources (api_*.hip).  Not part of the
+// public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -1,4 +1,4 @@
-// Launchers of the caustic-centred line kernels (lines.hip) used by api.hip.  Not part
+// Launchers of the caustic-centred line kernels (lines.hip) used by api_lines.hip.  Not part
 // of the public ABI.
 #pragma once
 

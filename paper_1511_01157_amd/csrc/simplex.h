@@ -1,4 +1,4 @@
-// Launcher of the line-simplex kernel (simplex.hip) used by api.hip.  Not part of the
+// Launcher of the line-simplex kernel (simplex.hip) used by api_refine.hip.  Not part of the
 // public ABI.
 #pragma once
 

@@ -1,4 +1,4 @@
-// Launchers of the FFT convolution kernels (stack.hip) that api.hip uses for
+// Launchers of the FFT convolution kernels (stack.hip) that api_maps.hip uses for
 // finite-source map stacks with stencils too wide for the direct binary32 sum.  Not
 // part of the public ABI.
 #pragma once
