@@ -33,13 +33,15 @@ sys.path.insert(0, ROOT)
 # Algorithmic lane-operations per unit (one FP32/FP64 add, mul, compare, floor,
 # convert, divide, square root or fused multiply-add = 1), split by the unit that
 # executes them, (binary32 and integer, FP64):
-#   ray: lattice point 2, d 2, r 4, two divisions 2, zeta_x 4, zeta_y 4, scaled
-#        offsets 4, floors 2, bin compares/selects 4, index 2, count 1    = (31, 0)
+#   ray, shot in mirror pairs (one lens-equation solve for a ray and its image across
+#        the lens axis): per pair lattice point 2, d 2, r 4, two divisions 2,
+#        zeta_x 4, zeta_y 4, scaled offsets 4, floors 2, bin compares/selects 4,
+#        mirror row 1, and per ray index 2, count 1: 35 per pair    = (17.5, 0)
 #   point-evaluation: tau 2, zeta 4, grid coordinate 6, on-map test 4,
 #        floor/fraction 4, cell index 3, bilinear 9 (binary32) + FP64 sums 5 = (32, 5)
 #   adjoint point-evaluation: sample 32 (binary32) + fit sums 5, dA/dzeta 5, tau and
 #        alpha directions 5, five directions x (w D and three sums) 20 (FP64) = (32, 35)
-OPS_PER_RAY = (31, 0)
+OPS_PER_RAY = (17.5, 0)
 OPS_PER_POINT_EVAL = (32, 5)
 OPS_PER_ADJOINT_EVAL = (32, 35)
 # Vector peaks of one MI355X in lane-operations per second (an FMA counts once, so

@@ -16,6 +16,16 @@
 // with one global atomic each; otherwise (tiles straddling a lens, whose rays scatter
 // over the whole source plane) each ray goes to a global atomic directly.  Integer
 // addition is order-free, so the counts are bit-identical whatever the schedule.
+//
+// Mirror pairs.  With both lenses on the x axis, a lattice centred on y = 0 with an
+// even row count and a window centred on y = 0, the ray of row ny - 1 - j is the
+// mirror image of the ray of row j: its y is exactly -y, and since binary32 rounding
+// commutes with negation every step of Eq. 2 gives exactly the same x and the negated
+// y, so its bin is (bx, 2h - 1 - by) by the symmetric bin rule (h = my / 2), unless
+// its y offset in the window is +-0, when both rays fall in row h.  Rows that have
+// their mirror row in the same call are then shot once, from the upper half, and each
+// binned ray is counted in both bins (the +-0 rays twice in their own bin); the ray
+// statistics count every shot ray twice.
 
 #include <algorithm>
 
@@ -96,6 +106,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
+template <bool kMirror>
 __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* __restrict__ counts,
                                                          unsigned long long* __restrict__ stats) {
   __shared__ uint32_t hist[RS_CAP];
@@ -143,7 +154,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
           int32_t bx, by;
           const bool inx = bin1(vx, p.mx, bx);
           const bool iny = bin1(vy, p.my, by);
-          if (inx && iny) {
+          if (inx && iny && kMirror && vy == 0.0f) {
+            // the ray and its mirror share the bin (bx, h)
+            atomicAdd(&counts[(size_t)by * (size_t)p.mx + (size_t)bx], 2u);
+            ++n_zero;
+          } else if (inx && iny) {
             bin = (by << 16) | bx;
             n_zero += (vy == 0.0f) ? 1u : 0u;
             bxmin = min(bxmin, bx);
@@ -160,9 +175,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
   }
 
   // ray statistics: one 64-bit atomic per wave and counter, only when non-zero
-  n_out = wave_sum_u32(n_out);
-  n_nf = wave_sum_u32(n_nf);
-  n_zero = wave_sum_u32(n_zero);
+  constexpr uint32_t kRays = kMirror ? 2u : 1u;  // rays each shot ray stands for
+  n_out = wave_sum_u32(n_out) * kRays;
+  n_nf = wave_sum_u32(n_nf) * kRays;
+  n_zero = wave_sum_u32(n_zero) * kRays;
   if (lane == 0 && stats) {
     if (n_out) atomicAdd(&stats[0], (unsigned long long)n_out);
     if (n_nf) atomicAdd(&stats[1], (unsigned long long)n_nf);
@@ -203,15 +219,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
       }
     }
     __syncthreads();
+    const int top = 2 * (p.my >> 1) - 1;  // mirror row of by is top - by
     for (int k = tid; k < area; k += RS_THREADS) {
       const uint32_t v = hist[k];
       if (v) {
         const int r = k / pitch;
         const int c = k - r * pitch;
         atomicAdd(&counts[(size_t)(bymin + r) * (size_t)p.mx + (size_t)(bxmin + c)], v);
+        if (kMirror)
+          atomicAdd(&counts[(size_t)(top - (bymin + r)) * (size_t)p.mx + (size_t)(bxmin + c)], v);
       }
     }
   } else {
+    const int top = 2 * (p.my >> 1) - 1;
 #pragma unroll
     for (int k = 0; k < RS_A * RS_B; ++k) {
       const int bin = bins[k];
@@ -219,6 +239,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
         const int bx = bin & 0xffff;
         const int by = bin >> 16;
         atomicAdd(&counts[(size_t)by * (size_t)p.mx + (size_t)bx], 1u);
+        if (kMirror) atomicAdd(&counts[(size_t)(top - by) * (size_t)p.mx + (size_t)bx], 1u);
       }
     }
   }
@@ -297,13 +318,36 @@ hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps
 }
 
 
+namespace {
+
+// Rows [row0, row1) of p, each ray shot once (kMirror false) or, for rows of the upper
+// half whose mirror rows are part of the call, once for the pair (kMirror true).
+template <bool kMirror>
+hipError_t shoot_rows(RayParams p, int32_t row0, int32_t row1, uint32_t* counts,
+                      unsigned long long* stats, hipStream_t st) {
+  const int rows = row1 - row0;
+  if (rows <= 0) return hipSuccess;
+  p.row0 = row0;
+  p.row1 = row1;
+  dim3 grid((p.nx + RS_TX - 1) / RS_TX, (rows + RS_TY - 1) / RS_TY);
+  hipLaunchKernelGGL(k_rayshoot<kMirror>, grid, dim3(RS_THREADS), 0, st, p, counts, stats);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
                            hipStream_t st) {
-  const int rows = p.row1 - p.row0;
-  if (rows <= 0) return hipSuccess;
-  dim3 grid((p.nx + RS_TX - 1) / RS_TX, (rows + RS_TY - 1) / RS_TY);
-  hipLaunchKernelGGL(k_rayshoot, grid, dim3(RS_THREADS), 0, st, p, counts, stats);
-  return hipGetLastError();
+  if (p.row1 <= p.row0) return hipSuccess;
+  // Mirror pairs need a lattice and a window centred on y = 0 and an even row count;
+  // the rows paired inside [row0, row1) form [a, b) with a + b = ny.
+  const int32_t a = std::max(p.row0, p.ny - p.row1), b = std::min(p.row1, p.ny - p.row0);
+  if (!(p.cy == 0.0f && p.sy == 0.0f && (p.ny & 1) == 0 && a < b))
+    return shoot_rows<false>(p, p.row0, p.row1, counts, stats, st);
+  hipError_t e = shoot_rows<true>(p, p.ny / 2, b, counts, stats, st);
+  if (e == hipSuccess) e = shoot_rows<false>(p, p.row0, a, counts, stats, st);
+  if (e == hipSuccess) e = shoot_rows<false>(p, b, p.row1, counts, stats, st);
+  return e;
 }
 
 hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,

@@ -41,20 +41,29 @@ def test_tiny_counts_bit_exact_and_stats():
     (1.0, 0.0, (0.0, 0.0, 4.0, 4.0, 1024, 1024), (0.0, 0.0, 2.0, 2.0, 128, 128)),      # single lens
     (1.0, 1e-3, (0.0, 0.0, 0.5, 0.5, 256, 256), (5.0, 5.0, 1.0, 1.0, 64, 64)),         # window missed
     (0.3, 0.1, (0.0, 0.0, 2.0, 2.0, 2, 2), (0.0, 0.0, 2.0, 2.0, 2, 2)),                # minimal grids
+    (0.5, 0.0, (-0.3, 0.0, 4.0, 4.0, 1026, 1026), (0.0, 0.0, 2.0, 2.0, 128, 128)),    # zero-axis rays
+    (2.0, 1.0, (-0.3, 0.0, 1.0, 1.0, 768, 768), (0.2, 0.0, 2.0, 2.0, 128, 128)),      # zero-axis rays
 ])
 def test_counts_bit_exact_edge_cases(s, q, rays, window):
+    """Lattices and windows centred on the lens axis go through mirror pairs (the last
+    two cases have rays whose window y offset is exactly zero, which the pairing counts
+    twice in their own bin); the others shoot every ray."""
     note(f"rayshoot edge s={s} q={q} rays={rays} window={window}")
     g, gst = gpu_counts(s, q, rays, window)
     o, ost = rayshoot_mirror32_c(s, q, rays, window, nthreads=8)
     assert np.array_equal(g, o)
     assert gst == ost
+    if rays[0] == -0.3:
+        assert ost["zero_axis"] > 0
 
 
 def test_large_counts_row_slices_bit_exact():
-    """Full-size lattice (32768^2 rays into 2048^2): row slices through the lens axis,
-    the lattice edge and a ragged end, each bit-exact against the mirror."""
+    """Full-size lattice (32768^2 rays into 2048^2): row slices through the lens axis
+    (all rows paired with their mirror rows; a ragged part paired, the rest not; the two
+    middle rows), the lattice edge and a ragged end, each bit-exact against the mirror."""
     c = W.config("large")
-    for rows in [(16320, 16448), (0, 64), (32700, 32768), (9000, 9037)]:
+    for rows in [(16320, 16448), (16000, 16500), (16383, 16385), (0, 64), (32700, 32768),
+                 (9000, 9037)]:
         note(f"rayshoot large rows {rows}")
         g, gst = gpu_counts(c["s"], c["q"], c["rays"], c["window"], rows=rows)
         o, ost = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], rows=rows, nthreads=16)
