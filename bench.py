@@ -293,7 +293,7 @@ def main():
     if args.copy_bytes:
         return copy_kernel(args.copy_bytes)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(on several GPUs the path would deal maps or ray rows to GPUs and gather "
               "the per-GPU top-k lists)", file=sys.stderr)
         sys.exit(2)

@@ -37,7 +37,7 @@ enum morse_status {
   MORSE_ENOMEM = -2,       /* device workspace allocation failed */
   MORSE_EHIP = -3,         /* a HIP runtime call failed */
   MORSE_ERANGE = -4,       /* a size limit would be exceeded (e.g. counts > 2^24) */
-  MORSE_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  MORSE_EUNSUPPORTED = -5  /* valid request that the library does not implement */
 };
 
 typedef struct morse_ctx morse_ctx;

@@ -2,8 +2,8 @@
 
 Refines (t0, u0, tE, alpha) of a candidate trajectory on its map by minimising the
 profiled chi-square with the gradient of ``adjoint`` (mirror32 samples).  The paper
-refines its seeds with MCMC (sec. 5); gradient refinement on the maps is this build's
-method, so the details below are this build's choices, fixed here and mirrored by the GPU.
+refines its seeds with MCMC (sec. 5); gradient refinement on the maps is the method
+here, so the details below are choices of this refinement, fixed here and mirrored by the GPU.
 
 Variables: the optimiser works on p in binary32, a scaled displacement from the
 candidate's FP64 anchor (t0_i, u0_i, tE_i, a_i):

@@ -7,7 +7,7 @@ magnification of each light-curve point is computed once by
 ``tests/golden/lc_amag_<name>.npz``; ``load_lightcurve`` combines it with the seeded
 times and noise deviates into an observed light curve.
 
-Workloads (sizes follow the five benchmark configurations of this build):
+Workloads (the five benchmark configurations):
   tiny      s=1, q=1e-3, 3200^2 rays over [-2,2]^2 -> 512^2 map over [-1,1]^2, point
             source; 1000-point light curve, 32 u0 x 32 alpha grid at fixed t0, tE.
   large     s=0.8, q=5e-3, 32768^2 rays over [-3,3]^2 -> 2048^2 map over [-1.5,1.5]^2,
