@@ -608,6 +608,10 @@ def main():
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
+                     # the measured bytes over the same launch time, against HBM's 8 TB/s
+                     "traffic_gbs": traffic / (dom_ms * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac_of_hbm": (traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                             if traffic else None),
                      "launch_ms": dom_ms, "launches": dom_launches,
                      "ops_per_launch": ops_per_launch[dom],
                      "ops_are_upper_bound": dom == "k_chi2_grad",
