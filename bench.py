@@ -117,15 +117,19 @@ def short_name(name):
 def summarize_trace(path):
     import sqlite3
     cur = sqlite3.connect(path).cursor()
+    # the gradient kernel is listed per grid size: a refinement of many candidates runs
+    # two half-size chains side by side, a timed or small one a single full-size chain
     rows = cur.execute(
-        "select name, count(*), sum(duration), avg(duration), min(duration), max(duration), "
-        "max(vgpr_count), max(sgpr_count), max(lds_size) from kernels group by name "
+        "select name, case when name like '%k_chi2_grad%' then grid_x else 0 end, count(*), "
+        "sum(duration), avg(duration), min(duration), max(duration), "
+        "max(vgpr_count), max(sgpr_count), max(lds_size) from kernels group by 1, 2 "
         "order by sum(duration) desc").fetchall()
-    tot = sum(r[2] for r in rows)
+    tot = sum(r[3] for r in rows)
     print("| kernel | calls | total ms | avg us | min us | max us | % | VGPR | SGPR | LDS B |")
     print("|---|---|---|---|---|---|---|---|---|---|")
-    for n, c, t, a, mn, mx, v, sg, lds in rows:
-        print(f"| {short_name(n)} | {c} | {t / 1e6:.3f} | {a / 1e3:.2f} | {mn / 1e3:.2f} | "
+    for n, g, c, t, a, mn, mx, v, sg, lds in rows:
+        label = short_name(n) + (f" (grid_x {g})" if g else "")
+        print(f"| {label} | {c} | {t / 1e6:.3f} | {a / 1e3:.2f} | {mn / 1e3:.2f} | "
               f"{mx / 1e3:.2f} | {100 * t / tot:.2f} | {v} | {sg} | {lds} |")
 
 

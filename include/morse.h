@@ -381,7 +381,11 @@ typedef struct {
  * pair, or -(1e-2/|g|) g with no pairs or no descent; t = 1, p_t = fl32(p + t d).
  * Dot products are left-to-right FP64 without fused multiply-add.  d_params
  * [n][4] FP64 is read as the start and overwritten with the refined parameters;
- * d_chi2_out [n] receives the final chi2, d_chi2_init [n] (nullable) the initial. */
+ * d_chi2_out [n] receives the final chi2, d_chi2_init [n] (nullable) the initial.
+ * Candidates are independent: with 1024 or more, the two halves run as two chains of
+ * launches, one on the context's stream and one on a second stream of the context that
+ * starts after the work already enqueued and that the context's stream waits for at
+ * the end (results identical to one chain). */
 int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                  const morse_lightcurves* lcs, int64_t n, double* d_params,
                  const int32_t* d_event, const int32_t* d_map_index,

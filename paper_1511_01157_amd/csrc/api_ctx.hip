@@ -40,10 +40,17 @@ int morse_ctx_create(int device, void* stream, morse_ctx** out) {
     }
     c->own_stream = true;
   }
-  if (hipStreamCreate(&c->capture_stream) != hipSuccess) {
+  if (hipStreamCreate(&c->capture_stream) != hipSuccess ||
+      hipStreamCreate(&c->fork_stream) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->fork_stream) (void)hipStreamDestroy(c->fork_stream);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
-    return fail(nullptr, MORSE_EHIP, "hipStreamCreate failed");
+    return fail(nullptr, MORSE_EHIP, "stream or event creation failed");
   }
   *out = c;
   return MORSE_OK;
@@ -67,6 +74,10 @@ int morse_ctx_destroy(morse_ctx* ctx) {
     (void)hipEventDestroy(t.b);
   }
   for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(ctx->fork_stream);
+  (void)hipEventDestroy(ctx->join_ev);
+  (void)hipEventDestroy(ctx->fork_ev);
+  (void)hipStreamDestroy(ctx->fork_stream);
   (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;

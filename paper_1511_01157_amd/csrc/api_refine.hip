@@ -77,6 +77,53 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
 }
 }  // namespace
 
+namespace {
+
+// Refinements of at least kRefineSplitMin candidates run as two chains on two streams
+// (kRefineStreams), others as one captured graph.
+constexpr bool kRefineStreams = true;
+constexpr int64_t kRefineSplitMin = 1024;
+
+// Views of the candidates [c0, c0 + n) of a refinement's state and evaluation arguments.
+LbfgsState part_state(const LbfgsState& s, int64_t c0, int64_t n) {
+  LbfgsState r = s;
+  r.n = n;
+  r.anchor = s.anchor + 4 * c0;
+  r.p = s.p + 4 * c0;
+  r.pt = s.pt + 4 * c0;
+  r.f = s.f + c0;
+  r.g = s.g + 4 * c0;
+  r.d = s.d + 4 * c0;
+  r.step = s.step + c0;
+  r.S = s.S + 4 * (int64_t)s.m * c0;
+  r.Y = s.Y + 4 * (int64_t)s.m * c0;
+  r.R = s.R + (int64_t)s.m * c0;
+  r.nhist = s.nhist + c0;
+  r.nls = s.nls + c0;
+  r.active = s.active + c0;
+  return r;
+}
+
+GradArgs part_args(const GradArgs& a, int64_t c0, int64_t n) {
+  GradArgs r = a;
+  r.n = n;
+  if (a.params) r.params = a.params + 4 * c0;
+  if (a.anchor) r.anchor = a.anchor + 4 * c0;
+  if (a.pt) r.pt = a.pt + 4 * c0;
+  if (a.active) r.active = a.active + c0;
+  r.event = a.event + c0;
+  r.mapidx = a.mapidx + c0;
+  r.tc = a.tc + c0;
+  r.tEv = a.tEv + c0;
+  if (a.chi2) r.chi2 = a.chi2 + c0;
+  if (a.grad) r.grad = a.grad + 4 * c0;
+  if (a.fs) r.fs = a.fs + c0;
+  if (a.fb) r.fb = a.fb + c0;
+  return r;
+}
+
+}  // namespace
+
 extern "C" {
 
 
@@ -250,22 +297,41 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     h.pod(maps[i].window);
   }
   h.pod(ctx->cmeta.p);
-  // start, steps + 1 rounds, write-back; with `timing`, events bracket each evaluation
-  auto enqueue = [&](hipStream_t cs, bool timing) -> hipError_t {
-    hipError_t e = launch_refine_init(s, a, d_params, anchor, cs);
+  // start, steps + 1 rounds, write-back of candidates [c0, c0 + nc); with `timing`,
+  // events bracket each evaluation
+  auto enqueue = [&](hipStream_t cs, int64_t c0, int64_t nc, bool timing) -> hipError_t {
+    const LbfgsState sp = part_state(s, c0, nc);
+    const GradArgs ap = part_args(a, c0, nc);
+    double* params = d_params + 4 * c0;
+    double* init = d_chi2_init ? d_chi2_init + c0 : nullptr;
+    hipError_t e = launch_refine_init(sp, ap, params, anchor + 4 * c0, cs);
     for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
       LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
       if (timing) e = tm.begin(cs);
-      if (e == hipSuccess) e = launch_chi2_grad(a, cs);
+      if (e == hipSuccess) e = launch_chi2_grad(ap, cs);
       if (e == hipSuccess && timing) e = tm.end(cs);
       if (e == hipSuccess)
-        e = launch_lbfgs_update(s, a, r, ft, gt, r == 0 ? d_chi2_init : nullptr, cs);
+        e = launch_lbfgs_update(sp, ap, r, ft + c0, gt + 4 * c0, r == 0 ? init : nullptr, cs);
     }
-    if (e == hipSuccess) e = launch_lbfgs_finish(s, d_params, d_chi2_out, cs);
+    if (e == hipSuccess) e = launch_lbfgs_finish(sp, params, d_chi2_out + c0, cs);
     return e;
   };
   if (timed(ctx, MORSE_KERNEL_GRADIENT)) {  // same kernels, launched one by one
-    HIP_TRY(ctx, enqueue(ctx->stream, true));
+    HIP_TRY(ctx, enqueue(ctx->stream, 0, n, true));
+    return MORSE_OK;
+  }
+  if (kRefineStreams && n >= kRefineSplitMin) {
+    // Candidates are independent: the two halves run as two chains of launches on two
+    // streams, so that one chain's evaluations keep the GPU busy while the other waits
+    // between its dependent launches.  Both chains start after the work already on the
+    // context's stream, and the stream waits for both.
+    const int64_t n_a = n / 2;
+    HIP_TRY(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->fork_stream, ctx->fork_ev, 0));
+    HIP_TRY(ctx, enqueue(ctx->stream, 0, n_a, false));
+    HIP_TRY(ctx, enqueue(ctx->fork_stream, n_a, n - n_a, false));
+    HIP_TRY(ctx, hipEventRecord(ctx->join_ev, ctx->fork_stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0));
     return MORSE_OK;
   }
   if (!ctx->refine_gexec || ctx->refine_key != h.h) {
@@ -277,7 +343,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     hipGraph_t g = nullptr;
     hipStream_t cs = ctx->capture_stream;
     HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue(cs, false);
+    hipError_t e = enqueue(cs, 0, n, false);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);

@@ -36,6 +36,8 @@ struct morse_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   hipStream_t capture_stream = nullptr;  // private stream for graph capture
+  hipStream_t fork_stream = nullptr;     // second chain of a refinement
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int num_cu = 256;
   char* ws = nullptr;
   size_t ws_size = 0;
