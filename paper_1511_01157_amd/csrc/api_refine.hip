@@ -297,41 +297,55 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     h.pod(maps[i].window);
   }
   h.pod(ctx->cmeta.p);
-  // start, steps + 1 rounds, write-back of candidates [c0, c0 + nc); with `timing`,
-  // events bracket each evaluation
-  auto enqueue = [&](hipStream_t cs, int64_t c0, int64_t nc, bool timing) -> hipError_t {
-    const LbfgsState sp = part_state(s, c0, nc);
-    const GradArgs ap = part_args(a, c0, nc);
-    double* params = d_params + 4 * c0;
-    double* init = d_chi2_init ? d_chi2_init + c0 : nullptr;
-    hipError_t e = launch_refine_init(sp, ap, params, anchor + 4 * c0, cs);
-    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
-      LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
-      if (timing) e = tm.begin(cs);
-      if (e == hipSuccess) e = launch_chi2_grad(ap, cs);
-      if (e == hipSuccess && timing) e = tm.end(cs);
-      if (e == hipSuccess)
-        e = launch_lbfgs_update(sp, ap, r, ft + c0, gt + 4 * c0, r == 0 ? init : nullptr, cs);
+  // start, steps + 1 rounds, write-back of the candidate ranges [c0[k], c0[k] + nc[k])
+  // on streams cs[k], k < parts, their launches interleaved round by round; with
+  // `timing`, events bracket each evaluation
+  auto enqueue = [&](int parts, const hipStream_t* cs, const int64_t* c0, const int64_t* nc,
+                     bool timing) -> hipError_t {
+    LbfgsState sp[2];
+    GradArgs ap[2];
+    for (int k = 0; k < parts; ++k) {
+      sp[k] = part_state(s, c0[k], nc[k]);
+      ap[k] = part_args(a, c0[k], nc[k]);
     }
-    if (e == hipSuccess) e = launch_lbfgs_finish(sp, params, d_chi2_out + c0, cs);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < parts && e == hipSuccess; ++k)
+      e = launch_refine_init(sp[k], ap[k], d_params + 4 * c0[k], anchor + 4 * c0[k], cs[k]);
+    for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
+      for (int k = 0; k < parts && e == hipSuccess; ++k) {
+        LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
+        if (timing) e = tm.begin(cs[k]);
+        if (e == hipSuccess) e = launch_chi2_grad(ap[k], cs[k]);
+        if (e == hipSuccess && timing) e = tm.end(cs[k]);
+        double* init = (r == 0 && d_chi2_init) ? d_chi2_init + c0[k] : nullptr;
+        if (e == hipSuccess)
+          e = launch_lbfgs_update(sp[k], ap[k], r, ft + c0[k], gt + 4 * c0[k], init, cs[k]);
+      }
+    }
+    for (int k = 0; k < parts && e == hipSuccess; ++k)
+      e = launch_lbfgs_finish(sp[k], d_params + 4 * c0[k], d_chi2_out + c0[k], cs[k]);
     return e;
   };
+  const int64_t whole0 = 0;
   if (timed(ctx, MORSE_KERNEL_GRADIENT)) {  // same kernels, launched one by one
-    HIP_TRY(ctx, enqueue(ctx->stream, 0, n, true));
+    HIP_TRY(ctx, enqueue(1, &ctx->stream, &whole0, &n, true));
     return MORSE_OK;
   }
   if (kRefineStreams && n >= kRefineSplitMin) {
     // Candidates are independent: the two halves run as two chains of launches on two
     // streams, so that one chain's evaluations keep the GPU busy while the other waits
     // between its dependent launches.  Both chains start after the work already on the
-    // context's stream, and the stream waits for both.
-    const int64_t n_a = n / 2;
+    // context's stream, and the stream waits for both; once forked, the join is
+    // recorded even if a launch failed, so later work never overlaps the second chain.
+    const hipStream_t cs[2] = {ctx->stream, ctx->fork_stream};
+    const int64_t c0[2] = {0, n / 2}, nc[2] = {n / 2, n - n / 2};
     HIP_TRY(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
     HIP_TRY(ctx, hipStreamWaitEvent(ctx->fork_stream, ctx->fork_ev, 0));
-    HIP_TRY(ctx, enqueue(ctx->stream, 0, n_a, false));
-    HIP_TRY(ctx, enqueue(ctx->fork_stream, n_a, n - n_a, false));
-    HIP_TRY(ctx, hipEventRecord(ctx->join_ev, ctx->fork_stream));
-    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0));
+    const hipError_t e = enqueue(2, cs, c0, nc, false);
+    hipError_t ej = hipEventRecord(ctx->join_ev, ctx->fork_stream);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
+    HIP_TRY(ctx, e);
+    HIP_TRY(ctx, ej);
     return MORSE_OK;
   }
   if (!ctx->refine_gexec || ctx->refine_key != h.h) {
@@ -343,7 +357,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     hipGraph_t g = nullptr;
     hipStream_t cs = ctx->capture_stream;
     HIP_TRY(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue(cs, 0, n, false);
+    hipError_t e = enqueue(1, &cs, &whole0, &n, false);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
