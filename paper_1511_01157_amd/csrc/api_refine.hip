@@ -79,9 +79,8 @@ int setup_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
 
 namespace {
 
-// Refinements of at least kRefineSplitMin candidates run as two chains on two streams
-// (kRefineStreams), others as one captured graph.
-constexpr bool kRefineStreams = true;
+// Refinements of at least kRefineSplitMin candidates run as two chains on two streams,
+// others as one captured graph.
 constexpr int64_t kRefineSplitMin = 1024;
 
 // Views of the candidates [c0, c0 + n) of a refinement's state and evaluation arguments.
@@ -331,7 +330,7 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     HIP_TRY(ctx, enqueue(1, &ctx->stream, &whole0, &n, true));
     return MORSE_OK;
   }
-  if (kRefineStreams && n >= kRefineSplitMin) {
+  if (n >= kRefineSplitMin) {
     // Candidates are independent: the two halves run as two chains of launches on two
     // streams, so that one chain's evaluations keep the GPU busy while the other waits
     // between its dependent launches.  Both chains start after the work already on the
