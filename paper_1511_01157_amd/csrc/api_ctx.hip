@@ -60,6 +60,7 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   if (!ctx) return MORSE_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->fork_stream);  // before the workspace it reads is freed
   if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
   if (ctx->refine_gexec) (void)hipGraphExecDestroy(ctx->refine_gexec);
   if (ctx->ws) (void)hipFree(ctx->ws);
@@ -74,7 +75,6 @@ int morse_ctx_destroy(morse_ctx* ctx) {
     (void)hipEventDestroy(t.b);
   }
   for (hipEvent_t e : ctx->free_events) (void)hipEventDestroy(e);
-  (void)hipStreamSynchronize(ctx->fork_stream);
   (void)hipEventDestroy(ctx->join_ev);
   (void)hipEventDestroy(ctx->fork_ev);
   (void)hipStreamDestroy(ctx->fork_stream);
