@@ -41,7 +41,9 @@ int morse_ctx_create(int device, void* stream, morse_ctx** out) {
     c->own_stream = true;
   }
   if (hipStreamCreate(&c->capture_stream) != hipSuccess ||
-      hipStreamCreate(&c->fork_stream) != hipSuccess ||
+      // non-blocking, default priority: ordered against the context's stream by the
+      // refinement's own fork and join events only, also when that is the null stream
+      hipStreamCreateWithFlags(&c->fork_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
