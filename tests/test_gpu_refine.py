@@ -129,23 +129,24 @@ def test_refine_vs_oracle_state_machine(tiny_oracle_map):
 
 
 def test_refine_two_chains_match_single_chain_calls(tiny_oracle_map):
-    """A refinement of 2048 candidates runs its two halves as two chains of launches on
-    two streams; the endpoints equal, bit for bit, those of four refinements of 512
-    candidates each (one chain, one captured graph), since candidates are independent."""
+    """A refinement of 2047 candidates runs its two halves (1023 and 1024) as two chains
+    of launches on two streams; the endpoints equal, bit for bit, those of four
+    refinements of at most 512 candidates each (one chain, one captured graph), since
+    candidates are independent."""
     c = W.config("tiny")
     amap = tiny_oracle_map[2]
     ev = W.load_lightcurve("tiny")
-    n = 2048
+    n = 2047
     P = torch.from_numpy(candidates(n, 9, ev["truth"], spread=(0.5, 0.01, 1.0, 0.02))).to(DEV)
     lcs = M.LightCurveBatch.from_events([ev], DEV)
     maps = [(dmap(amap), c["window"])]
     z = torch.zeros(n, dtype=torch.int32, device=DEV)
-    note("refine tiny 2048 candidates, two chains")
+    note("refine tiny 2047 candidates, two chains")
     out, chi2, chi2_0 = M.refine(maps, lcs, P, z, z, steps=50)
     parts = []
     for k in range(4):
-        note(f"refine tiny candidates {512 * k}..{512 * (k + 1)}, one chain")
-        sl = slice(512 * k, 512 * (k + 1))
+        sl = slice(512 * k, min(512 * (k + 1), n))
+        note(f"refine tiny candidates {sl.start}..{sl.stop}, one chain")
         parts.append(M.refine(maps, lcs, P[sl].contiguous(), z[sl], z[sl], steps=50))
     torch.cuda.synchronize()
     for got, want in ((out, torch.cat([p[0] for p in parts])), (chi2, torch.cat([p[1] for p in parts])),
