@@ -33,7 +33,8 @@ import numpy as np
 
 from .adjoint import chi2_grad
 
-__all__ = ["LbfgsOptions", "natural_params", "refine_one", "refine"]
+__all__ = ["LbfgsOptions", "natural_params", "two_loop_direction", "store_pair", "minimize",
+           "refine_one", "refine"]
 
 
 class LbfgsOptions:
@@ -63,8 +64,49 @@ def _eval(amap, window, tt, F, w, t_ref, anchor, p):
     return float(chi2[0]), gp
 
 
-def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=None):
-    """Refine one candidate; returns (natural params [4], chi2, history of f)."""
+def two_loop_direction(S, Y, R, g):
+    """d = -H g by the two-loop recursion over the stored pairs (oldest first), with
+    H0 = gamma I, gamma = s.y / y.y of the newest pair (no pairs: 1e-2/|g|)."""
+    q = list(g)
+    alph = []
+    for i in range(len(S) - 1, -1, -1):
+        a = R[i] * _dot(S[i], q)
+        alph.append(a)
+        q = [q[k] - a * Y[i][k] for k in range(4)]
+    alph.reverse()
+    gn = math.sqrt(_dot(g, g))
+    if S:
+        gamma = _dot(S[-1], Y[-1]) / _dot(Y[-1], Y[-1])
+    else:
+        gamma = 1e-2 / gn if gn > 0 else 0.0
+    r = [gamma * q[k] for k in range(4)]
+    for i in range(len(S)):
+        b = R[i] * _dot(Y[i], r)
+        r = [r[k] + S[i][k] * (alph[i] - b) for k in range(4)]
+    return [-r[k] for k in range(4)]
+
+
+def store_pair(S, Y, R, s, y, m):
+    """Append the curvature pair (s, y) when s.y > 1e-12 |s| |y|, dropping the oldest
+    pair beyond m; returns whether the pair was kept."""
+    sy = _dot(s, y)
+    if not sy > 1e-12 * math.sqrt(_dot(s, s)) * math.sqrt(_dot(y, y)):
+        return False
+    S.append(list(s))
+    Y.append(list(y))
+    R.append(1.0 / sy)
+    while len(S) > m:
+        S.pop(0)
+        Y.pop(0)
+        R.pop(0)
+    return True
+
+
+def minimize(evaluate, opt: LbfgsOptions, trace=None):
+    """Run the state machine above on evaluate(p) -> (f, grad) (p: 4 binary32 values,
+    grad: 4 floats); returns (p, f, history of accepted f).  When trace is a list, each
+    new direction appends a dict with the accepted point p, its f and g, the direction
+    d and the number of stored pairs."""
     S, Y, R = [], [], []
     p = [np.float32(0.0)] * 4
     pt = [np.float32(0.0)] * 4
@@ -76,28 +118,16 @@ def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=N
 
     def new_direction():
         nonlocal d, t, nls, pt, active, S, Y, R
-        q = list(g)
-        alph = []
-        for i in range(len(S) - 1, -1, -1):
-            a = R[i] * _dot(S[i], q)
-            alph.append(a)
-            q = [q[k] - a * Y[i][k] for k in range(4)]
-        alph.reverse()
-        gn = math.sqrt(_dot(g, g))
-        if S:
-            gamma = _dot(S[-1], Y[-1]) / _dot(Y[-1], Y[-1])
-        else:
-            gamma = 1e-2 / gn if gn > 0 else 0.0
-        r = [gamma * q[k] for k in range(4)]
-        for i in range(len(S)):
-            b = R[i] * _dot(Y[i], r)
-            r = [r[k] + S[i][k] * (alph[i] - b) for k in range(4)]
-        d = [-r[k] for k in range(4)]
+        d = two_loop_direction(S, Y, R, g)
         gd = _dot(g, d)
         if not (gd < 0.0) or not all(math.isfinite(v) for v in d):
             S, Y, R = [], [], []
+            gn = math.sqrt(_dot(g, g))
             gamma = 1e-2 / gn if gn > 0 else 0.0
             d = [-(gamma * g[k]) for k in range(4)]
+        if trace is not None:
+            trace.append({"p": [float(v) for v in p], "f": f, "g": list(g), "d": list(d),
+                          "pairs": len(S)})
         t = 1.0
         nls = 0
         pt = [np.float32(float(p[k]) + t * d[k]) for k in range(4)]
@@ -107,7 +137,7 @@ def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=N
     for rnd in range(opt.steps + 1):
         if not active:
             break
-        ft, gt = _eval(amap, window, tt, F, w, t_ref, anchor, pt)
+        ft, gt = evaluate(pt)
         if rnd == 0:
             p, f, g = list(pt), ft, gt
             fs.append(f)
@@ -117,15 +147,7 @@ def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=N
         if math.isfinite(ft) and ft <= f + (opt.c1 * t) * gd:
             s = [float(pt[k]) - float(p[k]) for k in range(4)]
             y = [gt[k] - g[k] for k in range(4)]
-            sy = _dot(s, y)
-            if sy > 1e-12 * math.sqrt(_dot(s, s)) * math.sqrt(_dot(y, y)):
-                S.append(s)
-                Y.append(y)
-                R.append(1.0 / sy)
-                if len(S) > opt.history:
-                    S.pop(0)
-                    Y.pop(0)
-                    R.pop(0)
+            store_pair(S, Y, R, s, y, opt.history)
             p, f, g = list(pt), ft, gt
             fs.append(f)
             new_direction()
@@ -136,6 +158,12 @@ def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=N
             else:
                 t *= opt.shrink
                 pt = [np.float32(float(p[k]) + t * d[k]) for k in range(4)]
+    return p, f, fs
+
+
+def refine_one(amap, window, tt, F, w, t_ref, anchor, opt: LbfgsOptions, trace=None):
+    """Refine one candidate; returns (natural params [4], chi2, history of f)."""
+    p, f, fs = minimize(lambda pt: _eval(amap, window, tt, F, w, t_ref, anchor, pt), opt, trace)
     return natural_params(anchor, p), f, fs
 
 

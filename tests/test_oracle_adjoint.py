@@ -66,8 +66,7 @@ def test_lbfgs_decreases_and_converges_noise_free():
     p, f, fs = refine_one(amap, WIN, tt, F, w, 0.0, anchor, LbfgsOptions(steps=80))
     assert all(b <= a for a, b in zip(fs, fs[1:]))
     assert f < 1e-3 * fs[0]
-    assert np.abs(p - truth).max() < 2e-3 * np.array([20, 1, 20, 1]).max()
-    assert abs(p[1] - truth[1]) < 1e-3 and abs(p[3] - truth[3]) < 1e-3
+    assert np.abs(p - truth).max() < 1e-3
 
 
 def test_lbfgs_batch_equals_single():
