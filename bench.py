@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the MORSE map-build + trajectory-search hot path on one MI355X.
 
-One step = the whole path over one batch of synthetic input of the large workload
-(s=0.8, q=5e-3): ray shooting of 32768^2 rays into a 2048^2 count map, normalisation
-and rho=2e-3 disk convolution, the batched (persistent, graph-replayed) chi-square
-search of the 64x64x16x8 = 524288-trajectory grid against a 3000-point light curve
-with a top-4096 selection, and 50 L-BFGS rounds on those 4096 candidates.
+One step = the whole path over the batched-events workload, the largest configuration:
+  * the 64-map (s, q) bank built twice from rays: at 1024^2 from 16384^2 rays each (the
+    search maps, point source) and at 2048^2 from 32768^2 rays each (the refinement
+    maps): ray shooting, binning and normalisation, 8.6e10 rays;
+  * the batched (persistent, graph-replayed) chi-square search of 256 ragged events
+    (200..20000 points, 903,548 in all) x 64 maps x 32768 trajectories per event,
+    1.9e12 light-curve point-evaluations, with the top 4096 (chi2, map, trajectory) of
+    every event;
+  * 50 L-BFGS rounds with the chi-square adjoint of the top 4096 candidates of the first
+    64 events (262,144 candidates) on their 2048^2 maps.
 
-value = grid-search light-curve point-evaluations per second of the whole step (the
-map build and the refinement are charged to the same clock), steps one after another.
-The line also reports the step time with consecutive steps pipelined (the map of step
-i + 1 built on a second stream while step i is searched and refined; --pipelined makes
-that the timed mode), rays/s of the ray kernel, the batched and plain search rates,
-the adjoint rate, the roofline of the dominant kernel and the CPU oracle timed on this
-host.
+value = search point-evaluations per second of the whole step (map builds and the
+refinement charged to the same clock), steps one after another in the library's
+production schedule (graph-replayed search, two-stream refinement, no per-kernel
+timing).  A separate pass times each kernel family with HIP events around its launches
+for the roofline.  Also reported: rays/s, the plain (one launch per event and map)
+search of the same problem, the adjoint rate, the (s, q)-grid workload (384 maps) and
+the large single-map workload with the finite-source stack, the caustic-line filter and
+the line simplex, and the CPU oracle on this host (single thread and all cores).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -49,6 +55,7 @@ OPS_PER_ADJOINT_EVAL = (32, 35)
 # 256 CUs x 2.4 GHz x 128 binary32 lanes / 64 FP64 lanes per clock.
 PEAK_F32 = 256 * 2.4e9 * 128
 PEAK_F64 = 256 * 2.4e9 * 64
+HBM_PEAK_GBS = 8000.0
 
 
 def peak_for(ops):
@@ -57,20 +64,19 @@ def peak_for(ops):
     return (n32 + n64) / (n32 / PEAK_F32 + n64 / PEAK_F64)
 
 
-# HBM-side traffic per launch (bytes) of the dominant kernel from two rocprofv3 --pmc
-# runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
-# dispatches of one warm-up and one timed step), each scaled by what the same counter
-# reads for a 1 GiB device-to-device copy (FETCH_SIZE 524301 KiB: factor 1.99995;
-# WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel and a hash of the sources
-# it is built from; a changed kernel reports null until it is measured again.
-TRAFFIC = {
-    ("k_chi2_grad", "70de781c55d8e4c4"): 2.846e+08,  # 138882 KiB fetched, 173 KiB written
-}
+# HBM-side traffic per launch (bytes) of a kernel on a workload, from two rocprofv3
+# --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
+# by what the same counter reads for a 1 GiB device-to-device copy (FETCH_SIZE 524301
+# KiB: factor 1.99995; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
+# hash of the sources it is built from and the workload; a changed kernel reports null
+# until it is measured again.
+TRAFFIC = {}
 STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
 STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
 KERNEL_SOURCES = {"k_rayshoot": ("maps.hip", "internal.h"),
                   "k_search_batched": ("search.hip", "internal.h"),
                   "k_chi2_grad": ("refine.hip", "internal.h")}
+CPU_WORKERS = 16          # the host-core share of one GPU
 
 
 def kernel_sha(kernel):
@@ -81,22 +87,23 @@ def kernel_sha(kernel):
     return h.hexdigest()[:16]
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--top-k", type=int, default=4096)
-    ap.add_argument("--refine-steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kernel-steps", type=int, default=2,
+                    help="steps of the separate per-kernel timing pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-lines", action="store_true",
-                    help="skip the (untimed-step) caustic-line filter measurement")
-    ap.add_argument("--no-stack", action="store_true",
-                    help="skip the (untimed-step) seven-radius finite-source stack measurement")
-    ap.add_argument("--pipelined", action="store_true",
-                    help="time steps with the next step's map built on a second stream "
-                         "(default: each step's map build, search and refinement in turn)")
+    ap.add_argument("--no-sqgrid", action="store_true", help="skip the (s, q)-grid workload")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large single-map workload (and its stack / line rows)")
+    ap.add_argument("--large-steps", type=int, default=5)
     # profiling aids: a plain device copy of known size (the reference for scaling
     # the FETCH_SIZE / WRITE_SIZE counters), and text summaries of rocprofv3 output
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -159,57 +166,423 @@ def copy_kernel(nbytes):
     print(f"copied {n * 4} bytes x 5", flush=True)
 
 
-def cpu_baseline(c, ev, axes, P_sample_every=128, rows=8192, n_refine=2):
-    """The oracle as it stands, on a bounded sample of one step, scaled to the step."""
+def roofline(kernel, ops, units, total_ms, launches, workload, upper=False):
+    """Roofline record of one kernel family: algorithmic lane-operations of all its
+    timed launches over their summed launch times."""
+    peak = peak_for(ops) / 1e12
+    ms = total_ms / max(launches, 1)
+    achieved = sum(ops) * units / (total_ms * 1e-3) / 1e12
+    traffic = TRAFFIC.get((kernel, kernel_sha(kernel), workload))
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "traffic_gbs": traffic / (ms * 1e-3) / 1e9 if traffic else None,
+            "traffic_frac_of_hbm": traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "launch_ms": ms, "launches": launches,
+            "ops_per_launch": sum(ops) * units / max(launches, 1),
+            "ops_are_upper_bound": upper, "ops_per_unit_f32_f64": list(ops)}
+
+
+OP_NOTE = ("achieved and peak in tera lane-operations/s (one FP32/FP64 add, mul, compare, "
+           "floor, cvt, div, sqrt or FMA per lane = 1); peak = the kernel's binary32/FP64 op "
+           "mix at 256 CU x 2.4 GHz x 128 binary32 or 64 FP64 lanes per clock (half the "
+           "published 157.3/78.6 TFLOP/s, which count an FMA twice); launch times from HIP "
+           "events around each launch on the library's stream, in a pass apart from the "
+           "timed steps; traffic from rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, "
+           "calibrated on a device copy")
+
+
+# ----------------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands on this host's cores, on a bounded sample of
+# one step of the batched-events workload, single thread and CPU_WORKERS processes,
+# each figure the median of three runs.  It runs before anything touches the GPU (the
+# worker processes are forked from this one).
+_CB = {}
+
+
+def _cb_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _cb_search(task):
+    """Oracle search of one event's first n trajectories on the sample map; returns
+    (seconds, point-evaluations, the best trajectory)."""
+    from oracle.search import search_mirror32
+    e, n = task
+    ev = _CB["events"][e]
+    P = _CB["P"][e][:n]
+    t = time.perf_counter()
+    chi2 = search_mirror32(_CB["map1"], _CB["win1"], ev["tt"], ev["F"], ev["w"], P, ev["t_ref"])[0]
+    return time.perf_counter() - t, n * len(ev["tt"]), P[int(chi2.argmin())]
+
+
+CB_REFINE_ROUNDS = 10  # L-BFGS rounds timed per candidate (one evaluation each)
+
+
+def _cb_refine(task):
+    """Oracle L-BFGS of one candidate on the 2048^2 sample map, CB_REFINE_ROUNDS rounds
+    after the first evaluation; returns (seconds, candidate-round-points)."""
+    import numpy as np
+    from oracle.lbfgs import LbfgsOptions, refine
+    e, anchor = task
+    ev = _CB["events"][e]
+    t = time.perf_counter()
+    with np.errstate(all="ignore"):  # trial points far out give non-finite chi2, rejected
+        refine(_CB["map2"], _CB["win2"], ev["tt"], ev["F"], ev["w"], ev["t_ref"], anchor[None, :],
+               LbfgsOptions(steps=CB_REFINE_ROUNDS))
+    return time.perf_counter() - t, (CB_REFINE_ROUNDS + 1) * len(ev["tt"])
+
+
+def _cb_norm(task):
+    """Oracle normalisation (point source: scale only) of the 2048^2 sample counts."""
+    from oracle.maps import normalize_convolve_mirror32
+    t = time.perf_counter()
+    normalize_convolve_mirror32(_CB["counts2"], _CB["scale2"], _CB["w0"])
+    return time.perf_counter() - t, _CB["counts2"].size
+
+
+def _median_rate(fn, reps=3):
+    rates = sorted(fn() for _ in range(reps))
+    return rates[len(rates) // 2]
+
+
+def cpu_baseline_batched(units):
+    """units: the step's rays, map pixels, search point-evaluations and refinement
+    candidate-round-points (candidates x evaluations x points).  Returns the
+    cpu_baseline record."""
+    import multiprocessing as mp
+    import platform
+
     import numpy as np
     import workloads as W
-    from oracle.lbfgs import LbfgsOptions, refine
-    from oracle.maps import disk_pixel_weights, map_scale, normalize_convolve_mirror32
+    from oracle.maps import disk_pixel_weights, map_scale
     from oracle.rays import rayshoot_mirror32_c
-    from oracle.search import grid_params, search_mirror32
 
-    nthreads = max(1, min(16, os.cpu_count() or 1))
-    ny = c["rays"][5]
-    j0 = ny // 2 - rows // 2
-    t = time.perf_counter()
-    rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], rows=(j0, j0 + rows), nthreads=nthreads)
-    t_rays = (time.perf_counter() - t) * ny / rows
-    counts, _ = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], c["window"], rows=(j0, j0 + 64), nthreads=nthreads)
-    dx = c["window"][2] / c["window"][4]
-    t = time.perf_counter()
-    amap = normalize_convolve_mirror32(counts, map_scale(c["rays"], c["window"]), disk_pixel_weights(c["rho"], dx, dx))
-    t_norm = time.perf_counter() - t
-    P = grid_params(*axes)
-    sample = P[::P_sample_every]
-    t = time.perf_counter()
-    search_mirror32(amap, c["window"], ev["tt"], ev["F"], ev["w"], sample, ev["t_ref"])
-    t_search = (time.perf_counter() - t) * len(P) / len(sample)
-    cand = P[:: len(P) // n_refine][:n_refine]
-    t = time.perf_counter()
-    refine(amap, c["window"], ev["tt"], ev["F"], ev["w"], ev["t_ref"], cand, LbfgsOptions(steps=50))
-    t_refine = (time.perf_counter() - t) * 4096 / n_refine
-    t_step = t_rays + t_norm + t_search + t_refine
-    evals = len(P) * len(ev["tt"])
+    nw = max(1, min(CPU_WORKERS, os.cpu_count() or 1))
+    cb, cr = W.config("batched"), W.config("refine")
+    bank = W.map_bank("batched")
+    mi = 27  # a mid-bank (s, q) with a resonant-size caustic
+    s, q = bank[mi]
+    progress(f"cpu baseline: oracle maps s={s:.3g} q={q:.3g} at 1024^2 and 2048^2")
+    c1, _ = rayshoot_mirror32_c(s, q, cb["rays"], cb["window"], nthreads=nw)
+    c2, _ = rayshoot_mirror32_c(s, q, cr["rays"], cr["window"], nthreads=nw)
+    w0 = disk_pixel_weights(0.0, 1, 1)
+    from oracle.maps import normalize_convolve_mirror32
+    # events of the refinement set (the first 64) nearest the median length
+    lens = np.array([t["npts"] for t in W.truths("refine")])
+    pick = [int(e) for e in np.argsort(np.abs(lens - np.median(lens)))[:nw]]
+    _CB.update(map1=normalize_convolve_mirror32(c1, map_scale(cb["rays"], cb["window"]), w0),
+               map2=normalize_convolve_mirror32(c2, map_scale(cr["rays"], cr["window"]), w0),
+               win1=cb["window"], win2=cr["window"], counts2=c2, w0=w0,
+               scale2=map_scale(cr["rays"], cr["window"]),
+               events={e: W.load_lightcurve("batched", e) for e in pick},
+               P={e: W.random_trajectories("batched", e) for e in pick})
+    _cb_init()
+    n_tr = 512
+    pool = mp.get_context("fork").Pool(nw, initializer=_cb_init)
+    try:
+        def pool_rate(fn, tasks):
+            t = time.perf_counter()
+            res = pool.map(fn, tasks)
+            return sum(r[1] for r in res) / (time.perf_counter() - t), res
+
+        progress("cpu baseline: rays")
+        ny = cb["rays"][5]
+
+        def rays_rate(threads, rows):
+            j0 = ny // 2 - rows // 2
+            t = time.perf_counter()
+            rayshoot_mirror32_c(s, q, cb["rays"], cb["window"], rows=(j0, j0 + rows), nthreads=threads)
+            return rows * cb["rays"][4] / (time.perf_counter() - t)
+        r_rays = (_median_rate(lambda: rays_rate(1, 256)), _median_rate(lambda: rays_rate(nw, 256 * nw)))
+        progress("cpu baseline: normalisation")
+        r_norm = (_median_rate(lambda: (lambda r: r[1] / r[0])(_cb_norm(None))),
+                  _median_rate(lambda: pool_rate(_cb_norm, [None] * nw)[0]))
+        progress("cpu baseline: search")
+        r_s1 = _median_rate(lambda: (lambda r: r[1] / r[0])(_cb_search((pick[0], n_tr))))
+        runs = [pool_rate(_cb_search, [(e, n_tr) for e in pick]) for _ in range(3)]
+        r_sa = sorted(r for r, _ in runs)[1]
+        seeds = [(e, r[2]) for e, r in zip(pick, runs[0][1])]  # the oracle's own best per event
+        progress("cpu baseline: refinement")
+        r_c1 = _median_rate(lambda: (lambda r: r[1] / r[0])(_cb_refine(seeds[0])))
+        r_ca = _median_rate(lambda: pool_rate(_cb_refine, seeds)[0])
+    finally:
+        pool.terminate()
+        pool.join()
+    out = {}
+    for j, (label, cores) in enumerate((("single_thread", 1), ("all_cores", nw))):
+        rr, rn, rs, rc = r_rays[j], r_norm[j], (r_s1, r_sa)[j], (r_c1, r_ca)[j]
+        t = {"rays": units["rays"] / rr, "normalise": units["pixels"] / rn,
+             "search": units["evals"] / rs, "refine": units["cand_round_points"] / rc}
+        out[label] = {"value": units["evals"] / sum(t.values()), "cores": cores,
+                      "step_s": sum(t.values()), "leg_s": t,
+                      "rates": {"rays_per_s": rr, "pixels_per_s": rn, "point_evals_per_s": rs,
+                                "candidate_round_points_per_s": rc}}
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except Exception:
+        model = platform.processor()
     return {
-        "value": evals / t_step, "unit": "point-evals/s", "cores": nthreads, "kind": "oracle",
-        "sample": (f"large workload step scaled from: C FP32-mirror ray shooting of {rows} of "
-                   f"{ny} lattice rows on {nthreads} threads ({t_rays:.1f} s scaled), numpy "
-                   f"normalise/convolve of the 2048^2 map ({t_norm:.2f} s), numpy binary32 "
-                   f"search of every {P_sample_every}th grid trajectory ({len(sample)} of "
-                   f"{len(P)}, {t_search:.1f} s scaled), L-BFGS of {n_refine} of 4096 "
-                   f"candidates ({t_refine:.1f} s scaled); numpy parts single-threaded"),
-        "step_s": t_step,
+        "value": out["all_cores"]["value"], "unit": "point-evals/s", "cores": nw, "kind": "oracle",
+        "sample": (f"one batched-events step extrapolated from timed samples, median of 3 each, "
+                   f"on map {mi} of the bank (s={s:.3g}, q={q:.3g}): C binary32 ray mirror on 256 "
+                   f"central lattice rows per thread; normalisation of the 2048^2 counts once per "
+                   f"process; numpy binary32 search of {n_tr} trajectories of one event per "
+                   f"process ({len(pick)} events of median length); numpy L-BFGS (FP64 adjoint) of "
+                   f"each event's best sampled trajectory on the 2048^2 map, {CB_REFINE_ROUNDS} "
+                   f"rounds timed and scaled per round to the step's 51 evaluations; "
+                   f"all-core figures from {nw} forked processes (wall clock), single-thread "
+                   f"from one; each leg scaled by the step's own units"),
+        "single_thread": out["single_thread"], "all_cores": out["all_cores"],
+        "host": {"cpu": model, "nproc": os.cpu_count()},
     }
 
 
-# Algorithmic work of the rows measured beside the step:
+# ----------------------------------------------------------------------------------
+# GPU legs
+def events_timer(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def leg_batched(args, M, W, torch, np, dev):
+    """The headline step on the batched-events workload (module docstring)."""
+    cb, cr = W.config("batched"), W.config("refine")
+    bank = W.map_bank("batched")
+    n_ev, n_r, k = cb["n_events"], cr["n_events"], cr["top_k"]
+    evs = [W.load_lightcurve("batched", e) for e in range(n_ev)]
+    P = np.stack([W.random_trajectories("batched", e) for e in range(n_ev)])
+    n_pts = np.array([len(e["tt"]) for e in evs])
+    n_traj = P.shape[1]
+    stream = torch.cuda.Stream(device=dev)
+    ctx = M.Context.bound(stream)
+    (w1, r1), (w2, r2) = (cb["window"], cb["rays"]), (cr["window"], cr["rays"])
+    units = {"rays": len(bank) * (r1[4] * r1[5] + r2[4] * r2[5]),
+             "pixels": len(bank) * (w1[4] * w1[5] + w2[4] * w2[5]),
+             "evals": int(n_pts.sum()) * len(bank) * n_traj,
+             "cand_points": k * int(n_pts[:n_r].sum())}
+    with torch.cuda.stream(stream):
+        lcs = M.LightCurveBatch.from_events(evs, dev)
+        Pd = torch.from_numpy(P).to(dev)
+        trajs = M.list_trajectories(Pd, shared=False)
+        trajs_r = M.list_trajectories(Pd[:n_r], shared=False)
+        bank1 = torch.empty((len(bank), w1[5], w1[4]), dtype=torch.float32, device=dev)
+        bank2 = torch.empty((len(bank), w2[5], w2[4]), dtype=torch.float32, device=dev)
+        cnt1 = torch.empty((w1[5], w1[4]), dtype=torch.int32, device=dev)
+        cnt2 = torch.empty((w2[5], w2[4]), dtype=torch.int32, device=dev)
+        views1 = [(bank1[i], w1) for i in range(len(bank))]
+        views2 = [(bank2[i], w2) for i in range(len(bank))]
+        sbuf = {}
+        cand = (torch.empty((n_r * k, 4), dtype=torch.float64, device=dev),
+                torch.empty(n_r * k, dtype=torch.int32, device=dev),
+                torch.empty(n_r * k, dtype=torch.int32, device=dev))
+        rbuf = (torch.empty(n_r * k, dtype=torch.float64, device=dev),
+                torch.empty(n_r * k, dtype=torch.float64, device=dev))
+
+        def build_bank(cfg, maps, cnt):
+            for i, (s, q) in enumerate(bank):
+                M.rayshoot(s, q, cfg["rays"], cfg["window"], cnt, ctx=ctx)
+                M.normalize_convolve(cnt, cfg["rays"], cfg["window"], cfg["rho"], out=maps[i], ctx=ctx)
+
+        def step(ev=None):
+            mark = (lambda j: ev[j].record(stream)) if ev else (lambda j: None)
+            mark(0)
+            build_bank(cb, bank1, cnt1)
+            build_bank(cr, bank2, cnt2)
+            mark(1)
+            r = M.search(views1, lcs, trajs, "batched", chi2=False, top_k=k, out=sbuf, ctx=ctx)
+            sbuf.update(r)
+            mark(2)
+            Pc, e_idx, m_idx = M.candidates_from_topk(trajs_r, r["topk_idx"][:n_r], len(bank),
+                                                      out=cand, ctx=ctx)
+            out, chi2, chi2_0 = M.refine(views2, lcs, Pc, e_idx, m_idx, steps=cr["steps"],
+                                         inplace=True, chi2_out=rbuf, ctx=ctx)
+            mark(3)
+            return chi2, chi2_0
+
+        progress("batched: bank build + autotune")
+        build_bank(cb, bank1, cnt1)
+        tuned = M.autotune(views1, lcs, trajs, ctx=ctx)
+        progress(f"batched: warm-up x{max(1, args.warmup)} (autotuned shape {tuned})")
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        progress(f"batched: {args.steps} timed steps")
+        ev = [events_timer(torch, 4) for _ in range(args.steps)]
+        t0, t1 = events_timer(torch, 2)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        wall0 = time.perf_counter()
+        for i in range(args.steps):
+            res = step(ev[i])
+        t1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_step = t0.elapsed_time(t1) / args.steps
+        stage = np.mean([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in ev], axis=0)
+        chi2, chi2_0 = res
+        improved = float((chi2 <= chi2_0).float().mean())
+        strictly = float((chi2 < chi2_0).float().mean())
+
+        # kernel times: a separate pass with HIP events around every launch of each
+        # family (the refinement then runs as one chain of launches)
+        ks = max(1, args.kernel_steps)
+        progress(f"batched: kernel timing pass x{ks}")
+        fams = {"k_rayshoot": M.KERNEL_RAYSHOOT, "k_search_batched": M.KERNEL_SEARCH,
+                "k_chi2_grad": M.KERNEL_GRADIENT}
+        ctx.set_timing(list(fams.values()))
+        for f in fams.values():
+            ctx.kernel_time(f, reset=True)
+        for _ in range(ks):
+            step()
+        torch.cuda.synchronize()
+        ktime = {n: ctx.kernel_time(f, reset=True) for n, f in fams.items()}
+        ctx.set_timing([])
+
+        plain_ms = None
+        if not args.no_plain:
+            progress("batched: plain search (one launch per event and map)")
+            pbuf = {}
+            e0, e1 = events_timer(torch, 2)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            pr = M.search(views1, lcs, trajs, "plain", chi2=False, top_k=k, out=pbuf, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            plain_ms = e0.elapsed_time(e1)
+            same_topk = bool(torch.equal(pr["topk_idx"], sbuf["topk_idx"]) and
+                             torch.equal(pr["topk_chi2"], sbuf["topk_chi2"]))
+
+    build_ms, search_ms, refine_ms = stage
+    rounds = cr["steps"] + 1
+    kr = {
+        "k_rayshoot": roofline("k_rayshoot", OPS_PER_RAY, ks * units["rays"], *ktime["k_rayshoot"],
+                               "batched"),
+        "k_search_batched": roofline("k_search_batched", OPS_PER_POINT_EVAL, ks * units["evals"],
+                                     *ktime["k_search_batched"], "batched"),
+        "k_chi2_grad": roofline("k_chi2_grad", OPS_PER_ADJOINT_EVAL,
+                                ks * rounds * units["cand_points"], *ktime["k_chi2_grad"],
+                                "batched", upper=True),
+    }
+    per_step = {n: t / ks for n, (t, _) in ktime.items()}
+    dom = max(per_step, key=per_step.get)
+    rec = {
+        "ms_per_step": ms_step, "wall_s_timed": wall,
+        "value": units["evals"] / (ms_step * 1e-3),
+        "stages_ms": {"map_banks": build_ms, "search_batched": search_ms,
+                      "candidates_refine": refine_ms},
+        "rays_per_s": units["rays"] / (build_ms * 1e-3),
+        "search_point_evals_per_s": {
+            "batched": units["evals"] / (search_ms * 1e-3),
+            "plain": units["evals"] / (plain_ms * 1e-3) if plain_ms else None,
+            "batched_shape": {"autotuned_index": tuned, "note": "trajectories per item, waves "
+                              "per workgroup, workgroups per CU and TU of the library's shape "
+                              "table entry; one persistent launch over (event, map, trajectory "
+                              "block) items, graph-replayed"},
+            "plain_shape": "one launch per (event, map): one wavefront per trajectory (TU = 1), "
+                           "4 wavefronts per workgroup",
+            "plain_topk_equal": same_topk if plain_ms else None},
+        "adjoint_point_evals_per_s_upper": rounds * units["cand_points"] / (refine_ms * 1e-3),
+        "refine_chi2_not_raised": improved, "refine_chi2_lowered": strictly,
+        "kernel_ms_per_step": per_step, "kernels": kr, "dominant": dom,
+        "units": units,
+        "config": {"workload": ("batched events: 256 ragged events (lognormal lengths, median "
+                                "2000, 200-20000 points, 903548 in all) x 64-map (s, q) bank at "
+                                "1024^2 from 16384^2 rays each, point source, x 32768 random "
+                                "trajectories per event per map, top-4096 per event; then 50 "
+                                "L-BFGS rounds of the top-4096 of the first 64 events (262144 "
+                                "candidates) on the bank rebuilt at 2048^2 from 32768^2 rays"),
+                   "n_events": n_ev, "n_maps": len(bank), "n_traj_per_event": n_traj,
+                   "n_points": int(n_pts.sum()), "maps": [[w1[5], w1[4]], [w2[5], w2[4]]],
+                   "rays_per_map": [r1[4] * r1[5], r2[4] * r2[5]], "top_k": k,
+                   "refine_events": n_r, "refine_rounds": cr["steps"],
+                   "parallelism": "single GPU", "autotuned_search_shape": tuned},
+    }
+    del bank1, bank2, sbuf, cand, rbuf
+    torch.cuda.empty_cache()
+    return rec
+
+
+def leg_sqgrid(args, M, W, torch, np, dev):
+    """(s, q) grid: 384 maps of 16384^2 rays at 1024^2 (rho = 1e-3, the identity), one
+    3000-point light curve, 1e5 random trajectories shared by all maps, best per map."""
+    c = W.config("sqgrid")
+    bank = W.map_bank("sqgrid")
+    ev = W.load_lightcurve("sqgrid")
+    P = W.random_trajectories("sqgrid")
+    win, rays = c["window"], c["rays"]
+    stream = torch.cuda.Stream(device=dev)
+    ctx = M.Context.bound(stream)
+    n_rays = len(bank) * rays[4] * rays[5]
+    evals = len(bank) * len(P) * len(ev["tt"])
+    with torch.cuda.stream(stream):
+        maps = torch.empty((len(bank), win[5], win[4]), dtype=torch.float32, device=dev)
+        cnt = torch.empty((win[5], win[4]), dtype=torch.int32, device=dev)
+        views = [(maps[i], win) for i in range(len(bank))]
+        lcs = M.LightCurveBatch.from_events([ev], dev)
+        trajs = M.list_trajectories(torch.from_numpy(P).to(dev))
+        out = {}
+
+        def step(e=None):
+            mark = (lambda j: e[j].record(stream)) if e else (lambda j: None)
+            mark(0)
+            for i, (s, q) in enumerate(bank):
+                M.rayshoot(s, q, rays, win, cnt, ctx=ctx)
+                M.normalize_convolve(cnt, rays, win, c["rho"], out=maps[i], ctx=ctx)
+            mark(1)
+            r = M.search(views, lcs, trajs, "batched", chi2=False, best=True, out=out, ctx=ctx)
+            out.update(r)
+            mark(2)
+            return r
+
+        progress("sqgrid: 384 maps, autotune, warm-up")
+        step()
+        tuned = M.autotune(views, lcs, trajs, ctx=ctx)
+        step()
+        n = 3
+        ev_ = [events_timer(torch, 3) for _ in range(n)]
+        torch.cuda.synchronize()
+        for i in range(n):
+            r = step(ev_[i])
+        torch.cuda.synchronize()
+        st = np.mean([[e[j].elapsed_time(e[j + 1]) for j in range(2)] for e in ev_], axis=0)
+        plain_ms = None
+        if not args.no_plain:
+            progress("sqgrid: plain search")
+            e0, e1 = events_timer(torch, 2)
+            e0.record(stream)
+            M.search(views, lcs, trajs, "plain", chi2=False, best=True, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            plain_ms = e0.elapsed_time(e1)
+        best = r["best_chi2"][0].cpu().numpy()
+    mb = int(np.argmin(best))
+    rec = {"workload": "(s, q) grid: 24 s x 16 q = 384 maps at 1024^2 from 16384^2 rays each, "
+                       "rho = 1e-3 (the identity at this pixel size), one 3000-point light "
+                       "curve, 1e5 random trajectories shared by all maps, best per map",
+           "ms_per_step": float(sum(st)), "stages_ms": {"maps": st[0], "search_batched": st[1]},
+           "rays_per_s": n_rays / (st[0] * 1e-3),
+           "search_point_evals_per_s": {"batched": evals / (st[1] * 1e-3),
+                                        "plain": evals / (plain_ms * 1e-3) if plain_ms else None},
+           "autotuned_search_shape": tuned, "rays": n_rays, "point_evals": evals,
+           "best_map": {"index": mb, "s": float(bank[mb][0]), "q": float(bank[mb][1]),
+                        "chi2": float(best[mb])},
+           "truth": {"s": c["s"], "q": c["q"]},
+           "best_chi2_quantiles": [float(v) for v in np.quantile(best, [0.0, 0.5, 1.0])]}
+    del maps
+    torch.cuda.empty_cache()
+    return rec
+
+
+# Algorithmic work of the rows measured beside the large workload's step:
 # one line-filter sample = tau 2, position 2, zeta 4, grid coordinates 4, on-map tests
 # 4, floor/fraction 4, cell index 3, bilinear blend 9, max 1 (binary32/integer); one
 # point of a simplex chi-square evaluation = the search's sample (32) + b, w b and the
 # three FP64 sums (6).
 OPS_PER_FILTER_SAMPLE = (33, 0)
 OPS_PER_SIMPLEX_POINT = (32, 6)
-HBM_PEAK_GBS = 8000.0
 
 
 def fft_passes(n):
@@ -246,7 +619,7 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
     win = c["window"]
     ny_r = c["rays"][5]
     counts, _ = rayshoot_mirror32_c(c["s"], c["q"], c["rays"], win, rows=(ny_r // 2 - 32, ny_r // 2 + 32),
-                                    nthreads=max(1, min(16, os.cpu_count() or 1)))
+                                    nthreads=max(1, min(CPU_WORKERS, os.cpu_count() or 1)))
     mx, my = win[4], win[5]
     d = win[2] / mx
     s32 = map_scale(c["rays"], win)
@@ -288,29 +661,13 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
     )
 
 
-def main():
-    args = parse()
-    if args.summarize_trace:
-        return summarize_trace(args.summarize_trace)
-    if args.summarize_pmc:
-        return summarize_pmc(args.summarize_pmc)
-    if args.copy_bytes:
-        return copy_kernel(args.copy_bytes)
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(on several GPUs the path would deal maps or ray rows to GPUs and gather "
-              "the per-GPU top-k lists)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-
-    import paper_1511_01157_amd as M
-    import workloads as W
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    # stream_b runs the search and the refinement; stream_a builds maps, in the
-    # pipelined mode the map of step i + 1 while stream_b works on step i
+def leg_large(args, M, W, torch, np, dev):
+    """Large single map (s = 0.8, q = 5e-3): 32768^2 rays into a 2048^2 map, rho = 2e-3
+    disk convolution, the batched search of the 524288-trajectory grid against one
+    3000-point light curve with its top 4096, and 50 L-BFGS rounds on those; steps
+    serial and pipelined (the next step's map built on a second stream).  Beside it, on
+    the step's counts and map: the seven-radius finite-source stack, the caustic-line
+    filter and the line simplex."""
     stream = torch.cuda.Stream(device=dev)
     stream_a = torch.cuda.Stream(device=dev)
     ctx_b = M.Context.bound(stream)
@@ -320,37 +677,29 @@ def main():
     axes = W.grid_axes("large")
     n_traj = int(np.prod([len(a) for a in axes]))
     n_pts = len(ev["tt"])
-    k = args.top_k
+    k = 4096
     rays_per_step = c["rays"][4] * c["rays"][5]
     evals_per_step = n_traj * n_pts
-
     with torch.cuda.stream(stream):
         lcs = M.LightCurveBatch.from_events([ev], dev)
         trajs = M.grid_trajectories(*axes)
         shape = (c["window"][5], c["window"][4])
         counts = torch.empty(shape, dtype=torch.int32, device=dev)
-        amap = torch.empty(shape, dtype=torch.float32, device=dev)        # read by the search
-        amap_build = torch.empty(shape, dtype=torch.float32, device=dev)  # written by stream_a
+        amap = torch.empty(shape, dtype=torch.float32, device=dev)
+        amap_build = torch.empty(shape, dtype=torch.float32, device=dev)
         maps = [(amap, c["window"])]
-        # the batched search shape comes from the autotuner (setup, not timed); the
-        # map it tunes on is built once here
         M.rayshoot(c["s"], c["q"], c["rays"], c["window"], counts, ctx=ctx_b)
         M.normalize_convolve(counts, c["rays"], c["window"], c["rho"], out=amap, ctx=ctx_b)
         tuned = M.autotune(maps, lcs, trajs, ctx=ctx_b)
-
-        # step buffers, allocated once so the captured graphs replay every step
         sbuf = {}
         cand = (torch.empty((k, 4), dtype=torch.float64, device=dev),
                 torch.empty(k, dtype=torch.int32, device=dev),
                 torch.empty(k, dtype=torch.int32, device=dev))
         rbuf = (torch.empty(k, dtype=torch.float64, device=dev),
                 torch.empty(k, dtype=torch.float64, device=dev))
-        e_built = torch.cuda.Event()
-        e_copied = torch.cuda.Event()
+        e_built, e_copied = torch.cuda.Event(), torch.cuda.Event()
 
         def build(pipelined, evs=None):
-            """Ray shooting + normalisation of one step's map (stream_a when pipelined:
-            into amap_build, after the search has copied out the previous map)."""
             if not pipelined:
                 mark = (lambda j: evs[j].record(stream)) if evs else (lambda j: None)
                 mark(0)
@@ -369,7 +718,6 @@ def main():
             e_built.record(stream_a)
 
         def take_map():
-            """Stream_b takes the built map (a 16 MiB device copy) and frees amap_build."""
             stream.wait_event(e_built)
             amap.copy_(amap_build)
             e_copied.record(stream)
@@ -381,264 +729,216 @@ def main():
             sbuf.update(r)
             mark(4)
             P, e_idx, m_idx = M.candidates_from_topk(trajs, r["topk_idx"], 1, out=cand, ctx=ctx_b)
-            out, chi2, chi2_0 = M.refine(maps, lcs, P, e_idx, m_idx, steps=args.refine_steps,
-                                         inplace=True, chi2_out=rbuf, ctx=ctx_b)
+            M.refine(maps, lcs, P, e_idx, m_idx, steps=50, inplace=True, chi2_out=rbuf, ctx=ctx_b)
             mark(5)
-            return r, out, chi2, chi2_0
 
         def run(n, pipelined, ev_sets=None):
-            """n whole steps; pipelined: the map of step i + 1 is built on stream_a
-            while stream_b searches and refines step i."""
             evs = (lambda i: ev_sets[i]) if ev_sets else (lambda i: None)
-            res = None
             if not pipelined:
                 for i in range(n):
                     build(False, evs(i))
-                    res = solve(evs(i))
-                return res
+                    solve(evs(i))
+                return
             build(True, evs(0))
             for i in range(n):
                 take_map()
                 if i + 1 < n:
                     build(True, evs(i + 1))
-                res = solve(evs(i))
-            return res
+                solve(evs(i))
 
         def timed(n, pipelined):
-            # per step: build start, rays done, map done (build stream); search start,
-            # search done, refinement done (search stream)
-            ev_sets = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(n)]
-            t_start = torch.cuda.Event(enable_timing=True)
-            t_end = torch.cuda.Event(enable_timing=True)
+            ev_sets = [events_timer(torch, 6) for _ in range(n)]
+            t0, t1 = events_timer(torch, 2)
             torch.cuda.synchronize()
-            t_start.record(stream_a if pipelined else stream)
-            wall0 = time.perf_counter()
-            res = run(n, pipelined, ev_sets)
-            t_end.record(stream)
+            t0.record(stream_a if pipelined else stream)
+            run(n, pipelined, ev_sets)
+            t1.record(stream)
             torch.cuda.synchronize()
-            wall = time.perf_counter() - wall0
-            ms = t_start.elapsed_time(t_end) / n
             stage = np.mean([[e[j].elapsed_time(e[j + 1]) for j in (0, 1, 3, 4)] for e in ev_sets],
                             axis=0)
-            return ms, stage, wall, res
+            return t0.elapsed_time(t1) / n, stage
 
-        pipelined = args.pipelined
-        # Warm-up with every kernel family timed (HIP events around each launch on the
-        # library's streams) picks the kernel with the most time per step; the timed
-        # steps then time that kernel only.  One untimed step in between captures the
-        # graphs of the entry points outside the timed region.
-        fams = {"k_rayshoot": (M.KERNEL_RAYSHOOT, ctx_a if pipelined else ctx_b),
-                "k_search_batched": (M.KERNEL_SEARCH, ctx_b),
-                "k_chi2_grad": (M.KERNEL_GRADIENT, ctx_b)}
-        for fam, cx in fams.values():
-            cx.set_timing([f for f, x in fams.values() if x is cx])
-        n_warm = max(1, args.warmup)
-        run(n_warm, pipelined)
-        per_step = {n: cx.kernel_time(f, reset=True)[0] / n_warm for n, (f, cx) in fams.items()}
-        dom = max(per_step, key=per_step.get)
-        dom_fam, dom_ctx = fams[dom]
-        ctx_a.set_timing([])
-        ctx_b.set_timing([])
-        dom_ctx.set_timing([dom_fam])
-        run(1, pipelined)
+        progress("large: warm-up")
+        run(1, False)
+        run(1, True)
+        n = max(1, args.large_steps)
+        progress(f"large: {n} serial + {n} pipelined steps")
+        serial_ms, stage = timed(n, False)
+        pipe_ms, _ = timed(n, True)
+        rec = {"workload": "large: s=0.8 q=5e-3, 32768^2 rays -> 2048^2 map, rho=2e-3, 3000-point "
+                           "light curve, 524288-trajectory grid, top-4096 + 50 L-BFGS rounds",
+               "serial_ms_per_step": serial_ms, "pipelined_ms_per_step": pipe_ms,
+               "autotuned_search_shape": tuned,
+               "stages_ms": dict(zip(("rayshoot", "normalize_convolve", "search_batched",
+                                      "candidates_refine"), stage)),
+               "rays_per_s": rays_per_step / (stage[0] * 1e-3),
+               "search_point_evals_per_s_batched": evals_per_step / (stage[2] * 1e-3),
+               "adjoint_point_evals_per_s_upper": 51 * k * n_pts / (stage[3] * 1e-3)}
+
+        # Finite-source stack of the step's counts: seven radii log-spaced over [0.001, 1]
+        # with limb-darkening coefficient 0.53.
+        progress("large: finite-source stack")
+        rhos = np.logspace(-3.0, 0.0, 7)
+        sout = M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, ctx=ctx_b)
         torch.cuda.synchronize()
-        dom_ctx.kernel_time(dom_fam, reset=True)
-        ms_step, stage, wall, res = timed(args.steps, pipelined)
-        dom_total_ms, dom_launches = dom_ctx.kernel_time(dom_fam, reset=True)
-        dom_ctx.set_timing([])
-        r, out, chi2, chi2_0 = res
-        improved = float((chi2 <= chi2_0).float().mean())
-        # the other schedule of the same steps, for reference
-        run(1, not pipelined)
-        other_ms = timed(args.steps, not pipelined)[0]
-        serial_ms, pipe_ms = (other_ms, ms_step) if pipelined else (ms_step, other_ms)
+        e0, e1 = events_timer(torch, 2)
+        e0.record(stream)
+        for _ in range(5):
+            M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, out=sout, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st_ms = e0.elapsed_time(e1) / 5
+        d = c["window"][2] / c["window"][4]
+        fft_r = [r for r in rhos if math.ceil(r / d + 0.5) > 15 or
+                 np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS]
+        mx, my = c["window"][4], c["window"][5]
+        r_fft = max([math.ceil(r / d + 0.5) for r in fft_r], default=0)
+        nfx = 1 << max(1, (mx + 2 * r_fft - 1).bit_length())
+        nfy = 1 << max(1, (my + 2 * r_fft - 1).bit_length())
+        sb = stack_bytes(mx, my, nfx, nfy, len(fft_r), len(rhos) - len(fft_r))
+        rec["rho_stack"] = {
+            "radii": [float(r) for r in rhos], "gamma": STACK_GAMMA, "ms": st_ms,
+            "maps_per_s": len(rhos) / (st_ms * 1e-3), "fft_radii": len(fft_r),
+            "map": [my, mx], "fft_size": [nfy, nfx],
+            "roofline": {"bound": "hbm", "achieved": sb / (st_ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": sb / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bytes_per_call": sb,
+                         "traffic": None,
+                         "note": "algorithmic bytes of the whole call (transform passes, "
+                                 "products, stores, direct radii) over the call's time"}}
 
-        plain_ms = None
-        if not args.no_plain:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            pbuf = M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, ctx=ctx_b)
-            e0.record(stream)
-            for _ in range(3):
-                M.search(maps, lcs, trajs, "plain", chi2=False, top_k=k, out=pbuf, ctx=ctx_b)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            plain_ms = e0.elapsed_time(e1) / 3
+        # Caustic-centred lines (sec. 4.2) through the minimum-magnification filter
+        # (sec. 4.3) on the step's map, then the downhill simplex of every kept line.
+        progress("large: caustic-line filter and line simplex")
+        caus = M.caustics(c["s"], c["q"])
+        r_ax, phi = np.linspace(0.0, 4.0, 32), np.linspace(0.0, 2 * np.pi, 257)[:-1]
+        L = M.caustic_lines(caus, r_ax, phi)
+        dl = torch.from_numpy(L).to(dev)
+        Fv = np.asarray(ev["F"])
+        a_min = 0.9 * float(Fv.max() / Fv.min())
+        _, _, kept = M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lf_ms = e0.elapsed_time(e1) / 5
+        w = c["window"]
+        ns = math.ceil(2.0 * 0.5 * math.hypot(w[2], w[3]) * max(w[4] / w[2], w[5] / w[3])) + 1
+        f_ops = sum(OPS_PER_FILTER_SAMPLE) * len(L) * ns / (lf_ms * 1e-3) / 1e12
+        fpk = peak_for(OPS_PER_FILTER_SAMPLE) / 1e12
+        lines_rec = {"caustics": int(len(caus)), "lines": int(len(L)), "kept": int(len(kept)),
+                     "a_min": a_min, "samples_per_line": ns, "filter_ms": lf_ms,
+                     "samples_per_s": len(L) * ns / (lf_ms * 1e-3),
+                     "roofline": {"bound": "alu", "achieved": f_ops, "peak": fpk,
+                                  "unit": "TFLOP/s", "frac": f_ops / fpk,
+                                  "ops_per_unit_f32_f64": OPS_PER_FILTER_SAMPLE, "traffic": None,
+                                  "note": "tera lane-operations/s over the whole call (packing "
+                                          "the map and the compaction included)"}}
+        kl = dl[kept].contiguous()
+        st0 = torch.tensor([[0.0, 20.0]], dtype=torch.float64, device=dev).repeat(len(kl), 1)
+        sx_opts = dict(max_iter=5000, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
+        M.line_simplex(maps, lcs, kl, st0, ctx=ctx_b, **sx_opts)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sx = M.line_simplex(maps, lcs, kl, st0, ctx=ctx_b, **sx_opts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sx_ms = e0.elapsed_time(e1)
+        its = sx[3].double()
+        n_eval = int(sx[4].long().sum())
+        s_ops = sum(OPS_PER_SIMPLEX_POINT) * n_eval * n_pts / (sx_ms * 1e-3) / 1e12
+        spk = peak_for(OPS_PER_SIMPLEX_POINT) / 1e12
+        lines_rec["simplex"] = {
+            "lines": int(len(kl)), "ms": sx_ms, "max_iter": 5000,
+            "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+            "chi2_evaluations": n_eval, "best_chi2": float(sx[0].min()),
+            "simplex_iterations_per_s": float(its.sum()) / (sx_ms * 1e-3),
+            "point_evals_per_s": n_eval * n_pts / (sx_ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": s_ops, "peak": spk, "unit": "TFLOP/s",
+                         "frac": s_ops / spk, "ops_per_unit_f32_f64": OPS_PER_SIMPLEX_POINT,
+                         "traffic": None,
+                         "note": "the longest simplex (iterations_max) bounds the launch"}}
+        rec["caustic_lines"] = lines_rec
+        beside = dict(c=c, ev=ev, rhos=rhos, gamma=STACK_GAMMA, r=r_ax, phi=phi, a_min=a_min,
+                      n_kept=int(len(kl)), n_eval=n_eval)
+    del counts, amap, amap_build
+    torch.cuda.empty_cache()
+    return rec, beside
 
-        # Finite-source stack of this step's counts: seven radii log-spaced over
-        # [0.001, 1] with limb-darkening coefficient 0.53, timed apart from the step.
-        stack = None
-        if not args.no_stack:
-            rhos = np.logspace(-3.0, 0.0, 7)
-            sout = M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, ctx=ctx_b)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(5):
-                M.convolve_stack(counts, c["rays"], c["window"], rhos, STACK_GAMMA, out=sout, ctx=ctx_b)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            st_ms = e0.elapsed_time(e1) / 5
-            d = c["window"][2] / c["window"][4]
-            # the library's split: stencil half-width above 15 pixels or at least
-            # STACK_FFT_MIN_TAPS non-zero taps -> transforms
-            n_fft = sum(1 for r in rhos if math.ceil(r / d + 0.5) > 15 or
-                        np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS)
-            mx, my = c["window"][4], c["window"][5]
-            r_fft = max([math.ceil(r / d + 0.5) for r in rhos if math.ceil(r / d + 0.5) > 15 or
-                         np.count_nonzero(M.profile_weights(r, d, d, STACK_GAMMA)) >= STACK_FFT_MIN_TAPS],
-                        default=0)
-            nfx = 1 << max(1, (mx + 2 * r_fft - 1).bit_length())
-            nfy = 1 << max(1, (my + 2 * r_fft - 1).bit_length())
-            sb = stack_bytes(mx, my, nfx, nfy, n_fft, len(rhos) - n_fft)
-            stack = {"radii": [float(r) for r in rhos], "gamma": STACK_GAMMA, "ms": st_ms,
-                     "maps_per_s": len(rhos) / (st_ms * 1e-3), "fft_radii": n_fft,
-                     "map": [my, mx], "fft_size": [nfy, nfx],
-                     "roofline": {"bound": "hbm", "achieved": sb / (st_ms * 1e-3) / 1e9,
-                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": sb / (st_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                  "bytes_per_call": sb, "traffic": None,
-                                  "note": "algorithmic bytes of the whole call (transform "
-                                          "passes, products, stores, direct radii) over the "
-                                          "call's time"}}
 
-        # Caustic-centred lines of this lens (sec. 4.2) through the minimum-magnification
-        # filter (sec. 4.3) on the step's map, timed apart from the step.
-        lines_rec = None
-        if not args.no_lines:
-            caus = M.caustics(c["s"], c["q"])
-            L = M.caustic_lines(caus, np.linspace(0.0, 4.0, 32), np.linspace(0.0, 2 * np.pi, 257)[:-1])
-            dl = torch.from_numpy(L).to(dev)
-            Fv = np.asarray(ev["F"])
-            a_min = 0.9 * float(Fv.max() / Fv.min())
-            best, keep, kept = M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(5):
-                M.line_filter(amap, c["window"], dl, a_min, ctx=ctx_b)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            lf_ms = e0.elapsed_time(e1) / 5
-            w = c["window"]
-            ns = math.ceil(2.0 * 0.5 * math.hypot(w[2], w[3]) * max(w[4] / w[2], w[5] / w[3])) + 1
-            f_ops = sum(OPS_PER_FILTER_SAMPLE) * len(L) * ns / (lf_ms * 1e-3) / 1e12
-            lines_rec = {"caustics": int(len(caus)), "lines": int(len(L)), "kept": int(len(kept)),
-                         "a_min": a_min, "samples_per_line": ns, "filter_ms": lf_ms,
-                         "samples_per_s": len(L) * ns / (lf_ms * 1e-3),
-                         "roofline": {"bound": "alu", "achieved": f_ops,
-                                      "peak": peak_for(OPS_PER_FILTER_SAMPLE) / 1e12,
-                                      "unit": "TFLOP/s",
-                                      "frac": f_ops / (peak_for(OPS_PER_FILTER_SAMPLE) / 1e12),
-                                      "ops_per_unit_f32_f64": OPS_PER_FILTER_SAMPLE,
-                                      "traffic": None,
-                                      "note": "tera lane-operations/s over the whole call "
-                                              "(packing the map and the compaction included)"}}
-            # downhill simplex over (t0', ln tE) of every kept line (sec. 4.2), from the
-            # single-lens estimate (t0', tE) = (0, 20)
-            kl = dl[kept].contiguous()
-            st = torch.tensor([[0.0, 20.0]], dtype=torch.float64, device=dev).repeat(len(kl), 1)
-            sx_opts = dict(max_iter=5000, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
-            M.line_simplex(maps, lcs, kl, st, ctx=ctx_b, **sx_opts)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            sx = M.line_simplex(maps, lcs, kl, st, ctx=ctx_b, **sx_opts)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            sx_ms = e0.elapsed_time(e1)
-            its = sx[3].double()
-            n_eval = int(sx[4].long().sum())
-            s_ops = sum(OPS_PER_SIMPLEX_POINT) * n_eval * n_pts / (sx_ms * 1e-3) / 1e12
-            lines_rec["simplex"] = {"lines": int(len(kl)), "ms": sx_ms, "max_iter": 5000,
-                                    "iterations_mean": float(its.mean()),
-                                    "iterations_max": int(its.max()),
-                                    "chi2_evaluations": n_eval,
-                                    "best_chi2": float(sx[0].min()),
-                                    "simplex_iterations_per_s": float(its.sum()) / (sx_ms * 1e-3),
-                                    "point_evals_per_s": n_eval * n_pts / (sx_ms * 1e-3),
-                                    "roofline": {"bound": "alu", "achieved": s_ops,
-                                                 "peak": peak_for(OPS_PER_SIMPLEX_POINT) / 1e12,
-                                                 "unit": "TFLOP/s",
-                                                 "frac": s_ops / (peak_for(OPS_PER_SIMPLEX_POINT) / 1e12),
-                                                 "ops_per_unit_f32_f64": OPS_PER_SIMPLEX_POINT,
-                                                 "traffic": None,
-                                                 "note": "the longest simplex (iterations_max) "
-                                                         "bounds the launch"}}
-            beside = dict(rhos=np.logspace(-3.0, 0.0, 7), r=np.linspace(0.0, 4.0, 32),
-                          phi=np.linspace(0.0, 2 * np.pi, 257)[:-1], a_min=a_min,
-                          n_kept=int(len(kl)), n_eval=n_eval)
+def main():
+    args = parse()
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc)
+    if args.copy_bytes:
+        return copy_kernel(args.copy_bytes)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(on several GPUs the path would deal maps or ray rows to GPUs and gather "
+              "the per-GPU top-k lists)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import workloads as W
 
-    rays_ms, norm_ms, search_ms, refine_ms = stage
-    adjoint_evals = (args.refine_steps + 1) * k * n_pts  # upper bound: all candidates active
-    # algorithmic lane-operations of one launch of each kernel, and their peak rate
-    unit_ops = {"k_rayshoot": (OPS_PER_RAY, rays_per_step),
-                "k_search_batched": (OPS_PER_POINT_EVAL, evals_per_step),
-                "k_chi2_grad": (OPS_PER_ADJOINT_EVAL, k * n_pts)}
-    ops_per_launch = {kn: sum(o) * units for kn, (o, units) in unit_ops.items()}
-    peak = peak_for(unit_ops[dom][0]) / 1e12
-    dom_ms = dom_total_ms / dom_launches
-    traffic = TRAFFIC.get((dom, kernel_sha(dom)))
-    achieved = ops_per_launch[dom] / (dom_ms * 1e-3) / 1e12
+    # the oracle's baseline first, before anything touches the GPU (its workers fork)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cb, cr = W.config("batched"), W.config("refine")
+        n_pts = np.array([t["npts"] for t in W.truths("batched")])
+        nb = len(W.map_bank("batched"))
+        units = {"rays": nb * (cb["rays"][4] * cb["rays"][5] + cr["rays"][4] * cr["rays"][5]),
+                 "pixels": nb * (cb["window"][4] * cb["window"][5] + cr["window"][4] * cr["window"][5]),
+                 "evals": int(n_pts.sum()) * nb * cb["n_traj"],
+                 "cand_round_points": (cr["steps"] + 1) * cr["top_k"] * int(n_pts[:cr["n_events"]].sum())}
+        cpu = cpu_baseline_batched(units)
+
+    import torch
+
+    import paper_1511_01157_amd as M
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    head = leg_batched(args, M, W, torch, np, dev)
+    sq = None if args.no_sqgrid else leg_sqgrid(args, M, W, torch, np, dev)
+    large, beside = (None, None) if args.no_large else leg_large(args, M, W, torch, np, dev)
+    if cpu is not None and beside is not None:
+        progress("cpu baseline beside the large workload (stack, line filter, simplex)")
+        b_st, b_lf, b_sx = cpu_baseline_beside(beside["c"], beside["ev"], beside["rhos"],
+                                              beside["gamma"], beside["r"], beside["phi"],
+                                              beside["a_min"], beside["n_kept"], beside["n_eval"])
+        large["rho_stack"]["cpu_baseline"] = b_st
+        large["caustic_lines"]["cpu_baseline"] = b_lf
+        large["caustic_lines"]["simplex"]["cpu_baseline"] = b_sx
+
+    dom = head["dominant"]
     line = {
         "metric": "light-curve point-evals/s (chi2 search) + rays/s (map build); batched vs plain",
-        "value": evals_per_step / (ms_step * 1e-3),
-        "unit": "point-evals/s",
+        "value": head["value"], "unit": "point-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "pipelined": pipelined,
-        "serial_ms_per_step": serial_ms,
-        "pipelined_ms_per_step": pipe_ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 samples, f64 sums",
-        "data": "synthetic (seeded light curve, oracle-computed magnifications)",
-        "config": {"workload": "large: s=0.8 q=5e-3, 32768^2 rays -> 2048^2 map, rho=2e-3, "
-                               "3000-point light curve, 524288-trajectory grid, top-4096 + 50 L-BFGS rounds",
-                   "rays": rays_per_step, "map": [c["window"][5], c["window"][4]],
-                   "n_traj": n_traj, "n_points": n_pts, "top_k": k,
-                   "refine_rounds": args.refine_steps, "parallelism": "single GPU",
-                   "autotuned_search_shape": tuned},
-        "stages_ms": {"rayshoot": rays_ms, "normalize_convolve": norm_ms,
-                      "search_batched": search_ms, "candidates_refine": refine_ms},
-        "rays_per_s": rays_per_step / (rays_ms * 1e-3),
-        "search_point_evals_per_s": {"batched": evals_per_step / (search_ms * 1e-3),
-                                     "plain": evals_per_step / (plain_ms * 1e-3) if plain_ms else None},
-        "adjoint_point_evals_per_s_upper": adjoint_evals / (refine_ms * 1e-3),
-        "refine_improved_fraction": improved,
-        "rho_stack": stack,
-        "caustic_lines": lines_rec,
-        "wall_s_timed": wall,
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     # the measured bytes over the same launch time, against HBM's 8 TB/s
-                     "traffic_gbs": traffic / (dom_ms * 1e-3) / 1e9 if traffic else None,
-                     "traffic_frac_of_hbm": (traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                             if traffic else None),
-                     "launch_ms": dom_ms, "launches": dom_launches,
-                     "ops_per_launch": ops_per_launch[dom],
-                     "ops_are_upper_bound": dom == "k_chi2_grad",
-                     "kernel_ms_per_step_warmup": per_step,
-                     "ops_per_unit_f32_f64": unit_ops[dom][0],
-                     "op_note": "achieved and peak in tera lane-operations/s (one FP32/FP64 "
-                                "add, mul, compare, floor, cvt, div, sqrt or FMA per lane = 1); "
-                                "peak = the kernel's binary32/FP64 op mix at 256 CU x 2.4 GHz x "
-                                "128 binary32 or 64 FP64 lanes per clock (half the published "
-                                "157.3/78.6 TFLOP/s, which count an FMA twice); launch time from "
-                                "HIP events around each launch over the timed steps"},
+        "data": "synthetic (seeded light curves, oracle-computed magnifications)",
+        "config": head["config"],
+        "stages_ms": head["stages_ms"],
+        "rays_per_s": head["rays_per_s"],
+        "search_point_evals_per_s": head["search_point_evals_per_s"],
+        "adjoint_point_evals_per_s_upper": head["adjoint_point_evals_per_s_upper"],
+        "refine_chi2_not_raised": head["refine_chi2_not_raised"],
+        "refine_chi2_lowered": head["refine_chi2_lowered"],
+        "wall_s_timed": head["wall_s_timed"],
+        "roofline": dict(head["kernels"][dom], op_note=OP_NOTE,
+                         kernel_ms_per_step=head["kernel_ms_per_step"]),
+        "kernels": head["kernels"],
+        "sqgrid": sq,
+        "large": large,
     }
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(c, ev, axes)
-        cb.pop("step_s")
-        line["cpu_baseline"] = cb
-        if stack is not None and lines_rec is not None and "simplex" in lines_rec:
-            b_st, b_lf, b_sx = cpu_baseline_beside(c, ev, beside["rhos"], STACK_GAMMA, beside["r"],
-                                                  beside["phi"], beside["a_min"], beside["n_kept"],
-                                                  beside["n_eval"])
-            stack["cpu_baseline"] = b_st
-            lines_rec["cpu_baseline"] = b_lf
-            lines_rec["simplex"]["cpu_baseline"] = b_sx
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

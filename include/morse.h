@@ -181,7 +181,9 @@ typedef struct {
 } morse_map_view;
 
 /* Light curves of n_events events, concatenated (CSR).  Event e owns points
- * [h_offsets[e], h_offsets[e+1]), at least 3 each, times non-decreasing.
+ * [h_offsets[e], h_offsets[e+1]), at least 3 and at most 2^28 each (longer events
+ * return ERANGE: the kernels address an event's arrays with 32-bit byte offsets),
+ * h_offsets[0] = 0, times non-decreasing.
  * d_t: binary32 offsets t - h_t_ref[e]; d_flux: FP64 flux; d_weight: FP64
  * w = 1/sigma^2 > 0.  h_offsets and h_t_ref are host arrays. */
 typedef struct {

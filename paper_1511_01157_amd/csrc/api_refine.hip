@@ -17,12 +17,7 @@ int plan_candidates(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     if (!maps[i].d_map) return fail(ctx, MORSE_EINVAL, "map %d: d_map is NULL", i);
     if ((rc = check_window(ctx, &maps[i].window, "map window"))) return rc;
   }
-  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
-      !lcs->d_weight)
-    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
-  for (int e = 0; e < lcs->n_events; ++e)
-    if (lcs->h_offsets[e + 1] - lcs->h_offsets[e] < 3)
-      return fail(ctx, MORSE_EINVAL, "event %d has fewer than 3 points", e);
+  if ((rc = check_lightcurves(ctx, lcs))) return rc;
   if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
   if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
   i_sums = pl.add(24 * (size_t)lcs->n_events);

@@ -56,16 +56,7 @@ int validate_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     if (!maps[i].d_map) return fail(ctx, MORSE_EINVAL, "map %d: d_map is NULL", i);
     if ((rc = check_window(ctx, &maps[i].window, "map window"))) return rc;
   }
-  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
-      !lcs->d_weight)
-    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
-  if (lcs->h_offsets[0] != 0) return fail(ctx, MORSE_EINVAL, "light curves: offsets[0] must be 0");
-  for (int e = 0; e < lcs->n_events; ++e) {
-    const int64_t n = lcs->h_offsets[e + 1] - lcs->h_offsets[e];
-    if (n < 3) return fail(ctx, MORSE_EINVAL, "event %d has %lld < 3 points", e, (long long)n);
-    if (n > (1ll << 30)) return fail(ctx, MORSE_ERANGE, "event %d too long", e);
-    if (!std::isfinite(lcs->h_t_ref[e])) return fail(ctx, MORSE_EINVAL, "event %d: t_ref not finite", e);
-  }
+  if ((rc = check_lightcurves(ctx, lcs))) return rc;
   if (!trajs) return fail(ctx, MORSE_EINVAL, "trajs is NULL");
   if (trajs->kind == MORSE_TRAJ_GRID) {
     if (trajs->n_u0 <= 0 || trajs->n_alpha <= 0 || trajs->n_t0 <= 0 || trajs->n_tE <= 0 ||

@@ -317,6 +317,26 @@ inline void assign_quads(std::vector<MapC>& hm, char* region) {
   }
 }
 
+// Light curves: arrays present, CSR offsets from 0, each event at least 3 and at most
+// kMaxEventPoints points (the kernels address an event's FP64 arrays with 32-bit byte
+// offsets from the event's base, 8 B x 2^28 < 2^32), finite reference times.
+constexpr int64_t kMaxEventPoints = (int64_t)1 << 28;
+
+inline int check_lightcurves(morse_ctx* ctx, const morse_lightcurves* lcs) {
+  if (!lcs || lcs->n_events <= 0 || !lcs->h_offsets || !lcs->h_t_ref || !lcs->d_t || !lcs->d_flux ||
+      !lcs->d_weight)
+    return fail(ctx, MORSE_EINVAL, "light curves: missing arrays or n_events <= 0");
+  if (lcs->h_offsets[0] != 0) return fail(ctx, MORSE_EINVAL, "light curves: offsets[0] must be 0");
+  for (int e = 0; e < lcs->n_events; ++e) {
+    const int64_t n = lcs->h_offsets[e + 1] - lcs->h_offsets[e];
+    if (n < 3) return fail(ctx, MORSE_EINVAL, "event %d has %lld < 3 points", e, (long long)n);
+    if (n > kMaxEventPoints)
+      return fail(ctx, MORSE_ERANGE, "event %d has %lld points, more than 2^28", e, (long long)n);
+    if (!std::isfinite(lcs->h_t_ref[e])) return fail(ctx, MORSE_EINVAL, "event %d: t_ref not finite", e);
+  }
+  return MORSE_OK;
+}
+
 inline int check_quad_size(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps) {
   for (int i = 0; i < n_maps; ++i)
     if (quad_bytes(maps[i].window.nx, maps[i].window.ny) >= ((size_t)1 << 32))

@@ -285,22 +285,50 @@ __device__ __forceinline__ void wave_sums(double (&v)[N]) {
   for (int q = 0; q < N; ++q) v[q] = read_lane(mine, rs_lane<N>(q));
 }
 
+// Neumaier's compensated addition: s + c carries the sum, c the rounding errors.
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
+  double t = s + v;
+  if (fabs(s) >= fabs(v))
+    c += (s - t) + v;
+  else
+    c += (v - t) + s;
+  s = t;
+}
+
 // Profiled fit (Eqs. 5-6) in centred form.  With b = A - 1 and per-point
 // wFc = w (F - Fbar), one pass gives B1 = sum w b, B2 = sum w b^2, C = sum b wFc.
 // Then S_bb = B2 - B1^2/S_w equals det/S_w of the normal equations
 // (det = S_AA S_w - S_A^2, S_AA = B2 + 2 B1 + S_w), and
 //   F_s = C / S_bb,  F_b = Fbar - F_s (1 + B1/S_w),  chi2 = V - F_s C.
 // Degenerate (det <= 1e-12 S_AA S_w, i.e. S_bb <= 1e-12 S_AA): F_s = 0, F_b = Fbar,
-// chi2 = V.  The one-pass chi2 loses about eps * (S_AA/S_bb) * (V/chi2) relative
-// accuracy; `recheck` is set when that bound exceeds 1e-9 (an ill-conditioned or
-// near-perfect fit), and the caller then sums w r^2 directly in a second pass.
+// chi2 = V.
+//
+// The sums are plain (uncompensated) FP64, so the one-pass chi2 comes with a worst-case
+// error bound, and `recheck` is set when that bound exceeds 1e-8 chi2; the caller then
+// sums w r^2 directly (Neumaier-compensated second pass).  Each of B1, B2, C is a
+// recursive sum over one lane's points followed by a fixed reduction tree, so with n
+// = the terms per lane + the tree depth + the roundings of one term (fit_terms), its
+// error is at most n u sum|terms| (u = 2^-53; Higham, Accuracy and Stability of
+// Numerical Algorithms, sec. 4.2), and by Cauchy-Schwarz sum|w b| <= sqrt(S_w B2),
+// sum|b wFc| <= sqrt(B2 V).  Through chi2 = V - C^2/S_bb, with F_s^2 S_bb <= V and
+// kappa = B2/S_bb >= 1 (V carries its own compensated error, u V):
+//   |d chi2| <= u V (n (3 kappa + 2 sqrt(kappa)) + 6 kappa + 5).
+// For noisy data chi2 is near the number of points and the bound stays far below the
+// threshold; a near-perfect or ill-conditioned fit takes the second pass.
 struct Fit {
   double Fs, Fb, chi2;
   bool degenerate, recheck;
 };
 
+// Terms per lane plus reduction depth for the bound above: np points over `lanes`
+// lanes, a tree of at most 8 levels, at most 2 serial cross-wave additions and 2
+// roundings per term.
+__device__ __forceinline__ double fit_terms(int32_t np, int lanes) {
+  return (double)((np + lanes - 1) / lanes + 12);
+}
+
 __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, double B1, double B2,
-                                           double C) {
+                                           double C, double nterms) {
   Fit f;
   const double SAA = (B2 + 2.0 * B1) + Sw;
   const double Sbb = B2 - (B1 * B1) / Sw;
@@ -315,7 +343,9 @@ __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, dou
   f.Fs = C / Sbb;
   f.Fb = Fbar - f.Fs * (1.0 + B1 / Sw);
   f.chi2 = V - f.Fs * C;
-  f.recheck = !(f.chi2 > 0.0) || (SAA * V > 1e7 * Sbb * f.chi2);
+  const double kappa = B2 / Sbb;
+  const double bound = (nterms * (3.0 * kappa + 2.0 * sqrt(kappa)) + 6.0 * kappa + 5.0) * V;
+  f.recheck = !(f.chi2 > 0.0) || (bound > 9.007199254740992e7 * f.chi2);  // 1e-8 / u
   return f;
 }
 

@@ -192,7 +192,7 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
     if (i0 + STEP < np) add_point(lb, vb, wb, fb);
   }
   block_sum<kSums>(acc, s_part);
-  const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2]);
+  const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2], fit_terms(np, GRAD_THREADS));
   const double Fs = fit.Fs, Fb = fit.Fb;
   double G[kDirs];  // sum w r D
   double chi2;
@@ -203,9 +203,10 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
       G[k] = acc[5 + 3 * k] - Fs * (acc[4 + 3 * k] - c0 * acc[3 + 3 * k]);
     chi2 = fit.chi2;
   } else {  // uniform per workgroup: the sums are identical on every thread
-    double n2[1 + kDirs];
+    // direct sums of w r^2 and w r D, Neumaier-compensated per thread
+    double n2[1 + kDirs], n2c[1 + kDirs];
 #pragma unroll
-    for (int q = 0; q <= kDirs; ++q) n2[q] = 0.0;
+    for (int q = 0; q <= kDirs; ++q) n2[q] = n2c[q] = 0.0;
     for (int32_t i = tid; i < np; i += GRAD_THREADS) {
       const uint32_t u = (uint32_t)i;
       const Sample sm = sample_full(m, ldg(t, u), t0p, iE, ca, sa, bx, by);
@@ -215,13 +216,15 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
       double dAx, dAy;
       sample_dA(sm, kx, ky, dAx, dAy);
       const double tau = (double)sm.tau;
-      n2[0] = fma(wr, r, n2[0]);
-      n2[1] = fma(wr, dAx, n2[1]);
-      n2[2] = fma(wr, dAy, n2[2]);
-      n2[3] = fma(wr * dAx, tau, n2[3]);
-      n2[4] = fma(wr * dAy, tau, n2[4]);
-      n2[5] = fma(wr, (double)sm.zx * dAy - (double)sm.zy * dAx, n2[5]);
+      neumaier_add(n2[0], n2c[0], wr * r);
+      neumaier_add(n2[1], n2c[1], wr * dAx);
+      neumaier_add(n2[2], n2c[2], wr * dAy);
+      neumaier_add(n2[3], n2c[3], (wr * dAx) * tau);
+      neumaier_add(n2[4], n2c[4], (wr * dAy) * tau);
+      neumaier_add(n2[5], n2c[5], wr * ((double)sm.zx * dAy - (double)sm.zy * dAx));
     }
+#pragma unroll
+    for (int q = 0; q <= kDirs; ++q) n2[q] += n2c[q];
     // reuse the first 1 + kDirs columns of the partial-sum buffer
     block_sum<1 + kDirs>(n2, reinterpret_cast<double (*)[1 + kDirs]>(&s_part[0][0]));
     chi2 = n2[0];

@@ -32,14 +32,6 @@ namespace {
 // Light-curve preparation, one workgroup per event: S_w and S_F with
 // Neumaier-compensated partial sums combined by a fixed pairwise tree, Fbar = S_F/S_w, then
 // wFc = w (F - Fbar) per point and V = sum w (F - Fbar)^2 the same way.
-__device__ __forceinline__ void neumaier_add(double& s, double& c, double v) {
-  double t = s + v;
-  if (fabs(s) >= fabs(v))
-    c += (s - t) + v;
-  else
-    c += (v - t) + s;
-  s = t;
-}
 
 // Pairwise tree over the workgroup's Neumaier partials (sum, compensation) held in
 // columns (2q, 2q + 1) of s_part, q < NQ, in a fixed order; every thread returns the
@@ -198,19 +190,20 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
   wave_sums<3 * TU>(acc);
 #pragma unroll
   for (int v = 0; v < TU; ++v) {
-    const Fit f = centred_fit(Sw, Fbar, V, acc[3 * v], acc[3 * v + 1], acc[3 * v + 2]);
+    const Fit f = centred_fit(Sw, Fbar, V, acc[3 * v], acc[3 * v + 1], acc[3 * v + 2],
+                              fit_terms(np, kWave));
     Fs[v] = f.Fs;
     Fb[v] = f.Fb;
     chi2[v] = f.chi2;
     if (f.recheck) {  // wave-uniform: the sums are identical on every lane
-      double q = 0.0;
+      double q = 0.0, qc = 0.0;
       for (int32_t i = lane; i < np; i += kWave) {
         const double a = (double)sample_A(m, ldg(t, (uint32_t)i), t0p[v], c[v].iE, c[v].ca,
                                           c[v].sa, c[v].bx, c[v].by);
         const double r = ldg(F, (uint32_t)i) - Fs[v] * a - Fb[v];
-        q = fma(ldg(w, (uint32_t)i) * r, r, q);
+        neumaier_add(q, qc, (ldg(w, (uint32_t)i) * r) * r);
       }
-      chi2[v] = wave_sum(q);
+      chi2[v] = wave_sum(q + qc);
     }
   }
 }

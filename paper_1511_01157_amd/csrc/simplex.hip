@@ -129,15 +129,16 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
         }
       }
       block_sums<3>(v, s_red);
-      const Fit fit = centred_fit(Sw, Fbar, V, v[0], v[1], v[2]);
+      const Fit fit = centred_fit(Sw, Fbar, V, v[0], v[1], v[2], fit_terms(np, kItemThreads));
       double c2 = fit.chi2;
       if (fit.degenerate || fit.recheck) {
-        double r2[1] = {0.0};
+        double r2[1] = {0.0}, r2c = 0.0;
         for (int32_t i = tid; i < np; i += kItemThreads) {
           const double A = (double)sample_A(m, t[i], t0p, iE, ca, sa, bx, by);
           const double r = F[i] - fit.Fs * A - fit.Fb;
-          r2[0] = fma(w[i] * r, r, r2[0]);
+          neumaier_add(r2[0], r2c, (w[i] * r) * r);
         }
+        r2[0] += r2c;
         block_sums<1>(r2, s_red);
         c2 = r2[0];
       }
