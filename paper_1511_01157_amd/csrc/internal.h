@@ -39,21 +39,23 @@ static_assert(sizeof(TrajC) == 32, "TrajC layout");
 // once per call into `quad`: cell (i, j), 0 <= i < mx - 1, 0 <= j < my - 1, holds the
 // four pixel-centre values (A[j][i], A[j][i+1], A[j+1][i], A[j+1][i+1]) as one 16-byte
 // Quad, and the cells are grouped in tiles of 4 (x) by 2 (y) cells, one 128-byte
-// cache line each, tiles in row-major order:
-//   q(i, j) = ((j / 2) tiles_x + i / 4) 8 + (j % 2) 4 + i % 4.
-// A bilinear sample is then one aligned load, and the samples of a wavefront along a
-// trajectory touch about 2.5x fewer cache lines than two row-major row loads.
+// cache line each, tiles in row-major order, cells inside a tile column-major:
+//   q(i, j) = ((j / 2) (4 tiles_x) + i) 2 + j % 2
+// (= 8 tile + 2 (i % 4) + j % 2, tile = (j / 2) tiles_x + i / 4), so the byte offset
+// is one 24-bit multiply-add and two shifts.  A bilinear sample is then one aligned
+// load, and the samples of a wavefront along a trajectory touch about 2.5x fewer
+// cache lines than two row-major row loads.
 // One packed cell: the four pixel-centre values around it.
 struct alignas(16) Quad {
   float v00, v10, v01, v11;
 };
 
-// Load of cell q (one global_load_dwordx4; see ldg).
-__device__ __forceinline__ Quad ldq(const Quad* __restrict__ base, uint32_t q) {
+// Load of the cell at byte offset qb (one global_load_dwordx4; see ldg).
+__device__ __forceinline__ Quad ldq(const Quad* __restrict__ base, uint32_t qb) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   typedef const __attribute__((address_space(1))) char gchar;
   typedef const __attribute__((address_space(1))) f4 gf4;
-  const f4 v = *(gf4*)((gchar*)base + (size_t)(q * 16u));
+  const f4 v = *(gf4*)((gchar*)base + (size_t)qb);
   return Quad{v.x, v.y, v.z, v.w};
 }
 
@@ -107,11 +109,15 @@ __device__ __forceinline__ T ldg(const T* __restrict__ base, uint32_t i) {
   return *(gT*)((gchar*)base + (size_t)(i * (uint32_t)sizeof(T)));
 }
 
+// Byte offset of packed cell (i, j); (j / 2) (4 tiles_x) + i < 2^27 since the packed
+// map is below 4 GiB, and both factors fit 24 bits.
+__device__ __forceinline__ uint32_t cell_offset(const MapC& m, uint32_t i, uint32_t j) {
+  return ((__umul24(j >> 1, m.tiles_x << 2) + i) << 5) | ((j & 1u) << 4);
+}
+
 __device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, float& v00, float& v10,
                                          float& v01, float& v11) {
-  const uint32_t i = (uint32_t)(int)fi, j = (uint32_t)(int)fj;
-  const uint32_t q = ((((j >> 1) * m.tiles_x + (i >> 2)) << 3) | ((j & 1u) << 2)) | (i & 3u);
-  const Quad v = ldq(m.quad, q);
+  const Quad v = ldq(m.quad, cell_offset(m, (uint32_t)(int)fi, (uint32_t)(int)fj));
   v00 = v.v00;
   v10 = v.v10;
   v01 = v.v01;
@@ -124,7 +130,7 @@ __device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, floa
 // The arithmetic is that of sample_A / sample_full.
 struct Loc {
   float tau, zx, zy, fx, fy;
-  uint32_t q;  // packed cell index (0 off the map)
+  uint32_t q;  // byte offset of the packed cell (0 off the map)
   bool on;
 };
 
@@ -137,12 +143,10 @@ __device__ __forceinline__ Loc locate(const MapC& m, float tt, float t0p, float 
   const float gx = ((l.zx - m.sx) * m.kx) + m.ox;
   const float gy = ((l.zy - m.sy) * m.ky) + m.oy;
   l.on = (gx >= 0.0f && gx < m.lx && gy >= 0.0f && gy < m.ly);
-  const float fi = l.on ? floorf(gx) : 0.0f;
-  const float fj = l.on ? floorf(gy) : 0.0f;
-  l.fx = gx - fi;
-  l.fy = gy - fj;
-  const uint32_t i = (uint32_t)(int)fi, j = (uint32_t)(int)fj;
-  l.q = ((((j >> 1) * m.tiles_x + (i >> 2)) << 3) | ((j & 1u) << 2)) | (i & 3u);
+  // on the map g >= 0, so truncation is the floor and fract(g) = g - floor(g) exactly
+  l.fx = __builtin_amdgcn_fractf(gx);
+  l.fy = __builtin_amdgcn_fractf(gy);
+  l.q = l.on ? cell_offset(m, (uint32_t)gx, (uint32_t)gy) : 0u;
   return l;
 }
 

@@ -66,8 +66,8 @@ __global__ void k_quad_pack(const MapC* __restrict__ maps) {
        q += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t tile = q >> 3;
     const uint32_t r = (uint32_t)(q & 7);
-    const uint64_t i = (tile % m.tiles_x) * 4 + (r & 3u);
-    const uint64_t j = (tile / m.tiles_x) * 2 + (r >> 2);
+    const uint64_t i = (tile % m.tiles_x) * 4 + (r >> 1);
+    const uint64_t j = (tile / m.tiles_x) * 2 + (r & 1u);
     Quad v = {0.0f, 0.0f, 0.0f, 0.0f};
     if (i + 1 < (uint64_t)m.mx && j + 1 < (uint64_t)m.my) {
       const float* row = m.map + j * (uint64_t)m.mx + i;

@@ -139,18 +139,14 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 
 // ---------------------------------------------------------------------------
 // Score TU trajectories with one wavefront.  All lanes return the same values.
-// Each lane takes SU points per iteration (i, i + 64, ...), with their light-curve
-// loads issued together and shared by the TU trajectories; only lanes whose point is
-// on the map read the map (a wavefront's lanes hold neighbouring times, so they mostly
-// agree), the others take the single-lens branch.  Every trajectory's sums see the
+// Each lane takes the points lane, lane + 64, ... in order; the light-curve values of
+// the next point are loaded while the current one is scored, and the TU trajectories'
+// cells are all located and requested before the first is blended, so a wavefront has
+// TU gathers and one light-curve load in flight at a time.  A lane off the map
+// requests cell 0 and takes the single-lens branch.  Every trajectory's sums see the
 // points in the same order for any TU, and wave_sums reduces each over the butterfly
 // tree, so the results do not depend on TU.  Arrays are addressed by 32-bit offsets
 // from uniform bases.
-#ifndef MORSE_SU
-#define MORSE_SU 1
-#endif
-constexpr int SU = MORSE_SU;  // points per lane per iteration (tuning knob)
-
 template <int TU>
 __device__ __forceinline__ void score_group(const MapC& m, const float* __restrict__ t,
                                             const double* __restrict__ w,
@@ -162,29 +158,34 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
   double acc[3 * TU];  // (B1, B2, C) per trajectory
 #pragma unroll
   for (int q = 0; q < 3 * TU; ++q) acc[q] = 0.0;
-  for (int32_t i0 = lane; i0 < np; i0 += SU * kWave) {
-    float tt[SU];
-    double wv[SU], fv[SU];
+  uint32_t in = (uint32_t)min(lane, np - 1);
+  float tn = ldg(t, in);
+  double wn = ldg(w, in), fn = ldg(wFc, in);
+  for (int32_t i0 = lane; i0 < np; i0 += kWave) {
+    const float tt = tn;
+    const double wv = wn, fv = fn;
+    in = (uint32_t)min(i0 + kWave, np - 1);  // past the end: the last point, never used
+    tn = ldg(t, in);
+    wn = ldg(w, in);
+    fn = ldg(wFc, in);
+    Loc l[TU];
+    Quad cell[TU];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-      const uint32_t i = (uint32_t)min(i0 + u * kWave, np - 1);
-      tt[u] = ldg(t, i);
-      wv[u] = ldg(w, i);
-      fv[u] = ldg(wFc, i);
-    }
+    for (int v = 0; v < TU; ++v)
+      l[v] = locate(m, tt, t0p[v], c[v].iE, c[v].ca, c[v].sa, c[v].bx, c[v].by);
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
+    for (int v = 0; v < TU; ++v) cell[v] = ldq(m.quad, l[v].q);
 #pragma unroll
-      for (int v = 0; v < TU; ++v) {
-        const float A = sample_A(m, tt[u], t0p[v], c[v].iE, c[v].ca, c[v].sa, c[v].bx, c[v].by);
-        if (SU == 1 || i0 + u * kWave < np) {
-          const double b = (double)A - 1.0;
-          const double wb = wv[u] * b;
-          acc[3 * v] += wb;
-          acc[3 * v + 1] = fma(wb, b, acc[3 * v + 1]);
-          acc[3 * v + 2] = fma(b, fv[u], acc[3 * v + 2]);
-        }
-      }
+    for (int v = 0; v < TU; ++v) {
+      const float e0 = cell[v].v10 - cell[v].v00, e1 = cell[v].v11 - cell[v].v01;
+      const float ax0 = cell[v].v00 + l[v].fx * e0, ax1 = cell[v].v01 + l[v].fx * e1;
+      float A = ax0 + l[v].fy * (ax1 - ax0);
+      if (!l[v].on) A = point_lens_A(l[v].zx, l[v].zy);
+      const double b = (double)A - 1.0;
+      const double wb = wv * b;
+      acc[3 * v] += wb;
+      acc[3 * v + 1] = fma(wb, b, acc[3 * v + 1]);
+      acc[3 * v + 2] = fma(b, fv, acc[3 * v + 2]);
     }
   }
   wave_sums<3 * TU>(acc);
