@@ -363,6 +363,24 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                     const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
                     double* d_grad, double* d_fs, double* d_fb);
 
+/* morse_chi2_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same arguments,
+ * kernels and results, with no hipMalloc, hipFree or allocating library call; the
+ * context must already exist.  Its scratch (event offsets, reference times and map
+ * table, the light-curve preparation, candidate constants and the packed cells of every
+ * map: 24 B per event + 8 B per point + 40 B per candidate + 16 B per map cell, each
+ * part rounded up to 256 B, plus the table) lives in one static device array of
+ * 128 MiB on each GPU the library runs on, held until the process ends.  Every call on
+ * a GPU shares that GPU's array and leaves its contents there, so calls that overlap on
+ * one GPU (other streams or contexts) race; calls on one stream are ordered.  The host
+ * metadata is copied into the array on every call (host-synchronous copies from the
+ * caller's arrays).  Errors: as morse_chi2_grad, and ERANGE when the scratch would
+ * exceed 128 MiB (e.g. more than one 2048^2 map with long light curves). */
+int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                            const morse_lightcurves* lcs, int64_t n, const double* d_params,
+                            const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
+                            double* d_grad, double* d_fs, double* d_fb);
+
 typedef struct {
   int32_t steps;    /* evaluation rounds after the initial one (e.g. 50) */
   int32_t history;  /* L-BFGS memory m, 1..16 */

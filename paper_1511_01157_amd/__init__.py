@@ -452,8 +452,10 @@ def _cand_args(params, event, map_index):
     return n
 
 
-def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True, ctx=None):
-    """chi2 [n], grad [n, 4] (d/d t0, u0, tE, alpha), Fs [n], Fb [n]."""
+def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True, ctx=None,
+              noalloc=False):
+    """chi2 [n], grad [n, 4] (d/d t0, u0, tE, alpha), Fs [n], Fb [n].  ``noalloc``
+    calls the allocation-free entry point (scratch in the library's static array)."""
     n = _cand_args(params, event, map_index)
     ctx = ctx or Context.get(_device_of(params))
     dev = params.device
@@ -463,9 +465,9 @@ def chi2_grad(maps, lcs: LightCurveBatch, params, event, map_index, grad=True, c
     fb = torch.empty(n, dtype=torch.float64, device=dev)
     views = _map_views(maps)
     lca = lcs.abi()
-    ctx.check(ctx.lib.morse_chi2_grad(ctx.handle, views, len(maps), ctypes.byref(lca), n,
-                                      _ptr(params), _ptr(event), _ptr(map_index), _ptr(chi2),
-                                      _ptr(g), _ptr(fs), _ptr(fb)))
+    fn = ctx.lib.morse_chi2_grad_noalloc if noalloc else ctx.lib.morse_chi2_grad
+    ctx.check(fn(ctx.handle, views, len(maps), ctypes.byref(lca), n, _ptr(params), _ptr(event),
+                 _ptr(map_index), _ptr(chi2), _ptr(g), _ptr(fs), _ptr(fb)))
     return chi2, g, fs, fb
 
 

@@ -96,6 +96,9 @@ SIGNATURES = {
     "morse_chi2_grad": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves),
                                   c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p]),
+    "morse_chi2_grad_noalloc": (c_int32, [c_void_p, POINTER(MapView), c_int32,
+                                          POINTER(LightCurves), c_int64, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "morse_refine": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves), c_int64,
                                c_void_p, c_void_p, c_void_p, POINTER(LbfgsOpts), c_void_p,
                                c_void_p]),

@@ -54,6 +54,13 @@ int morse_ctx_create(int device, void* stream, morse_ctx** out) {
     delete c;
     return fail(nullptr, MORSE_EHIP, "stream or event creation failed");
   }
+  // the allocation-free entry point's scratch address on this device, looked up once
+  char* scratch = nullptr;
+  const int rc = noalloc_scratch(device, &scratch);
+  if (rc != MORSE_OK) {
+    morse_ctx_destroy(c);
+    return rc;
+  }
   *out = c;
   return MORSE_OK;
 }

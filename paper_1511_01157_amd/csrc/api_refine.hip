@@ -3,8 +3,45 @@
 
 #include "host.h"
 
+#include <mutex>
+
 using namespace morse;
 using namespace morse::host;
+
+// Scratch of the allocation-free entry point (morse_chi2_grad_noalloc): one array per
+// GPU, held until the process ends.  Host code uses its device address from
+// hipGetSymbolAddress (kept per device), never the array's name.
+constexpr size_t kNoallocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+namespace morse {
+namespace host {
+// Called by morse_ctx_create with `device` current (and again, cached, by the entry
+// point).
+int noalloc_scratch(int device, char** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(nullptr, MORSE_EUNSUPPORTED, "device %d: at most %d devices", device,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, MORSE_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return MORSE_OK;
+}
+}  // namespace host
+}  // namespace morse
 
 namespace {
 
@@ -200,6 +237,69 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   HIP_TRY(ctx, tm.begin(ctx->stream));
   HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
   HIP_TRY(ctx, tm.end(ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
+                            const morse_lightcurves* lcs, int64_t n, const double* d_params,
+                            const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
+                            double* d_grad, double* d_fs, double* d_fb) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  Plan pl;
+  size_t i_sums, i_wF, i_quad;
+  if ((rc = plan_candidates(ctx, maps, n_maps, lcs, n, pl, i_sums, i_wF, i_quad))) return rc;
+  if (n > 0 && (!d_params || !d_event || !d_map_index))
+    return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
+  const int32_t ne = lcs->n_events;
+  const size_t b_off = (8 * (size_t)(ne + 1) + 255) & ~size_t(255);
+  const size_t b_tref = (8 * (size_t)ne + 255) & ~size_t(255);
+  const size_t i_meta = pl.add(b_off + b_tref + sizeof(MapC) * n_maps);
+  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n);
+  if (pl.total() > kNoallocScratchBytes)
+    return fail(ctx, MORSE_ERANGE,
+                "needs %.1f MiB of scratch; the allocation-free entry point holds %zu MiB "
+                "(packed maps, light-curve preparation and candidate constants)",
+                pl.total() / 1048576.0, kNoallocScratchBytes >> 20);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  char* base = nullptr;
+  if ((rc = noalloc_scratch(ctx->device, &base))) return fail(ctx, rc, "%s", morse_last_error(nullptr));
+  // metadata: event offsets | reference times | map table, uploaded on every call (the
+  // array keeps whatever the last call on this GPU left in it)
+  std::vector<MapC> hm(n_maps);
+  for (int i = 0; i < n_maps; ++i) hm[i] = make_mapc(maps[i].d_map, maps[i].window);
+  assign_quads(hm, pl.ptr_at(base, i_quad));
+  char* meta = pl.ptr_at(base, i_meta);
+  MapC* d_maps = (MapC*)(meta + b_off + b_tref);
+  if ((rc = upload(ctx, meta, lcs->h_offsets, 8 * (size_t)(ne + 1)))) return rc;
+  if ((rc = upload(ctx, meta + b_off, lcs->h_t_ref, 8 * (size_t)ne))) return rc;
+  if ((rc = upload(ctx, d_maps, hm.data(), sizeof(MapC) * n_maps))) return rc;
+  GradArgs a{};
+  a.lc.t = lcs->d_t;
+  a.lc.w = lcs->d_weight;
+  a.lc.F = lcs->d_flux;
+  a.lc.wFc = (double*)pl.ptr_at(base, i_wF);
+  a.lc.off = (const int64_t*)meta;
+  a.lc.sums = (double*)pl.ptr_at(base, i_sums);
+  a.lc.t_ref = (const double*)(meta + b_off);
+  HIP_TRY(ctx, launch_quad_pack(d_maps, hm.data(), n_maps, ctx->stream));
+  HIP_TRY(ctx, launch_lc_prep(a.lc.t, a.lc.F, a.lc.w, a.lc.off, ne, (double*)a.lc.wFc,
+                              (double*)a.lc.sums, ctx->stream));
+  a.tc = (TrajC*)pl.ptr_at(base, i_tc);
+  a.tEv = (double*)pl.ptr_at(base, i_tE);
+  a.n = n;
+  a.params = d_params;
+  a.event = d_event;
+  a.mapidx = d_map_index;
+  a.maps = d_maps;
+  a.n_events = ne;
+  a.n_maps = n_maps;
+  a.chi2 = d_chi2;
+  a.grad = d_grad;
+  a.fs = d_fs;
+  a.fb = d_fb;
+  HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
+  HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
   return MORSE_OK;
 }
 

@@ -193,10 +193,11 @@ struct Plan {
     for (size_t s : sizes) t += s;
     return t;
   }
-  char* ptr(morse_ctx* ctx, size_t id) const {
+  char* ptr(morse_ctx* ctx, size_t id) const { return ptr_at(ctx->ws, id); }
+  char* ptr_at(char* base, size_t id) const {
     size_t off = 0;
     for (size_t i = 0; i < id; ++i) off += sizes[i];
-    return ctx->ws + off;
+    return base + off;
   }
 };
 
@@ -316,6 +317,11 @@ inline void assign_quads(std::vector<MapC>& hm, char* region) {
     region += (quad_bytes(m.mx, m.my) + 255) & ~size_t(255);
   }
 }
+
+// Device address of the allocation-free entry point's scratch array on `device`
+// (looked up once per device, with that device current; defined beside the entry
+// point).  Returns MORSE_OK and sets *out, or an error code.
+int noalloc_scratch(int device, char** out);
 
 // Light curves: arrays present, CSR offsets from 0, each event at least 3 and at most
 // kMaxEventPoints points (the kernels address an event's FP64 arrays with 32-bit byte
