@@ -23,6 +23,21 @@ Readings fixed here (the paper gives none of these details):
   * trajectories of a line: for a time of closest approach to the caustic centre t0'
     and Einstein time tE, t0 = t0' - shift tE (same u0, tE, alpha); ordered line, then
     t0', then tE.
+  * peaks (sec. 4.3, third optimisation): a peak is where the magnification along the
+    line stops rising and starts falling.  On the filter's binary32 samples A_k, in
+    order of tau, with relative hysteresis h >= 0 (so that the counting noise of a
+    ray-shooting map does not make peaks; h = 0 is the literal definition): after a
+    trough m (initially the first sample), a rise is a sample a > fl32(m fl32(1 + h));
+    after a rise, the running maximum M (first sample of equal maxima) becomes a peak
+    when a sample a < fl32(M fl32(1 - h)) follows, and that sample starts the next
+    trough.  A maximum at the first sample or one still rising at the last is no peak.
+    The library keeps the count and the positions tau (from the t0 point, the M_p of
+    Eqs. 7-8) and values of the first K peaks.
+  * starts (sec. 4.3, fourth and fifth optimisations): with one observed peak time t_p
+    and a given tE, the line's highest peak M_p gives t0 = t_p - M_p tE (Eq. 7); with two
+    observed times t_p1 < t_p2 its two highest peaks, in tau order M_1 < M_2, give
+    tE = (t_p2 - t_p1)/(M_2 - M_1) (Eq. 8) and t0 = t_p1 - M_1 tE.  The simplex start is
+    (t0' = t0 + shift tE, tE); a line with fewer peaks than observed times gets NaN.
   * filter: the line is sampled across the map window, over tau' in
     [tau_c - R, tau_c + R] with tau_c = cxw cos phi + cyw sin phi (window centre) and R
     half the window diagonal, at n_s = ceil(2 R kmax) + 1 points (kmax = the larger of
@@ -42,7 +57,7 @@ from .lens import lens_equation
 from .sampling import sample_mirror32
 
 __all__ = ["caustic_components", "caustic_lines", "line_filter_mirror32", "line_samples",
-           "lines_to_trajectories"]
+           "lines_to_trajectories", "count_peaks", "line_peaks_mirror32", "peak_starts"]
 
 _f = np.float32
 
@@ -138,3 +153,80 @@ def line_filter_mirror32(amap, window, lines, a_min):
                       sa=np.array([sn], _f), bx=np.array([-u0 * sn], _f), by=np.array([u0 * cn], _f))
         best[i] = sample_mirror32(amap, window, consts, tau)[0].max()
     return best, best >= _f(a_min)
+
+
+def count_peaks(a, h=0.0, k_max=8):
+    """Peaks of the sequence a (float32) with relative hysteresis h: (count, indices of
+    the first k_max peaks).  Pure-Python scan of the rule above."""
+    a = np.asarray(a, dtype=np.float32)
+    up, down = _f(1.0 + h), _f(1.0 - h)
+    count, idx = 0, []
+    trough = a[0]
+    rising = False
+    top, top_i = a[0], 0
+    for i in range(1, len(a)):
+        v = a[i]
+        if not rising:
+            if v < trough:
+                trough = v
+            elif v > _f(trough * up):
+                rising, top, top_i = True, v, i
+        else:
+            if v > top:
+                top, top_i = v, i
+            elif v < _f(top * down):
+                if count < k_max:
+                    idx.append(top_i)
+                count += 1
+                rising, trough = False, v
+    return count, idx
+
+
+def line_peaks_mirror32(amap, window, lines, h=0.0, k_max=8):
+    """Peak library of each line on the binary32 samples of the filter: count [n] int,
+    positions tau [n, k_max] float32 and values A [n, k_max] float32 (NaN past the
+    count), and the largest sample [n] float32."""
+    L = np.asarray(lines, dtype=np.float64).reshape(-1, 3)
+    n = len(L)
+    cnt = np.zeros(n, dtype=np.int32)
+    ptau = np.full((n, k_max), np.nan, dtype=np.float32)
+    pA = np.full((n, k_max), np.nan, dtype=np.float32)
+    best = np.empty(n, dtype=np.float32)
+    for i, (u0, al, _) in enumerate(L):
+        tau, _ = line_samples(window, al)
+        sn, cn = math.sin(al), math.cos(al)
+        consts = dict(t0p=np.array([0.0], _f), iE=np.array([1.0], _f), ca=np.array([cn], _f),
+                      sa=np.array([sn], _f), bx=np.array([-u0 * sn], _f), by=np.array([u0 * cn], _f))
+        A = sample_mirror32(amap, window, consts, tau)[0]
+        best[i] = A.max()
+        cnt[i], idx = count_peaks(A, h, k_max)
+        ptau[i, :len(idx)] = tau[idx]
+        pA[i, :len(idx)] = A[idx]
+    return cnt, ptau, pA, best
+
+
+def peak_starts(lines, count, ptau, pA, tp, tE_default=None):
+    """Simplex starts (t0', tE) [n, 2] FP64 from observed peak times tp (one or two,
+    ascending) by Eqs. 7-8 on each line's highest peaks; NaN rows for lines with fewer
+    peaks than observed times."""
+    L = np.asarray(lines, dtype=np.float64).reshape(-1, 3)
+    tp = [float(v) for v in np.atleast_1d(tp)]
+    out = np.full((len(L), 2), np.nan)
+    for i in range(len(L)):
+        k = min(int(count[i]), ptau.shape[1])
+        if k < len(tp):
+            continue
+        vals = [float(v) for v in pA[i, :k]]
+        # highest first; equal heights: the earlier peak first
+        order = sorted(range(k), key=lambda j: (-vals[j], j))
+        shift = L[i, 2]
+        if len(tp) == 1:
+            tE = float(tE_default)
+            t0 = tp[0] - float(ptau[i, order[0]]) * tE
+        else:
+            j1, j2 = sorted(order[:2])
+            m1, m2 = float(ptau[i, j1]), float(ptau[i, j2])
+            tE = (tp[1] - tp[0]) / (m2 - m1)
+            t0 = tp[0] - m1 * tE
+        out[i] = (t0 + shift * tE, tE)
+    return out

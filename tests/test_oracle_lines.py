@@ -107,3 +107,93 @@ def test_filter_on_a_single_lens_map_reads_the_peak():
     far = np.array([[1.8, 0.0, 0.0]])
     b2, _ = line_filter_mirror32(amap, win, far, 1.0)
     assert b2[0] == pytest.approx(paczynski(1.8), rel=1e-6)
+
+
+# ---- peak library and peak-time starts (sec. 4.3, third to fifth optimisations) ----
+from oracle.lines import count_peaks, line_peaks_mirror32, peak_starts
+
+
+def test_count_peaks_follows_the_gradient_sign_change():
+    # a peak is where the gradient turns from positive to negative
+    assert count_peaks([1, 2, 3, 2, 1]) == (1, [2])
+    assert count_peaks([1, 2, 2, 2, 1]) == (1, [1])      # plateau: its first sample
+    assert count_peaks([1, 3, 1, 3, 1]) == (2, [1, 3])
+    assert count_peaks([3, 2, 1, 2]) == (0, [])          # maximum at the first sample
+    assert count_peaks([1, 2, 3]) == (0, [])             # still rising at the end
+    assert count_peaks([1, 2, 1, 2, 1, 2, 1], k_max=2) == (3, [1, 3])
+    # hysteresis: wiggles within the relative band are not peaks
+    assert count_peaks([1, 1.05, 1.0, 2, 1], h=0.1) == (1, [3])
+    assert count_peaks([1, 1.05, 1.0, 2, 1], h=0.0) == (2, [1, 3])
+    assert count_peaks([1, 2, 1.9, 2.1, 1], h=0.1) == (1, [3])
+
+
+def _pixel_centres(n, V):
+    c = -V / 2 + (np.arange(n) + 0.5) * V / n
+    return np.meshgrid(c, c)
+
+
+def test_single_lens_lines_have_one_peak_at_closest_approach():
+    n, V = 256, 3.0
+    X, Y = _pixel_centres(n, V)
+    amap = paczynski(np.hypot(X, Y)).astype(np.float32)
+    win = (0.0, 0.0, V, V, n, n)
+    rng = np.random.default_rng(0)
+    L = np.stack([rng.uniform(0.05, 0.8, 40), rng.uniform(0, 2 * np.pi, 40), np.zeros(40)], 1)
+    tau, _ = line_samples(win, 0.0)
+    spacing = float(tau[1] - tau[0])
+    cnt, ptau, pA, best = line_peaks_mirror32(amap, win, L, h=0.0)
+    assert np.all(cnt == 1)
+    assert np.all(np.abs(ptau[:, 0]) <= 0.5 * spacing)   # M_p = 0: the closest approach
+    assert np.array_equal(pA[:, 0], best)
+
+
+@pytest.mark.parametrize("s,q", [(1.0, 1.0), (0.8, 0.2)])
+def test_peaks_at_the_caustic_crossings(s, q):
+    """On a smooth point-source map (quintic magnification at pixel centres) a horizontal
+    line has a peak within 1.5 pixels of each place where it crosses the caustic."""
+    from oracle.caustics import caustic_points
+    from oracle.lens import point_source_magnification
+    n, V = 256, 3.0
+    X, Y = _pixel_centres(n, V)
+    amap = point_source_magnification((X + 1j * Y).ravel(), s, q).reshape(n, n).astype(np.float32)
+    win = (0.0, 0.0, V, V, n, n)
+    z = np.asarray(caustic_points(s, q, 8192)).reshape(-1)
+    for u0 in (0.03, 0.1, -0.07):
+        cnt, ptau, _, _ = line_peaks_mirror32(amap, win, np.array([[u0, 0.0, 0.0]]), h=0.05)
+        xs = np.sort(z[np.abs(z.imag - u0) < 2e-3].real)
+        groups = np.split(xs, np.flatnonzero(np.diff(xs) > 0.02) + 1)
+        crossings = [g.mean() for g in groups if len(g)]
+        assert len(crossings) >= 2
+        peaks = ptau[0, :cnt[0]]
+        for x in crossings:
+            assert np.min(np.abs(peaks - x)) < 1.5 * V / n, (u0, x, peaks)
+
+
+def test_peak_times_recover_t0_and_tE():
+    """Eqs. 7-8: peaks observed at t_pi = t0 + M_pi tE give back (t0, tE) of each line."""
+    rng = np.random.default_rng(3)
+    n, K = 30, 8
+    lines = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(0, 2 * np.pi, n),
+                      rng.uniform(-1, 1, n)], 1)
+    cnt = rng.integers(2, 6, n).astype(np.int32)
+    ptau = np.full((n, K), np.nan, np.float32)
+    pA = np.full((n, K), np.nan, np.float32)
+    for i in range(n):
+        ptau[i, :cnt[i]] = np.sort(rng.uniform(-1.5, 1.5, cnt[i])).astype(np.float32)
+        pA[i, :cnt[i]] = rng.uniform(1.5, 30.0, cnt[i]).astype(np.float32)
+    t0, tE = 2456123.4, 23.5
+    for i in range(n):
+        top = sorted(np.argsort(-pA[i, :cnt[i]])[:2])
+        m1, m2 = float(ptau[i, top[0]]), float(ptau[i, top[1]])
+        tp = [t0 + m1 * tE, t0 + m2 * tE]
+        st = peak_starts(lines[i:i + 1], cnt[i:i + 1], ptau[i:i + 1], pA[i:i + 1], tp)[0]
+        assert abs(st[1] - tE) < 1e-9 * tE
+        assert abs((st[0] - lines[i, 2] * st[1]) - t0) < 1e-6     # t0 = t0' - shift tE
+        # one observed peak: the highest, with tE given (Eq. 7)
+        hi = int(np.argmax(pA[i, :cnt[i]]))
+        st1 = peak_starts(lines[i:i + 1], cnt[i:i + 1], ptau[i:i + 1], pA[i:i + 1],
+                          [t0 + float(ptau[i, hi]) * tE], tE_default=tE)[0]
+        assert abs((st1[0] - lines[i, 2] * tE) - t0) < 1e-6 and st1[1] == tE
+    # a line with fewer peaks than observed times gets no start
+    one = np.array([1], np.int32)
+    assert np.isnan(peak_starts(lines[:1], one, ptau[:1], pA[:1], [1.0, 2.0])).all()
