@@ -644,6 +644,10 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
     t = time.perf_counter()
     line_filter_mirror32(amap, win, L[:n_sub], a_min)
     t_filter = (time.perf_counter() - t) * len(L) / n_sub
+    from oracle.lines import line_peaks_mirror32
+    t = time.perf_counter()
+    line_peaks_mirror32(amap, win, L[:n_sub], 0.2, 8)
+    t_peaks = (time.perf_counter() - t) * len(L) / n_sub
     n_sx = 20  # chi-square evaluations timed; the simplex makes n_eval of them
     t = time.perf_counter()
     for k in range(n_sx):
@@ -658,6 +662,9 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
         {"value": n_kept / t_sx, "unit": "lines/s", "cores": 1, "kind": "oracle",
          "sample": f"{n_sx} chi-square evaluations of the oracle's simplex, scaled to the "
                    f"{n_eval} the GPU simplex made for {n_kept} lines ({t_sx:.0f} s scaled)"},
+        {"value": len(L) / t_peaks, "unit": "lines/s", "cores": 1, "kind": "oracle",
+         "sample": f"binary32 samples and peak scan of {n_sub} of {len(L)} lines "
+                   f"({t_peaks:.1f} s scaled)"},
     )
 
 
@@ -836,6 +843,29 @@ def leg_large(args, M, W, torch, np, dev):
                                   "ops_per_unit_f32_f64": OPS_PER_FILTER_SAMPLE, "traffic": None,
                                   "note": "tera lane-operations/s over the whole call (packing "
                                           "the map and the compaction included)"}}
+        # peak library + peak-count rejection (sec. 4.3, third optimisation) on the same
+        # lines, and the simplex starts from the light curve's peak time (Eq. 7)
+        pk_h, pk_min = 0.2, 2
+        pk = M.line_peaks(amap, c["window"], dl, a_min, pk_min, pk_h, 8, ctx=ctx_b)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            pk = M.line_peaks(amap, c["window"], dl, a_min, pk_min, pk_h, 8, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pk_ms = e0.elapsed_time(e1) / 5
+        tp = float(ev["t"][int(np.argmax(Fv))])
+        e0.record(stream)
+        pst = M.peak_starts(dl, pk[5], pk[1], pk[2], pk[3], [tp], 20.0, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lines_rec["peaks"] = {"hysteresis": pk_h, "min_peaks": pk_min, "ms": pk_ms,
+                              "lines_per_s": len(L) / (pk_ms * 1e-3),
+                              "samples_per_s": len(L) * ns / (pk_ms * 1e-3),
+                              "kept": int(len(pk[5])),
+                              "peaks_mean": float(pk[1].double().mean()),
+                              "starts_ms": e0.elapsed_time(e1),
+                              "starts_finite": int(torch.isfinite(pst[:, 0]).sum())}
         kl = dl[kept].contiguous()
         st0 = torch.tensor([[0.0, 20.0]], dtype=torch.float64, device=dev).repeat(len(kl), 1)
         sx_opts = dict(max_iter=5000, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
@@ -907,12 +937,13 @@ def main():
     large, beside = (None, None) if args.no_large else leg_large(args, M, W, torch, np, dev)
     if cpu is not None and beside is not None:
         progress("cpu baseline beside the large workload (stack, line filter, simplex)")
-        b_st, b_lf, b_sx = cpu_baseline_beside(beside["c"], beside["ev"], beside["rhos"],
+        b_st, b_lf, b_sx, b_pk = cpu_baseline_beside(beside["c"], beside["ev"], beside["rhos"],
                                               beside["gamma"], beside["r"], beside["phi"],
                                               beside["a_min"], beside["n_kept"], beside["n_eval"])
         large["rho_stack"]["cpu_baseline"] = b_st
         large["caustic_lines"]["cpu_baseline"] = b_lf
         large["caustic_lines"]["simplex"]["cpu_baseline"] = b_sx
+        large["caustic_lines"]["peaks"]["cpu_baseline"] = b_pk
 
     dom = head["dominant"]
     line = {

@@ -313,6 +313,39 @@ int morse_line_filter(morse_ctx* ctx, const morse_map_view* map, const double* d
                       double a_min, float* d_best, uint8_t* d_keep, int64_t* d_kept,
                       int64_t* d_count, int64_t* h_count);
 
+/* Peak library and peak-count rejection (sec. 4.3, third optimisation: a trajectory is
+ * rejected when its point-source magnification has fewer than the required number of
+ * peaks, a peak being where the magnification gradient changes from positive to
+ * negative) on the samples of morse_line_filter.  Scanning the samples in order: the
+ * first sample starts a trough m; a rise is a sample a > fl32(m fl32(1 + h)); after a
+ * rise the running maximum M (the first of equal maxima) becomes a peak when a sample
+ * a < fl32(M fl32(1 - h)) follows, which starts the next trough (h = hysteresis in
+ * [0, 1), relative; h = 0 is the literal rule, h > 0 keeps the counting noise of a
+ * ray-shooting map from making peaks).  Outputs, device: d_best [n] as the filter,
+ * d_npeaks [n] (int32) the peak count, d_peak_tau / d_peak_A [n][max_peaks] (float) the
+ * position tau along the line (from its t0 point: the M_p of Eqs. 7-8) and value of the
+ * first max_peaks peaks (NaN past the count), d_keep [n] = d_best >= fl32(a_min) and
+ * d_npeaks >= min_peaks (the first and third optimisations together); d_kept, d_count,
+ * h_count as the filter.  Workspace as the filter.  Errors: as the filter, EINVAL
+ * (hysteresis outside [0, 1), max_peaks outside [1, 64], min_peaks < 0). */
+int morse_line_peaks(morse_ctx* ctx, const morse_map_view* map, const double* d_lines, int64_t n,
+                     double a_min, int32_t min_peaks, double hysteresis, int32_t max_peaks,
+                     float* d_best, int32_t* d_npeaks, float* d_peak_tau, float* d_peak_A,
+                     uint8_t* d_keep, int64_t* d_kept, int64_t* d_count, int64_t* h_count);
+
+/* Simplex starts from observed peak times (sec. 4.3, fourth and fifth optimisations):
+ * for k < n, line l = d_kept[k] (k when d_kept is NULL) of the peak library above
+ * (max_peaks per line), d_start[k] = (t0', tE) in FP64 with t0' = t0 + shift tE:
+ * n_tp = 1 (h_tp[0] = t_p, tE given): the line's highest peak M_p (ties: the earlier),
+ * t0 = t_p - M_p tE (Eq. 7); n_tp = 2 (h_tp[0] < h_tp[1]): its two highest peaks in tau
+ * order M_1 < M_2, tE = (t_p2 - t_p1)/(M_2 - M_1) (Eq. 8), t0 = t_p1 - M_1 tE.  Lines
+ * with fewer stored peaks than n_tp get (NaN, NaN).  Errors: EINVAL (n < 0, n_tp not 1
+ * or 2, times not finite and increasing, tE <= 0 with n_tp = 1, NULL arrays). */
+int morse_peak_starts(morse_ctx* ctx, const double* d_lines, const int64_t* d_kept, int64_t n,
+                      const int32_t* d_npeaks, const float* d_peak_tau, const float* d_peak_A,
+                      int32_t max_peaks, const double* h_tp, int32_t n_tp, double tE,
+                      double* d_start);
+
 /* Trajectory list of the kept lines: d_params[(k n_t0 + a) n_tE + b][4] =
  * (t0_a - shift tE_b, u0, tE_b, alpha) of line d_kept[k] (line k when d_kept is NULL),
  * k < n_kept: t0 is the time of closest approach to the caustic centre.  The result is

@@ -42,7 +42,7 @@ from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut,
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
            "normalize_convolve", "convolve_stack", "profile_weights", "caustics", "caustic_lines",
-           "line_filter", "lines_to_trajectories", "line_simplex", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "line_filter", "line_peaks", "peak_starts", "lines_to_trajectories", "line_simplex", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -321,6 +321,45 @@ def line_filter(amap, window, lines, a_min, ctx=None):
     ctx.check(ctx.lib.morse_line_filter(ctx.handle, ctypes.byref(view), _ptr(lines), n, float(a_min),
                                         _ptr(best), _ptr(keep), _ptr(kept), None, ctypes.byref(count)))
     return best, keep, kept[:count.value]
+
+
+def line_peaks(amap, window, lines, a_min, min_peaks=0, hysteresis=0.0, max_peaks=8, ctx=None):
+    """Peak library of device lines float64 [n, 3] on one map, with the rejection of
+    lines below a_min or with fewer than min_peaks peaks: (best float32 [n], npeaks int32
+    [n], peak_tau float32 [n, max_peaks], peak_A float32 [n, max_peaks], keep uint8 [n],
+    kept int64 [count] ascending)."""
+    ctx = ctx or Context.get(_device_of(amap))
+    if lines.dtype != torch.float64 or not lines.is_contiguous() or lines.shape[-1] != 3:
+        raise ValueError("lines must be contiguous float64 [n, 3]")
+    n = lines.shape[0]
+    dev = lines.device
+    best = torch.empty(n, dtype=torch.float32, device=dev)
+    npk = torch.empty(n, dtype=torch.int32, device=dev)
+    ptau = torch.empty((n, max_peaks), dtype=torch.float32, device=dev)
+    pA = torch.empty((n, max_peaks), dtype=torch.float32, device=dev)
+    keep = torch.empty(n, dtype=torch.uint8, device=dev)
+    kept = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    count = ctypes.c_int64()
+    view = MapView(amap.data_ptr(), _grid(window))
+    ctx.check(ctx.lib.morse_line_peaks(ctx.handle, ctypes.byref(view), _ptr(lines), n, float(a_min),
+                                       int(min_peaks), float(hysteresis), int(max_peaks), _ptr(best),
+                                       _ptr(npk), _ptr(ptau), _ptr(pA), _ptr(keep), _ptr(kept), None,
+                                       ctypes.byref(count)))
+    return best, npk, ptau, pA, keep, kept[:count.value]
+
+
+def peak_starts(lines, kept, npeaks, peak_tau, peak_A, tp, tE=0.0, ctx=None):
+    """Simplex starts float64 [len(kept), 2] (t0', tE) from one or two observed peak
+    times tp (Eqs. 7-8); ``kept`` None means every line."""
+    ctx = ctx or Context.get(_device_of(lines))
+    tp = np.ascontiguousarray(np.atleast_1d(tp), dtype=np.float64)
+    n = lines.shape[0] if kept is None else kept.shape[0]
+    start = torch.empty((n, 2), dtype=torch.float64, device=lines.device)
+    ctx.check(ctx.lib.morse_peak_starts(ctx.handle, _ptr(lines), _ptr(kept) if kept is not None else None,
+                                        n, _ptr(npeaks), _ptr(peak_tau), _ptr(peak_A),
+                                        int(peak_tau.shape[1]), tp.ctypes.data, len(tp), float(tE),
+                                        _ptr(start)))
+    return start
 
 
 def lines_to_trajectories(lines, kept, t0, tE, ctx=None):

@@ -80,6 +80,11 @@ SIGNATURES = {
     "morse_caustic_lines": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "morse_line_filter": (c_int32, [c_void_p, POINTER(MapView), c_void_p, c_int64, c_double, c_void_p,
                                     c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "morse_line_peaks": (c_int32, [c_void_p, POINTER(MapView), c_void_p, c_int64, c_double, c_int32,
+                                   c_double, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
+    "morse_peak_starts": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                    c_void_p, c_int32, c_void_p, c_int32, c_double, c_void_p]),
     "morse_lines_to_trajectories": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                               c_void_p, c_int32, c_void_p]),
     "morse_line_simplex": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves), c_int32,

@@ -128,6 +128,76 @@ void caustic_components(double s, double q, int32_t nphi, std::vector<double>& o
 }
 }  // namespace
 
+namespace {
+
+// Shared set-up of the line filter and the peak library: validation, the map packed
+// into cells (descriptor resident in ctx->lmeta), the sampling of the lines across the
+// window, and the workspace of the compaction.
+int setup_lines(morse_ctx* ctx, const morse_map_view* map, const double* d_lines, int64_t n,
+                double a_min, bool compact, LineFilterArgs& a, Plan& pl, size_t& is, size_t& ic) {
+  int rc;
+  if (!map || !map->d_map) return fail(ctx, MORSE_EINVAL, "map is NULL");
+  if ((rc = check_window(ctx, &map->window, "map window"))) return rc;
+  if ((rc = check_quad_size(ctx, map, 1))) return rc;
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if (!std::isfinite(a_min)) return fail(ctx, MORSE_EINVAL, "a_min must be finite");
+  if (n == 0) return MORSE_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  const morse_grid2d& w = map->window;
+  const double R = 0.5 * std::sqrt(w.wx * w.wx + w.wy * w.wy);
+  const double kmax = std::max(w.nx / w.wx, w.ny / w.wy);
+  const double ns64 = std::ceil(2.0 * R * kmax) + 1.0;
+  if (ns64 > 1.0e7) return fail(ctx, MORSE_ERANGE, "more than 1e7 samples per line");
+  const size_t iq = pl.add(quad_bytes(w.nx, w.ny));
+  is = pl.add(compact ? compact_scratch_elems(n) * sizeof(int64_t) : 0);
+  ic = pl.add(sizeof(int64_t));
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  std::vector<MapC> hm(1, make_mapc(map->d_map, w));
+  assign_quads(hm, pl.ptr(ctx, iq));
+  if ((rc = reserve_meta(ctx, ctx->lmeta, sizeof(MapC)))) return rc;
+  Hasher key;
+  key.pod(ctx->lmeta.p);
+  key.bytes(hm.data(), sizeof(MapC));
+  if (ctx->lmeta.key != key.h) {
+    ctx->lmeta.key = 0;
+    if ((rc = upload(ctx, ctx->lmeta.p, hm.data(), sizeof(MapC)))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // hm goes out of scope
+    ctx->lmeta.key = key.h;
+  }
+  HIP_TRY(ctx, launch_quad_pack((const MapC*)ctx->lmeta.p, hm.data(), 1, ctx->stream));
+  a.m = hm[0];
+  a.lines = d_lines;
+  a.n = n;
+  a.cxw = w.cx;
+  a.cyw = w.cy;
+  a.half_diag = R;
+  a.ns = (int32_t)ns64;
+  a.h = (float)(2.0 * R / (ns64 - 1.0));
+  a.amin = (float)a_min;
+  return MORSE_OK;
+}
+
+int finish_empty(morse_ctx* ctx, int64_t* d_count, int64_t* h_count) {
+  if (d_count) HIP_TRY(ctx, launch_fill_u64((uint64_t*)d_count, 1, 0ull, ctx->stream));
+  if (h_count) *h_count = 0;
+  return MORSE_OK;
+}
+
+// Kept lines in ascending order (optional list, device and host counts).
+int compact_kept(morse_ctx* ctx, const Plan& pl, size_t is, size_t ic, const uint8_t* d_keep,
+                 int64_t n, int64_t* d_kept, int64_t* d_count, int64_t* h_count) {
+  if (!(d_kept || d_count || h_count)) return MORSE_OK;
+  int64_t* cnt = d_count ? d_count : (int64_t*)pl.ptr(ctx, ic);
+  HIP_TRY(ctx, launch_compact(d_keep, n, (int64_t*)pl.ptr(ctx, is), d_kept, cnt, ctx->stream));
+  if (h_count) {
+    HIP_TRY(ctx, hipMemcpyAsync(h_count, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return MORSE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 // ---------------------------------------------------------------------------
@@ -176,63 +246,79 @@ int morse_line_filter(morse_ctx* ctx, const morse_map_view* map, const double* d
                       int64_t* d_count, int64_t* h_count) {
   if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
   int rc;
-  if (!map || !map->d_map) return fail(ctx, MORSE_EINVAL, "map is NULL");
-  if ((rc = check_window(ctx, &map->window, "map window"))) return rc;
-  if ((rc = check_quad_size(ctx, map, 1))) return rc;
-  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
-  if (!std::isfinite(a_min)) return fail(ctx, MORSE_EINVAL, "a_min must be finite");
   if (n > 0 && (!d_lines || !d_best || !d_keep)) return fail(ctx, MORSE_EINVAL, "d_lines / d_best / d_keep is NULL");
-  if (n == 0) {
-    if (d_count) HIP_TRY(ctx, launch_fill_u64((uint64_t*)d_count, 1, 0ull, ctx->stream));
-    if (h_count) *h_count = 0;
-    return MORSE_OK;
-  }
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  const morse_grid2d& w = map->window;
-  const double R = 0.5 * std::sqrt(w.wx * w.wx + w.wy * w.wy);
-  const double kmax = std::max(w.nx / w.wx, w.ny / w.wy);
-  const double ns64 = std::ceil(2.0 * R * kmax) + 1.0;
-  if (ns64 > 1.0e7) return fail(ctx, MORSE_ERANGE, "more than 1e7 samples per line");
-  const bool compact = d_kept || d_count || h_count;
-  Plan pl;
-  const size_t iq = pl.add(quad_bytes(w.nx, w.ny));
-  const size_t is = pl.add(compact ? compact_scratch_elems(n) * sizeof(int64_t) : 0);
-  const size_t ic = pl.add(sizeof(int64_t));
-  if ((rc = reserve(ctx, pl.total()))) return rc;
-  std::vector<MapC> hm(1, make_mapc(map->d_map, w));
-  assign_quads(hm, pl.ptr(ctx, iq));
-  if ((rc = reserve_meta(ctx, ctx->lmeta, sizeof(MapC)))) return rc;
-  Hasher key;
-  key.pod(ctx->lmeta.p);
-  key.bytes(hm.data(), sizeof(MapC));
-  if (ctx->lmeta.key != key.h) {
-    ctx->lmeta.key = 0;
-    if ((rc = upload(ctx, ctx->lmeta.p, hm.data(), sizeof(MapC)))) return rc;
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // hm goes out of scope
-    ctx->lmeta.key = key.h;
-  }
-  HIP_TRY(ctx, launch_quad_pack((const MapC*)ctx->lmeta.p, hm.data(), 1, ctx->stream));
   LineFilterArgs a;
-  a.m = hm[0];
-  a.lines = d_lines;
-  a.n = n;
-  a.cxw = w.cx;
-  a.cyw = w.cy;
-  a.half_diag = R;
-  a.ns = (int32_t)ns64;
-  a.h = (float)(2.0 * R / (ns64 - 1.0));
-  a.amin = (float)a_min;
+  Plan pl;
+  size_t is = 0, ic = 0;
+  if ((rc = setup_lines(ctx, map, d_lines, n, a_min, d_kept || d_count || h_count, a, pl, is, ic)))
+    return rc;
+  if (n == 0) return finish_empty(ctx, d_count, h_count);
   a.best = d_best;
   a.keep = d_keep;
   HIP_TRY(ctx, launch_line_filter(a, ctx->stream));
-  if (compact) {
-    int64_t* cnt = d_count ? d_count : (int64_t*)pl.ptr(ctx, ic);
-    HIP_TRY(ctx, launch_compact(d_keep, n, (int64_t*)pl.ptr(ctx, is), d_kept, cnt, ctx->stream));
-    if (h_count) {
-      HIP_TRY(ctx, hipMemcpyAsync(h_count, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    }
-  }
+  return compact_kept(ctx, pl, is, ic, d_keep, n, d_kept, d_count, h_count);
+}
+
+int morse_line_peaks(morse_ctx* ctx, const morse_map_view* map, const double* d_lines, int64_t n,
+                     double a_min, int32_t min_peaks, double hysteresis, int32_t max_peaks,
+                     float* d_best, int32_t* d_npeaks, float* d_peak_tau, float* d_peak_A,
+                     uint8_t* d_keep, int64_t* d_kept, int64_t* d_count, int64_t* h_count) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if (!(std::isfinite(hysteresis) && hysteresis >= 0.0 && hysteresis < 1.0))
+    return fail(ctx, MORSE_EINVAL, "hysteresis must lie in [0, 1)");
+  if (max_peaks < 1 || max_peaks > 64) return fail(ctx, MORSE_EINVAL, "max_peaks must lie in [1, 64]");
+  if (min_peaks < 0) return fail(ctx, MORSE_EINVAL, "min_peaks < 0");
+  if (n > 0 && (!d_lines || !d_best || !d_npeaks || !d_peak_tau || !d_peak_A || !d_keep))
+    return fail(ctx, MORSE_EINVAL, "NULL device array");
+  LinePeakArgs a;
+  Plan pl;
+  size_t is = 0, ic = 0;
+  if ((rc = setup_lines(ctx, map, d_lines, n, a_min, d_kept || d_count || h_count, a.f, pl, is, ic)))
+    return rc;
+  if (n == 0) return finish_empty(ctx, d_count, h_count);
+  a.f.best = d_best;
+  a.f.keep = d_keep;
+  a.up = (float)(1.0 + hysteresis);
+  a.down = (float)(1.0 - hysteresis);
+  a.min_peaks = min_peaks;
+  a.kmax = max_peaks;
+  a.npeaks = d_npeaks;
+  a.ptau = d_peak_tau;
+  a.pA = d_peak_A;
+  HIP_TRY(ctx, launch_line_peaks(a, ctx->stream));
+  return compact_kept(ctx, pl, is, ic, d_keep, n, d_kept, d_count, h_count);
+}
+
+int morse_peak_starts(morse_ctx* ctx, const double* d_lines, const int64_t* d_kept, int64_t n,
+                      const int32_t* d_npeaks, const float* d_peak_tau, const float* d_peak_A,
+                      int32_t max_peaks, const double* h_tp, int32_t n_tp, double tE,
+                      double* d_start) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if (n_tp != 1 && n_tp != 2) return fail(ctx, MORSE_EINVAL, "n_tp must be 1 or 2");
+  if (max_peaks < 1 || max_peaks > 64) return fail(ctx, MORSE_EINVAL, "max_peaks must lie in [1, 64]");
+  if (!h_tp || !std::isfinite(h_tp[0]) || (n_tp == 2 && !(std::isfinite(h_tp[1]) && h_tp[1] > h_tp[0])))
+    return fail(ctx, MORSE_EINVAL, "peak times must be finite and increasing");
+  if (n_tp == 1 && !(std::isfinite(tE) && tE > 0.0)) return fail(ctx, MORSE_EINVAL, "tE must be finite and > 0");
+  if (n == 0) return MORSE_OK;
+  if (!d_lines || !d_npeaks || !d_peak_tau || !d_peak_A || !d_start)
+    return fail(ctx, MORSE_EINVAL, "NULL device array");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  PeakStartArgs a;
+  a.lines = d_lines;
+  a.kept = d_kept;
+  a.n = n;
+  a.npeaks = d_npeaks;
+  a.ptau = d_peak_tau;
+  a.pA = d_peak_A;
+  a.kmax = max_peaks;
+  a.n_tp = n_tp;
+  a.tp1 = h_tp[0];
+  a.tp2 = n_tp == 2 ? h_tp[1] : 0.0;
+  a.tE = tE;
+  a.start = d_start;
+  HIP_TRY(ctx, launch_peak_starts(a, ctx->stream));
   return MORSE_OK;
 }
 

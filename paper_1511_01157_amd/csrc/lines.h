@@ -21,6 +21,37 @@ struct LineFilterArgs {
 
 hipError_t launch_line_filter(const LineFilterArgs& a, hipStream_t st);
 
+// The filter's samples, their largest value and the peak library of each line: peaks
+// with relative hysteresis (rise above fl32(trough * up), fall below fl32(top * down)),
+// their count and the tau and value of the first kmax; keep = best >= amin and
+// count >= min_peaks.
+struct LinePeakArgs {
+  LineFilterArgs f;
+  float up, down;     // fl32(1 + h), fl32(1 - h)
+  int32_t min_peaks;
+  int32_t kmax;       // peaks stored per line
+  int32_t* npeaks;    // [n]
+  float* ptau;        // [n][kmax], NaN past the count
+  float* pA;          // [n][kmax]
+};
+hipError_t launch_line_peaks(const LinePeakArgs& a, hipStream_t st);
+
+// Simplex starts (t0', tE) of lines kept[k] (k when kept is null), k < n, from n_tp
+// observed peak times (Eq. 7 with the highest peak and tE; Eq. 8 with the two highest).
+struct PeakStartArgs {
+  const double* lines;
+  const int64_t* kept;
+  int64_t n;
+  const int32_t* npeaks;
+  const float* ptau;
+  const float* pA;
+  int32_t kmax;
+  int32_t n_tp;
+  double tp1, tp2, tE;
+  double* start;      // [n][2]
+};
+hipError_t launch_peak_starts(const PeakStartArgs& a, hipStream_t st);
+
 // Indices of the set flags of keep[n], ascending, into kept[]; their number into
 // *d_count.  scratch: compact_scratch_elems(n) int64 values.
 size_t compact_scratch_elems(int64_t n);

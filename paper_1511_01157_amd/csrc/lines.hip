@@ -59,6 +59,112 @@ __global__ __launch_bounds__(kFilterThreads) void k_line_filter(LineFilterArgs a
   }
 }
 
+// Peak library.  One wavefront per line (one per workgroup): each chunk of 64 samples is
+// computed lane-parallel exactly as in the filter, then every lane scans the chunk in
+// order (the values broadcast by readlane), so the scan state stays uniform.  A peak is
+// a rise above fl32(trough * up) followed by a fall below fl32(top * down); the first
+// sample starts the first trough; equal maxima keep the first.
+__global__ __launch_bounds__(kWave) void k_line_peaks(LinePeakArgs a) {
+  const LineFilterArgs& f = a.f;
+  const int lane = threadIdx.x;
+  const float nan = __builtin_nanf("");
+  for (int64_t l = blockIdx.x; l < f.n; l += gridDim.x) {
+    const double u0 = f.lines[3 * l], al = f.lines[3 * l + 1];
+    double sn, cn;
+    sincos(al, &sn, &cn);
+    const float ca = (float)cn, sa = (float)sn;
+    const float bx = (float)(-u0 * sn), by = (float)(u0 * cn);
+    const double tau_c = f.cxw * cn + f.cyw * sn;
+    const float lo = (float)(tau_c - f.half_diag);
+    float best = -__builtin_inff();
+    float trough = 0.0f, top = 0.0f;
+    int32_t top_i = 0, count = 0;
+    bool rising = false;
+    for (int32_t c0 = 0; c0 < f.ns; c0 += kWave) {
+      const int32_t k = c0 + lane;
+      float A = nan;
+      if (k < f.ns) {
+        A = sample_A(f.m, lo + (float)k * f.h, 0.0f, 1.0f, ca, sa, bx, by);
+        best = nanmax(best, A);
+      }
+      const int32_t nk = min(kWave, f.ns - c0);
+      for (int32_t j = 0; j < nk; ++j) {
+        const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A), j));
+        const int32_t i = c0 + j;
+        if (i == 0) {
+          trough = v;
+        } else if (!rising) {
+          if (v < trough) {
+            trough = v;
+          } else if (v > trough * a.up) {
+            rising = true;
+            top = v;
+            top_i = i;
+          }
+        } else if (v > top) {
+          top = v;
+          top_i = i;
+        } else if (v < top * a.down) {
+          if (lane == 0 && count < a.kmax) {
+            a.ptau[l * a.kmax + count] = lo + (float)top_i * f.h;
+            a.pA[l * a.kmax + count] = top;
+          }
+          ++count;
+          rising = false;
+          trough = v;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) best = nanmax(best, __shfl_xor(best, off));
+    for (int32_t j = count + lane; j < a.kmax; j += kWave) {
+      a.ptau[l * a.kmax + j] = nan;
+      a.pA[l * a.kmax + j] = nan;
+    }
+    if (lane == 0) {
+      f.best[l] = best;
+      a.npeaks[l] = count;
+      f.keep[l] = (best >= f.amin && count >= a.min_peaks) ? 1 : 0;
+    }
+  }
+}
+
+// Eqs. 7-8 per line, in FP64: one observed time -> the highest peak (ties: the earlier)
+// with the given tE; two -> the two highest, in tau order.  t0' = t0 + shift tE.
+__global__ __launch_bounds__(256) void k_peak_starts(PeakStartArgs a) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = a.kept ? a.kept[k] : k;
+    const int32_t np = min(a.npeaks[l], a.kmax);
+    double s0 = __builtin_nan(""), s1 = __builtin_nan("");
+    if (np >= a.n_tp) {
+      const float* A = a.pA + l * a.kmax;
+      const float* T = a.ptau + l * a.kmax;
+      int32_t j1 = 0;  // highest
+      for (int32_t j = 1; j < np; ++j)
+        if (A[j] > A[j1]) j1 = j;
+      const double shift = a.lines[3 * l + 2];
+      double tE, t0;
+      if (a.n_tp == 1) {
+        tE = a.tE;
+        t0 = a.tp1 - (double)T[j1] * tE;
+      } else {
+        int32_t j2 = -1;  // second highest
+        for (int32_t j = 0; j < np; ++j)
+          if (j != j1 && (j2 < 0 || A[j] > A[j2])) j2 = j;
+        const int32_t lo = min(j1, j2), hi = max(j1, j2);
+        const double m1 = (double)T[lo], m2 = (double)T[hi];
+        tE = (a.tp2 - a.tp1) / (m2 - m1);
+        t0 = a.tp1 - m1 * tE;
+      }
+      s0 = t0 + shift * tE;
+      s1 = tE;
+    }
+    a.start[2 * k] = s0;
+    a.start[2 * k + 1] = s1;
+  }
+}
+
 // Block b counts the set flags of keep[b B, (b + 1) B).
 __global__ __launch_bounds__(kCompactThreads) void k_compact_count(const uint8_t* keep, int64_t n,
                                                                    int64_t* counts) {
@@ -150,6 +256,24 @@ hipError_t launch_line_filter(const LineFilterArgs& a, hipStream_t st) {
   int64_t blocks = (a.n + per_block - 1) / per_block;
   if (blocks > (1 << 20)) blocks = 1 << 20;
   hipLaunchKernelGGL(k_line_filter, dim3((unsigned)blocks), dim3(kFilterThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_line_peaks(const LinePeakArgs& a, hipStream_t st) {
+  if (a.f.n <= 0) return hipSuccess;
+  if (!a.f.lines || !a.f.best || !a.f.keep || !a.npeaks || !a.ptau || !a.pA || a.f.ns < 2 ||
+      !a.f.m.quad || a.kmax < 1)
+    return hipErrorInvalidValue;
+  const int64_t blocks = a.f.n < (1 << 20) ? a.f.n : (1 << 20);
+  hipLaunchKernelGGL(k_line_peaks, dim3((unsigned)blocks), dim3(kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_peak_starts(const PeakStartArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  int64_t blocks = (a.n + 255) / 256;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_peak_starts, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -75,3 +75,72 @@ def test_filter_and_search_large_map():
     idx = np.unique(np.concatenate([order[:8], np.random.default_rng(5).choice(len(oP), 40, replace=False)]))
     oc = search_mirror32(amap, win, ev["tt"], ev["F"], ev["w"], oP[idx], ev["t_ref"])[0]
     assert rel_err(g[idx], oc).max() < 1e-6
+
+
+# ---- peak library, peak-count rejection and peak-time starts (sec. 4.3) ----
+from oracle.lines import line_peaks_mirror32, peak_starts
+
+
+def bits(a):
+    return np.asarray(a, np.float32).view(np.uint32)
+
+
+def peaks_case(amap, win, lines, a_min, min_peaks, h, kmax=8):
+    dmap = torch.from_numpy(np.ascontiguousarray(amap)).to(DEV)
+    dl = torch.from_numpy(lines).to(DEV)
+    best, npk, ptau, pA, keep, kept = M.line_peaks(dmap, win, dl, a_min, min_peaks, h, kmax)
+    oc, ot, oA, ob = line_peaks_mirror32(amap, win, lines, h, kmax)
+    assert np.array_equal(bits(best.cpu().numpy()), bits(ob))
+    assert np.array_equal(npk.cpu().numpy(), oc)
+    assert np.array_equal(bits(ptau.cpu().numpy()), bits(ot))     # NaN past the count too
+    assert np.array_equal(bits(pA.cpu().numpy()), bits(oA))
+    ok = (ob >= np.float32(a_min)) & (oc >= min_peaks)
+    assert np.array_equal(keep.cpu().numpy().astype(bool), ok)
+    assert np.array_equal(kept.cpu().numpy(), np.flatnonzero(ok))
+    return dl, npk, ptau, pA, kept, (oc, ot, oA)
+
+
+@pytest.mark.parametrize("h", [0.0, 0.1])
+def test_peak_library_tiny_map(h):
+    c = W.config("tiny")
+    note(f"peaks: tiny oracle map, hysteresis {h}")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], c["window"], 0.0)
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.0, 0.5, 1.0, 2.0]), np.linspace(0.0, 2 * np.pi, 33)[:-1])
+    lines = np.vstack([lines, [[5.0, 0.3, 0.0]]])          # a line that misses the window
+    dl, npk, ptau, pA, kept, (oc, ot, oA) = peaks_case(amap, c["window"], lines, 2.0, 2, h, 8)
+    assert oc.max() > 8 if h == 0.0 else oc.max() >= 2     # counting noise at h = 0
+    # starts from one and from two observed peak times, against the oracle, bitwise
+    for tp, tE in (([3.0], 20.0), ([-4.0, 6.5], 0.0)):
+        kk = kept if len(kept) else None
+        st = M.peak_starts(dl, kk, npk, ptau, pA, tp, tE).cpu().numpy()
+        sel = kept.cpu().numpy() if len(kept) else np.arange(len(lines))
+        ost = peak_starts(lines[sel], oc[sel], ot[sel], oA[sel], tp, tE)
+        assert np.array_equal(np.isnan(st), np.isnan(ost))
+        assert np.array_equal(st[~np.isnan(st)], ost[~np.isnan(ost)])
+
+
+def test_peak_library_large_map_and_simplex_from_peak_starts():
+    c = W.config("large")
+    win = c["window"]
+    note("peaks: large oracle map (2^30 rays)")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, c["rho"])
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.linspace(0.0, 3.0, 8), np.linspace(0.0, 2 * np.pi, 25)[:-1])
+    ev = W.load_lightcurve("large")
+    F = np.asarray(ev["F"])
+    a_min = 0.9 * float(F.max() / F.min())
+    dl, npk, ptau, pA, kept, (oc, ot, oA) = peaks_case(amap, win, lines, a_min, 2, 0.2, 8)
+    assert 0 < len(kept) < len(lines)
+    # the observed peak time of the light curve (largest flux) starts the simplex (Eq. 7)
+    tp = float(ev["t"][int(np.argmax(F))])
+    st = M.peak_starts(dl, kept, npk, ptau, pA, [tp], 20.0)
+    sel = kept.cpu().numpy()
+    ost = peak_starts(lines[sel], oc[sel], ot[sel], oA[sel], [tp], 20.0)
+    assert np.array_equal(st.cpu().numpy(), ost)
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    dmap = torch.from_numpy(np.ascontiguousarray(amap)).to(DEV)
+    kl = dl[kept].contiguous()
+    note(f"peaks: simplex of {len(kl)} kept lines from peak-time starts")
+    chi2, t0p, tE, it, evals = M.line_simplex([(dmap, win)], lcs, kl, st, max_iter=500)
+    assert bool(torch.isfinite(chi2).all()) and int(it.max()) <= 500
