@@ -606,7 +606,7 @@ def stack_bytes(mx, my, nx, ny, n_fft, n_direct):
     return (fwd + pairs * inv if n_fft else 0) + n_direct * 8 * mx * my
 
 
-def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
+def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval, fs_info=None):
     """The oracle timed on bounded samples of the stack, line-filter and simplex
     measurements (single-threaded numpy; oracle counts of 64 central ray rows)."""
     import numpy as np
@@ -645,6 +645,29 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
     line_filter_mirror32(amap, win, L[:n_sub], a_min)
     t_filter = (time.perf_counter() - t) * len(L) / n_sub
     from oracle.lines import line_peaks_mirror32
+    fs = None
+    if fs_info is not None:
+        from oracle.fsmag import critical_points_and_caustic, fs_magnification
+        tr, nreg = fs_info["truth"], fs_info["nreg"]
+        tau = fs_info["zeta"]
+        zs = (tau * math.cos(tr["alpha"]) - tr["u0"] * math.sin(tr["alpha"])) + \
+            1j * (tau * math.sin(tr["alpha"]) + tr["u0"] * math.cos(tr["alpha"]))
+        crit = critical_points_and_caustic(c["s"], c["q"], 1024)
+        near_i = np.flatnonzero(nreg > 0)[:: max(1, int((nreg > 0).sum()) // 6)][:6]
+        far_i = np.flatnonzero(nreg == -1)[:200]
+        t = time.perf_counter()
+        for k in near_i:
+            fs_magnification(zs[k], tr["rho"], 0.0, c["s"], c["q"], crit=crit)
+        t_near = (time.perf_counter() - t) / max(len(near_i), 1)
+        t = time.perf_counter()
+        for k in far_i:
+            fs_magnification(zs[k], tr["rho"], 0.0, c["s"], c["q"], crit=crit)
+        t_far = (time.perf_counter() - t) / max(len(far_i), 1)
+        t_lc = t_near * int((nreg > 0).sum()) + t_far * int((nreg == -1).sum())
+        fs = {"value": len(nreg) / t_lc, "unit": "epochs/s", "cores": 1, "kind": "oracle",
+              "sample": f"{len(near_i)} image-centred and {len(far_i)} point-source epochs of the "
+                        f"light curve, scaled to its {int((nreg > 0).sum())} and "
+                        f"{int((nreg == -1).sum())} ({t_lc:.0f} s scaled)"}
     t = time.perf_counter()
     line_peaks_mirror32(amap, win, L[:n_sub], 0.2, 8)
     t_peaks = (time.perf_counter() - t) * len(L) / n_sub
@@ -665,6 +688,7 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval):
         {"value": len(L) / t_peaks, "unit": "lines/s", "cores": 1, "kind": "oracle",
          "sample": f"binary32 samples and peak scan of {n_sub} of {len(L)} lines "
                    f"({t_peaks:.1f} s scaled)"},
+        fs,
     )
 
 
@@ -891,7 +915,41 @@ def leg_large(args, M, W, torch, np, dev):
                          "traffic": None,
                          "note": "the longest simplex (iterations_max) bounds the launch"}}
         rec["caustic_lines"] = lines_rec
-        beside = dict(c=c, ev=ev, rhos=rhos, gamma=STACK_GAMMA, r=r_ax, phi=phi, a_min=a_min,
+
+        # Finite-source magnification without maps (sec. 5): the light curve's epochs on
+        # its true trajectory, uniform disk of the true radius, image-centred ray shooting
+        # within 10 rho of the caustic and the point source elsewhere
+        progress("large: image-centred finite-source light curve")
+        tr = ev["truth"]
+        fs_params = (tr["t0"], tr["u0"], tr["tE"], tr["alpha"])
+        td = torch.from_numpy(np.ascontiguousarray(ev["t"], dtype=np.float64)).to(dev)
+        zeta = M.trajectory_positions(fs_params, td, ctx=ctx_b)
+        A_fs, nreg = M.fs_magnification(c["s"], c["q"], zeta, tr["rho"], 0.0, ctx=ctx_b)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            zeta = M.trajectory_positions(fs_params, td, ctx=ctx_b)
+            A_fs, nreg = M.fs_magnification(c["s"], c["q"], zeta, tr["rho"], 0.0, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fs_ms = e0.elapsed_time(e1) / 3
+        with np.load(W.golden_path("large")) as z:
+            amag = np.asarray(z["e0"], dtype=np.float64)
+        A_np, nr_np = A_fs.cpu().numpy(), nreg.cpu().numpy()
+        rel = np.abs(A_np / amag - 1)
+        rec["fs_lightcurve"] = {"epochs": int(len(A_np)), "rho": tr["rho"], "gamma": 0.0,
+                                "ms": fs_ms, "epochs_per_s": len(A_np) / (fs_ms * 1e-3),
+                                "image_centred_epochs": int((nr_np > 0).sum()),
+                                "point_source_epochs": int((nr_np == -1).sum()),
+                                "failed_epochs": int((nr_np < -1).sum()),
+                                "grid": [512, 512],
+                                "vs_synthesis_max_rel": float(rel.max()),
+                                "vs_synthesis_median_rel": float(np.median(rel)),
+                                "note": "synthesis magnifications: the oracle's quintic disk "
+                                        "average within 10 rho of the caustic (quadrature), "
+                                        "the point source elsewhere"}
+        fs_info = dict(zeta=(np.asarray(ev["t"]) - tr["t0"]) / tr["tE"], nreg=nr_np, truth=tr)
+        beside = dict(c=c, ev=ev, rhos=rhos, gamma=STACK_GAMMA, r=r_ax, phi=phi, a_min=a_min, fs=fs_info,
                       n_kept=int(len(kl)), n_eval=n_eval)
     del counts, amap, amap_build
     torch.cuda.empty_cache()
@@ -937,13 +995,15 @@ def main():
     large, beside = (None, None) if args.no_large else leg_large(args, M, W, torch, np, dev)
     if cpu is not None and beside is not None:
         progress("cpu baseline beside the large workload (stack, line filter, simplex)")
-        b_st, b_lf, b_sx, b_pk = cpu_baseline_beside(beside["c"], beside["ev"], beside["rhos"],
-                                              beside["gamma"], beside["r"], beside["phi"],
-                                              beside["a_min"], beside["n_kept"], beside["n_eval"])
+        b_st, b_lf, b_sx, b_pk, b_fs = cpu_baseline_beside(
+            beside["c"], beside["ev"], beside["rhos"], beside["gamma"], beside["r"], beside["phi"],
+            beside["a_min"], beside["n_kept"], beside["n_eval"], beside.get("fs"))
         large["rho_stack"]["cpu_baseline"] = b_st
         large["caustic_lines"]["cpu_baseline"] = b_lf
         large["caustic_lines"]["simplex"]["cpu_baseline"] = b_sx
         large["caustic_lines"]["peaks"]["cpu_baseline"] = b_pk
+        if b_fs is not None:
+            large["fs_lightcurve"]["cpu_baseline"] = b_fs
 
     dom = head["dominant"]
     line = {

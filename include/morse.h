@@ -382,6 +382,57 @@ int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_map
                        int32_t* d_evals);
 
 /* ------------------------------------------------------------------------------
+ * Finite-source magnification without maps (sec. 5: image-centred ray shooting).
+ * --------------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t n_b;      /* source boundary points (192) */
+  int32_t n_crit;   /* critical-curve phases (1024; 4 critical points each) */
+  int32_t n_side;   /* samples per region side in the growth test (128) */
+  int32_t n_grow;   /* growth rounds at most (40) */
+  int32_t n_r;      /* radial segments per region (256) */
+  int32_t n_theta;  /* angular columns per region (256) */
+  int32_t n_shrink; /* cuts of a region to its inside cells (2) */
+  int32_t reserved;
+  double near;      /* point source beyond near * rho from the caustic (10) */
+  double gap;       /* angle gap (rad) and relative radius gap that separate regions (0.2) */
+} morse_fs_opts;
+
+/* Finite-source magnification of n sources d_zeta[n][2] (device FP64 positions, lens
+ * centre of mass at the origin, masses on the x axis as morse_build_map) of radius rho
+ * with the limb-darkened profile I = 1 - gamma (1 - 1.5 sqrt(1 - r^2/rho^2)) (gamma = 0:
+ * uniform), binary lens (s, q).  As in sec. 5: a source whose centre lies more than
+ * near * rho from every caustic point (the Eq. 2 images of the critical points at
+ * n_crit phases) takes the point-source magnification of its images (the quintic of
+ * Eq. 2; Eqs. 3-4).  Otherwise the images of its centre and of n_b boundary points and
+ * the critical points whose caustic image lies inside it are seeds, in polar
+ * coordinates (r, theta) about the centre of mass; the seeds sorted by theta are cut at
+ * gaps wider than gap, each run sorted by r is cut where consecutive radii differ by
+ * more than max(gap r, 4 rho); each run is a region [r0, r1] x [t0, t1], padded by 10 %
+ * of its extent plus rho (r) and rho / r1 (theta), grown (a side with any of n_side
+ * samples mapping inside the source moves out by a quarter extent, at most n_grow
+ * rounds; 2 pi in theta makes a ring); overlapping regions merge; each region is
+ * integrated over n_theta columns of n_r radial segments (f = rho^2 - |zeta(z) -
+ * zeta_s|^2 linear along a segment, the limb at f = 0, the square root of the profile
+ * integrated exactly for linear f), cut to its inside cells one cell wider and
+ * integrated again (n_shrink times); A = the integral over pi rho^2.  Outputs, device:
+ * d_A [n] (FP64), d_nreg [n] (int32, nullable): -1 point source, >= 1 regions, -2 more
+ * than 2048 seeds, -3 more than 64 regions (A is NaN for -2 and -3).  All arithmetic
+ * FP64.  Workspace: the critical points, 8 B per source.  Errors: EINVAL (s, q, rho,
+ * gamma outside their ranges, opts out of range, NULL arrays), ERANGE (n > 2^31). */
+int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_zeta, int64_t n,
+                           double rho, double gamma, const morse_fs_opts* opts, double* d_A,
+                           int32_t* d_nreg);
+
+/* Source positions of one trajectory at n times (sec. 4.1 parameters; the trajectory
+ * form of morse_search): h_params = (t0, u0, tE, alpha) host FP64, d_t [n] device FP64
+ * times, d_zeta [n][2] = tau (cos alpha, sin alpha) + u0 (-sin alpha, cos alpha) with
+ * tau = (t - t0)/tE, FP64 (the input of morse_fs_magnification for a light curve).
+ * Errors: EINVAL (non-finite parameters, tE <= 0, NULL arrays, n < 0). */
+int morse_trajectory_positions(morse_ctx* ctx, const double* h_params, const double* d_t, int64_t n,
+                               double* d_zeta);
+
+/* ------------------------------------------------------------------------------
  * Gradient and refinement (candidates from the search refined on their maps).
  * --------------------------------------------------------------------------- */
 

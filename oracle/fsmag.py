@@ -13,9 +13,10 @@ fixed here (and mirrored, in its own code, by the GPU) are:
     points (Eq. 2 images of the critical-curve points at n_crit phases); > 10 rho ->
     point-source magnification of the centre's images (Eqs. 3-4).
   * seeds: the images of the centre and of n_b boundary points zeta_s + rho
-    exp(2 pi i (j + 1/2)/n_b), and every critical point whose caustic image lies inside
-    the source (where a grazing source creates images the boundary samples may miss),
-    in polar coordinates (r, theta) about the centre of mass.
+    exp(2 pi i (j + 1/2)/n_b), and the critical points whose caustic image lies inside
+    the source (where a grazing source creates images the boundary samples may miss):
+    of those at phases p with p mod m = 0, m the smallest stride >= ceil(count / 512)
+    that keeps at most 512; in polar coordinates (r, theta) about the centre of mass.
   * regions: seeds sorted by theta; the circle is cut at every gap wider than
     ``gap`` (0.2 rad); each run of seeds is a region [r_min, r_max] x [theta_a,
     theta_b] (a full ring when no gap is wider), padded by 10 % of its extent plus
@@ -77,11 +78,19 @@ def _inside(z, zeta_s, rho, s, q):
     return np.abs(lens_equation(z, s, q) - zeta_s) < rho
 
 
+CRIT_SEEDS = 512  # critical-point seeds at most
+
+
 def _seeds(zeta_s, rho, s, q, zc, cc, opt):
     pts = [zeta_s] + list(zeta_s + rho * np.exp(2j * np.pi * (np.arange(opt.n_b) + 0.5) / opt.n_b))
     roots, isimg = image_positions(np.array(pts), s, q)
     z = roots[isimg]
-    z = np.concatenate([z, zc[np.abs(cc - zeta_s) < rho]])
+    inside = np.abs(cc - zeta_s) < rho
+    phase = np.arange(len(cc)) // 4
+    m = max(1, -(-int(inside.sum()) // CRIT_SEEDS))
+    while int((inside & (phase % m == 0)).sum()) > CRIT_SEEDS:
+        m += 1
+    z = np.concatenate([z, zc[inside & (phase % m == 0)]])
     return z
 
 

@@ -37,12 +37,12 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import (Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut, Trajectories,
+from ._abi import (FsOpts, Grid2D, LbfgsOpts, LightCurves, MapStats, MapView, SearchOut, Trajectories,
                    SEARCH_BATCHED, SEARCH_PLAIN, TRAJ_GRID, TRAJ_LIST)
 
 __all__ = ["MorseError", "Context", "LightCurveBatch", "build_map", "rayshoot",
            "normalize_convolve", "convolve_stack", "profile_weights", "caustics", "caustic_lines",
-           "line_filter", "line_peaks", "peak_starts", "lines_to_trajectories", "line_simplex", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
+           "fs_magnification", "trajectory_positions", "line_filter", "line_peaks", "peak_starts", "lines_to_trajectories", "line_simplex", "search", "autotune", "autotune_load", "candidates_from_topk", "chi2_grad", "refine", "Chi2Fn",
            "grid_trajectories", "list_trajectories", "abi_version", "KERNEL_RAYSHOOT",
            "KERNEL_SEARCH", "KERNEL_GRADIENT"]
 
@@ -478,6 +478,39 @@ def candidates_from_topk(trajs, topk_idx, n_maps, out=None, ctx=None):
                                                  int(k), _ptr(topk_idx.contiguous()), _ptr(params),
                                                  _ptr(event), _ptr(mapi)))
     return params, event, mapi
+
+
+# --------------------------------------------------- finite-source magnification
+def fs_magnification(s, q, zeta, rho, gamma=0.0, n_b=192, n_crit=1024, n_side=128, n_grow=40,
+                     n_r=512, n_theta=512, n_shrink=2, near=10.0, gap=0.2, ctx=None):
+    """Image-centred ray-shooting magnification of sources at device positions zeta
+    float64 [n, 2] (or complex128 [n]): (A float64 [n], regions int32 [n])."""
+    if zeta.dtype == torch.complex128:
+        zeta = torch.view_as_real(zeta.contiguous())
+    if zeta.dtype != torch.float64 or zeta.dim() != 2 or zeta.shape[1] != 2 or not zeta.is_contiguous():
+        raise ValueError("zeta must be contiguous float64 [n, 2] or complex128 [n]")
+    ctx = ctx or Context.get(_device_of(zeta))
+    n = zeta.shape[0]
+    A = torch.empty(n, dtype=torch.float64, device=zeta.device)
+    nreg = torch.empty(n, dtype=torch.int32, device=zeta.device)
+    o = FsOpts(int(n_b), int(n_crit), int(n_side), int(n_grow), int(n_r), int(n_theta), int(n_shrink), 0,
+               float(near), float(gap))
+    ctx.check(ctx.lib.morse_fs_magnification(ctx.handle, float(s), float(q), _ptr(zeta), n, float(rho),
+                                             float(gamma), ctypes.byref(o), _ptr(A), _ptr(nreg)))
+    return A, nreg
+
+
+def trajectory_positions(params, t, ctx=None):
+    """Source positions float64 [n, 2] of the trajectory params (t0, u0, tE, alpha) at
+    device FP64 times t [n]."""
+    if t.dtype != torch.float64 or t.dim() != 1 or not t.is_contiguous():
+        raise ValueError("t must be contiguous float64 [n]")
+    ctx = ctx or Context.get(_device_of(t))
+    p = np.ascontiguousarray(params, dtype=np.float64).reshape(4)
+    zeta = torch.empty((t.shape[0], 2), dtype=torch.float64, device=t.device)
+    ctx.check(ctx.lib.morse_trajectory_positions(ctx.handle, p.ctypes.data, _ptr(t), t.shape[0],
+                                                 _ptr(zeta)))
+    return zeta
 
 
 # ------------------------------------------------------------------ gradient / refine

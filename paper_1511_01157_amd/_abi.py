@@ -28,6 +28,12 @@ class MapView(ctypes.Structure):
     _fields_ = [("d_map", c_void_p), ("window", Grid2D)]
 
 
+class FsOpts(ctypes.Structure):
+    _fields_ = [("n_b", c_int32), ("n_crit", c_int32), ("n_side", c_int32), ("n_grow", c_int32),
+                ("n_r", c_int32), ("n_theta", c_int32), ("n_shrink", c_int32), ("reserved", c_int32),
+                ("near", c_double), ("gap", c_double)]
+
+
 class LightCurves(ctypes.Structure):
     _fields_ = [("n_events", c_int32), ("reserved", c_int32), ("h_offsets", c_void_p),
                 ("h_t_ref", c_void_p), ("d_t", c_void_p), ("d_flux", c_void_p),
@@ -85,6 +91,9 @@ SIGNATURES = {
                                    c_void_p, c_void_p, c_void_p, POINTER(c_int64)]),
     "morse_peak_starts": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
                                     c_void_p, c_int32, c_void_p, c_int32, c_double, c_void_p]),
+    "morse_fs_magnification": (c_int32, [c_void_p, c_double, c_double, c_void_p, c_int64, c_double,
+                                         c_double, POINTER(FsOpts), c_void_p, c_void_p]),
+    "morse_trajectory_positions": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "morse_lines_to_trajectories": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                               c_void_p, c_int32, c_void_p]),
     "morse_line_simplex": (c_int32, [c_void_p, POINTER(MapView), c_int32, POINTER(LightCurves), c_int32,

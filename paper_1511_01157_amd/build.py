@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmorse.so")
 SOURCES = ["maps.hip", "search.hip", "refine.hip", "stack.hip", "lines.hip", "simplex.hip",
-           "api_ctx.hip", "api_maps.hip", "api_lines.hip", "api_search.hip", "api_refine.hip"]
+           "fsmag.hip", "api_ctx.hip", "api_maps.hip", "api_lines.hip", "api_search.hip",
+           "api_refine.hip", "api_fsmag.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-fhip-fp32-correctly-rounded-divide-sqrt",

@@ -1,0 +1,99 @@
+// C ABI, finite-source magnification by image-centred ray shooting (sec. 5): the
+// critical curves on the host, then the proximity kernel and the image-centred kernel.
+
+#include "host.h"
+#include "fsmag.h"
+
+using namespace morse;
+using namespace morse::host;
+
+extern "C" {
+
+int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_zeta, int64_t n,
+                           double rho, double gamma, const morse_fs_opts* opts, double* d_A,
+                           int32_t* d_nreg) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  int rc;
+  if ((rc = check_lens(ctx, s, q))) return rc;
+  if (!(std::isfinite(rho) && rho > 0.0)) return fail(ctx, MORSE_EINVAL, "rho must be finite and > 0");
+  if (!(gamma >= 0.0 && gamma <= 1.0)) return fail(ctx, MORSE_EINVAL, "gamma must lie in [0, 1]");
+  if (!opts) return fail(ctx, MORSE_EINVAL, "opts is NULL");
+  const morse_fs_opts& o = *opts;
+  if (o.n_b < 8 || o.n_b > 1024 || o.n_crit < 16 || o.n_crit > (1 << 16) || o.n_side < 2 ||
+      o.n_side > 4096 || o.n_grow < 0 || o.n_grow > 1000 || o.n_r < 2 || o.n_r > 65536 ||
+      o.n_theta < 2 || o.n_theta > 65536 || o.n_shrink < 0 || o.n_shrink > 16)
+    return fail(ctx, MORSE_EINVAL, "opts out of range");
+  if (!(std::isfinite(o.near) && o.near >= 0.0 && std::isfinite(o.gap) && o.gap > 0.0))
+    return fail(ctx, MORSE_EINVAL, "near must be >= 0 and gap > 0");
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if (n == 0) return MORSE_OK;
+  if (!d_zeta || !d_A) return fail(ctx, MORSE_EINVAL, "d_zeta / d_A is NULL");
+  if (n > (int64_t)1 << 31) return fail(ctx, MORSE_ERANGE, "more than 2^31 sources");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // critical points and their caustic images (Eq. 2), host FP64
+  std::vector<std::complex<double>> zc;
+  critical_points(s, q, o.n_crit, zc);
+  const double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);
+  const double x1 = -s * q / (1.0 + q), x2 = s / (1.0 + q);
+  const size_t nc = zc.size();
+  std::vector<double> crit(2 * nc), caus(2 * nc);
+  for (size_t j = 0; j < nc; ++j) {
+    const std::complex<double> z = zc[j];
+    const std::complex<double> zeta = z - m1 / std::conj(z - x1) - m2 / std::conj(z - x2);
+    crit[2 * j] = z.real();
+    crit[2 * j + 1] = z.imag();
+    caus[2 * j] = zeta.real();
+    caus[2 * j + 1] = zeta.imag();
+  }
+  Plan pl;
+  const size_t i_crit = pl.add(16 * nc), i_caus = pl.add(16 * nc), i_list = pl.add(4 * (size_t)n),
+               i_cnt = pl.add(4), i_nreg = pl.add(d_nreg ? 0 : 4 * (size_t)n);
+  if ((rc = reserve(ctx, pl.total()))) return rc;
+  FsArgs a;
+  a.m1 = m1;
+  a.m2 = m2;
+  a.x1 = x1;
+  a.x2 = x2;
+  a.zeta = d_zeta;
+  a.n = n;
+  a.rho = rho;
+  a.gamma = gamma;
+  a.crit = (const double*)pl.ptr(ctx, i_crit);
+  a.caus = (const double*)pl.ptr(ctx, i_caus);
+  a.n_crit = (int32_t)nc;
+  a.n_b = o.n_b;
+  a.n_side = o.n_side;
+  a.n_grow = o.n_grow;
+  a.n_r = o.n_r;
+  a.n_theta = o.n_theta;
+  a.n_shrink = o.n_shrink;
+  a.near = o.near;
+  a.gap = o.gap;
+  a.A = d_A;
+  a.nreg = d_nreg ? d_nreg : (int32_t*)pl.ptr(ctx, i_nreg);
+  a.near_list = (int32_t*)pl.ptr(ctx, i_list);
+  a.near_count = (uint32_t*)pl.ptr(ctx, i_cnt);
+  if ((rc = upload(ctx, (void*)a.crit, crit.data(), 16 * nc))) return rc;
+  if ((rc = upload(ctx, (void*)a.caus, caus.data(), 16 * nc))) return rc;
+  HIP_TRY(ctx, launch_fs_classify(a, ctx->stream));
+  HIP_TRY(ctx, launch_fs_images(a, 4 * ctx->num_cu, ctx->stream));
+  return MORSE_OK;
+}
+
+int morse_trajectory_positions(morse_ctx* ctx, const double* h_params, const double* d_t, int64_t n,
+                               double* d_zeta) {
+  if (!ctx) return fail(nullptr, MORSE_EINVAL, "ctx is NULL");
+  if (!h_params) return fail(ctx, MORSE_EINVAL, "h_params is NULL");
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(h_params[k])) return fail(ctx, MORSE_EINVAL, "trajectory parameters must be finite");
+  if (!(h_params[2] > 0.0)) return fail(ctx, MORSE_EINVAL, "tE must be > 0");
+  if (n < 0) return fail(ctx, MORSE_EINVAL, "n < 0");
+  if (n == 0) return MORSE_OK;
+  if (!d_t || !d_zeta) return fail(ctx, MORSE_EINVAL, "d_t / d_zeta is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, launch_traj_positions(d_t, n, h_params[0], h_params[1], h_params[2], h_params[3],
+                                     d_zeta, ctx->stream));
+  return MORSE_OK;
+}
+
+}  // extern "C"

@@ -53,12 +53,17 @@ void quartic_roots(const std::complex<double> (&c)[5], std::complex<double> (&z)
 // curve, whose Eq. 2 image is one caustic.  Output rows (cx, cy, half_w, half_h,
 // size) of the caustics' bounding boxes (size = the larger half-side), ordered by
 // (round(1e9 cy), cx).
-void caustic_components(double s, double q, int32_t nphi, std::vector<double>& out) {
+}  // namespace
+
+namespace morse {
+namespace host {
+// Critical points at nphi equally spaced phases (4 per phase, phase-major).
+void critical_points(double s, double q, int32_t nphi, std::vector<std::complex<double>>& z) {
   typedef std::complex<double> C;
   const double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);
   const double x1 = -s * q / (1.0 + q), x2 = s / (1.0 + q);
   const double S = x1 + x2, P = x1 * x2;
-  std::vector<C> z((size_t)nphi * 4);
+  z.assign((size_t)nphi * 4, C(0.0, 0.0));
   C r[4];
   for (int p = 0; p < nphi; ++p) {
     const double ph = 2.0 * M_PI * p / nphi;
@@ -69,6 +74,18 @@ void caustic_components(double s, double q, int32_t nphi, std::vector<double>& o
     quartic_roots(c, r, p > 0);
     for (int k = 0; k < 4; ++k) z[(size_t)p * 4 + k] = r[k];
   }
+}
+}  // namespace host
+}  // namespace morse
+
+namespace {
+
+void caustic_components(double s, double q, int32_t nphi, std::vector<double>& out) {
+  typedef std::complex<double> C;
+  const double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);
+  const double x1 = -s * q / (1.0 + q), x2 = s / (1.0 + q);
+  std::vector<C> z;
+  critical_points(s, q, nphi, z);
   std::vector<int> parent((size_t)nphi * 4);
   for (size_t i = 0; i < parent.size(); ++i) parent[i] = (int)i;
   auto find = [&](int a) {

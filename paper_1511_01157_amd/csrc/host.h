@@ -318,6 +318,10 @@ inline void assign_quads(std::vector<MapC>& hm, char* region) {
   }
 }
 
+// Critical points of the binary lens at nphi equally spaced phases of the critical-curve
+// quartic (4 per phase, phase-major; defined with the caustic geometry).
+void critical_points(double s, double q, int32_t nphi, std::vector<std::complex<double>>& z);
+
 // Device address of the allocation-free entry point's scratch array on `device`
 // (looked up once per device, with that device current; defined beside the entry
 // point).  Returns MORSE_OK and sets *out, or an error code.
