@@ -648,26 +648,27 @@ def cpu_baseline_beside(c, ev, rhos, gamma, r, phi, a_min, n_kept, n_eval, fs_in
     fs = None
     if fs_info is not None:
         from oracle.fsmag import critical_points_and_caustic, fs_magnification
-        tr, nreg = fs_info["truth"], fs_info["nreg"]
+        tr, tri, nreg = fs_info["truth"], fs_info["trial"], fs_info["nreg_trial"]
         tau = fs_info["zeta"]
-        zs = (tau * math.cos(tr["alpha"]) - tr["u0"] * math.sin(tr["alpha"])) + \
-            1j * (tau * math.sin(tr["alpha"]) + tr["u0"] * math.cos(tr["alpha"]))
+        zs = (tau * math.cos(tri["alpha"]) - tri["u0"] * math.sin(tri["alpha"])) + \
+            1j * (tau * math.sin(tri["alpha"]) + tri["u0"] * math.cos(tri["alpha"]))
         crit = critical_points_and_caustic(c["s"], c["q"], 1024)
-        near_i = np.flatnonzero(nreg > 0)[:: max(1, int((nreg > 0).sum()) // 6)][:6]
+        near_i = np.flatnonzero(nreg > 0)[:: max(1, int((nreg > 0).sum()) // 4)][:4]
         far_i = np.flatnonzero(nreg == -1)[:200]
         t = time.perf_counter()
         for k in near_i:
-            fs_magnification(zs[k], tr["rho"], 0.0, c["s"], c["q"], crit=crit)
+            fs_magnification(zs[k], tr["rho"], STACK_GAMMA, c["s"], c["q"], crit=crit)
         t_near = (time.perf_counter() - t) / max(len(near_i), 1)
         t = time.perf_counter()
         for k in far_i:
-            fs_magnification(zs[k], tr["rho"], 0.0, c["s"], c["q"], crit=crit)
+            fs_magnification(zs[k], tr["rho"], STACK_GAMMA, c["s"], c["q"], crit=crit)
         t_far = (time.perf_counter() - t) / max(len(far_i), 1)
         t_lc = t_near * int((nreg > 0).sum()) + t_far * int((nreg == -1).sum())
         fs = {"value": len(nreg) / t_lc, "unit": "epochs/s", "cores": 1, "kind": "oracle",
-              "sample": f"{len(near_i)} image-centred and {len(far_i)} point-source epochs of the "
-                        f"light curve, scaled to its {int((nreg > 0).sum())} and "
-                        f"{int((nreg == -1).sum())} ({t_lc:.0f} s scaled)"}
+              "sample": f"caustic-crossing trial light curve: {len(near_i)} image-centred and "
+                        f"{len(far_i)} point-source epochs, scaled to its "
+                        f"{int((nreg > 0).sum())} and {int((nreg == -1).sum())} ({t_lc:.0f} s "
+                        f"scaled)"}
     t = time.perf_counter()
     line_peaks_mirror32(amap, win, L[:n_sub], 0.2, 8)
     t_peaks = (time.perf_counter() - t) * len(L) / n_sub
@@ -948,7 +949,27 @@ def leg_large(args, M, W, torch, np, dev):
                                 "note": "synthesis magnifications: the oracle's quintic disk "
                                         "average within 10 rho of the caustic (quadrature), "
                                         "the point source elsewhere"}
-        fs_info = dict(zeta=(np.asarray(ev["t"]) - tr["t0"]) / tr["tE"], nreg=nr_np, truth=tr)
+        # a trial through the central caustic (u0 = 0), limb-darkened: the image-centred
+        # branch at the caustic crossings
+        trial = (tr["t0"], 0.0, tr["tE"], tr["alpha"])
+        zt = M.trajectory_positions(trial, td, ctx=ctx_b)
+        A_t, nreg_t = M.fs_magnification(c["s"], c["q"], zt, tr["rho"], STACK_GAMMA, ctx=ctx_b)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            zt = M.trajectory_positions(trial, td, ctx=ctx_b)
+            A_t, nreg_t = M.fs_magnification(c["s"], c["q"], zt, tr["rho"], STACK_GAMMA, ctx=ctx_b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tr_ms = e0.elapsed_time(e1) / 3
+        nt = nreg_t.cpu().numpy()
+        rec["fs_lightcurve"]["caustic_crossing_trial"] = {
+            "params_t0_u0_tE_alpha": list(trial), "gamma": STACK_GAMMA, "ms": tr_ms,
+            "epochs_per_s": len(nt) / (tr_ms * 1e-3), "image_centred_epochs": int((nt > 0).sum()),
+            "point_source_epochs": int((nt == -1).sum()), "failed_epochs": int((nt < -1).sum()),
+            "A_max": float(A_t.max())}
+        fs_info = dict(zeta=(np.asarray(ev["t"]) - tr["t0"]) / tr["tE"], nreg=nr_np, truth=tr,
+                       trial=dict(tr, u0=0.0), nreg_trial=nt)
         beside = dict(c=c, ev=ev, rhos=rhos, gamma=STACK_GAMMA, r=r_ax, phi=phi, a_min=a_min, fs=fs_info,
                       n_kept=int(len(kl)), n_eval=n_eval)
     del counts, amap, amap_build
@@ -1003,7 +1024,7 @@ def main():
         large["caustic_lines"]["simplex"]["cpu_baseline"] = b_sx
         large["caustic_lines"]["peaks"]["cpu_baseline"] = b_pk
         if b_fs is not None:
-            large["fs_lightcurve"]["cpu_baseline"] = b_fs
+            large["fs_lightcurve"]["caustic_crossing_trial"]["cpu_baseline"] = b_fs
 
     dom = head["dominant"]
     line = {

@@ -418,7 +418,8 @@ typedef struct {
  * integrated again (n_shrink times); A = the integral over pi rho^2.  Outputs, device:
  * d_A [n] (FP64), d_nreg [n] (int32, nullable): -1 point source, >= 1 regions, -2 more
  * than 2048 seeds, -3 more than 64 regions (A is NaN for -2 and -3).  All arithmetic
- * FP64.  Workspace: the critical points, 8 B per source.  Errors: EINVAL (s, q, rho,
+ * FP64.  The critical points stay resident in the context (32 B each) until a call needs
+ * another (s, q, n_crit); workspace 8 B per source.  Errors: EINVAL (s, q, rho,
  * gamma outside their ranges, opts out of range, NULL arrays), ERANGE (n > 2^31). */
 int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_zeta, int64_t n,
                            double rho, double gamma, const morse_fs_opts* opts, double* d_A,

@@ -77,7 +77,7 @@ int morse_ctx_destroy(morse_ctx* ctx) {
   if (ctx->taps) (void)hipFree(ctx->taps);
   if (ctx->smeta.p) (void)hipFree(ctx->smeta.p);
   if (ctx->cmeta.p) (void)hipFree(ctx->cmeta.p);
-  for (MetaBuf* mb : {&ctx->stack_taps, &ctx->fft_tw, &ctx->fft_spec, &ctx->lmeta})
+  for (MetaBuf* mb : {&ctx->stack_taps, &ctx->fft_tw, &ctx->fft_spec, &ctx->lmeta, &ctx->fs_crit})
     if (mb->p) (void)hipFree(mb->p);
   for (const auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);

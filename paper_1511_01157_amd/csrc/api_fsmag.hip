@@ -30,24 +30,37 @@ int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_z
   if (!d_zeta || !d_A) return fail(ctx, MORSE_EINVAL, "d_zeta / d_A is NULL");
   if (n > (int64_t)1 << 31) return fail(ctx, MORSE_ERANGE, "more than 2^31 sources");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  // critical points and their caustic images (Eq. 2), host FP64
-  std::vector<std::complex<double>> zc;
-  critical_points(s, q, o.n_crit, zc);
   const double m1 = 1.0 / (1.0 + q), m2 = q / (1.0 + q);
   const double x1 = -s * q / (1.0 + q), x2 = s / (1.0 + q);
-  const size_t nc = zc.size();
-  std::vector<double> crit(2 * nc), caus(2 * nc);
-  for (size_t j = 0; j < nc; ++j) {
-    const std::complex<double> z = zc[j];
-    const std::complex<double> zeta = z - m1 / std::conj(z - x1) - m2 / std::conj(z - x2);
-    crit[2 * j] = z.real();
-    crit[2 * j + 1] = z.imag();
-    caus[2 * j] = zeta.real();
-    caus[2 * j + 1] = zeta.imag();
+  // critical points and their caustic images (Eq. 2), host FP64, resident in the context
+  // until a call needs another (s, q, phases)
+  const size_t nc = (size_t)o.n_crit * 4;
+  if ((rc = reserve_meta(ctx, ctx->fs_crit, 32 * nc))) return rc;
+  Hasher key;
+  key.pod(ctx->fs_crit.p);
+  key.pod(s);
+  key.pod(q);
+  key.pod(o.n_crit);
+  if (ctx->fs_crit.key != key.h) {
+    ctx->fs_crit.key = 0;
+    std::vector<std::complex<double>> zc;
+    critical_points(s, q, o.n_crit, zc);
+    std::vector<double> buf(4 * nc);
+    for (size_t j = 0; j < nc; ++j) {
+      const std::complex<double> z = zc[j];
+      const std::complex<double> zeta = z - m1 / std::conj(z - x1) - m2 / std::conj(z - x2);
+      buf[2 * j] = z.real();
+      buf[2 * j + 1] = z.imag();
+      buf[2 * nc + 2 * j] = zeta.real();
+      buf[2 * nc + 2 * j + 1] = zeta.imag();
+    }
+    if ((rc = upload(ctx, ctx->fs_crit.p, buf.data(), 32 * nc))) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));  // buf goes out of scope
+    ctx->fs_crit.key = key.h;
   }
   Plan pl;
-  const size_t i_crit = pl.add(16 * nc), i_caus = pl.add(16 * nc), i_list = pl.add(4 * (size_t)n),
-               i_cnt = pl.add(4), i_nreg = pl.add(d_nreg ? 0 : 4 * (size_t)n);
+  const size_t i_list = pl.add(4 * (size_t)n), i_cnt = pl.add(4),
+               i_nreg = pl.add(d_nreg ? 0 : 4 * (size_t)n);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   FsArgs a;
   a.m1 = m1;
@@ -58,8 +71,8 @@ int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_z
   a.n = n;
   a.rho = rho;
   a.gamma = gamma;
-  a.crit = (const double*)pl.ptr(ctx, i_crit);
-  a.caus = (const double*)pl.ptr(ctx, i_caus);
+  a.crit = (const double*)ctx->fs_crit.p;
+  a.caus = (const double*)ctx->fs_crit.p + 2 * nc;
   a.n_crit = (int32_t)nc;
   a.n_b = o.n_b;
   a.n_side = o.n_side;
@@ -73,8 +86,6 @@ int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_z
   a.nreg = d_nreg ? d_nreg : (int32_t*)pl.ptr(ctx, i_nreg);
   a.near_list = (int32_t*)pl.ptr(ctx, i_list);
   a.near_count = (uint32_t*)pl.ptr(ctx, i_cnt);
-  if ((rc = upload(ctx, (void*)a.crit, crit.data(), 16 * nc))) return rc;
-  if ((rc = upload(ctx, (void*)a.caus, caus.data(), 16 * nc))) return rc;
   HIP_TRY(ctx, launch_fs_classify(a, ctx->stream));
   HIP_TRY(ctx, launch_fs_images(a, 4 * ctx->num_cu, ctx->stream));
   return MORSE_OK;

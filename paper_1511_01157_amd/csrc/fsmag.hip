@@ -100,8 +100,8 @@ __device__ __forceinline__ void poly_eval(const cd (&a)[6], cd z, cd& p, cd& dp)
   }
 }
 
-// Roots of the quintic: Aberth-Ehrlich from a circle (Cauchy bound), then two Newton
-// steps per root.
+// Roots of the quintic: Aberth-Ehrlich from a circle (Cauchy bound) until the largest
+// relative step is below 1e-14, then two Newton steps per root.
 __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
   const cd inv5 = crecip(a[5]);
   double rad = 0.0;
@@ -127,7 +127,7 @@ __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
       z[k] = csub(z[k], step);
       moved = fmax(moved, cabs(step) / (1.0 + cabs(z[k])));
     }
-    if (moved < 1e-16) break;
+    if (moved < 1e-14) break;  // the Newton steps below finish to full precision
   }
   for (int k = 0; k < 5; ++k)
     for (int it = 0; it < 2; ++it) {
@@ -138,63 +138,74 @@ __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
 }
 
 // Images of zeta: the 5 roots when all satisfy Eq. 2 to 1e-6 (1 + |zeta|), else the 3
-// with the smallest residuals when at least 3 do, else those that do.  Returns the
-// count; img[0..count) the images.
-__device__ int images_of(const Lens& L, cd zeta, cd (&img)[5]) {
-  cd a[6], z[5];
+// with the smallest residuals (ties: the lower root index) when at least 3 do, else
+// those that do.  sel[k] marks the images among the roots z[k]; returns their number.
+// Written without indexing by a runtime value, so the arrays stay in registers.
+__device__ __forceinline__ int images_of(const Lens& L, cd zeta, cd (&z)[5], bool (&sel)[5]) {
+  cd a[6];
   quintic(L, zeta, a);
   quintic_roots(a, z);
   double res[5];
-  int ord[5];
+#pragma unroll
   for (int k = 0; k < 5; ++k) {
     const double r = cabs(csub(lens_eq(L, z[k]), zeta));
     res[k] = isfinite(r) ? r : __builtin_inf();
-    ord[k] = k;
   }
-  for (int i = 1; i < 5; ++i)  // stable insertion sort by residual
-    for (int j = i; j > 0 && res[ord[j]] < res[ord[j - 1]]; --j) {
-      const int t = ord[j];
-      ord[j] = ord[j - 1];
-      ord[j - 1] = t;
-    }
   const double tol = 1e-6 * (1.0 + cabs(zeta));
   int nvalid = 0;
+#pragma unroll
   for (int k = 0; k < 5; ++k) nvalid += res[k] < tol ? 1 : 0;
   const int nimg = nvalid >= 5 ? 5 : (nvalid >= 3 ? 3 : nvalid);
-  for (int k = 0; k < nimg; ++k) img[k] = z[ord[k]];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) rank += (res[j] < res[k] || (res[j] == res[k] && j < k)) ? 1 : 0;
+    sel[k] = rank < nimg;
+  }
   return nimg;
 }
 
 __device__ double point_source_A(const Lens& L, cd zeta) {
-  cd img[5];
-  const int n = images_of(L, zeta, img);
+  cd z[5];
+  bool sel[5];
+  images_of(L, zeta, z, sel);
   double A = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const cd w1 = {img[k].x - L.x1, -img[k].y}, w2 = {img[k].x - L.x2, -img[k].y};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const cd w1 = {z[k].x - L.x1, -z[k].y}, w2 = {z[k].x - L.x2, -z[k].y};
     const cd g = cadd(cscale(crecip(cmul(w1, w1)), L.m1), cscale(crecip(cmul(w2, w2)), L.m2));
     const double ag = cabs(g);
-    A += fabs(1.0 / (1.0 - ag * ag));
+    A += sel[k] ? fabs(1.0 / (1.0 - ag * ag)) : 0.0;
   }
   return A;
 }
 
+// One wavefront per source: the lanes share the caustic points, a butterfly minimum
+// gives the distance, and lane 0 solves the quintic of a far source.
 __global__ __launch_bounds__(256) void k_fs_classify(FsArgs a) {
   const Lens L{a.m1, a.m2, a.x1, a.x2};
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < a.n;
+       i += waves) {
     const cd zs = {a.zeta[2 * i], a.zeta[2 * i + 1]};
     double dmin = __builtin_inf();
-    for (int32_t j = 0; j < a.n_crit; ++j) {
+    for (int32_t j = lane; j < a.n_crit; j += kWave) {
       const double d = cabs(csub(cd{a.caus[2 * j], a.caus[2 * j + 1]}, zs));
       if (d < dmin) dmin = d;  // NaN points (a massless companion) never win
     }
-    if (dmin > a.near * a.rho) {
-      a.A[i] = point_source_A(L, zs);
-      a.nreg[i] = -1;
-    } else {
-      a.nreg[i] = 0;
-      const uint32_t slot = atomicAdd(a.near_count, 1u);
-      a.near_list[slot] = (int32_t)i;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) dmin = fmin(dmin, __shfl_xor(dmin, off));
+    if (lane == 0) {
+      if (dmin > a.near * a.rho) {
+        a.A[i] = point_source_A(L, zs);
+        a.nreg[i] = -1;
+      } else {
+        a.nreg[i] = 0;
+        const uint32_t slot = atomicAdd(a.near_count, 1u);
+        a.near_list[slot] = (int32_t)i;
+      }
     }
   }
 }
@@ -355,15 +366,18 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_images(FsArgs a) {
         sincos(two_pi * ((j - 1) + 0.5) / a.n_b, &sn, &cs);
         p = {zs.x + a.rho * cs, zs.y + a.rho * sn};
       }
-      cd img[5];
-      const int n = images_of(L, p, img);
-      for (int k = 0; k < n; ++k) {
-        const int slot = atomicAdd(&sh.n_seed, 1);
-        if (slot < kSeedCap) {
-          sh.r[slot] = cabs(img[k]);
-          sh.th[slot] = atan2(img[k].y, img[k].x);
+      cd z[5];
+      bool sel[5];
+      images_of(L, p, z, sel);
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        if (sel[k]) {
+          const int slot = atomicAdd(&sh.n_seed, 1);
+          if (slot < kSeedCap) {
+            sh.r[slot] = cabs(z[k]);
+            sh.th[slot] = atan2(z[k].y, z[k].x);
+          }
         }
-      }
     }
     // at most kCritSeeds of them: those of every m-th phase, m the smallest stride
     // >= ceil(count / kCritSeeds) that keeps at most kCritSeeds
@@ -617,7 +631,7 @@ hipError_t launch_traj_positions(const double* t, int64_t n, double t0, double u
 hipError_t launch_fs_classify(const FsArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32_fs, dim3(1), dim3(64), 0, st, a.near_count);
-  int64_t blocks = (a.n + 255) / 256;
+  int64_t blocks = (a.n + 3) / 4;  // four sources (wavefronts) per workgroup
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fs_classify, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -52,6 +52,9 @@ struct morse_ctx {
   MetaBuf stack_taps, fft_tw, fft_spec;
   // the packed-map descriptor of the line filter
   MetaBuf lmeta;
+  // critical points and their caustic images of the last finite-source call (key: s, q,
+  // phases)
+  MetaBuf fs_crit;
   // split of the last stack call's radii (key of its arguments): direct radii with
   // their tap counts (taps in stack_taps, in this order), FFT radii, widest FFT stencil
   struct StackSplit {
