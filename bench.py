@@ -153,6 +153,18 @@ def summarize_pmc(paths):
     print("|---|---|---|---|---|---|")
     for (k, cn), v in sorted(acc.items()):
         print(f"| {k} | {cn} | {len(v)} | {sum(v) / len(v):.6g} | {min(v):.6g} | {max(v):.6g} |")
+    # the same kernel also runs on sub-problems (the autotuner's, a warm-up's); the
+    # dispatches within a factor 4 of the largest are the full-size launches
+    print()
+    print("Full-size dispatches (counter value at least a quarter of the kernel's largest):")
+    print()
+    print("| kernel | counter | dispatches | mean per dispatch | min | max |")
+    print("|---|---|---|---|---|---|")
+    for (k, cn), v in sorted(acc.items()):
+        big = [x for x in v if x >= 0.25 * max(v)]
+        if len(big) < len(v):
+            print(f"| {k} | {cn} | {len(big)} | {sum(big) / len(big):.6g} | {min(big):.6g} | "
+                  f"{max(big):.6g} |")
 
 
 def copy_kernel(nbytes):

@@ -442,7 +442,11 @@ int morse_trajectory_positions(morse_ctx* ctx, const double* h_params, const dou
  * Gradient by the envelope theorem (F_s, F_b are exact minimisers):
  * -2 F_s sum w r dA/dtheta, r = F - F_s A - F_b, through the bilinear sample (or the
  * single-lens magnification off the map).  Samples as in morse_search; sums FP64.
- * Outputs (device, nullable): d_chi2 [n], d_grad [n][4], d_fs [n], d_fb [n]. */
+ * Outputs (device, nullable): d_chi2 [n], d_grad [n][4], d_fs [n], d_fb [n].
+ * Candidates are evaluated grouped by (map, event) (a device counting sort; by map
+ * alone past 2^20 pairs), so that the GPU samples one map at a time; the order changes
+ * the schedule only, never a result.  Workspace: 44 B per candidate + 4 B per
+ * (map, event) pair. */
 int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                     const morse_lightcurves* lcs, int64_t n, const double* d_params,
                     const int32_t* d_event, const int32_t* d_map_index, double* d_chi2,
@@ -453,8 +457,8 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
  * kernels and results, with no hipMalloc, hipFree or allocating library call; the
  * context must already exist.  Its scratch (event offsets, reference times and map
  * table, the light-curve preparation, candidate constants and the packed cells of every
- * map: 24 B per event + 8 B per point + 40 B per candidate + 16 B per map cell, each
- * part rounded up to 256 B, plus the table) lives in one static device array of
+ * map: 24 B per event + 8 B per point + 44 B per candidate + 4 B per (map, event)
+ * pair + 16 B per map cell, each part rounded up to 256 B, plus the table) lives in one static device array of
  * 128 MiB on each GPU the library runs on, held until the process ends.  Every call on
  * a GPU shares that GPU's array and leaves its contents there, so calls that overlap on
  * one GPU (other streams or contexts) race; calls on one stream are ordered.  The host
@@ -490,7 +494,8 @@ typedef struct {
  * Candidates are independent: with 1024 or more, the two halves run as two chains of
  * launches, one on the context's stream and one on a second stream of the context that
  * starts after the work already enqueued and that the context's stream waits for at
- * the end (results identical to one chain). */
+ * the end (results identical to one chain).  Each chain evaluates its candidates
+ * grouped by (map, event), as morse_chi2_grad. */
 int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                  const morse_lightcurves* lcs, int64_t n, double* d_params,
                  const int32_t* d_event, const int32_t* d_map_index,

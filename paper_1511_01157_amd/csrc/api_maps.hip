@@ -271,11 +271,13 @@ int morse_normalize_convolve(morse_ctx* ctx, const uint32_t* d_counts, const mor
     ctx->taps_key = key.h;
     ctx->taps_n = (int32_t)w.size();
     ctx->taps_wbytes = w_bytes;
+    tap_reach(off, ctx->taps_rx, ctx->taps_ry);
   }
   const float* d_w = (const float*)ctx->taps;
   const int32_t* d_off = (const int32_t*)(ctx->taps + ctx->taps_wbytes);
   HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_map, window->nx, window->ny, d_w, d_off,
-                                         ctx->taps_n, scale, nullptr, ctx->stream));
+                                         ctx->taps_n, ctx->taps_rx, ctx->taps_ry, scale, nullptr,
+                                         ctx->stream));
   return MORSE_OK;
 }
 
@@ -348,6 +350,7 @@ int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_g
     sp.direct_k.clear();
     sp.fft_k.clear();
     sp.ntaps.clear();
+    sp.reach.clear();
     sp.rmx = sp.rmy = 0;
     std::vector<float> w32;
     std::vector<int32_t> off;
@@ -363,6 +366,10 @@ int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_g
       if (direct) {
         sp.direct_k.push_back(k);
         sp.ntaps.push_back((int32_t)wk.size());
+        int32_t rx, ry;
+        tap_reach(ok, rx, ry);
+        sp.reach.push_back(rx);
+        sp.reach.push_back(ry);
         w32.insert(w32.end(), wk.begin(), wk.end());
         off.insert(off.end(), ok.begin(), ok.end());
       } else {
@@ -400,7 +407,8 @@ int morse_convolve_stack(morse_ctx* ctx, const uint32_t* d_counts, const morse_g
       const float* d_w = (const float*)(ctx->stack_taps.p) + at;
       const int32_t* d_off = (const int32_t*)(ctx->stack_taps.p + w_bytes) + 2 * at;
       HIP_TRY(ctx, launch_normalize_convolve(d_counts, d_maps + (size_t)direct_k[u] * npx, mx, my, d_w,
-                                             d_off, sp.ntaps[u], scale, nullptr, ctx->stream));
+                                             d_off, sp.ntaps[u], sp.reach[2 * u], sp.reach[2 * u + 1],
+                                             scale, nullptr, ctx->stream));
       at += (size_t)sp.ntaps[u];
     }
   }
@@ -536,8 +544,10 @@ int morse_build_map(morse_ctx* ctx, double s, double q, const morse_grid2d* rays
   if ((rc = morse_rayshoot(ctx, s, q, rays, window, 0, rays->ny, counts, 0, stats))) return rc;
   const double hx = (double)(float)(rays->wx / rays->nx), hy = (double)(float)(rays->wy / rays->ny);
   const float scale = (float)(hx * hy / (dx * dy));
+  int32_t rx, ry;
+  tap_reach(off, rx, ry);
   HIP_TRY(ctx, launch_normalize_convolve(counts, d_map, window->nx, window->ny, d_w, d_off,
-                                         (int32_t)w.size(), scale, maxc, ctx->stream));
+                                         (int32_t)w.size(), rx, ry, scale, maxc, ctx->stream));
   // the small host vectors must outlive their (possibly staged) copies
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   if (h_stats) {

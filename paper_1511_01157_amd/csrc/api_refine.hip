@@ -150,6 +150,7 @@ GradArgs part_args(const GradArgs& a, int64_t c0, int64_t n) {
   if (a.grad) r.grad = a.grad + 4 * c0;
   if (a.fs) r.fs = a.fs + c0;
   if (a.fb) r.fb = a.fb + c0;
+  if (a.order) r.order = a.order + c0;  // each part's order holds its own local indices
   return r;
 }
 
@@ -214,11 +215,14 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if (n > 0 && (!d_params || !d_event || !d_map_index))
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n);
+  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n),
+               i_order = pl.add(4 * (size_t)n),
+               i_hist = pl.add(4 * (size_t)order_bins(n_maps, lcs->n_events));
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
   a.tEv = (double*)pl.ptr(ctx, i_tE);
+  a.order = (const int32_t*)pl.ptr(ctx, i_order);
   MapC* d_maps;
   if ((rc = setup_candidates(ctx, maps, n_maps, lcs, pl, i_sums, i_wF, i_quad, a.lc, d_maps))) return rc;
   a.n = n;
@@ -232,6 +236,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.grad = d_grad;
   a.fs = d_fs;
   a.fb = d_fb;
+  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr(ctx, i_hist), (int32_t*)a.order, ctx->stream));
   HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
   LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
   HIP_TRY(ctx, tm.begin(ctx->stream));
@@ -255,7 +260,8 @@ int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t 
   const size_t b_off = (8 * (size_t)(ne + 1) + 255) & ~size_t(255);
   const size_t b_tref = (8 * (size_t)ne + 255) & ~size_t(255);
   const size_t i_meta = pl.add(b_off + b_tref + sizeof(MapC) * n_maps);
-  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n);
+  const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n),
+               i_order = pl.add(4 * (size_t)n), i_hist = pl.add(4 * (size_t)order_bins(n_maps, ne));
   if (pl.total() > kNoallocScratchBytes)
     return fail(ctx, MORSE_ERANGE,
                 "needs %.1f MiB of scratch; the allocation-free entry point holds %zu MiB "
@@ -287,6 +293,7 @@ int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t 
                               (double*)a.lc.sums, ctx->stream));
   a.tc = (TrajC*)pl.ptr_at(base, i_tc);
   a.tEv = (double*)pl.ptr_at(base, i_tE);
+  a.order = (const int32_t*)pl.ptr_at(base, i_order);
   a.n = n;
   a.params = d_params;
   a.event = d_event;
@@ -298,6 +305,7 @@ int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t 
   a.grad = d_grad;
   a.fs = d_fs;
   a.fb = d_fb;
+  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr_at(base, i_hist), (int32_t*)a.order, ctx->stream));
   HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
   HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
   return MORSE_OK;
@@ -326,7 +334,9 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
                i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(12 * n), i_ft = pl.add(8 * n),
                i_gt = pl.add(32 * n), i_tc = pl.add(sizeof(TrajC) * (size_t)n),
-               i_tE = pl.add(8 * (size_t)n);
+               i_tE = pl.add(8 * (size_t)n), i_order = pl.add(4 * (size_t)n);
+  const int64_t nbins = order_bins(n_maps, lcs->n_events);
+  const size_t i_hist0 = pl.add(4 * (size_t)nbins), i_hist1 = pl.add(4 * (size_t)nbins);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
   a.tc = (TrajC*)pl.ptr(ctx, i_tc);
@@ -367,9 +377,11 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   double* gt = (double*)pl.ptr(ctx, i_gt);
   a.chi2 = ft;
   a.grad = gt;
-  // The rounds are captured once per argument set and replayed: start (anchor copy,
-  // state reset, first-trial constants), steps + 1 rounds of (evaluation, update with
-  // the next trial's constants), write-back.
+  a.order = (const int32_t*)pl.ptr(ctx, i_order);
+  uint32_t* hist[2] = {(uint32_t*)pl.ptr(ctx, i_hist0), (uint32_t*)pl.ptr(ctx, i_hist1)};
+  // The rounds are captured once per argument set and replayed: start (evaluation
+  // order grouped by map, anchor copy, state reset, first-trial constants), steps + 1
+  // rounds of (evaluation, update with the next trial's constants), write-back.
   Hasher h;
   h.pod(ctx->ws_epoch);
   h.pod(n);
@@ -403,8 +415,11 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
       ap[k] = part_args(a, c0[k], nc[k]);
     }
     hipError_t e = hipSuccess;
-    for (int k = 0; k < parts && e == hipSuccess; ++k)
-      e = launch_refine_init(sp[k], ap[k], d_params + 4 * c0[k], anchor + 4 * c0[k], cs[k]);
+    for (int k = 0; k < parts && e == hipSuccess; ++k) {
+      e = launch_cand_order(ap[k], hist[k], const_cast<int32_t*>(ap[k].order), cs[k]);
+      if (e == hipSuccess)
+        e = launch_refine_init(sp[k], ap[k], d_params + 4 * c0[k], anchor + 4 * c0[k], cs[k]);
+    }
     for (int r = 0; r <= opts->steps && e == hipSuccess; ++r) {
       for (int k = 0; k < parts && e == hipSuccess; ++k) {
         LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -61,6 +62,7 @@ struct morse_ctx {
     uint64_t key = 0;
     std::vector<int> direct_k, fft_k;
     std::vector<int32_t> ntaps;
+    std::vector<int32_t> reach;  // per direct radius: the largest |offset| along x, then y
     size_t w_bytes = 0;  // the tap offsets follow the weights at this byte offset
     int rmx = 0, rmy = 0;
   } stack_split;
@@ -80,6 +82,7 @@ struct morse_ctx {
   size_t taps_size = 0;
   uint64_t taps_key = 0;
   int32_t taps_n = 0;
+  int32_t taps_rx = 0, taps_ry = 0;  // the largest |offset| of the taps along x and y
   size_t taps_wbytes = 0;
   // kernel timing: enabled families, pending event pairs, free events, totals
   uint32_t timing_mask = 0;
@@ -244,6 +247,15 @@ inline int reserve_aux(morse_ctx* ctx, size_t bytes) {
   }
   ctx->aux_size = want;
   return MORSE_OK;
+}
+
+// The largest |offset| along x and along y of a tap table (pairs dx, dy).
+inline void tap_reach(const std::vector<int32_t>& off, int32_t& rx, int32_t& ry) {
+  rx = ry = 0;
+  for (size_t k = 0; k + 1 < off.size(); k += 2) {
+    rx = std::max(rx, std::abs(off[k]));
+    ry = std::max(ry, std::abs(off[k + 1]));
+  }
 }
 
 // Grows a metadata buffer to at least `bytes` (its contents are then invalid).

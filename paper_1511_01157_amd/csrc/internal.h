@@ -363,9 +363,13 @@ hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st);
 hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long long* stats,
                            hipStream_t st);
+// Normalisation + convolution of a counts map with ntaps taps whose offsets reach at
+// most rx columns and ry rows from the pixel (rx = ry = 0: the single tap (0, 0);
+// otherwise at most 16 each).
 hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
                                      const float* d_w, const int32_t* d_off, int32_t ntaps,
-                                     float scale, uint32_t* d_maxc, hipStream_t st);
+                                     int32_t rx, int32_t ry, float scale, uint32_t* d_maxc,
+                                     hipStream_t st);
 hipError_t launch_lc_prep(const float* t, const double* F, const double* w, const int64_t* off,
                           int32_t n_events, double* wF, double* sums, hipStream_t st);
 hipError_t launch_traj_prep_list(const double* params, int64_t n, TrajC* out, hipStream_t st);
@@ -439,11 +443,22 @@ struct GradArgs {
   double* grad;             // [n][4] or nullptr
   double* fs;
   double* fb;
+  const int32_t* order;     // [n] the order in which candidates are evaluated, or nullptr
 };
 // Per-candidate constants (FP64 natural parameters -> binary32 TrajC), then the
 // evaluation kernel.
 hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st);
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st);
+// Evaluation order of candidates [0, a.n): grouped by (map, event) (by map alone when
+// n_maps x n_events exceeds kOrderBinsMax), so that candidates evaluated at the same
+// time sample the same map.  Within a group the order is unspecified: it changes only
+// the schedule, never a result.  hist: workspace of order_bins(a) counters.
+constexpr int64_t kOrderBinsMax = 1 << 20;
+inline int64_t order_bins(int32_t n_maps, int32_t n_events) {
+  const int64_t both = (int64_t)n_maps * n_events;
+  return both <= kOrderBinsMax ? both : n_maps;
+}
+hipError_t launch_cand_order(const GradArgs& a, uint32_t* hist, int32_t* order, hipStream_t st);
 
 struct LbfgsState {
   int64_t n;

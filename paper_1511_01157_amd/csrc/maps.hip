@@ -245,47 +245,93 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
   }
 }
 
-// Normalise + convolve: one thread per output pixel, 16 x 16 pixel blocks; taps
-// (row-major over the stencil, zero taps dropped on the host) come from a small
-// device table; neighbours clamp to the edge.  acc accumulates left to right in
-// binary32 and A = acc * scale.  Also reduces the largest count of the map.
-__global__ __launch_bounds__(256) void k_normalize_convolve(const uint32_t* __restrict__ counts,
-                                                            float* __restrict__ map, int32_t mx,
-                                                            int32_t my, const float* __restrict__ w,
-                                                            const int32_t* __restrict__ off,
-                                                            int32_t ntaps, float scale,
-                                                            uint32_t* __restrict__ maxc) {
+// Normalise + convolve.  Taps are row-major over the stencil with the zero taps dropped
+// on the host; neighbours clamp to the edge; acc accumulates the terms w[k] * count in
+// tap order in binary32 (the first term alone, then one addition per tap) and
+// A = acc * scale.  The kernels also reduce the largest count of the map (one atomic
+// per workgroup).  Two forms of the same arithmetic:
+//   * one tap at offset (0, 0) (a point source): elementwise, four pixels per thread
+//     with 16-byte loads and stores;
+//   * a stencil of half-width at most kNcHalo: the workgroup stages its 64 x 32 output
+//     tile plus halo in LDS (sized to the stencil, so small stencils keep many
+//     workgroups per CU) (counts converted to binary32 there; the conversion is the
+//     one every term applies), then each wave sweeps whole 64-pixel rows, so LDS reads
+//     are consecutive and stores 256 B per row.  The tap builders cap the half-width
+//     at 15 pixels.
+constexpr int kNcTw = 64, kNcTh = 32, kNcHalo = 16;
+
+__device__ __forceinline__ void nc_block_max(uint32_t cmax, uint32_t* maxc) {
   __shared__ uint32_t s_max[4];
-  const int i = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
-  uint32_t cmax = 0;
-  if (i < mx && j < my) {
-    const uint32_t c0 = counts[(size_t)j * mx + i];
-    cmax = c0;
-    float acc;
-    if (ntaps == 1) {
-      acc = w[0] * (float)c0;
-    } else {
-      acc = 0.0f;
-      for (int k = 0; k < ntaps; ++k) {
-        int ii = i + off[2 * k];
-        int jj = j + off[2 * k + 1];
-        ii = min(max(ii, 0), mx - 1);
-        jj = min(max(jj, 0), my - 1);
-        const float term = w[k] * (float)counts[(size_t)jj * mx + ii];
-        acc = (k == 0) ? term : acc + term;
-      }
-    }
-    map[(size_t)j * mx + i] = acc * scale;
-  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, kWave));
   if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = cmax;
   __syncthreads();
-  if (threadIdx.x == 0 && maxc) {
-    cmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
-    atomicMax(maxc, cmax);
+  if (threadIdx.x == 0 && maxc) atomicMax(maxc, max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3])));
+}
+
+__global__ __launch_bounds__(256) void k_normalize_point(const uint32_t* __restrict__ counts,
+                                                         float* __restrict__ map, int64_t npx,
+                                                         bool vec4, const float* __restrict__ w,
+                                                         float scale, uint32_t* __restrict__ maxc) {
+  const float w0 = w[0];
+  uint32_t cmax = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (vec4) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(counts);
+    float4* m4 = reinterpret_cast<float4*>(map);
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < npx / 4; v += stride) {
+      const uint4 c = c4[v];
+      cmax = max(max(cmax, max(c.x, c.y)), max(c.z, c.w));
+      m4[v] = make_float4((w0 * (float)c.x) * scale, (w0 * (float)c.y) * scale,
+                          (w0 * (float)c.z) * scale, (w0 * (float)c.w) * scale);
+    }
+  } else {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < npx; v += stride) {
+      const uint32_t c = counts[v];
+      cmax = max(cmax, c);
+      map[v] = (w0 * (float)c) * scale;
+    }
   }
+  nc_block_max(cmax, maxc);
+}
+
+__global__ __launch_bounds__(256) void k_normalize_convolve_lds(
+    const uint32_t* __restrict__ counts, float* __restrict__ map, int32_t mx, int32_t my,
+    const float* __restrict__ w, const int32_t* __restrict__ off, int32_t ntaps, int32_t rx,
+    int32_t ry, float scale, uint32_t* __restrict__ maxc) {
+  extern __shared__ float tile[];  // (kNcTw + 2 rx) x (kNcTh + 2 ry)
+  const int x0 = blockIdx.x * kNcTw, y0 = blockIdx.y * kNcTh;
+  const int lw = kNcTw + 2 * rx, lh = kNcTh + 2 * ry;
+  uint32_t cmax = 0;
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < lw * lh; idx += 256) {
+    const int ly = idx / lw, lx = idx - ly * lw;
+    const int gx = x0 - rx + lx, gy = y0 - ry + ly;
+    const uint32_t c = counts[(size_t)min(max(gy, 0), my - 1) * mx + min(max(gx, 0), mx - 1)];
+    tile[idx] = (float)c;
+    const bool own = lx >= rx && lx < rx + kNcTw && ly >= ry && ly < ry + kNcTh && gx < mx && gy < my;
+    if (own) cmax = max(cmax, c);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, row0 = threadIdx.x >> 6;
+  constexpr int kRows = kNcTh / 4;
+  float acc[kRows];
+  for (int k = 0; k < ntaps; ++k) {
+    const float wk = w[k];
+    const int base = (row0 + ry + off[2 * k + 1]) * lw + tx + rx + off[2 * k];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const float term = wk * tile[base + 4 * r * lw];
+      acc[r] = (k == 0) ? term : acc[r] + term;
+    }
+  }
+  const int gx = x0 + tx;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int gy = y0 + row0 + 4 * r;
+    if (gx < mx && gy < my) map[(size_t)gy * mx + gx] = acc[r] * scale;
+  }
+  nc_block_max(cmax, maxc);
 }
 
 }  // namespace
@@ -352,10 +398,24 @@ hipError_t launch_rayshoot(const RayParams& p, uint32_t* counts, unsigned long l
 
 hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t mx, int32_t my,
                                      const float* d_w, const int32_t* d_off, int32_t ntaps,
-                                     float scale, uint32_t* d_maxc, hipStream_t st) {
-  dim3 grid((mx + 15) / 16, (my + 15) / 16);
-  hipLaunchKernelGGL(k_normalize_convolve, grid, dim3(256), 0, st, counts, map, mx, my, d_w, d_off,
-                     ntaps, scale, d_maxc);
+                                     int32_t rx, int32_t ry, float scale, uint32_t* d_maxc,
+                                     hipStream_t st) {
+  if (mx <= 0 || my <= 0 || ntaps < 1 || rx < 0 || ry < 0) return hipErrorInvalidValue;
+  if (rx == 0 && ry == 0) {
+    if (ntaps != 1) return hipErrorInvalidValue;  // only the tap (0, 0) has no reach
+    const int64_t npx = (int64_t)mx * my;
+    const bool vec4 = npx % 4 == 0 && ((uintptr_t)counts % 16) == 0 && ((uintptr_t)map % 16) == 0;
+    int64_t blocks = ((vec4 ? npx / 4 : npx) + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_normalize_point, dim3((unsigned)blocks), dim3(256), 0, st, counts, map, npx,
+                       vec4, d_w, scale, d_maxc);
+  } else {
+    if (rx > kNcHalo || ry > kNcHalo) return hipErrorInvalidValue;
+    dim3 grid((mx + kNcTw - 1) / kNcTw, (my + kNcTh - 1) / kNcTh);
+    const size_t lds = sizeof(float) * (kNcTw + 2 * rx) * (kNcTh + 2 * ry);
+    hipLaunchKernelGGL(k_normalize_convolve_lds, grid, dim3(256), lds, st, counts, map, mx, my, d_w,
+                       d_off, ntaps, rx, ry, scale, d_maxc);
+  }
   return hipGetLastError();
 }
 

@@ -290,15 +290,18 @@ __global__ void k_cand_prep(GradArgs a) {
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn (the grid is a multiple of 8), so
-// slot s runs on XCD s % 8; that XCD takes the contiguous candidate range
-// [x per, (x + 1) per) and neighbouring candidates (similar trajectories after a
-// ranked selection) share its L2.
+// slot s runs on XCD s % 8.  With an evaluation order grouped by map, slot s takes the
+// s-th candidate of that order: the XCDs work through the same map at the same time
+// and share it in the last-level cache.  Without one, XCD x takes the contiguous
+// candidate range [x per, (x + 1) per), so that neighbouring candidates (similar
+// trajectories after a ranked selection) share its L2.
 __global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
   __shared__ double s_part[GRAD_THREADS / kWave][kSums];
   const int64_t per = (a.n + 7) / 8;
   for (int64_t slot = blockIdx.x; slot < 8 * per; slot += gridDim.x) {
-    const int64_t c = (slot % 8) * per + slot / 8;
-    if (c >= a.n) continue;
+    const int64_t pos = a.order ? slot : (slot % 8) * per + slot / 8;
+    if (pos >= a.n) continue;
+    const int64_t c = a.order ? (int64_t)uniform(a.order[pos]) : pos;
     if (a.active && !a.active[c]) continue;  // uniform per workgroup
     const Eval ev = grad_eval(a, c, s_part);
     if (threadIdx.x == 0) {
@@ -543,6 +546,64 @@ __global__ void k_lbfgs_finish(LbfgsState s, double* params, double* chi2_out) {
 hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cand_prep, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Counting sort of the candidates by map (and event): per-bin counts, one workgroup's
+// exclusive scan of them, then an atomic scatter.
+__device__ __forceinline__ uint32_t order_key(const GradArgs& a, int64_t c, bool by_event) {
+  const int32_t e = a.event[c], m = a.mapidx[c];
+  if (e < 0 || e >= a.n_events || m < 0 || m >= a.n_maps) return 0u;  // NaN outputs anyway
+  return by_event ? (uint32_t)m * (uint32_t)a.n_events + (uint32_t)e : (uint32_t)m;
+}
+
+__global__ void k_order_count(GradArgs a, bool by_event, uint32_t* hist) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[order_key(a, c, by_event)], 1u);
+}
+
+__global__ __launch_bounds__(1024) void k_order_scan(uint32_t* hist, int64_t nb) {
+  __shared__ uint32_t part[1024];
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  uint32_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += hist[b];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t h = hist[b];
+    hist[b] = run;
+    run += h;
+  }
+}
+
+__global__ void k_order_scatter(GradArgs a, bool by_event, uint32_t* cursor, int32_t* order) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.n;
+       c += (int64_t)gridDim.x * blockDim.x)
+    order[atomicAdd(&cursor[order_key(a, c, by_event)], 1u)] = (int32_t)c;
+}
+
+hipError_t launch_cand_order(const GradArgs& a, uint32_t* hist, int32_t* order, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.n > INT32_MAX || a.n_maps <= 0 || a.n_events <= 0) return hipErrorInvalidValue;
+  const int64_t nb = order_bins(a.n_maps, a.n_events);
+  const bool by_event = nb == (int64_t)a.n_maps * a.n_events;
+  hipError_t e = launch_fill_u32(hist, (size_t)nb, 0u, st);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (a.n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_order_count, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, nb);
+  hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist,
+                     order);
   return hipGetLastError();
 }
 

@@ -124,6 +124,36 @@ def test_normalize_convolve_vs_mirror(rho):
     assert np.max(np.abs(A - ref32)) <= 2e-7 * max(1.0, float(ref32.max()))
 
 
+@pytest.mark.parametrize("window,rho,shift", [
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.0, 0),     # 16-byte loads and stores
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.0, 1),     # buffers 4 B off 16: the scalar path
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.02, 0),    # ragged 64 x 32 tiles, a 3-pixel stencil
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.0862, 1),  # the widest stencil (15 pixels)
+    ((0.0, 0.0, 0.2, 2.0, 8, 70), 0.05, 0)])        # narrower than one tile, halo beyond both edges
+def test_build_map_ragged_tiles_bit_exact(window, rho, shift):
+    """Maps whose sides are not multiples of the 64 x 32 output tile, and buffers not
+    16-byte aligned: every pixel, the clamped halo and the largest count against the
+    binary32 mirror."""
+    s, q, rays = 1.0, 1e-3, (0.0, 0.0, 4.0, 4.0, 1600, 1600)
+    note(f"build_map ragged window={window} rho={rho} shift={shift}")
+    o, _ = rayshoot_mirror32_c(s, q, rays, window, nthreads=8)
+    npx = window[4] * window[5]
+    cbuf = torch.empty(npx + 4, dtype=torch.int32, device=DEV)
+    abuf = torch.empty(npx + 4, dtype=torch.float32, device=DEV)
+    cnt = cbuf[shift:shift + npx].view(window[5], window[4])
+    out = abuf[shift:shift + npx].view(window[5], window[4])
+    A, st = M.build_map(s, q, rays, window, rho, device=DEV, out=out, counts=cnt, stats=True)
+    assert np.array_equal(cnt.cpu().numpy().view(np.uint32), o)
+    assert st["max_count"] == int(o.max())
+    w = disk_pixel_weights(rho, window[2] / window[4], window[3] / window[5])
+    assert max(w.shape) <= 31
+    ref32 = normalize_convolve_mirror32(o, map_scale(rays, window), w)
+    A = A.cpu().numpy()
+    assert np.max(np.abs(A - ref32)) <= 2e-7 * max(1.0, float(ref32.max()))
+    B = M.normalize_convolve(cnt, rays, window, rho).cpu().numpy()
+    assert np.array_equal(A, B)
+
+
 def test_build_map_rejects_bad_arguments():
     note("build_map argument errors")
     with pytest.raises(M.MorseError) as e:

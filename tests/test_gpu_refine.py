@@ -105,6 +105,49 @@ def test_multi_event_multi_map_gradients():
         assert grad_ok(g[k:k + 1], og).all(), k
 
 
+def _grad_in_order(maps, lcs, P, ev_idx, mi, perm):
+    """chi2_grad of the candidates taken in the order perm, returned in input order."""
+    chi2, g, fs, fb = M.chi2_grad(maps, lcs, torch.from_numpy(P[perm]).to(DEV),
+                                  torch.from_numpy(ev_idx[perm]).to(DEV),
+                                  torch.from_numpy(mi[perm]).to(DEV))
+    out = np.empty((len(perm), 7))
+    out[perm] = np.concatenate([chi2.cpu().numpy()[:, None], g.cpu().numpy(),
+                                fs.cpu().numpy()[:, None], fb.cpu().numpy()[:, None]], 1)
+    return out
+
+
+@pytest.mark.parametrize("n_maps,n_events", [(2, 3), (1040, 1010)])
+def test_chi2_grad_independent_of_candidate_order(n_maps, n_events):
+    """The library evaluates candidates grouped by (map, event) (by map alone past 2^20
+    pairs, the second case); the order is a schedule only: permuted inputs give the
+    same bits, and out-of-range indices still give NaN."""
+    win = (0.0, 0.0, 1.6, 1.6, 64, 64) if n_maps > 2 else (0.0, 0.0, 1.6, 1.6, 256, 256)
+    rays = (0.0, 0.0, 4.0, 4.0, 8 * win[4], 8 * win[5])
+    built = [M.build_map(s, q, rays, win, 0.0, device=DEV) for s, q in [(0.9, 0.02), (1.2, 3e-3)]]
+    maps = [(built[k % 2], win) for k in range(n_maps)]
+    src = [W.load_lightcurve("batched", e) for e in (3, 7, 11)]
+    if n_events == 3:
+        evs = src
+    else:  # short pieces of the three light curves
+        evs = [dict(tt=src[k % 3]["tt"][40 * (k // 3) % 400:][:12], F=src[k % 3]["F"][40 * (k // 3) % 400:][:12],
+                    w=src[k % 3]["w"][40 * (k // 3) % 400:][:12], t_ref=src[k % 3]["t_ref"])
+               for k in range(n_events)]
+    lcs = M.LightCurveBatch.from_events(evs, DEV)
+    rng = np.random.default_rng(5)
+    n = 600
+    ev_idx = rng.integers(0, n_events, n).astype(np.int32)
+    mi = rng.integers(0, n_maps, n).astype(np.int32)
+    ev_idx[7], mi[9], ev_idx[11], mi[11] = n_events, -1, -3, n_maps  # out of range
+    P = np.stack([candidates(1, 100 + k, src[ev_idx[k] % 3]["truth"])[0] for k in range(n)])
+    note(f"chi2_grad order invariance n_maps={n_maps} n_events={n_events}")
+    a = _grad_in_order(maps, lcs, P, ev_idx, mi, np.arange(n))
+    b = _grad_in_order(maps, lcs, P, ev_idx, mi, rng.permutation(n))
+    assert np.array_equal(a, b, equal_nan=True)
+    bad = np.zeros(n, bool)
+    bad[[7, 9, 11]] = True
+    assert np.isnan(a[bad]).all() and np.isfinite(a[~bad, 0]).all()
+
+
 def test_refine_vs_oracle_state_machine(tiny_oracle_map):
     c = W.config("tiny")
     amap = tiny_oracle_map[2]
