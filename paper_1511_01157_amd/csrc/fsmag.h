@@ -26,8 +26,9 @@ struct FsArgs {
 hipError_t launch_traj_positions(const double* t, int64_t n, double t0, double u0, double tE,
                                  double alpha, double* zeta, hipStream_t st);
 
-// Caustic distance and point-source magnification (one thread per source); the sources
-// within near * rho of the caustic are listed for the image-centred kernel.
+// Caustic distance (one wavefront per source), then the point-source magnification of
+// the far sources (one thread each); the sources within near * rho of the caustic are
+// listed for the image-centred kernel.
 hipError_t launch_fs_classify(const FsArgs& a, hipStream_t st);
 // Image-centred integration of every listed source (one workgroup per source).
 hipError_t launch_fs_images(const FsArgs& a, int32_t max_blocks, hipStream_t st);

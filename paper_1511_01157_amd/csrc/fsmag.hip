@@ -101,7 +101,9 @@ __device__ __forceinline__ void poly_eval(const cd (&a)[6], cd z, cd& p, cd& dp)
 }
 
 // Roots of the quintic: Aberth-Ehrlich from a circle (Cauchy bound) until the largest
-// relative step is below 1e-14, then two Newton steps per root.
+// relative step is below 1e-14 or, below 1e-9, stops halving (the rounding floor of
+// the polynomial's evaluation, which ill-conditioned roots never get under), then two
+// Newton steps per root.
 __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
   const cd inv5 = crecip(a[5]);
   double rad = 0.0;
@@ -112,6 +114,7 @@ __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
     sincos(0.4 + 2.0 * M_PI * k / 5.0, &sn, &cs);
     z[k] = {rad * cs, rad * sn};
   }
+  double prev = __builtin_inf();
   for (int it = 0; it < 200; ++it) {
     double moved = 0.0;
     for (int k = 0; k < 5; ++k) {
@@ -127,7 +130,8 @@ __device__ void quintic_roots(const cd (&a)[6], cd (&z)[5]) {
       z[k] = csub(z[k], step);
       moved = fmax(moved, cabs(step) / (1.0 + cabs(z[k])));
     }
-    if (moved < 1e-14) break;  // the Newton steps below finish to full precision
+    if (moved < 1e-14 || (moved < 1e-9 && moved >= 0.5 * prev)) break;
+    prev = moved;
   }
   for (int k = 0; k < 5; ++k)
     for (int it = 0; it < 2; ++it) {
@@ -181,10 +185,10 @@ __device__ double point_source_A(const Lens& L, cd zeta) {
   return A;
 }
 
-// One wavefront per source: the lanes share the caustic points, a butterfly minimum
-// gives the distance, and lane 0 solves the quintic of a far source.
+// One wavefront per source: the lanes share the caustic points and a butterfly minimum
+// gives the distance.  Far sources are marked for the point-source kernel, near ones
+// listed for the image-centred kernel.
 __global__ __launch_bounds__(256) void k_fs_classify(FsArgs a) {
-  const Lens L{a.m1, a.m2, a.x1, a.x2};
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; i < a.n;
@@ -199,7 +203,6 @@ __global__ __launch_bounds__(256) void k_fs_classify(FsArgs a) {
     for (int off = kWave / 2; off > 0; off >>= 1) dmin = fmin(dmin, __shfl_xor(dmin, off));
     if (lane == 0) {
       if (dmin > a.near * a.rho) {
-        a.A[i] = point_source_A(L, zs);
         a.nreg[i] = -1;
       } else {
         a.nreg[i] = 0;
@@ -208,6 +211,14 @@ __global__ __launch_bounds__(256) void k_fs_classify(FsArgs a) {
       }
     }
   }
+}
+
+// Point-source magnification of the sources marked far (one thread per source).
+__global__ __launch_bounds__(256) void k_fs_point(FsArgs a) {
+  const Lens L{a.m1, a.m2, a.x1, a.x2};
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= a.n || a.nreg[i] != -1) return;
+  a.A[i] = point_source_A(L, cd{a.zeta[2 * i], a.zeta[2 * i + 1]});
 }
 
 // ---------------------------------------------------------------------------------
@@ -634,6 +645,7 @@ hipError_t launch_fs_classify(const FsArgs& a, hipStream_t st) {
   int64_t blocks = (a.n + 3) / 4;  // four sources (wavefronts) per workgroup
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fs_classify, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_fs_point, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
