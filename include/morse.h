@@ -419,8 +419,11 @@ typedef struct {
  * d_A [n] (FP64), d_nreg [n] (int32, nullable): -1 point source, >= 1 regions, -2 more
  * than 2048 seeds, -3 more than 64 regions (A is NaN for -2 and -3).  All arithmetic
  * FP64.  The critical points stay resident in the context (32 B each) until a call needs
- * another (s, q, n_crit); workspace 8 B per source.  Errors: EINVAL (s, q, rho,
- * gamma outside their ranges, opts out of range, NULL arrays), ERANGE (n > 2^31). */
+ * another (s, q, n_crit); workspace 8 B per source plus 2.8 KiB per source for at most
+ * 4096 of them (11 MiB).  The call synchronises the context's stream once (it reads
+ * the number of sources near a caustic, which sizes the image-centred passes: at most
+ * 4096 sources each), so it cannot be captured into a graph.  Errors: EINVAL (s, q, rho, gamma
+ * outside their ranges, opts out of range, NULL arrays), ERANGE (n > 2^31). */
 int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_zeta, int64_t n,
                            double rho, double gamma, const morse_fs_opts* opts, double* d_A,
                            int32_t* d_nreg);

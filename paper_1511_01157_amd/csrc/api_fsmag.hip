@@ -59,8 +59,12 @@ int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_z
     ctx->fs_crit.key = key.h;
   }
   Plan pl;
+  const int64_t batch = std::min<int64_t>(n, kFsBatch);
   const size_t i_list = pl.add(4 * (size_t)n), i_cnt = pl.add(4),
-               i_nreg = pl.add(d_nreg ? 0 : 4 * (size_t)n);
+               i_nreg = pl.add(d_nreg ? 0 : 4 * (size_t)n),
+               i_regs = pl.add(32 * (size_t)batch * kFsRegionCap), i_rc = pl.add(4 * (size_t)batch),
+               i_rv = pl.add(8 * (size_t)batch * kFsRegionCap),
+               i_work = pl.add(4 * (size_t)batch * kFsRegionCap), i_wc = pl.add(4);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   FsArgs a;
   a.m1 = m1;
@@ -86,8 +90,21 @@ int morse_fs_magnification(morse_ctx* ctx, double s, double q, const double* d_z
   a.nreg = d_nreg ? d_nreg : (int32_t*)pl.ptr(ctx, i_nreg);
   a.near_list = (int32_t*)pl.ptr(ctx, i_list);
   a.near_count = (uint32_t*)pl.ptr(ctx, i_cnt);
+  a.regs = (double*)pl.ptr(ctx, i_regs);
+  a.reg_count = (int32_t*)pl.ptr(ctx, i_rc);
+  a.reg_val = (double*)pl.ptr(ctx, i_rv);
+  a.work = (uint32_t*)pl.ptr(ctx, i_work);
+  a.work_count = (uint32_t*)pl.ptr(ctx, i_wc);
   HIP_TRY(ctx, launch_fs_classify(a, ctx->stream));
-  HIP_TRY(ctx, launch_fs_images(a, 4 * ctx->num_cu, ctx->stream));
+  // the number of sources near a caustic sizes the image-centred passes
+  uint32_t n_near = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&n_near, a.near_count, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int64_t b0 = 0; b0 < (int64_t)n_near; b0 += kFsBatch) {
+    a.item0 = b0;
+    a.n_items = std::min<int64_t>(kFsBatch, (int64_t)n_near - b0);
+    HIP_TRY(ctx, launch_fs_images(a, 4 * ctx->num_cu, ctx->stream));
+  }
   return MORSE_OK;
 }
 

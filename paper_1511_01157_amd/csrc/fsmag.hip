@@ -2,19 +2,21 @@
 // McDougall & Albrow 2015: point source beyond 10 rho from the caustic, otherwise polar
 // grids grown around the source's images and integrated with the source profile).
 //
-// Kernel 1, one thread per source: the distance from the source centre to the nearest
-// caustic point; far sources take the point-source magnification of their images
-// (Eqs. 3-4), near ones are listed.  Kernel 2, one 256-lane workgroup per listed
-// source: every lane solves the lens equation for one of the centre and n_b boundary
-// points (the quintic of Eq. 2, FP64 Aberth-Ehrlich), the images and the critical
-// points whose caustic image lies inside the source become seeds in polar coordinates
-// about the centre of mass; the seeds are sorted in LDS (bitonic), cut into angular
-// runs at gaps wider than `gap` and each run at radial gaps; every region grows until
-// none of its sides maps inside the source (side samples spread over the lanes);
-// overlapping regions merge; each region is integrated column by column (one lane per
-// theta column, radial segments with the limb crossing linear in f = rho^2 - |zeta -
-// zeta_s|^2 and the square-root edge of the limb-darkened profile integrated exactly),
-// then cut to its inside cells and integrated again.  All arithmetic is FP64.
+// Classification, one wavefront per source: the distance from the source centre to the
+// nearest caustic point; far sources take the point-source magnification of their
+// images (Eqs. 3-4, one thread each), near ones are listed.  Regions, one 256-lane
+// workgroup per listed source: every lane solves the lens equation for one of the
+// centre and n_b boundary points (the quintic of Eq. 2, FP64 Aberth-Ehrlich), the
+// images and the critical points whose caustic image lies inside the source become
+// seeds in polar coordinates about the centre of mass; the seeds are sorted in LDS
+// (bitonic), cut into angular runs at gaps wider than `gap` and each run at radial
+// gaps; every region grows until none of its sides maps inside the source (side samples
+// spread over the lanes); overlapping regions merge.  Integration, one 512-lane
+// workgroup per (source, region): column by column (one lane per theta column, radial
+// segments with the limb crossing linear in f = rho^2 - |zeta - zeta_s|^2 and the
+// square-root edge of the limb-darkened profile integrated exactly), then the region
+// cut to its inside cells and integrated again; a last kernel adds each source's region
+// integrals in region order.  All arithmetic is FP64.
 
 #include "fsmag.h"
 
@@ -24,7 +26,7 @@ namespace {
 
 constexpr int kFsThreads = 256;
 constexpr int kSeedCap = 2048;   // seeds per source (a power of two for the sort)
-constexpr int kRegionCap = 64;
+constexpr int kRegionCap = kFsRegionCap;
 constexpr int kCritSeeds = 512;  // critical-point seeds at most
 
 __global__ void k_fill_u32_fs(uint32_t* p) {
@@ -287,22 +289,28 @@ struct Shared {
   double key[kSeedCap], r[kSeedCap], th[kSeedCap];
   int run[kSeedCap];
   Region reg[kRegionCap];
-  double red[kFsThreads];
   int ired[4][kFsThreads];
   int n_seed, n_reg, flag[4];
 };
 
 // Integral of the profile over one region and the bounds of its inside nodes (all
-// lanes; box = {k0, k1, j0, j1}, k1 < 0 when nothing is inside).
+// NT lanes of the workgroup; box = {k0, k1, j0, j1}, k1 < 0 when nothing is inside).
+template <int NT>
+struct IntShared {
+  double red[NT];
+  int ired[4][NT];
+};
+
+template <int NT>
 __device__ double integrate_region(const FsArgs& a, const Lens& L, cd zs, const Region& g,
-                                   Shared& sh, int (&box)[4]) {
+                                   IntShared<NT>& sh, int (&box)[4]) {
   const double rho2 = a.rho * a.rho;
   const double dth = (g.t1 - g.t0) / a.n_theta;
   const double dr = (g.r1 - g.r0) / a.n_r;
   const double c_ld = 1.5 * a.gamma / a.rho;
   double acc = 0.0;
   int k0 = 1 << 30, k1 = -1, j0 = 1 << 30, j1 = -1;
-  for (int j = threadIdx.x; j < a.n_theta; j += kFsThreads) {
+  for (int j = threadIdx.x; j < a.n_theta; j += NT) {
     double sn, cs;
     sincos(g.t0 + (j + 0.5) * dth, &sn, &cs);
     double col = 0.0, fa = 0.0, ra = 0.0;
@@ -341,7 +349,7 @@ __device__ double integrate_region(const FsArgs& a, const Lens& L, cd zs, const 
   sh.ired[2][threadIdx.x] = j0;
   sh.ired[3][threadIdx.x] = j1;
   __syncthreads();
-  for (int w = kFsThreads / 2; w > 0; w >>= 1) {  // fixed tree: the same sum every time
+  for (int w = NT / 2; w > 0; w >>= 1) {  // fixed tree: the same sum every time
     if ((int)threadIdx.x < w) {
       sh.red[threadIdx.x] += sh.red[threadIdx.x + w];
       sh.ired[0][threadIdx.x] = min(sh.ired[0][threadIdx.x], sh.ired[0][threadIdx.x + w]);
@@ -357,14 +365,13 @@ __device__ double integrate_region(const FsArgs& a, const Lens& L, cd zs, const 
   return total;
 }
 
-__global__ __launch_bounds__(kFsThreads) void k_fs_images(FsArgs a) {
+__global__ __launch_bounds__(kFsThreads) void k_fs_regions(FsArgs a) {
   __shared__ Shared sh;
   const Lens L{a.m1, a.m2, a.x1, a.x2};
   const int tid = threadIdx.x;
   const double two_pi = 2.0 * M_PI;
-  const int64_t n_near = (int64_t)*a.near_count;
-  for (int64_t item = blockIdx.x; item < n_near; item += gridDim.x) {
-    const int64_t i = a.near_list[item];
+  for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
+    const int64_t i = a.near_list[a.item0 + item];
     const cd zs = {a.zeta[2 * i], a.zeta[2 * i + 1]};
     if (tid == 0) sh.n_seed = 0;
     __syncthreads();
@@ -425,6 +432,7 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_images(FsArgs a) {
       if (tid == 0) {
         a.A[i] = __builtin_nan("");
         a.nreg[i] = -2;
+        a.reg_count[item] = 0;
       }
       __syncthreads();
       continue;
@@ -501,6 +509,7 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_images(FsArgs a) {
       if (tid == 0) {
         a.A[i] = __builtin_nan("");
         a.nreg[i] = -3;
+        a.reg_count[item] = 0;
       }
       __syncthreads();
       continue;
@@ -583,35 +592,70 @@ __global__ __launch_bounds__(kFsThreads) void k_fs_images(FsArgs a) {
       }
     }
     __syncthreads();
-    // 7. integrals, each region cut to its inside cells and integrated again
-    double total = 0.0;
+    // 7. the regions and their work items for the integration kernel
     const int n_reg = sh.n_reg;
-    for (int g = 0; g < n_reg; ++g) {
-      Region R = sh.reg[g];
-      int box[4];
-      double val = integrate_region(a, L, zs, R, sh, box);
-      for (int it = 0; it < a.n_shrink; ++it) {
-        if (box[1] < 0) break;
-        const double dr = (R.r1 - R.r0) / a.n_r;
-        const int n0 = max(box[0] - 1, 0), n1 = min(box[1] + 1, a.n_r);
-        Region N = {R.r0 + n0 * dr, R.r0 + n1 * dr, R.t0, R.t1};
-        if (!is_ring(R)) {
-          const double dth = (R.t1 - R.t0) / a.n_theta;
-          N.t0 = R.t0 + max(box[2] - 1, 0) * dth;
-          N.t1 = R.t0 + min(box[3] + 2, a.n_theta) * dth;
-        }
-        if (N.r0 == R.r0 && N.r1 == R.r1 && N.t0 == R.t0 && N.t1 == R.t1) break;
-        R = N;
-        val = integrate_region(a, L, zs, R, sh, box);
-      }
-      total += val;
+    if (tid < n_reg) {
+      const Region R = sh.reg[tid];
+      double* out = a.regs + 4 * (item * kFsRegionCap + tid);
+      out[0] = R.r0;
+      out[1] = R.r1;
+      out[2] = R.t0;
+      out[3] = R.t1;
     }
     if (tid == 0) {
-      a.A[i] = total / (M_PI * a.rho * a.rho);
-      a.nreg[i] = n_reg;
+      a.reg_count[item] = n_reg;
+      sh.flag[0] = (int)atomicAdd(a.work_count, (uint32_t)n_reg);
     }
     __syncthreads();
+    if (tid < n_reg) a.work[sh.flag[0] + tid] = (uint32_t)(item * kFsRegionCap + tid);
+    __syncthreads();
   }
+}
+
+// 8. One workgroup per (source, region): the region's integral, then up to n_shrink
+// times the region cut to its inside cells (plus one cell) and integrated again.
+constexpr int kIntThreads = 512;
+__global__ __launch_bounds__(kIntThreads) void k_fs_integrate(FsArgs a) {
+  __shared__ IntShared<kIntThreads> sh;
+  const Lens L{a.m1, a.m2, a.x1, a.x2};
+  const uint32_t n_work = *a.work_count;
+  for (uint32_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const uint32_t slot = a.work[w];
+    const int64_t i = a.near_list[a.item0 + slot / kFsRegionCap];
+    const cd zs = {a.zeta[2 * i], a.zeta[2 * i + 1]};
+    const double* rg = a.regs + 4 * (int64_t)slot;
+    Region R{rg[0], rg[1], rg[2], rg[3]};
+    int box[4];
+    double val = integrate_region<kIntThreads>(a, L, zs, R, sh, box);
+    for (int it = 0; it < a.n_shrink; ++it) {
+      if (box[1] < 0) break;
+      const double dr = (R.r1 - R.r0) / a.n_r;
+      const int n0 = max(box[0] - 1, 0), n1 = min(box[1] + 1, a.n_r);
+      Region N = {R.r0 + n0 * dr, R.r0 + n1 * dr, R.t0, R.t1};
+      if (!is_ring(R)) {
+        const double dth = (R.t1 - R.t0) / a.n_theta;
+        N.t0 = R.t0 + max(box[2] - 1, 0) * dth;
+        N.t1 = R.t0 + min(box[3] + 2, a.n_theta) * dth;
+      }
+      if (N.r0 == R.r0 && N.r1 == R.r1 && N.t0 == R.t0 && N.t1 == R.t1) break;
+      R = N;
+      val = integrate_region<kIntThreads>(a, L, zs, R, sh, box);
+    }
+    if (threadIdx.x == 0) a.reg_val[slot] = val;
+  }
+}
+
+// 9. Per source: the region integrals summed in region order (one thread per source).
+__global__ __launch_bounds__(256) void k_fs_finish(FsArgs a) {
+  const int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (item >= a.n_items) return;
+  const int32_t nr = a.reg_count[item];
+  if (nr <= 0) return;  // a seed or region failure, already written
+  const int64_t i = a.near_list[a.item0 + item];
+  double total = 0.0;
+  for (int g = 0; g < nr; ++g) total += a.reg_val[item * kFsRegionCap + g];
+  a.A[i] = total / (M_PI * a.rho * a.rho);
+  a.nreg[i] = nr;
 }
 
 // Source positions along a trajectory (FP64): tau = (t - t0)/tE,
@@ -650,11 +694,15 @@ hipError_t launch_fs_classify(const FsArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fs_images(const FsArgs& a, int32_t max_blocks, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
-  if (a.n_b < 1 || a.n_side < 2 || a.n_r < 1 || a.n_theta < 1 || a.n_grow < 0 || a.n_shrink < 0)
+  if (a.n_items <= 0) return hipSuccess;
+  if (a.n_b < 1 || a.n_side < 2 || a.n_r < 1 || a.n_theta < 1 || a.n_grow < 0 || a.n_shrink < 0 ||
+      a.n_items > kFsBatch)
     return hipErrorInvalidValue;
-  int64_t blocks = a.n < max_blocks ? a.n : max_blocks;
-  hipLaunchKernelGGL(k_fs_images, dim3((unsigned)blocks), dim3(kFsThreads), 0, st, a);
+  hipLaunchKernelGGL(k_fill_u32_fs, dim3(1), dim3(64), 0, st, a.work_count);
+  const int64_t blocks = a.n_items < max_blocks ? a.n_items : max_blocks;
+  hipLaunchKernelGGL(k_fs_regions, dim3((unsigned)blocks), dim3(kFsThreads), 0, st, a);
+  hipLaunchKernelGGL(k_fs_integrate, dim3((unsigned)max_blocks), dim3(kIntThreads), 0, st, a);
+  hipLaunchKernelGGL(k_fs_finish, dim3((unsigned)((a.n_items + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
