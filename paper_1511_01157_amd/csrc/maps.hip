@@ -252,12 +252,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
 // per workgroup).  Two forms of the same arithmetic:
 //   * one tap at offset (0, 0) (a point source): elementwise, four pixels per thread
 //     with 16-byte loads and stores;
-//   * a stencil of half-width at most kNcHalo: the workgroup stages its 64 x 32 output
-//     tile plus halo in LDS (sized to the stencil, so small stencils keep many
-//     workgroups per CU) (counts converted to binary32 there; the conversion is the
-//     one every term applies), then each wave sweeps whole 64-pixel rows, so LDS reads
-//     are consecutive and stores 256 B per row.  The tap builders cap the half-width
-//     at 15 pixels.
+//   * a stencil of half-width at most kNcHalo: a workgroup stages a 64 x 32 output tile
+//     plus halo in LDS (sized to the stencil; counts converted to binary32 there, the
+//     conversion every term applies), then each wave sweeps whole 64-pixel rows, so LDS
+//     reads are consecutive and stores 256 B per row; each wave issues all its staging
+//     loads (whole tile rows) before the first LDS store.  The tap builders cap the
+//     half-width at 15 pixels.
 constexpr int kNcTw = 64, kNcTh = 32, kNcHalo = 16;
 
 __device__ __forceinline__ void nc_block_max(uint32_t cmax, uint32_t* maxc) {
@@ -302,33 +302,53 @@ __global__ __launch_bounds__(256) void k_normalize_convolve_lds(
   extern __shared__ float tile[];  // (kNcTw + 2 rx) x (kNcTh + 2 ry)
   const int x0 = blockIdx.x * kNcTw, y0 = blockIdx.y * kNcTh;
   const int lw = kNcTw + 2 * rx, lh = kNcTh + 2 * ry;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // staging: wave w takes tile rows w, w + 4, ...; lane l the columns l and 64 + l; all
+  // loads are issued before the first LDS store
+  constexpr int kRowsPerWave = (kNcTh + 2 * kNcHalo + 3) / 4;
+  uint32_t va[kRowsPerWave], vb[kRowsPerWave];
+  const int gxa = min(max(x0 - rx + lane, 0), mx - 1), gxb = min(max(x0 - rx + 64 + lane, 0), mx - 1);
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int ly = wave + 4 * r;
+    va[r] = vb[r] = 0u;
+    if (ly < lh) {  // uniform per wave
+      const uint32_t* row = counts + (size_t)min(max(y0 - ry + ly, 0), my - 1) * mx;
+      va[r] = row[gxa];
+      if (lane < lw - 64) vb[r] = row[gxb];
+    }
+  }
   uint32_t cmax = 0;
-#pragma unroll 4
-  for (int idx = threadIdx.x; idx < lw * lh; idx += 256) {
-    const int ly = idx / lw, lx = idx - ly * lw;
-    const int gx = x0 - rx + lx, gy = y0 - ry + ly;
-    const uint32_t c = counts[(size_t)min(max(gy, 0), my - 1) * mx + min(max(gx, 0), mx - 1)];
-    tile[idx] = (float)c;
-    const bool own = lx >= rx && lx < rx + kNcTw && ly >= ry && ly < ry + kNcTh && gx < mx && gy < my;
-    if (own) cmax = max(cmax, c);
+  const bool own_a = lane >= rx && x0 - rx + lane < mx;  // own columns: [rx, rx + 64)
+  const bool own_b = lane < rx && x0 - rx + 64 + lane < mx;  // and [64, 64 + rx)
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int ly = wave + 4 * r;
+    if (ly < lh) {
+      tile[ly * lw + lane] = (float)va[r];
+      if (lane < lw - 64) tile[ly * lw + 64 + lane] = (float)vb[r];
+      if (ly >= ry && ly < ry + kNcTh && y0 - ry + ly < my) {
+        if (own_a) cmax = max(cmax, va[r]);
+        if (own_b) cmax = max(cmax, vb[r]);
+      }
+    }
   }
   __syncthreads();
-  const int tx = threadIdx.x & 63, row0 = threadIdx.x >> 6;
   constexpr int kRows = kNcTh / 4;
   float acc[kRows];
   for (int k = 0; k < ntaps; ++k) {
     const float wk = w[k];
-    const int base = (row0 + ry + off[2 * k + 1]) * lw + tx + rx + off[2 * k];
+    const int base = (wave + ry + off[2 * k + 1]) * lw + lane + rx + off[2 * k];
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       const float term = wk * tile[base + 4 * r * lw];
       acc[r] = (k == 0) ? term : acc[r] + term;
     }
   }
-  const int gx = x0 + tx;
+  const int gx = x0 + lane;
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
-    const int gy = y0 + row0 + 4 * r;
+    const int gy = y0 + wave + 4 * r;
     if (gx < mx && gy < my) map[(size_t)gy * mx + gx] = acc[r] * scale;
   }
   nc_block_max(cmax, maxc);
@@ -411,8 +431,8 @@ hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t
                        vec4, d_w, scale, d_maxc);
   } else {
     if (rx > kNcHalo || ry > kNcHalo) return hipErrorInvalidValue;
-    dim3 grid((mx + kNcTw - 1) / kNcTw, (my + kNcTh - 1) / kNcTh);
     const size_t lds = sizeof(float) * (kNcTw + 2 * rx) * (kNcTh + 2 * ry);
+    dim3 grid((mx + kNcTw - 1) / kNcTw, (my + kNcTh - 1) / kNcTh);
     hipLaunchKernelGGL(k_normalize_convolve_lds, grid, dim3(256), lds, st, counts, map, mx, my, d_w,
                        d_off, ntaps, rx, ry, scale, d_maxc);
   }
