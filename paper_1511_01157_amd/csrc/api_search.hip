@@ -46,6 +46,10 @@ struct SearchPlan {
   int num_cu = 256;
   uint32_t* counter = nullptr;
   double* axes = nullptr;
+  // trajectory lists: scoring order of the batched kernel and its counting-sort counters
+  int32_t* perm = nullptr;
+  uint32_t* perm_hist = nullptr;
+  int32_t perm_lists = 0;
 };
 
 int validate_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
@@ -128,13 +132,22 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                          ? trajs->n_u0 + trajs->n_alpha + trajs->n_t0 + trajs->n_tE
                          : 0;
   if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
+  // lists are scored in an order grouped by direction (one counting sort per list)
+  sp.perm_lists = (trajs->kind == MORSE_TRAJ_LIST && sp.n_traj > 0) ? (int32_t)(n_tc / sp.n_traj) : 0;
+  if ((int64_t)sp.perm_lists * kPermBins > kPermBinsMax) sp.perm_lists = 0;
   Plan pl;
   const size_t i_quad = pl.add(quad_region_bytes(maps, n_maps)),
                i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(4 * kQueueWords),
                i_wF = pl.add(8 * (size_t)sp.n_pts), i_tc = pl.add(sizeof(TrajC) * (size_t)n_tc),
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
-               i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0);
+               i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0),
+               i_perm = pl.add(sp.perm_lists ? 4 * (size_t)n_tc : 0),
+               i_ph = pl.add(4 * (size_t)sp.perm_lists * kPermBins);
   if ((rc = reserve(ctx, pl.total()))) return rc;
+  if (sp.perm_lists) {
+    sp.perm = (int32_t*)pl.ptr(ctx, i_perm);
+    sp.perm_hist = (uint32_t*)pl.ptr(ctx, i_ph);
+  }
   double* d_sums = (double*)pl.ptr(ctx, i_sums);
   sp.counter = (uint32_t*)pl.ptr(ctx, i_cnt);
   double* d_wF = (double*)pl.ptr(ctx, i_wF);
@@ -195,7 +208,9 @@ hipError_t enqueue_prep(const SearchPlan& sp, const morse_trajectories* trajs, h
     return launch_traj_prep_grid(sp.axes, trajs->n_u0, trajs->n_alpha, trajs->n_t0, trajs->n_tE,
                                  sp.tc, st);
   const int64_t n = trajs->shared ? sp.n_traj : sp.n_traj * sp.n_events;
-  return launch_traj_prep_list(trajs->d_params, n, sp.tc, st);
+  e = launch_traj_prep_list(trajs->d_params, n, sp.tc, st);
+  if (e != hipSuccess || !sp.perm) return e;
+  return launch_traj_perm(sp.tc, sp.n_traj, sp.perm_lists, sp.perm_hist, sp.perm, st);
 }
 
 hipError_t enqueue_select(const SearchPlan& sp, const morse_search_out* out, hipStream_t st) {
@@ -230,6 +245,7 @@ BatchedArgs batched_args(morse_ctx* ctx, const SearchPlan& sp, const morse_traje
     a.nt = trajs->n_t0;
     a.ne = trajs->n_tE;
   }
+  a.perm = sp.perm;
   a.traj_per_item = cfg.traj_per_item;
   a.waves_per_block = cfg.waves_per_block;
   a.tu = cfg.tu;

@@ -358,6 +358,8 @@ __device__ __forceinline__ Fit centred_fit(double Sw, double Fbar, double V, dou
 // first HIP error.
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
+// Exclusive prefix sum of nb uint32 counters in place (one workgroup; counting sorts).
+hipError_t launch_scan_u32(uint32_t* v, int64_t nb, hipStream_t st);
 // Packs every map of the device table `maps` (n_maps entries; h_maps the same table on
 // the host, for the sizes) into its quad layout.
 hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st);
@@ -401,7 +403,18 @@ struct BatchedArgs {
   int32_t waves_per_block;
   int32_t grid_blocks;
   int32_t tu;               // trajectories scored together per wavefront (1, 2 or 4)
+  const int32_t* perm;      // trajectory lists: [lists][n_traj] scoring order, or nullptr
 };
+// Scoring order of trajectory lists (n_lists lists of n_traj, their constants in tc):
+// each list grouped by direction, kPermBins buckets of alpha, so that waves scoring at
+// the same time follow nearby lines through the map (a counting sort; the order within
+// a bucket is unspecified and changes the schedule only).  hist: n_lists * kPermBins
+// counters of workspace.  Lists with more than kPermBinsMax counters in all are not
+// reordered by the caller.
+constexpr int kPermBins = 256;
+constexpr int64_t kPermBinsMax = 1 << 22;
+hipError_t launch_traj_perm(const TrajC* tc, int64_t n_traj, int32_t n_lists, uint32_t* hist,
+                            int32_t* perm, hipStream_t st);
 // Work queues of the batched search (one per XCD) and the words they occupy.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;

@@ -354,7 +354,38 @@ __global__ __launch_bounds__(256) void k_normalize_convolve_lds(
   nc_block_max(cmax, maxc);
 }
 
+// Exclusive prefix sum of nb counters in place by one 1024-lane workgroup: each lane
+// sums a contiguous chunk, a Hillis-Steele scan over the 1024 chunk sums, then each
+// lane rewrites its chunk.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, int64_t nb) {
+  __shared__ uint32_t part[1024];
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  uint32_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += v[b];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint32_t h = v[b];
+    v[b] = run;
+    run += h;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_scan_u32(uint32_t* v, int64_t nb, hipStream_t st) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, v, nb);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return hipSuccess;

@@ -549,8 +549,8 @@ hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Counting sort of the candidates by map (and event): per-bin counts, one workgroup's
-// exclusive scan of them, then an atomic scatter.
+// Counting sort of the candidates by map (and event): per-bin counts, their exclusive
+// scan (launch_scan_u32), then an atomic scatter.
 __device__ __forceinline__ uint32_t order_key(const GradArgs& a, int64_t c, bool by_event) {
   const int32_t e = a.event[c], m = a.mapidx[c];
   if (e < 0 || e >= a.n_events || m < 0 || m >= a.n_maps) return 0u;  // NaN outputs anyway
@@ -561,28 +561,6 @@ __global__ void k_order_count(GradArgs a, bool by_event, uint32_t* hist) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.n;
        c += (int64_t)gridDim.x * blockDim.x)
     atomicAdd(&hist[order_key(a, c, by_event)], 1u);
-}
-
-__global__ __launch_bounds__(1024) void k_order_scan(uint32_t* hist, int64_t nb) {
-  __shared__ uint32_t part[1024];
-  const int64_t per = (nb + 1023) / 1024;
-  const int64_t b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
-  uint32_t sum = 0;
-  for (int64_t b = b0; b < b1; ++b) sum += hist[b];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[threadIdx.x] - sum;
-  for (int64_t b = b0; b < b1; ++b) {
-    const uint32_t h = hist[b];
-    hist[b] = run;
-    run += h;
-  }
 }
 
 __global__ void k_order_scatter(GradArgs a, bool by_event, uint32_t* cursor, int32_t* order) {
@@ -601,7 +579,8 @@ hipError_t launch_cand_order(const GradArgs& a, uint32_t* hist, int32_t* order, 
   int64_t blocks = (a.n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_order_count, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, hist, nb);
+  e = launch_scan_u32(hist, nb, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist,
                      order);
   return hipGetLastError();

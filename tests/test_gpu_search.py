@@ -122,6 +122,26 @@ def test_multi_event_multi_map_lists_vs_oracle():
         assert len(set(gi.tolist())) == 20
 
 
+def test_shared_list_batched_order_is_a_schedule_only():
+    """A shared trajectory list (directions spread over many turns, one NaN) scored by
+    the batched kernel in its direction-grouped order: every output equals the plain
+    search, which scores the list in its own order."""
+    maps = small_maps()[:2]
+    evs = events("batched", [5, 6])
+    params = W.random_trajectories("batched", 5, 300)
+    params[:, 3] += 2 * np.pi * (np.arange(300) % 7 - 3)   # alpha beyond [0, 2 pi)
+    params[17, 3] = np.nan
+    lcs = M.LightCurveBatch.from_events(evs, DEV)
+    tr = M.list_trajectories(torch.from_numpy(params).to(DEV), shared=True)
+    dm = [(dmap(a), w) for a, w in maps]
+    note("search shared list plain + batched")
+    rp = M.search(dm, lcs, tr, "plain", fs=True, best=True, top_k=10)
+    rb = M.search(dm, lcs, tr, "batched", fs=True, best=True, top_k=10)
+    for k in rp:
+        assert torch.equal(rp[k].nan_to_num(), rb[k].nan_to_num()), k
+        assert torch.equal(rp[k].isnan(), rb[k].isnan()), k
+
+
 def test_degenerate_and_off_map_cases():
     """A constant map makes A constant on the map (degenerate fit); a window far from
     every trajectory puts every sample off the map (single-lens magnification)."""
