@@ -70,13 +70,13 @@ def peak_for(ops):
 # KiB: factor 1.99995; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
 # hash of the sources it is built from and the workload; a changed kernel reports null
 # until it is measured again.  Batched-events workload: the search's full launch
-# (FETCH 5.56637e9 KiB, WRITE 6.12525e6 KiB), the gradient's full 262144-candidate
-# launch (9.61185e6, 14770 KiB) and the mean over the two map sizes of the ray kernel
-# (FETCH 241.05 and 238.91 KiB, WRITE 68854.7 and 17281.9 KiB).
+# (FETCH 2.47307e9 KiB, WRITE 1.97854e7 KiB), the gradient's full 262144-candidate
+# launch (9.61193e6, 14770.6 KiB) and the mean over the two map sizes of the ray kernel
+# (FETCH 241.07 and 238.94 KiB, WRITE 68854.7 and 17281.9 KiB).
 TRAFFIC = {
-    ("k_search_batched", "2a15774bb8a5d0d9", "batched"): 1.140591e13,
-    ("k_chi2_grad", "cb9c3f9ed6af0307", "batched"): 1.969970e10,
-    ("k_rayshoot", "e22deaf82c83a0c6", "batched"): 4.459341e7,
+    ("k_search_batched", "7e4187f311596ac8", "batched"): 5.084981e+12,
+    ("k_chi2_grad", "331cdd04d7398430", "batched"): 1.969987e+10,
+    ("k_rayshoot", "a907f99bc807fca4", "batched"): 4.459345e+07,
 }
 STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
 STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
