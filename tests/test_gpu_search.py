@@ -140,6 +140,41 @@ def test_shared_list_batched_order_is_a_schedule_only():
     for k in rp:
         assert torch.equal(rp[k].nan_to_num(), rb[k].nan_to_num()), k
         assert torch.equal(rp[k].isnan(), rb[k].isnan()), k
+    # replays of the captured search (its ordering kernels included) on the same
+    # buffers, with eager work between
+    for rep in range(3):
+        for v in rb.values():
+            v.fill_(-1)
+        torch.cuda.synchronize()
+        r2 = M.search(dm, lcs, tr, "batched", fs=True, best=True, top_k=10, out=rb)
+        torch.cuda.synchronize()
+        for k in rp:
+            assert torch.equal(rp[k].nan_to_num(), r2[k].nan_to_num()), (rep, k)
+        _ = M.search(dm, lcs, tr, "plain", best=True)
+
+
+def test_many_short_events_batched_without_reordering():
+    """16,400 events of 3-9 points with their own 4-trajectory lists: more direction
+    buckets than the ordering pass takes (2^22), so the batched kernel scores the lists
+    in their own order; it must still equal the plain search."""
+    maps = small_maps()[:1]
+    src = events("batched", [7])[0]
+    rng = np.random.default_rng(9)
+    evs = []
+    for k in range(16400):
+        n = 3 + k % 7
+        j = int(rng.integers(0, len(src["tt"]) - n))
+        evs.append({key: (v[j:j + n] if key in ("tt", "F", "w", "t") else v) for key, v in src.items()})
+    params = np.stack([W.random_trajectories("batched", 7, 4) for _ in range(1)] * 16400)
+    params[:, :, 3] += rng.uniform(0, 6.3, (16400, 1))
+    lcs = M.LightCurveBatch.from_events(evs, DEV)
+    tr = M.list_trajectories(torch.from_numpy(params).to(DEV), shared=False)
+    dm = [(dmap(a), w) for a, w in maps]
+    note("search 16400 short events plain + batched")
+    rp = M.search(dm, lcs, tr, "plain", best=True, top_k=2)
+    rb = M.search(dm, lcs, tr, "batched", best=True, top_k=2)
+    for k in rp:
+        assert torch.equal(rp[k], rb[k]), k
 
 
 def test_degenerate_and_off_map_cases():
