@@ -49,6 +49,25 @@ def test_fs_magnification_matches_the_oracle(s, q, rho, gamma):
     assert (nreg > 0).sum() >= 6 and (nreg == -1).sum() >= 2
 
 
+@pytest.mark.parametrize("kw", [dict(n_b=64, n_side=50, n_grow=20, n_r=200, n_theta=300, n_shrink=3),
+                                dict(n_b=40, n_side=16, n_grow=5, n_r=96, n_theta=700, n_shrink=0)])
+def test_fs_magnification_options_match_the_oracle(kw):
+    """Grids whose column count is not a multiple of the integration workgroup's 512
+    lanes (300, 700), more and no shrink passes, fewer boundary seeds."""
+    s, q, rho, gamma = 1.2, 0.3, 0.02, 0.53
+    z = sources(s, q, rho, 3)[:9]
+    note(f"fsmag options {kw}")
+    zt = torch.from_numpy(np.stack([z.real, z.imag], 1).copy()).to(DEV)
+    A, nreg = M.fs_magnification(s, q, zt, rho, gamma, **kw)
+    A, nreg = A.cpu().numpy(), nreg.cpu().numpy()
+    opt = FsOptions(**kw)
+    for k, zk in enumerate(z):
+        oA, d = fs_magnification(zk, rho, gamma, s, q, opt=opt, details=True)
+        assert nreg[k] == (-1 if d["point_source"] else len(d["regions"])), (k, nreg[k])
+        assert abs(A[k] / oA - 1) < 1e-8, (k, A[k], oA)
+    assert (nreg > 0).sum() >= 4
+
+
 def test_more_near_sources_than_one_pass():
     """4500 sources within 3 rho of the caustic: two passes of the image-centred kernels
     (at most 4096 sources each).  Splitting the call elsewhere gives the same bits, and
