@@ -368,7 +368,10 @@ int morse_lines_to_trajectories(morse_ctx* ctx, const double* d_lines, const int
  * chi-square, t0', tE, the iterations taken and (d_evals, nullable) the chi-square
  * evaluations made (3 initial, then 1 to 4 per iteration).  d_lines [n_lines][3] and d_start
  * [n_lines][2] are device FP64.  Several maps (a finite-source stack) give the source
- * radius as a map index.  Errors: EINVAL (as morse_chi2_grad; bad event, opts, NULL
+ * radius as a map index.  The lines start in descending order of their largest sample
+ * on the first map (the line filter's maximum, bucketed by log2), since high peaks take
+ * the most steps; results do not depend on the order.  Workspace: 8 B per line + 4 KiB
+ * beyond the packed maps.  Errors: EINVAL (as morse_chi2_grad; bad event, opts, NULL
  * arrays), ERANGE (maps too large to pack). */
 typedef struct {
   int32_t max_iter; /* 5000 */

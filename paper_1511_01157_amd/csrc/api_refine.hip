@@ -179,6 +179,15 @@ int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_map
   if (!d_lines || !d_start || !d_chi2 || !d_t0 || !d_tE || !d_iters)
     return fail(ctx, MORSE_EINVAL, "NULL device array");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // start order: lines by descending largest sample on the first map (the filter's
+  // sampling of the line across the window)
+  const morse_grid2d& w0 = maps[0].window;
+  const double R = 0.5 * std::sqrt(w0.wx * w0.wx + w0.wy * w0.wy);
+  const double ns64 = std::ceil(2.0 * R * std::max(w0.nx / w0.wx, w0.ny / w0.wy)) + 1.0;
+  const bool ordered = ns64 <= 1.0e7 && n_lines <= INT32_MAX;
+  const size_t i_key = pl.add(ordered ? 4 * (size_t)n_lines : 0),
+               i_hist = pl.add(ordered ? 4 * (size_t)kSimplexPrioBins : 0),
+               i_order = pl.add(ordered ? 4 * (size_t)n_lines : 0);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   SimplexArgs a{};
   MapC* d_maps;
@@ -199,6 +208,12 @@ int morse_line_simplex(morse_ctx* ctx, const morse_map_view* maps, int32_t n_map
   a.tE = d_tE;
   a.iters = d_iters;
   a.evals = d_evals;
+  if (ordered) {
+    HIP_TRY(ctx, launch_simplex_order(a, w0.cx, w0.cy, R, (int32_t)ns64, (float)(2.0 * R / (ns64 - 1.0)),
+                                      (uint32_t*)pl.ptr(ctx, i_key), (uint32_t*)pl.ptr(ctx, i_hist),
+                                      (int32_t*)pl.ptr(ctx, i_order), ctx->stream));
+    a.order = (const int32_t*)pl.ptr(ctx, i_order);
+  }
   HIP_TRY(ctx, launch_line_simplex(a, ctx->stream));
   return MORSE_OK;
 }

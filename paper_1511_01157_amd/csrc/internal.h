@@ -360,6 +360,10 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
 // Exclusive prefix sum of nb uint32 counters in place (one workgroup; counting sorts).
 hipError_t launch_scan_u32(uint32_t* v, int64_t nb, hipStream_t st);
+// order[0 .. n): the items 0 .. n - 1 by ascending key (key < nbins; the order among
+// equal keys is unspecified).  hist: nbins counters of workspace.
+hipError_t launch_bucket_order(const uint32_t* key, int64_t n, int32_t nbins, uint32_t* hist,
+                               int32_t* order, hipStream_t st);
 // Packs every map of the device table `maps` (n_maps entries; h_maps the same table on
 // the host, for the sizes) into its quad layout.
 hipError_t launch_quad_pack(const MapC* maps, const MapC* h_maps, int32_t n_maps, hipStream_t st);

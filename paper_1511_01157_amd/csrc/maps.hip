@@ -379,7 +379,35 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, int64_t nb) {
   }
 }
 
+__global__ void k_bucket_count(const uint32_t* __restrict__ key, int64_t n, uint32_t* hist) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[key[i]], 1u);
+}
+
+__global__ void k_bucket_scatter(const uint32_t* __restrict__ key, int64_t n, uint32_t* cursor,
+                                 int32_t* order) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    order[atomicAdd(&cursor[key[i]], 1u)] = (int32_t)i;
+}
+
 }  // namespace
+
+hipError_t launch_bucket_order(const uint32_t* key, int64_t n, int32_t nbins, uint32_t* hist,
+                               int32_t* order, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > INT32_MAX || nbins <= 0) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_u32(hist, (size_t)nbins, 0u, st);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)blocks), dim3(256), 0, st, key, n, hist);
+  e = launch_scan_u32(hist, nbins, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)blocks), dim3(256), 0, st, key, n, hist, order);
+  return hipGetLastError();
+}
 
 hipError_t launch_scan_u32(uint32_t* v, int64_t nb, hipStream_t st) {
   if (nb <= 0) return hipSuccess;

@@ -87,7 +87,8 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
   const double Sw = uniform(a.lc.sums[3 * e]), Fbar = uniform(a.lc.sums[3 * e + 1]),
                V = uniform(a.lc.sums[3 * e + 2]);
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t l = item / a.n_maps;
+    const int64_t l = a.order ? (int64_t)uniform(a.order[item / a.n_maps]) : item / a.n_maps;
+    const int64_t out = l * a.n_maps + item % a.n_maps;
     const MapC m = uniform(a.maps[item % a.n_maps]);
     const double u0 = uniform(a.lines[3 * l]), al = uniform(a.lines[3 * l + 1]),
                  shift = uniform(a.lines[3 * l + 2]);
@@ -241,16 +242,58 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
       state = kReflect;
     }
     if (tid == 0) {
-      a.chi2[item] = v[0].f;
-      a.t0[item] = v[0].x0;
-      a.tE[item] = exp(v[0].x1);
-      a.iters[item] = it;
-      if (a.evals) a.evals[item] = evals;
+      a.chi2[out] = v[0].f;
+      a.t0[out] = v[0].x0;
+      a.tE[out] = exp(v[0].x1);
+      a.iters[out] = it;
+      if (a.evals) a.evals[out] = evals;
+    }
+  }
+}
+
+// One wavefront per line: the largest sample along it on the first map (as the line
+// filter samples), as a descending log2 bucket (NaN and non-positive maxima last).
+__global__ __launch_bounds__(256) void k_simplex_prio(SimplexArgs a, double cxw, double cyw,
+                                                      double half_diag, int32_t ns, float h,
+                                                      uint32_t* key) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const MapC m = uniform(a.maps[0]);
+  for (int64_t l = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; l < a.n_lines;
+       l += waves) {
+    const double u0 = a.lines[3 * l], al = a.lines[3 * l + 1];
+    double sn, cn;
+    sincos(al, &sn, &cn);
+    const float ca = (float)cn, sa = (float)sn, bx = (float)(-u0 * sn), by = (float)(u0 * cn);
+    const float lo = (float)((cxw * cn + cyw * sn) - half_diag);
+    float best = 0.0f;
+    for (int k = lane; k < ns; k += kWave) {
+      const float A = sample_A(m, lo + (float)k * h, 0.0f, 1.0f, ca, sa, bx, by);
+      best = A > best ? A : best;  // NaN samples never win
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) best = fmaxf(best, __shfl_xor(best, off));
+    if (lane == 0) {
+      int b = 0;  // bucket of log2(best) over [2^-8, 2^13.3), 48 per octave
+      if (best > 0.0f) b = min(max((int)((log2f(best) + 8.0f) * 48.0f), 0), kSimplexPrioBins - 1);
+      key[l] = (uint32_t)(kSimplexPrioBins - 1 - b);
     }
   }
 }
 
 }  // namespace
+
+hipError_t launch_simplex_order(const SimplexArgs& a, double cxw, double cyw, double half_diag,
+                                int32_t ns, float h, uint32_t* key, uint32_t* hist, int32_t* order,
+                                hipStream_t st) {
+  if (a.n_lines <= 0) return hipSuccess;
+  if (a.n_lines > INT32_MAX || ns < 1 || a.n_maps < 1) return hipErrorInvalidValue;
+  int64_t blocks = (a.n_lines + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_simplex_prio, dim3((unsigned)blocks), dim3(256), 0, st, a, cxw, cyw, half_diag,
+                     ns, h, key);
+  return launch_bucket_order(key, a.n_lines, kSimplexPrioBins, hist, order, st);
+}
 
 hipError_t launch_line_simplex(const SimplexArgs& a, hipStream_t st) {
   const int64_t items = a.n_lines * a.n_maps;

@@ -62,6 +62,30 @@ def test_simplex_tiny_two_maps():
     assert it.max() > 10
 
 
+def test_simplex_start_order_is_a_schedule_only():
+    """The library starts lines in descending order of their peak on the first map;
+    permuting the input lines permutes every output, bit for bit, with two maps."""
+    c = W.config("tiny")
+    win = c["window"]
+    counts, _, amap = oracle_map(c["s"], c["q"], c["rays"], win, 0.0)
+    d = win[2] / win[4]
+    amap2 = normalize_convolve_mirror32(counts, map_scale(c["rays"], win), disk_pixel_weights(0.02, d, d))
+    ev = W.load_lightcurve("tiny")
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.0, 0.3, 0.8, 2.0]), np.linspace(0.0, 2 * np.pi, 33)[:-1])
+    start = np.tile([2.0, 15.0], (len(lines), 1))
+    perm = np.random.default_rng(4).permutation(len(lines))
+    dmaps = [(torch.from_numpy(np.ascontiguousarray(a)).to(DEV), win) for a in (amap, amap2)]
+    lcs = M.LightCurveBatch.from_events([ev], DEV)
+    note(f"simplex order: {len(lines)} lines x 2 maps, given and permuted")
+    opts = dict(max_iter=400, step_t0=2.0, step_ln_tE=0.2, ftol=1e-10)
+    a = M.line_simplex(dmaps, lcs, torch.from_numpy(lines).to(DEV), torch.from_numpy(start).to(DEV), **opts)
+    b = M.line_simplex(dmaps, lcs, torch.from_numpy(lines[perm].copy()).to(DEV),
+                       torch.from_numpy(start[perm].copy()).to(DEV), **opts)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.cpu().numpy()[perm], y.cpu().numpy(), equal_nan=True)
+
+
 def test_simplex_large_map_kept_lines():
     c = W.config("large")
     win = c["window"]
