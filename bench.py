@@ -933,7 +933,8 @@ def leg_large(args, M, W, torch, np, dev):
             "roofline": {"bound": "alu", "achieved": s_ops, "peak": spk, "unit": "TFLOP/s",
                          "frac": s_ops / spk, "ops_per_unit_f32_f64": OPS_PER_SIMPLEX_POINT,
                          "traffic": None,
-                         "note": "the longest simplex (iterations_max) bounds the launch"}}
+                         "note": "lines start in descending order of their peak; the longest simplex "
+                                 "(iterations_max) sets the tail"}}
         rec["caustic_lines"] = lines_rec
 
         # Finite-source magnification without maps (sec. 5): the light curve's epochs on
