@@ -84,6 +84,7 @@ KERNEL_SOURCES = {"k_rayshoot": ("maps.hip", "internal.h"),
                   "k_search_batched": ("search.hip", "internal.h"),
                   "k_chi2_grad": ("refine.hip", "internal.h")}
 CPU_WORKERS = 16          # the host-core share of one GPU
+TU1_SHAPE = 1             # the library's batched-search shape (8, 4, 16, TU = 1)
 
 
 def kernel_sha(kernel):
@@ -423,7 +424,9 @@ def leg_batched(args, M, W, torch, np, dev):
 
         progress("batched: bank build + autotune")
         build_bank(cb, bank1, cnt1)
-        tuned = M.autotune(views1, lcs, trajs, ctx=ctx)
+        import tempfile
+        tune_path = os.path.join(tempfile.mkdtemp(prefix="morse_bench_"), "tune.json")
+        tuned = M.autotune(views1, lcs, trajs, cache_path=tune_path, ctx=ctx)
         progress(f"batched: warm-up x{max(1, args.warmup)} (autotuned shape {tuned})")
         for _ in range(max(1, args.warmup)):
             step()
@@ -460,7 +463,7 @@ def leg_batched(args, M, W, torch, np, dev):
         ktime = {n: ctx.kernel_time(f, reset=True) for n, f in fams.items()}
         ctx.set_timing([])
 
-        plain_ms = None
+        plain_ms = tu1_ms = same_tu1 = None
         if not args.no_plain:
             progress("batched: plain search (one launch per event and map)")
             pbuf = {}
@@ -473,6 +476,25 @@ def leg_batched(args, M, W, torch, np, dev):
             plain_ms = e0.elapsed_time(e1)
             same_topk = bool(torch.equal(pr["topk_idx"], sbuf["topk_idx"]) and
                              torch.equal(pr["topk_chi2"], sbuf["topk_chi2"]))
+            # the batched kernel at a TU = 1 shape of its table, which separates the one
+            # persistent launch from scoring several trajectories per wavefront
+            progress("batched: persistent search at TU = 1")
+            with open(tune_path) as f:
+                classes = json.load(f)
+            with open(tune_path + ".tu1", "w") as f:
+                json.dump({cl: TU1_SHAPE for cl in classes}, f)
+            M.autotune_load(tune_path + ".tu1", ctx=ctx)
+            b1 = {}
+            b1 = M.search(views1, lcs, trajs, "batched", chi2=False, top_k=k, out=b1, ctx=ctx)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            b1 = M.search(views1, lcs, trajs, "batched", chi2=False, top_k=k, out=b1, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tu1_ms = e0.elapsed_time(e1)
+            same_tu1 = bool(torch.equal(b1["topk_idx"], sbuf["topk_idx"]) and
+                            torch.equal(b1["topk_chi2"], sbuf["topk_chi2"]))
+            M.autotune_load(tune_path, ctx=ctx)  # the tuned shape again
 
     build_ms, search_ms, refine_ms = stage
     rounds = cr["steps"] + 1
@@ -496,6 +518,10 @@ def leg_batched(args, M, W, torch, np, dev):
         "search_point_evals_per_s": {
             "batched": units["evals"] / (search_ms * 1e-3),
             "plain": units["evals"] / (plain_ms * 1e-3) if plain_ms else None,
+            "batched_tu1": units["evals"] / (tu1_ms * 1e-3) if tu1_ms else None,
+            "batched_tu1_shape": (f"entry {TU1_SHAPE} of the library's shape table: 8 trajectories "
+                                  "per item, 4 waves per workgroup, 16 workgroups per CU, TU = 1; "
+                                  f"top-k equal to the tuned run: {same_tu1}"),
             "batched_shape": {"autotuned_index": tuned, "note": "trajectories per item, waves "
                               "per workgroup, workgroups per CU and TU of the library's shape "
                               "table entry; one persistent launch over (event, map, trajectory "
@@ -567,7 +593,7 @@ def leg_sqgrid(args, M, W, torch, np, dev):
             r = step(ev_[i])
         torch.cuda.synchronize()
         st = np.mean([[e[j].elapsed_time(e[j + 1]) for j in range(2)] for e in ev_], axis=0)
-        plain_ms = None
+        plain_ms = tu1_ms = same_tu1 = None
         if not args.no_plain:
             progress("sqgrid: plain search")
             e0, e1 = events_timer(torch, 2)

@@ -240,8 +240,11 @@ enum { MORSE_SEARCH_PLAIN = 0, MORSE_SEARCH_BATCHED = 1 };
 /* search(map, lightcurve, traj_grid) over n_maps maps and all events.
  * PLAIN: one launch per (event, map).  BATCHED: one persistent launch over a work
  * queue of (event, map, trajectory block) items, captured once into a HIP graph
- * per argument set and replayed; tile shapes from the context's autotune table.
- * Both modes give bitwise identical results.  Errors: EINVAL (shapes, null
+ * per argument set and replayed; tile shapes from the context's autotune table.  The
+ * batched mode scores a trajectory list in an order grouped by direction (256 buckets
+ * of alpha per list, a device counting sort each call; workspace 8 B per trajectory
+ * and 1 KiB per list, lists of at most 16384 events), outputs staying in the list's
+ * own order.  Both modes give bitwise identical results.  Errors: EINVAL (shapes, null
  * pointers, w <= 0 is not checked on device), EUNSUPPORTED (top_k > 4096). */
 int morse_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                  const morse_lightcurves* lcs, const morse_trajectories* trajs, int32_t mode,
@@ -451,7 +454,7 @@ int morse_trajectory_positions(morse_ctx* ctx, const double* h_params, const dou
  * Outputs (device, nullable): d_chi2 [n], d_grad [n][4], d_fs [n], d_fb [n].
  * Candidates are evaluated grouped by (map, event) (a device counting sort; by map
  * alone past 2^20 pairs), so that the GPU samples one map at a time; the order changes
- * the schedule only, never a result.  Workspace: 44 B per candidate + 4 B per
+ * the schedule only, never a result.  Workspace: 48 B per candidate + 4 B per
  * (map, event) pair. */
 int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                     const morse_lightcurves* lcs, int64_t n, const double* d_params,
@@ -463,7 +466,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
  * kernels and results, with no hipMalloc, hipFree or allocating library call; the
  * context must already exist.  Its scratch (event offsets, reference times and map
  * table, the light-curve preparation, candidate constants and the packed cells of every
- * map: 24 B per event + 8 B per point + 44 B per candidate + 4 B per (map, event)
+ * map: 24 B per event + 8 B per point + 48 B per candidate + 4 B per (map, event)
  * pair + 16 B per map cell, each part rounded up to 256 B, plus the table) lives in one static device array of
  * 128 MiB on each GPU the library runs on, held until the process ends.  Every call on
  * a GPU shares that GPU's array and leaves its contents there, so calls that overlap on

@@ -231,7 +231,7 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     return fail(ctx, MORSE_EINVAL, "d_params / d_event / d_map_index is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n),
-               i_order = pl.add(4 * (size_t)n),
+               i_order = pl.add(4 * (size_t)n), i_key = pl.add(4 * (size_t)n),
                i_hist = pl.add(4 * (size_t)order_bins(n_maps, lcs->n_events));
   if ((rc = reserve(ctx, pl.total()))) return rc;
   GradArgs a{};
@@ -251,7 +251,8 @@ int morse_chi2_grad(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   a.grad = d_grad;
   a.fs = d_fs;
   a.fb = d_fb;
-  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr(ctx, i_hist), (int32_t*)a.order, ctx->stream));
+  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr(ctx, i_key), (uint32_t*)pl.ptr(ctx, i_hist),
+                                 (int32_t*)a.order, ctx->stream));
   HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
   LaunchTimer tm{ctx, MORSE_KERNEL_GRADIENT};
   HIP_TRY(ctx, tm.begin(ctx->stream));
@@ -276,7 +277,8 @@ int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t 
   const size_t b_tref = (8 * (size_t)ne + 255) & ~size_t(255);
   const size_t i_meta = pl.add(b_off + b_tref + sizeof(MapC) * n_maps);
   const size_t i_tc = pl.add(sizeof(TrajC) * (size_t)n), i_tE = pl.add(8 * (size_t)n),
-               i_order = pl.add(4 * (size_t)n), i_hist = pl.add(4 * (size_t)order_bins(n_maps, ne));
+               i_order = pl.add(4 * (size_t)n), i_key = pl.add(4 * (size_t)n),
+               i_hist = pl.add(4 * (size_t)order_bins(n_maps, ne));
   if (pl.total() > kNoallocScratchBytes)
     return fail(ctx, MORSE_ERANGE,
                 "needs %.1f MiB of scratch; the allocation-free entry point holds %zu MiB "
@@ -320,7 +322,8 @@ int morse_chi2_grad_noalloc(morse_ctx* ctx, const morse_map_view* maps, int32_t 
   a.grad = d_grad;
   a.fs = d_fs;
   a.fb = d_fb;
-  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr_at(base, i_hist), (int32_t*)a.order, ctx->stream));
+  HIP_TRY(ctx, launch_cand_order(a, (uint32_t*)pl.ptr_at(base, i_key), (uint32_t*)pl.ptr_at(base, i_hist),
+                                 (int32_t*)a.order, ctx->stream));
   HIP_TRY(ctx, launch_cand_prep(a, ctx->stream));
   HIP_TRY(ctx, launch_chi2_grad(a, ctx->stream));
   return MORSE_OK;
@@ -349,7 +352,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                i_S = pl.add(32 * (size_t)n * m), i_Y = pl.add(32 * (size_t)n * m),
                i_R = pl.add(8 * (size_t)n * m), i_int = pl.add(12 * n), i_ft = pl.add(8 * n),
                i_gt = pl.add(32 * n), i_tc = pl.add(sizeof(TrajC) * (size_t)n),
-               i_tE = pl.add(8 * (size_t)n), i_order = pl.add(4 * (size_t)n);
+               i_tE = pl.add(8 * (size_t)n), i_order = pl.add(4 * (size_t)n),
+               i_key = pl.add(4 * (size_t)n);
   const int64_t nbins = order_bins(n_maps, lcs->n_events);
   const size_t i_hist0 = pl.add(4 * (size_t)nbins), i_hist1 = pl.add(4 * (size_t)nbins);
   if ((rc = reserve(ctx, pl.total()))) return rc;
@@ -431,7 +435,8 @@ int morse_refine(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
     }
     hipError_t e = hipSuccess;
     for (int k = 0; k < parts && e == hipSuccess; ++k) {
-      e = launch_cand_order(ap[k], hist[k], const_cast<int32_t*>(ap[k].order), cs[k]);
+      e = launch_cand_order(ap[k], (uint32_t*)pl.ptr(ctx, i_key) + c0[k], hist[k],
+                            const_cast<int32_t*>(ap[k].order), cs[k]);
       if (e == hipSuccess)
         e = launch_refine_init(sp[k], ap[k], d_params + 4 * c0[k], anchor + 4 * c0[k], cs[k]);
     }

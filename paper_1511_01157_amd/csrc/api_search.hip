@@ -48,6 +48,7 @@ struct SearchPlan {
   double* axes = nullptr;
   // trajectory lists: scoring order of the batched kernel and its counting-sort counters
   int32_t* perm = nullptr;
+  uint32_t* perm_key = nullptr;
   uint32_t* perm_hist = nullptr;
   int32_t perm_lists = 0;
 };
@@ -134,7 +135,7 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
   if ((rc = check_quad_size(ctx, maps, n_maps))) return rc;
   // lists are scored in an order grouped by direction (one counting sort per list)
   sp.perm_lists = (trajs->kind == MORSE_TRAJ_LIST && sp.n_traj > 0) ? (int32_t)(n_tc / sp.n_traj) : 0;
-  if ((int64_t)sp.perm_lists * kPermBins > kPermBinsMax) sp.perm_lists = 0;
+  if ((int64_t)sp.perm_lists * kPermBins > kPermBinsMax || n_tc > INT32_MAX) sp.perm_lists = 0;
   Plan pl;
   const size_t i_quad = pl.add(quad_region_bytes(maps, n_maps)),
                i_sums = pl.add(24 * (size_t)sp.n_events), i_cnt = pl.add(4 * kQueueWords),
@@ -142,10 +143,12 @@ int plan_search(morse_ctx* ctx, const morse_map_view* maps, int32_t n_maps,
                i_chi = pl.add(need_chi2 ? 8 * (size_t)n_out : 0),
                i_tk = pl.add(k > 0 ? topk_scratch_bytes(sp.n_events, k) : 0),
                i_perm = pl.add(sp.perm_lists ? 4 * (size_t)n_tc : 0),
+               i_pk = pl.add(sp.perm_lists ? 4 * (size_t)n_tc : 0),
                i_ph = pl.add(4 * (size_t)sp.perm_lists * kPermBins);
   if ((rc = reserve(ctx, pl.total()))) return rc;
   if (sp.perm_lists) {
     sp.perm = (int32_t*)pl.ptr(ctx, i_perm);
+    sp.perm_key = (uint32_t*)pl.ptr(ctx, i_pk);
     sp.perm_hist = (uint32_t*)pl.ptr(ctx, i_ph);
   }
   double* d_sums = (double*)pl.ptr(ctx, i_sums);
@@ -210,7 +213,7 @@ hipError_t enqueue_prep(const SearchPlan& sp, const morse_trajectories* trajs, h
   const int64_t n = trajs->shared ? sp.n_traj : sp.n_traj * sp.n_events;
   e = launch_traj_prep_list(trajs->d_params, n, sp.tc, st);
   if (e != hipSuccess || !sp.perm) return e;
-  return launch_traj_perm(sp.tc, sp.n_traj, sp.perm_lists, sp.perm_hist, sp.perm, st);
+  return launch_traj_perm(sp.tc, sp.n_traj, sp.perm_lists, sp.perm_key, sp.perm_hist, sp.perm, st);
 }
 
 hipError_t enqueue_select(const SearchPlan& sp, const morse_search_out* out, hipStream_t st) {

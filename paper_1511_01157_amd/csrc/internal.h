@@ -412,13 +412,14 @@ struct BatchedArgs {
 // Scoring order of trajectory lists (n_lists lists of n_traj, their constants in tc):
 // each list grouped by direction, kPermBins buckets of alpha, so that waves scoring at
 // the same time follow nearby lines through the map (a counting sort; the order within
-// a bucket is unspecified and changes the schedule only).  hist: n_lists * kPermBins
-// counters of workspace.  Lists with more than kPermBinsMax counters in all are not
-// reordered by the caller.
+// a bucket is unspecified and changes the schedule only); perm holds indices over all
+// lists (list * n_traj + trajectory).  key: n_lists * n_traj words of workspace, hist:
+// n_lists * kPermBins counters.  Lists with more than kPermBinsMax counters in all are
+// not reordered by the caller.
 constexpr int kPermBins = 256;
 constexpr int64_t kPermBinsMax = 1 << 22;
-hipError_t launch_traj_perm(const TrajC* tc, int64_t n_traj, int32_t n_lists, uint32_t* hist,
-                            int32_t* perm, hipStream_t st);
+hipError_t launch_traj_perm(const TrajC* tc, int64_t n_traj, int32_t n_lists, uint32_t* key,
+                            uint32_t* hist, int32_t* perm, hipStream_t st);
 // Work queues of the batched search (one per XCD) and the words they occupy.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;
@@ -469,13 +470,15 @@ hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st);
 // Evaluation order of candidates [0, a.n): grouped by (map, event) (by map alone when
 // n_maps x n_events exceeds kOrderBinsMax), so that candidates evaluated at the same
 // time sample the same map.  Within a group the order is unspecified: it changes only
-// the schedule, never a result.  hist: workspace of order_bins(a) counters.
+// the schedule, never a result.  key: workspace of a.n words; hist: of order_bins(a)
+// counters.
 constexpr int64_t kOrderBinsMax = 1 << 20;
 inline int64_t order_bins(int32_t n_maps, int32_t n_events) {
   const int64_t both = (int64_t)n_maps * n_events;
   return both <= kOrderBinsMax ? both : n_maps;
 }
-hipError_t launch_cand_order(const GradArgs& a, uint32_t* hist, int32_t* order, hipStream_t st);
+hipError_t launch_cand_order(const GradArgs& a, uint32_t* key, uint32_t* hist, int32_t* order,
+                             hipStream_t st);
 
 struct LbfgsState {
   int64_t n;

@@ -549,41 +549,33 @@ hipError_t launch_cand_prep(const GradArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Counting sort of the candidates by map (and event): per-bin counts, their exclusive
-// scan (launch_scan_u32), then an atomic scatter.
+namespace {
+
+// Evaluation order: each candidate's (map, event) key, then the shared bucket sort.
 __device__ __forceinline__ uint32_t order_key(const GradArgs& a, int64_t c, bool by_event) {
   const int32_t e = a.event[c], m = a.mapidx[c];
   if (e < 0 || e >= a.n_events || m < 0 || m >= a.n_maps) return 0u;  // NaN outputs anyway
   return by_event ? (uint32_t)m * (uint32_t)a.n_events + (uint32_t)e : (uint32_t)m;
 }
 
-__global__ void k_order_count(GradArgs a, bool by_event, uint32_t* hist) {
+__global__ void k_order_keys(GradArgs a, bool by_event, uint32_t* key) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.n;
        c += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[order_key(a, c, by_event)], 1u);
+    key[c] = order_key(a, c, by_event);
 }
 
-__global__ void k_order_scatter(GradArgs a, bool by_event, uint32_t* cursor, int32_t* order) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.n;
-       c += (int64_t)gridDim.x * blockDim.x)
-    order[atomicAdd(&cursor[order_key(a, c, by_event)], 1u)] = (int32_t)c;
-}
+}  // namespace
 
-hipError_t launch_cand_order(const GradArgs& a, uint32_t* hist, int32_t* order, hipStream_t st) {
+hipError_t launch_cand_order(const GradArgs& a, uint32_t* key, uint32_t* hist, int32_t* order,
+                             hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (a.n > INT32_MAX || a.n_maps <= 0 || a.n_events <= 0) return hipErrorInvalidValue;
   const int64_t nb = order_bins(a.n_maps, a.n_events);
   const bool by_event = nb == (int64_t)a.n_maps * a.n_events;
-  hipError_t e = launch_fill_u32(hist, (size_t)nb, 0u, st);
-  if (e != hipSuccess) return e;
   int64_t blocks = (a.n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_order_count, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist);
-  e = launch_scan_u32(hist, nb, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, hist,
-                     order);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_order_keys, dim3((unsigned)blocks), dim3(256), 0, st, a, by_event, key);
+  return launch_bucket_order(key, a.n, (int32_t)nb, hist, order, st);
 }
 
 hipError_t launch_chi2_grad(const GradArgs& a, hipStream_t st) {

@@ -251,8 +251,11 @@ __global__ __launch_bounds__(256) void k_search_plain(const TrajC* __restrict__ 
 // direction, for the same reason.
 // Trajectory index of scoring position p of event e (see k_search_batched).
 __device__ __forceinline__ int64_t traj_of(const BatchedArgs& a, int64_t p, int32_t e) {
-  if (a.na <= 0)
-    return a.perm ? (int64_t)uniform(a.perm[(a.shared ? 0 : (int64_t)e * a.n_traj) + p]) : p;
+  if (a.na <= 0) {
+    if (!a.perm) return p;
+    const int64_t base = a.shared ? 0 : (int64_t)e * a.n_traj;  // perm holds indices over all lists
+    return (int64_t)uniform(a.perm[base + p]) - base;
+  }
   const uint32_t u = (uint32_t)p;  // n_traj < 2^31
   const uint32_t ie = u % (uint32_t)a.ne, r1 = u / (uint32_t)a.ne;
   const uint32_t it = r1 % (uint32_t)a.nt, r2 = r1 / (uint32_t)a.nt;
@@ -663,8 +666,8 @@ hipError_t launch_traj_prep_list(const double* params, int64_t n, TrajC* out, hi
 
 namespace {
 
-// Scoring order of trajectory lists: counts per (list, alpha bucket), their exclusive
-// scan, an atomic scatter of each trajectory's index within its list.
+// Scoring order of trajectory lists: each trajectory's (list, alpha bucket) key, then
+// the shared bucket sort (its order holds indices over all lists).
 __device__ __forceinline__ uint32_t perm_key(const TrajC* tc, int64_t i, int64_t n_traj) {
   const float a = atan2f(tc[i].sa, tc[i].ca);  // (-pi, pi]
   int b = 0;
@@ -672,36 +675,23 @@ __device__ __forceinline__ uint32_t perm_key(const TrajC* tc, int64_t i, int64_t
   return (uint32_t)((i / n_traj) * kPermBins + b);
 }
 
-__global__ void k_perm_count(const TrajC* __restrict__ tc, int64_t n, int64_t n_traj, uint32_t* hist) {
+__global__ void k_perm_keys(const TrajC* __restrict__ tc, int64_t n, int64_t n_traj, uint32_t* key) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[perm_key(tc, i, n_traj)], 1u);
-}
-
-__global__ void k_perm_scatter(const TrajC* __restrict__ tc, int64_t n, int64_t n_traj,
-                               uint32_t* cursor, int32_t* perm) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    perm[atomicAdd(&cursor[perm_key(tc, i, n_traj)], 1u)] = (int32_t)(i % n_traj);
+    key[i] = perm_key(tc, i, n_traj);
 }
 
 }  // namespace
 
-hipError_t launch_traj_perm(const TrajC* tc, int64_t n_traj, int32_t n_lists, uint32_t* hist,
-                            int32_t* perm, hipStream_t st) {
+hipError_t launch_traj_perm(const TrajC* tc, int64_t n_traj, int32_t n_lists, uint32_t* key,
+                            uint32_t* hist, int32_t* perm, hipStream_t st) {
   const int64_t n = n_traj * n_lists, nb = (int64_t)n_lists * kPermBins;
   if (n <= 0) return hipSuccess;
-  if (n_traj > INT32_MAX || n > UINT32_MAX || nb > kPermBinsMax) return hipErrorInvalidValue;
-  hipError_t e = launch_fill_u32(hist, (size_t)nb, 0u, st);
-  if (e != hipSuccess) return e;
+  if (n > INT32_MAX || nb > kPermBinsMax) return hipErrorInvalidValue;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_perm_count, dim3((unsigned)blocks), dim3(256), 0, st, tc, n, n_traj, hist);
-  e = launch_scan_u32(hist, nb, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_perm_scatter, dim3((unsigned)blocks), dim3(256), 0, st, tc, n, n_traj, hist,
-                     perm);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_perm_keys, dim3((unsigned)blocks), dim3(256), 0, st, tc, n, n_traj, key);
+  return launch_bucket_order(key, n, (int32_t)nb, hist, perm, st);
 }
 
 hipError_t launch_traj_prep_grid(const double* axes, int32_t nu, int32_t na, int32_t nt,
