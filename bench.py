@@ -70,13 +70,13 @@ def peak_for(ops):
 # KiB: factor 1.99995; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
 # hash of the sources it is built from and the workload; a changed kernel reports null
 # until it is measured again.  Batched-events workload: the search's full launch
-# (FETCH 2.47307e9 KiB, WRITE 1.97854e7 KiB), the gradient's full 262144-candidate
-# launch (9.61193e6, 14770.6 KiB) and the mean over the two map sizes of the ray kernel
-# (FETCH 241.07 and 238.94 KiB, WRITE 68854.7 and 17281.9 KiB).
+# (FETCH 2.47754e+09 KiB, WRITE 1.9785e+07 KiB), the gradient's full 262144-candidate
+# launch (9.62285e+06, 14768.2 KiB) and the mean over the two map sizes of the ray kernel
+# (FETCH 241.1 and 238.92 KiB, WRITE 68854.7 and 17281.9 KiB).
 TRAFFIC = {
-    ("k_search_batched", "7e4187f311596ac8", "batched"): 5.084981e+12,
-    ("k_chi2_grad", "331cdd04d7398430", "batched"): 1.969987e+10,
-    ("k_rayshoot", "a907f99bc807fca4", "batched"): 4.459345e+07,
+    ("k_search_batched", "1394b93c19e6dbc0", "batched"): 5.094064e+12,
+    ("k_chi2_grad", "c0d1ad21a75a5227", "batched"): 1.972198e+10,
+    ("k_rayshoot", "51e4a7ca1cbf207e", "batched"): 4.459342e+07,
 }
 STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
 STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
