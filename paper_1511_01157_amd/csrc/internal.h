@@ -150,10 +150,32 @@ __device__ __forceinline__ Loc locate(const MapC& m, float tt, float t0p, float 
   return l;
 }
 
-// Single-lens magnification about the barycentre, (uu + 2)/sqrt(uu (uu + 4)).
+// Single-lens magnification about the barycentre, (uu + 2)/sqrt(uu (uu + 4)), with a
+// correctly rounded binary32 square root and quotient.  A correctly rounded result is
+// unique, so any exact method gives the same bits.  When d = uu (uu + 4) lies in
+// [2^-60, 2^60] on every active lane the short form runs: the hardware square root
+// (within one ulp) corrected by the signs of the FMA residuals against its two
+// neighbours, then the reciprocal refined once and the quotient corrected twice by FMA.
+// These are the steps of the general IEEE sequences with their range scalings and
+// special-case fix-ups left out, which in this range change nothing.  Elsewhere the
+// general sequences run.
 __device__ __forceinline__ float point_lens_A(float zx, float zy) {
   const float uu = zx * zx + zy * zy;
-  return (uu + 2.0f) / sqrtf(uu * (uu + 4.0f));
+  const float p = uu + 2.0f, d = uu * (uu + 4.0f);
+  if (__all(d >= 0x1p-60f && d <= 0x1p60f)) {
+    float s = __builtin_amdgcn_sqrtf(d);
+    const float sdn = __uint_as_float(__float_as_uint(s) - 1u);
+    const float sup = __uint_as_float(__float_as_uint(s) + 1u);
+    const float rdn = fmaf(-sdn, s, d), rup = fmaf(-sup, s, d);
+    s = rdn <= 0.0f ? sdn : s;
+    s = rup > 0.0f ? sup : s;
+    float r = __builtin_amdgcn_rcpf(s);
+    r = fmaf(fmaf(-s, r, 1.0f), r, r);
+    float q = p * r;
+    q = fmaf(fmaf(-s, q, p), r, q);
+    return fmaf(fmaf(-s, q, p), r, q);
+  }
+  return p / sqrtf(d);
 }
 
 __device__ __forceinline__ float sample_A(const MapC& m, float tt, float t0p, float iE, float ca,
