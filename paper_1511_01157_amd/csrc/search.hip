@@ -142,9 +142,12 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 // Each lane takes the points lane, lane + 64, ... in order; the TU trajectories' cells
 // are all located and requested before the first is blended, so a wavefront has TU
 // gathers in flight at a time.  A lane off the map requests cell 0 and takes the
-// single-lens branch, which recomputes the source position from the point's time (the
-// same operations, so the same bits) rather than keeping it live across the gathers:
-// with fewer registers per lane, six wavefronts fit on a SIMD where four did.  Every trajectory's sums see the
+// single-lens branch.  With TU >= 4 registers set the occupancy, so the loop keeps
+// fewer live: no load of the next point ahead, and the single-lens branch recomputes
+// the source position from the point's time (the same operations, so the same bits)
+// rather than keeping it across the gathers; six wavefronts then fit on a SIMD where
+// four did.  With fewer trajectories per wavefront the next point's light-curve values
+// are loaded while the current one is scored.  Every trajectory's sums see the
 // points in the same order for any TU, and wave_sums reduces each over the butterfly
 // tree, so the results do not depend on TU.  Arrays are addressed by 32-bit offsets
 // from uniform bases.
@@ -156,12 +159,12 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
                                             double Fbar, double V, const float (&t0p)[TU],
                                             const TrajC (&c)[TU], int lane, double (&chi2)[TU],
                                             double (&Fs)[TU], double (&Fb)[TU]) {
+  constexpr bool kLean = TU >= 4;
   double acc[3 * TU];  // (B1, B2, C) per trajectory
 #pragma unroll
   for (int q = 0; q < 3 * TU; ++q) acc[q] = 0.0;
-  for (int32_t i0 = lane; i0 < np; i0 += kWave) {
-    const float tt = ldg(t, (uint32_t)i0);
-    const double wv = ldg(w, (uint32_t)i0), fv = ldg(wFc, (uint32_t)i0);
+  // the point (tt, wv, fv) for the TU trajectories
+  auto add_point = [&](float tt, double wv, double fv) {
     Loc l[TU];
     Quad cell[TU];
 #pragma unroll
@@ -175,16 +178,37 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
       const float ax0 = cell[v].v00 + l[v].fx * e0, ax1 = cell[v].v01 + l[v].fx * e1;
       float A = ax0 + l[v].fy * (ax1 - ax0);
       if (!l[v].on) {
-        float tr = tt;
-        asm volatile("" : "+v"(tr));  // opaque copy: the compiler cannot reuse locate's zx, zy
-        const float tau = (tr - t0p[v]) * c[v].iE;
-        A = point_lens_A(tau * c[v].ca + c[v].bx, tau * c[v].sa + c[v].by);
+        if constexpr (kLean) {
+          float tr = tt;
+          asm volatile("" : "+v"(tr));  // opaque copy: the compiler cannot reuse locate's zx, zy
+          const float tau = (tr - t0p[v]) * c[v].iE;
+          A = point_lens_A(tau * c[v].ca + c[v].bx, tau * c[v].sa + c[v].by);
+        } else {
+          A = point_lens_A(l[v].zx, l[v].zy);
+        }
       }
       const double b = (double)A - 1.0;
       const double wb = wv * b;
       acc[3 * v] += wb;
       acc[3 * v + 1] = fma(wb, b, acc[3 * v + 1]);
       acc[3 * v + 2] = fma(b, fv, acc[3 * v + 2]);
+    }
+  };
+  if constexpr (kLean) {
+    for (int32_t i0 = lane; i0 < np; i0 += kWave)
+      add_point(ldg(t, (uint32_t)i0), ldg(w, (uint32_t)i0), ldg(wFc, (uint32_t)i0));
+  } else {  // the next point's light-curve values are loaded while this one is scored
+    uint32_t in = (uint32_t)min(lane, np - 1);
+    float tn = ldg(t, in);
+    double wn = ldg(w, in), fn = ldg(wFc, in);
+    for (int32_t i0 = lane; i0 < np; i0 += kWave) {
+      const float tt = tn;
+      const double wv = wn, fv = fn;
+      in = (uint32_t)min(i0 + kWave, np - 1);  // past the end: the last point, never used
+      tn = ldg(t, in);
+      wn = ldg(w, in);
+      fn = ldg(wFc, in);
+      add_point(tt, wv, fv);
     }
   }
   wave_sums<3 * TU>(acc);
