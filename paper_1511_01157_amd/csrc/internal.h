@@ -50,15 +50,6 @@ struct alignas(16) Quad {
   float v00, v10, v01, v11;
 };
 
-// Load of the cell at byte offset qb (one global_load_dwordx4; see ldg).
-__device__ __forceinline__ Quad ldq(const Quad* __restrict__ base, uint32_t qb) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  typedef const __attribute__((address_space(1))) char gchar;
-  typedef const __attribute__((address_space(1))) f4 gf4;
-  const f4 v = *(gf4*)((gchar*)base + (size_t)qb);
-  return Quad{v.x, v.y, v.z, v.w};
-}
-
 struct MapC {
   const float* map;
   const Quad* quad;
@@ -67,6 +58,22 @@ struct MapC {
   float sx, sy, kx, ky, ox, oy;  // grid coordinate g = (zeta - s) k + o
   float lx, ly;                  // on-map bound: g < M - 1
 };
+// Load of the cell at byte offset qb: one buffer_load_dwordx4 through a raw buffer
+// resource over the map's packed cells.  The resource is uniform (scalar registers) and
+// the offset one 32-bit register, so a load needs no 64-bit address arithmetic, and an
+// offset outside the packed map reads zeros instead of faulting (the hardware range
+// check).  Word 3 of the resource: data format 32 bits (bits 15-18 = 4), nothing else.
+constexpr int kRawBufferWord3 = 0x00020000;
+__device__ __forceinline__ Quad ldq(const MapC& m, uint32_t qb) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  // tiles_x tiles_y 128 < 2^32: the host rejects larger packed maps
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)m.quad, (short)0, (int)(m.tiles_x * m.tiles_y * 128u), kRawBufferWord3);
+  const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)qb, 0, 0);
+  return Quad{__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+              __uint_as_float(v.w)};
+}
+
 // Packed size of a map with mx x my pixels (bytes).
 inline size_t quad_bytes(int32_t mx, int32_t my) {
   return (size_t)((mx - 1 + 3) / 4) * (size_t)((my - 1 + 1) / 2) * 128;
@@ -117,7 +124,7 @@ __device__ __forceinline__ uint32_t cell_offset(const MapC& m, uint32_t i, uint3
 
 __device__ __forceinline__ void map_cell(const MapC& m, float fi, float fj, float& v00, float& v10,
                                          float& v01, float& v11) {
-  const Quad v = ldq(m.quad, cell_offset(m, (uint32_t)(int)fi, (uint32_t)(int)fj));
+  const Quad v = ldq(m, cell_offset(m, (uint32_t)(int)fi, (uint32_t)(int)fj));
   v00 = v.v00;
   v10 = v.v10;
   v01 = v.v01;
@@ -162,7 +169,7 @@ __device__ __forceinline__ Loc locate(const MapC& m, float tt, float t0p, float 
 __device__ __forceinline__ float point_lens_A(float zx, float zy) {
   const float uu = zx * zx + zy * zy;
   const float p = uu + 2.0f, d = uu * (uu + 4.0f);
-  if (__all(d >= 0x1p-60f && d <= 0x1p60f)) {
+  if (__builtin_amdgcn_ballot_w64(!(d >= 0x1p-60f && d <= 0x1p60f)) == 0) {
     float s = __builtin_amdgcn_sqrtf(d);
     const float sdn = __uint_as_float(__float_as_uint(s) - 1u);
     const float sup = __uint_as_float(__float_as_uint(s) + 1u);

@@ -173,20 +173,20 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   constexpr int32_t STEP = GRAD_THREADS;
   auto idx = [&](int32_t j) -> uint32_t { return (uint32_t)(j < np ? j : np - 1); };
   Loc la = locate(m, ldg(t, idx(tid)), t0p, iE, ca, sa, bx, by);
-  Quad va = ldq(m.quad, la.q);
+  Quad va = ldq(m, la.q);
   double wa = ldg(w, idx(tid)), fa = ldg(wFc, idx(tid));
   float ta = ldg(t, idx(tid + STEP));
   for (int32_t i0 = tid; i0 < np; i0 += 2 * STEP) {
     // set b: point i0 + STEP (time ta); time of i0 + 2 STEP
     const float tb = ldg(t, idx(i0 + 2 * STEP));
     const Loc lb = locate(m, ta, t0p, iE, ca, sa, bx, by);
-    const Quad vb = ldq(m.quad, lb.q);
+    const Quad vb = ldq(m, lb.q);
     const double wb = ldg(w, idx(i0 + STEP)), fb = ldg(wFc, idx(i0 + STEP));
     add_point(la, va, wa, fa);
     // set a: point i0 + 2 STEP (time tb); time of i0 + 3 STEP
     ta = ldg(t, idx(i0 + 3 * STEP));
     la = locate(m, tb, t0p, iE, ca, sa, bx, by);
-    va = ldq(m.quad, la.q);
+    va = ldq(m, la.q);
     wa = ldg(w, idx(i0 + 2 * STEP));
     fa = ldg(wFc, idx(i0 + 2 * STEP));
     if (i0 + STEP < np) add_point(lb, vb, wb, fb);

@@ -171,7 +171,7 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
     for (int v = 0; v < TU; ++v)
       l[v] = locate(m, tt, t0p[v], c[v].iE, c[v].ca, c[v].sa, c[v].bx, c[v].by);
 #pragma unroll
-    for (int v = 0; v < TU; ++v) cell[v] = ldq(m.quad, l[v].q);
+    for (int v = 0; v < TU; ++v) cell[v] = ldq(m, l[v].q);
 #pragma unroll
     for (int v = 0; v < TU; ++v) {
       const float e0 = cell[v].v10 - cell[v].v00, e1 = cell[v].v11 - cell[v].v01;

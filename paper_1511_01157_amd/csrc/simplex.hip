@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kItemThreads) void k_line_simplex(SimplexArgs a) {
           const int32_t j = i0 + k * kItemThreads;
           const uint32_t jj = (uint32_t)(j < np ? j : np - 1);
           lc[k] = locate(m, kStaged ? s_t[jj] : ldg(t, jj), t0p, iE, ca, sa, bx, by);
-          q[k] = ldq(m.quad, lc[k].q);
+          q[k] = ldq(m, lc[k].q);
           wv[k] = kStaged ? s_w[jj] : ldg(w, jj);
           fv[k] = kStaged ? s_f[jj] : ldg(wFc, jj);
         }
