@@ -153,7 +153,8 @@ __device__ __forceinline__ Loc locate(const MapC& m, float tt, float t0p, float 
   // a positive bound L, bits(g) < bits(L) iff +0 <= g < L; negative values and NaN
   // have larger patterns).  Only g = -0 would differ, and g is a sum with the nonzero
   // constant o = M/2 - 1/2, which an IEEE sum never rounds to -0.
-  l.on = (__float_as_uint(gx) < __float_as_uint(m.lx)) & (__float_as_uint(gy) < __float_as_uint(m.ly));
+  l.on = ((unsigned)(__float_as_uint(gx) < __float_as_uint(m.lx)) &
+          (unsigned)(__float_as_uint(gy) < __float_as_uint(m.ly))) != 0u;
   // on the map g >= 0, so truncation is the floor and fract(g) = g - floor(g) exactly
   l.fx = __builtin_amdgcn_fractf(gx);
   l.fy = __builtin_amdgcn_fractf(gy);

@@ -135,16 +135,23 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   double acc[kSums];
 #pragma unroll
   for (int q = 0; q < kSums; ++q) acc[q] = 0.0;
-  auto add_point = [&](const Loc& l, const Quad& v, double wi, double wfc) {
+  // The point at time tl: tau and the source position are recomputed from tl (the
+  // same operations as locate, so the same bits) rather than kept live across the
+  // gathers, which keeps the kernel within 96 VGPRs: five wavefronts per SIMD.
+  auto add_point = [&](const Loc& l, float tl, const Quad& v, double wi, double wfc) {
+    float tr = tl;
+    asm volatile("" : "+v"(tr));  // opaque copy: the compiler cannot reuse locate's values
+    const float ltau = (tr - t0p) * iE;
+    const float lzx = ltau * ca + bx, lzy = ltau * sa + by;
     const float e0 = v.v10 - v.v00, e1 = v.v11 - v.v01;
     const float ax0 = v.v00 + l.fx * e0, ax1 = v.v01 + l.fx * e1;
     float A = ax0 + l.fy * (ax1 - ax0);
     double dAx = kx * ((double)e0 + (double)l.fy * ((double)e1 - (double)e0));
     double dAy = ky * ((double)ax1 - (double)ax0);
     if (!l.on) {
-      A = point_lens_A(l.zx, l.zy);
+      A = point_lens_A(lzx, lzy);
       // dA/dzeta = dA/du zeta/u = -8 zeta / (u^2 (u^2+4) sqrt(u^2 (u^2+4)))
-      const double zx = (double)l.zx, zy = (double)l.zy;
+      const double zx = (double)lzx, zy = (double)lzy;
       const double u2 = zx * zx + zy * zy;
       const double pp = u2 * (u2 + 4.0);
       const double f = -8.0 / (pp * sqrt(pp));
@@ -156,9 +163,9 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
     acc[0] += wb;
     acc[1] = fma(wb, b, acc[1]);
     acc[2] = fma(b, wfc, acc[2]);
-    const double tau = (double)l.tau;
+    const double tau = (double)ltau;
     const double D[kDirs] = {dAx, dAy, dAx * tau, dAy * tau,
-                             (double)l.zx * dAy - (double)l.zy * dAx};
+                             (double)lzx * dAy - (double)lzy * dAx};
 #pragma unroll
     for (int k = 0; k < kDirs; ++k) {
       acc[3 + 3 * k] = fma(wi, D[k], acc[3 + 3 * k]);
@@ -172,24 +179,27 @@ __device__ Eval grad_eval(const GradArgs& a, int64_t c, double (*s_part)[kSums])
   // last point and never added.
   constexpr int32_t STEP = GRAD_THREADS;
   auto idx = [&](int32_t j) -> uint32_t { return (uint32_t)(j < np ? j : np - 1); };
-  Loc la = locate(m, ldg(t, idx(tid)), t0p, iE, ca, sa, bx, by);
+  float tla = ldg(t, idx(tid));
+  Loc la = locate(m, tla, t0p, iE, ca, sa, bx, by);
   Quad va = ldq(m, la.q);
   double wa = ldg(w, idx(tid)), fa = ldg(wFc, idx(tid));
   float ta = ldg(t, idx(tid + STEP));
   for (int32_t i0 = tid; i0 < np; i0 += 2 * STEP) {
     // set b: point i0 + STEP (time ta); time of i0 + 2 STEP
     const float tb = ldg(t, idx(i0 + 2 * STEP));
+    const float tlb = ta;
     const Loc lb = locate(m, ta, t0p, iE, ca, sa, bx, by);
     const Quad vb = ldq(m, lb.q);
     const double wb = ldg(w, idx(i0 + STEP)), fb = ldg(wFc, idx(i0 + STEP));
-    add_point(la, va, wa, fa);
+    add_point(la, tla, va, wa, fa);
     // set a: point i0 + 2 STEP (time tb); time of i0 + 3 STEP
     ta = ldg(t, idx(i0 + 3 * STEP));
+    tla = tb;
     la = locate(m, tb, t0p, iE, ca, sa, bx, by);
     va = ldq(m, la.q);
     wa = ldg(w, idx(i0 + 2 * STEP));
     fa = ldg(wFc, idx(i0 + 2 * STEP));
-    if (i0 + STEP < np) add_point(lb, vb, wb, fb);
+    if (i0 + STEP < np) add_point(lb, tlb, vb, wb, fb);
   }
   block_sum<kSums>(acc, s_part);
   const Fit fit = centred_fit(Sw, Fbar, V, acc[0], acc[1], acc[2], fit_terms(np, GRAD_THREADS));
@@ -295,7 +305,9 @@ __global__ void k_cand_prep(GradArgs a) {
 // and share it in the last-level cache.  Without one, XCD x takes the contiguous
 // candidate range [x per, (x + 1) per), so that neighbouring candidates (similar
 // trajectories after a ranked selection) share its L2.
-__global__ __launch_bounds__(GRAD_THREADS) void k_chi2_grad(GradArgs a) {
+// At most 96 VGPRs (five wavefronts per SIMD): the compiler fits the kernel without
+// spilling (four wavefronts measured 2% slower).
+__global__ __launch_bounds__(GRAD_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_chi2_grad(GradArgs a) {
   __shared__ double s_part[GRAD_THREADS / kWave][kSums];
   const int64_t per = (a.n + 7) / 8;
   for (int64_t slot = blockIdx.x; slot < 8 * per; slot += gridDim.x) {
