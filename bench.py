@@ -66,17 +66,17 @@ def peak_for(ops):
 
 # HBM-side traffic per launch (bytes) of a kernel on a workload, from two rocprofv3
 # --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
-# by what the same counter reads for a 1 GiB device-to-device copy (FETCH_SIZE 524301
-# KiB: factor 1.99995; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
+# by what the same counter reads for a 1 GiB device-to-device copy (FETCH_SIZE at most
+# 524308 KiB: factor 1.99992; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
 # hash of the sources it is built from and the workload; a changed kernel reports null
 # until it is measured again.  Batched-events workload: the search's full launch
-# (FETCH 2.47754e+09 KiB, WRITE 1.9785e+07 KiB), the gradient's full 262144-candidate
-# launch (9.62285e+06, 14768.2 KiB) and the mean over the two map sizes of the ray kernel
-# (FETCH 241.1 and 238.92 KiB, WRITE 68854.7 and 17281.9 KiB).
+# (FETCH 2.76208e+09 KiB, WRITE 1.96708e+07 KiB), the gradient's full 262144-candidate
+# launch (1.00355e+07, 14766.5 KiB) and the mean over the two map sizes of the ray kernel
+# (FETCH 241.1 and 238.94 KiB, WRITE 68854.7 and 17281.9 KiB).
 TRAFFIC = {
-    ("k_search_batched", "1394b93c19e6dbc0", "batched"): 5.094064e+12,
-    ("k_chi2_grad", "c0d1ad21a75a5227", "batched"): 1.972198e+10,
-    ("k_rayshoot", "51e4a7ca1cbf207e", "batched"): 4.459342e+07,
+    ("k_search_batched", "f7e9409ef6623e40", "batched"): 5.676662e+12,
+    ("k_chi2_grad", "98c959850a2a8b8a", "batched"): 2.056695e+10,
+    ("k_rayshoot", "3a11ac46994ec86d", "batched"): 4.459343e+07,
 }
 STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
 STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
