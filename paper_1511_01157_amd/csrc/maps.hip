@@ -249,7 +249,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
 // on the host; neighbours clamp to the edge; acc accumulates the terms w[k] * count in
 // tap order in binary32 (the first term alone, then one addition per tap) and
 // A = acc * scale.  The kernels also reduce the largest count of the map (one atomic
-// per workgroup).  Two forms of the same arithmetic:
+// per workgroup).  Three forms of the same arithmetic:
 //   * one tap at offset (0, 0) (a point source): elementwise, four pixels per thread
 //     with 16-byte loads and stores;
 //   * a stencil of half-width at most kNcHalo: a workgroup stages a 64 x 32 output tile
@@ -257,8 +257,18 @@ __global__ __launch_bounds__(RS_THREADS) void k_rayshoot(RayParams p, uint32_t* 
 //     conversion every term applies), then each wave sweeps whole 64-pixel rows, so LDS
 //     reads are consecutive and stores 256 B per row; each wave issues all its staging
 //     loads (whole tile rows) before the first LDS store.  The tap builders cap the
-//     half-width at 15 pixels.
+//     half-width at 15 pixels;
+//   * a stencil of reach at most one pixel (3 x 3) on a map whose width is a multiple
+//     of 4 with 16-byte aligned buffers: no LDS.  A wavefront takes kR1Cols = 256
+//     columns (four per lane, 16-byte loads and stores) and kR1Rows rows, loading the
+//     rows y0 - 1 .. y0 + kR1Rows (clamped) and, by scalar loads, the column on each
+//     side of its 256; a lane's outer neighbours come from the adjacent lanes by DPP
+//     wavefront shifts, the wavefront's outer lanes taking the side columns.  The terms are added in raster order over the 3 x 3 neighbourhood with a
+//     zero weight where the tap list has no tap: that is the tap order, and a zero term
+//     (0 * count = +0) leaves a sum of non-negative terms unchanged, so the arithmetic
+//     is that of the tap list.
 constexpr int kNcTw = 64, kNcTh = 32, kNcHalo = 16;
+constexpr int kR1Cols = 256, kR1Rows = 8;
 
 __device__ __forceinline__ void nc_block_max(uint32_t cmax, uint32_t* maxc) {
   __shared__ uint32_t s_max[4];
@@ -350,6 +360,99 @@ __global__ __launch_bounds__(256) void k_normalize_convolve_lds(
   for (int r = 0; r < kRows; ++r) {
     const int gy = y0 + wave + 4 * r;
     if (gx < mx && gy < my) map[(size_t)gy * mx + gx] = acc[r] * scale;
+  }
+  nc_block_max(cmax, maxc);
+}
+
+// v of lane l - 1 (lane 0 takes lo) and of lane l + 1 (lane 63 takes hi), by DPP
+// wavefront shifts.
+__device__ __forceinline__ float from_lane_below(float v, float lo) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(lo), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_lane_above(float v, float hi) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(hi), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+__global__ __launch_bounds__(256) void k_normalize_convolve_r1(
+    const uint32_t* __restrict__ counts, float* __restrict__ map, int32_t mx, int32_t my,
+    const float* __restrict__ w, const int32_t* __restrict__ off, int32_t ntaps, float scale,
+    uint32_t* __restrict__ maxc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ncx = (mx + kR1Cols - 1) / kR1Cols;
+  // the wave's index, read from the first lane so that everything derived from it (tile
+  // origin, row offsets, the neighbouring columns' loads) stays in scalar registers;
+  // 32-bit arithmetic: the launcher admits maps below 2^30 pixels
+  const int item = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int x0 = item % ncx * kR1Cols;
+  const int y0 = item / ncx * kR1Rows;
+  uint32_t cmax = 0;
+  if (y0 < my) {  // uniform per wave (the last workgroup's waves may lie past the map)
+    // the 3 x 3 weights in raster order (uniform), zero where there is no tap
+    float W[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) W[i] = 0.0f;
+    for (int k = 0; k < ntaps; ++k) {
+      const int i = (off[2 * k + 1] + 1) * 3 + off[2 * k] + 1;
+      const float wk = w[k];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) W[j] = j == i ? wk : W[j];
+    }
+    const int xq = x0 + 4 * lane;  // the lane's four columns xq .. xq + 3
+    const bool own = xq < mx;      // mx % 4 == 0: a quad lies wholly inside or outside
+    const bool has_right = xq + 4 < mx;
+    const uint32_t qx = (uint32_t)min(xq, mx - 4);
+    // the columns beside the wavefront's 256, clamped to the map (uniform: scalar loads)
+    const uint32_t hl = (uint32_t)max(x0 - 1, 0), hr = (uint32_t)min(x0 + kR1Cols, mx - 1);
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 q[kR1Rows + 2];  // all the rows' loads in flight before the first use
+    uint32_t ql[kR1Rows + 2], qr[kR1Rows + 2];
+#pragma unroll
+    for (int r = 0; r < kR1Rows + 2; ++r) {
+      const uint32_t row = (uint32_t)min(max(y0 - 1 + r, 0), my - 1) * (uint32_t)mx;
+      q[r] = ldg(reinterpret_cast<const u4*>(counts), (row + qx) >> 2);
+      ql[r] = counts[row + hl];
+      qr[r] = counts[row + hr];
+    }
+    // per row: the lane's four values and their outer neighbours (the left one of column
+    // 0 is column 0 itself through the clamped load; the right one of column mx - 1 is
+    // column mx - 1 itself)
+    float V[kR1Rows + 2][6];
+#pragma unroll
+    for (int r = 0; r < kR1Rows + 2; ++r) {
+      V[r][1] = (float)q[r].x;
+      V[r][2] = (float)q[r].y;
+      V[r][3] = (float)q[r].z;
+      V[r][4] = (float)q[r].w;
+      V[r][0] = from_lane_below(V[r][4], (float)ql[r]);
+      const float rn = from_lane_above(V[r][1], (float)qr[r]);
+      V[r][5] = has_right ? rn : V[r][4];
+    }
+#pragma unroll
+    for (int r = 0; r < kR1Rows; ++r) {
+      float o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {  // column xq + j: values V[.][j .. j + 2]
+        float acc = W[0] * V[r][j];
+        acc = acc + W[1] * V[r][j + 1];
+        acc = acc + W[2] * V[r][j + 2];
+        acc = acc + W[3] * V[r + 1][j];
+        acc = acc + W[4] * V[r + 1][j + 1];
+        acc = acc + W[5] * V[r + 1][j + 2];
+        acc = acc + W[6] * V[r + 2][j];
+        acc = acc + W[7] * V[r + 2][j + 1];
+        acc = acc + W[8] * V[r + 2][j + 2];
+        o[j] = acc * scale;
+      }
+      const int y = y0 + r;
+      if (own && y < my) {
+        reinterpret_cast<float4*>(map)[((uint32_t)y * (uint32_t)mx + (uint32_t)xq) >> 2] =
+            make_float4(o[0], o[1], o[2], o[3]);
+        const u4 c = q[r + 1];
+        cmax = max(cmax, max(max(c.x, c.y), max(c.z, c.w)));
+      }
+    }
   }
   nc_block_max(cmax, maxc);
 }
@@ -488,6 +591,12 @@ hipError_t launch_normalize_convolve(const uint32_t* counts, float* map, int32_t
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(k_normalize_point, dim3((unsigned)blocks), dim3(256), 0, st, counts, map, npx,
                        vec4, d_w, scale, d_maxc);
+  } else if (rx <= 1 && ry <= 1 && (int64_t)mx * my < ((int64_t)1 << 30) && mx % 4 == 0 &&
+             ((uintptr_t)counts % 16) == 0 && ((uintptr_t)map % 16) == 0) {
+    if (ntaps > 9) return hipErrorInvalidValue;
+    const int64_t waves = (int64_t)((mx + kR1Cols - 1) / kR1Cols) * ((my + kR1Rows - 1) / kR1Rows);
+    hipLaunchKernelGGL(k_normalize_convolve_r1, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st,
+                       counts, map, mx, my, d_w, d_off, ntaps, scale, d_maxc);
   } else {
     if (rx > kNcHalo || ry > kNcHalo) return hipErrorInvalidValue;
     const size_t lds = sizeof(float) * (kNcTw + 2 * rx) * (kNcTh + 2 * ry);

@@ -154,6 +154,31 @@ def test_build_map_ragged_tiles_bit_exact(window, rho, shift):
     assert np.array_equal(A, B)
 
 
+@pytest.mark.parametrize("window,rho,shift", [
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.005, 0),   # 3 x 3, nine taps, ragged wavefront tiles
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.0033, 1),  # 3 x 3, five taps, buffers 4 B off 16
+    ((0.0, 0.0, 0.2, 2.0, 8, 70), 0.02, 0),         # narrower than one wavefront's columns
+    ((0.0, 0.0, 2.0, 5.0, 100, 100), 0.015, 0),     # reach 1 in x, 0 in y
+    ((0.1, -0.05, 2.0, 1.3, 334, 218), 0.02, 0)])   # 7 x 7: the LDS-tiled kernel
+def test_normalize_bitwise_with_the_library_weights(window, rho, shift):
+    """Every pixel bit for bit against the binary32 mirror run with the library's own
+    FP64 weights: the taps' order, their offsets' directions and the edge clamp."""
+    s, q, rays = 1.0, 1e-3, (0.0, 0.0, 4.0, 4.0, 1600, 1600)
+    note(f"normalize bitwise window={window} rho={rho} shift={shift}")
+    o, _ = rayshoot_mirror32_c(s, q, rays, window, nthreads=8)
+    npx = window[4] * window[5]
+    cbuf = torch.empty(npx + 4, dtype=torch.int32, device=DEV)
+    abuf = torch.empty(npx + 4, dtype=torch.float32, device=DEV)
+    cnt = cbuf[shift:shift + npx].view(window[5], window[4])
+    out = abuf[shift:shift + npx].view(window[5], window[4])
+    cnt.copy_(torch.from_numpy(o.view(np.int32)))
+    M.normalize_convolve(cnt, rays, window, rho, out=out)
+    w = M.profile_weights(rho, window[2] / window[4], window[3] / window[5], 0.0)
+    ref32 = normalize_convolve_mirror32(o, map_scale(rays, window), w)
+    A = out.cpu().numpy()
+    assert np.array_equal(A, ref32), int(np.count_nonzero(A != ref32))
+
+
 def test_build_map_rejects_bad_arguments():
     note("build_map argument errors")
     with pytest.raises(M.MorseError) as e:
