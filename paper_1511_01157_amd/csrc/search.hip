@@ -144,9 +144,8 @@ __global__ void k_traj_prep_grid(const double* __restrict__ axes, int32_t nu, in
 // gathers in flight at a time.  A lane off the map requests cell 0 and takes the
 // single-lens branch.  With TU >= 4 registers set the occupancy, so the loop keeps
 // fewer live: no load of the next point ahead, and the single-lens branch recomputes
-// the source position from the point's time (the same operations, so the same bits)
-// rather than keeping it across the gathers; six wavefronts then fit on a SIMD where
-// four did.  With fewer trajectories per wavefront the next point's light-curve values
+// the source position from tau (the same operations, so the same bits) rather than
+// keeping it across the gathers; six wavefronts then fit on a SIMD where four did.  With fewer trajectories per wavefront the next point's light-curve values
 // are loaded while the current one is scored.  Every trajectory's sums see the
 // points in the same order for any TU, and wave_sums reduces each over the butterfly
 // tree, so the results do not depend on TU.  Arrays are addressed by 32-bit offsets
@@ -174,14 +173,17 @@ __device__ __forceinline__ void score_group(const MapC& m, const float* __restri
     for (int v = 0; v < TU; ++v) cell[v] = ldq(m, l[v].q);
 #pragma unroll
     for (int v = 0; v < TU; ++v) {
-      const float e0 = cell[v].v10 - cell[v].v00, e1 = cell[v].v11 - cell[v].v01;
-      const float ax0 = cell[v].v00 + l[v].fx * e0, ax1 = cell[v].v01 + l[v].fx * e1;
-      float A = ax0 + l[v].fy * (ax1 - ax0);
+      float A = 0.0f;
+      // with TU >= 4 a wavefront whose lanes are all off the map skips the interpolation
+      if (!kLean || __builtin_amdgcn_ballot_w64(l[v].on) != 0) {
+        const float e0 = cell[v].v10 - cell[v].v00, e1 = cell[v].v11 - cell[v].v01;
+        const float ax0 = cell[v].v00 + l[v].fx * e0, ax1 = cell[v].v01 + l[v].fx * e1;
+        A = ax0 + l[v].fy * (ax1 - ax0);
+      }
       if (!l[v].on) {
         if constexpr (kLean) {
-          float tr = tt;
-          asm volatile("" : "+v"(tr));  // opaque copy: the compiler cannot reuse locate's zx, zy
-          const float tau = (tr - t0p[v]) * c[v].iE;
+          float tau = l[v].tau;
+          asm volatile("" : "+v"(tau));  // opaque copy: the compiler cannot reuse locate's zx, zy
           A = point_lens_A(tau * c[v].ca + c[v].bx, tau * c[v].sa + c[v].by);
         } else {
           A = point_lens_A(l[v].zx, l[v].zy);
