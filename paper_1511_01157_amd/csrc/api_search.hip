@@ -18,13 +18,23 @@ struct TuneCfg {
 // Candidate shapes of the batched search tried by the autotuner; index 0 is the
 // default before tuning.  traj_per_item = trajectories per wavefront work item,
 // tu = trajectories scored together by one wavefront (sharing light-curve loads).
-const TuneCfg kTune[] = {
+constexpr TuneCfg kTune[] = {
     {8, 4, 16, 2},  {8, 4, 16, 1},  {16, 4, 16, 2}, {8, 8, 8, 2},
     {32, 8, 8, 2},  {4, 4, 16, 2},  {16, 8, 4, 4},  {8, 2, 32, 2},
     {16, 4, 16, 4}, {32, 8, 8, 1},  {8, 2, 32, 1},  {64, 4, 8, 4},
     {32, 8, 4, 4},  {16, 4, 8, 4},  {8, 8, 4, 4},   {16, 8, 2, 4},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
+// k_search_batched is compiled for at most 512 lanes (8 wavefronts) per workgroup and
+// instantiated for TU = 1, 2 and 4; a shape outside that would not launch.
+constexpr bool tune_shapes_valid() {
+  for (const TuneCfg& c : kTune)
+    if (c.waves_per_block < 1 || c.waves_per_block > 8 || c.blocks_per_cu < 1 ||
+        c.traj_per_item < 1 || !(c.tu == 1 || c.tu == 2 || c.tu == 4))
+      return false;
+  return true;
+}
+static_assert(tune_shapes_valid(), "a batched-search shape the kernel cannot launch");
 
 
 }  // namespace
