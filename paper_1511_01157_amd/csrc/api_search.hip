@@ -18,11 +18,14 @@ struct TuneCfg {
 // Candidate shapes of the batched search tried by the autotuner; index 0 is the
 // default before tuning.  traj_per_item = trajectories per wavefront work item,
 // tu = trajectories scored together by one wavefront (sharing light-curve loads).
+// The last two take one TU group per item (traj_per_item = tu), the fastest shapes on
+// batches of many events and maps.
 constexpr TuneCfg kTune[] = {
     {8, 4, 16, 2},  {8, 4, 16, 1},  {16, 4, 16, 2}, {8, 8, 8, 2},
     {32, 8, 8, 2},  {4, 4, 16, 2},  {16, 8, 4, 4},  {8, 2, 32, 2},
     {16, 4, 16, 4}, {32, 8, 8, 1},  {8, 2, 32, 1},  {64, 4, 8, 4},
     {32, 8, 4, 4},  {16, 4, 8, 4},  {8, 8, 4, 4},   {16, 8, 2, 4},
+    {4, 8, 4, 4},   {4, 4, 8, 4},
 };
 constexpr int kNumTune = sizeof(kTune) / sizeof(kTune[0]);
 // k_search_batched is compiled for at most 512 lanes (8 wavefronts) per workgroup and
