@@ -625,9 +625,14 @@ def leg_sqgrid(args, M, W, torch, np, dev):
 # one line-filter sample = tau 2, position 2, zeta 4, grid coordinates 4, on-map tests
 # 4, floor/fraction 4, cell index 3, bilinear blend 9, max 1 (binary32/integer); one
 # point of a simplex chi-square evaluation = the search's sample (32) + b, w b and the
-# three FP64 sums (6).
+# three FP64 sums (6); one lens-equation sample of the image-centred integration (FP64)
+# = radius 2, position 2, offsets from the lenses 2, y^2 1, two squared distances 4,
+# two divisions 2, the image position 10, squared distance to the source 3, the limb
+# test 2.
 OPS_PER_FILTER_SAMPLE = (33, 0)
 OPS_PER_SIMPLEX_POINT = (32, 6)
+OPS_PER_FS_SAMPLE = (0, 28)
+FS_THETA, FS_R, FS_SHRINK = 512, 512, 2   # the library's image-centred grid and passes
 
 
 def fft_passes(n):
@@ -1009,11 +1014,24 @@ def leg_large(args, M, W, torch, np, dev):
         torch.cuda.synchronize()
         tr_ms = e0.elapsed_time(e1) / 3
         nt = nreg_t.cpu().numpy()
+        # the image-centred integration's lens-equation samples: at most 1 + n_shrink
+        # passes of n_theta x (n_r + 1) per region (the library's defaults)
+        fs_samples = float(nt[nt > 0].sum()) * (1 + FS_SHRINK) * FS_THETA * (FS_R + 1)
+        f_ops = fs_samples * sum(OPS_PER_FS_SAMPLE) / (tr_ms * 1e-3) / 1e12
+        f_pk = peak_for(OPS_PER_FS_SAMPLE) / 1e12
         rec["fs_lightcurve"]["caustic_crossing_trial"] = {
             "params_t0_u0_tE_alpha": list(trial), "gamma": STACK_GAMMA, "ms": tr_ms,
             "epochs_per_s": len(nt) / (tr_ms * 1e-3), "image_centred_epochs": int((nt > 0).sum()),
+            "regions": int(nt[nt > 0].sum()),
             "point_source_epochs": int((nt == -1).sum()), "failed_epochs": int((nt < -1).sum()),
-            "A_max": float(A_t.max())}
+            "A_max": float(A_t.max()),
+            "roofline": {"bound": "alu", "achieved": f_ops, "peak": f_pk, "unit": "TFLOP/s",
+                         "frac": f_ops / f_pk, "ops_per_unit_f32_f64": OPS_PER_FS_SAMPLE,
+                         "ops_are_upper_bound": True, "traffic": None,
+                         "note": "tera lane-operations/s of the image-centred integration's "
+                                 "lens-equation samples (at most 1 + n_shrink passes per region) "
+                                 "over the whole light-curve call, which also classifies the "
+                                 "epochs, solves the far ones and builds the regions"}}
         fs_info = dict(zeta=(np.asarray(ev["t"]) - tr["t0"]) / tr["tE"], nreg=nr_np, truth=tr,
                        trial=dict(tr, u0=0.0), nreg_trial=nt)
         beside = dict(c=c, ev=ev, rhos=rhos, gamma=STACK_GAMMA, r=r_ax, phi=phi, a_min=a_min, fs=fs_info,

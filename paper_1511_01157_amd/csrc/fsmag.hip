@@ -61,6 +61,18 @@ __device__ __forceinline__ cd lens_eq(const Lens& L, cd z) {
   return csub(csub(z, cscale(crecip(w1), L.m1)), cscale(crecip(w2), L.m2));
 }
 
+// |zeta(z) - zs|^2 by Eq. 2 with each lens term written as m_k (z - x_k) / |z - x_k|^2,
+// the conjugate's reciprocal: one division per lens and no square root (the samples of
+// the image-centred integration and the growth test; a sample on a lens gives inf or
+// NaN, which compare as outside the source).
+__device__ __forceinline__ double lens_dist2(const Lens& L, cd z, cd zs) {
+  const double d1 = z.x - L.x1, d2 = z.x - L.x2, yy = z.y * z.y;
+  const double a1 = L.m1 / (d1 * d1 + yy), a2 = L.m2 / (d2 * d2 + yy);
+  const double ex = ((z.x - a1 * d1) - a2 * d2) - zs.x;
+  const double ey = ((z.y - a1 * z.y) - a2 * z.y) - zs.y;
+  return ex * ex + ey * ey;
+}
+
 // The quintic whose roots contain the images of zeta.  With Q = (z - x1)(z - x2) and
 // P_k = (conj zeta - x_k) Q + m1 (z - x2) + m2 (z - x1) (so 1/(conj z - x_k) = Q/P_k on
 // an image, from the conjugate of Eq. 2), Eq. 2 times P1 P2 reads
@@ -257,7 +269,7 @@ __device__ void bitonic(double* key, double* v1, double* v2) {
 }
 
 __device__ __forceinline__ bool inside_source(const Lens& L, cd z, cd zs, double rho) {
-  return cabs(csub(lens_eq(L, z), zs)) < rho;
+  return lens_dist2(L, z, zs) < rho * rho;
 }
 
 // numpy.linspace(a, b, n)[k]
@@ -317,8 +329,7 @@ __device__ double integrate_region(const FsArgs& a, const Lens& L, cd zs, const 
     bool any = false;
     for (int k = 0; k <= a.n_r; ++k) {
       const double r = g.r0 + k * dr;
-      const double d = cabs(csub(lens_eq(L, cd{r * cs, r * sn}), zs));
-      const double f = rho2 - d * d;
+      const double f = rho2 - lens_dist2(L, cd{r * cs, r * sn}, zs);
       if (f > 0.0) {
         any = true;
         k0 = min(k0, k);
