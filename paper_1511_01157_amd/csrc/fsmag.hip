@@ -41,7 +41,14 @@ __device__ __forceinline__ cd csub(cd a, cd b) { return {a.x - b.x, a.y - b.y}; 
 __device__ __forceinline__ cd cmul(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ cd cscale(cd a, double s) { return {a.x * s, a.y * s}; }
 __device__ __forceinline__ double cabs(cd a) { return hypot(a.x, a.y); }
-__device__ __forceinline__ cd cdivc(cd a, cd b) {  // a / b, scaled (Smith)
+// a / b: directly as a conj(b) / |b|^2 while |b|^2 stays well inside the FP64 range,
+// else scaled (Smith).
+__device__ __forceinline__ cd cdivc(cd a, cd b) {
+  const double n = b.x * b.x + b.y * b.y;
+  if (n > 1e-280 && n < 1e280) {
+    const double s = 1.0 / n;
+    return {(a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s};
+  }
   if (fabs(b.x) >= fabs(b.y)) {
     const double r = b.y / b.x, d = b.x + b.y * r;
     return {(a.x + a.y * r) / d, (a.y - a.x * r) / d};
