@@ -70,13 +70,13 @@ def peak_for(ops):
 # 524308 KiB: factor 1.99992; WRITE_SIZE 1048576 KiB: factor 1.0).  Keyed by the kernel, a
 # hash of the sources it is built from and the workload; a changed kernel reports null
 # until it is measured again.  Batched-events workload: the search's full launch
-# (FETCH 9.40986e+08 KiB, WRITE 2.32676e+07 KiB), the gradient's full 262144-candidate
-# launch (1.00127e+07, 14767.1 KiB) and the mean over the two map sizes of the ray kernel
-# (FETCH 241.07 and 238.91 KiB, WRITE 68854.7 and 17281.9 KiB).
+# (FETCH 9.41794e+08 KiB, WRITE 2.32661e+07 KiB), the gradient's full 262144-candidate
+# launch (1.00305e+07, 14766.7 KiB) and the mean over the two map sizes of the ray kernel
+# (FETCH 241.05 and 238.9 KiB, WRITE 68854.7 and 17281.9 KiB).
 TRAFFIC = {
-    ("k_search_batched", "95093939f55768c2", "batched"): 1.950890e+12,
-    ("k_chi2_grad", "98c959850a2a8b8a", "batched"): 2.052039e+10,
-    ("k_rayshoot", "eae3ebd5e214d8e9", "batched"): 4.459338e+07,
+    ("k_search_batched", "95093939f55768c2", "batched"): 1.952545e+12,
+    ("k_chi2_grad", "98c959850a2a8b8a", "batched"): 2.055676e+10,
+    ("k_rayshoot", "eae3ebd5e214d8e9", "batched"): 4.459335e+07,
 }
 STACK_GAMMA = 0.53        # limb-darkening coefficient of the finite-source stack
 STACK_FFT_MIN_TAPS = 256  # the library's default split between direct sums and transforms
