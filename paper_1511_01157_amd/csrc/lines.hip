@@ -26,6 +26,13 @@ constexpr int kCompactThreads = 256;
 constexpr int kCompactPer = 4;  // flags per thread
 constexpr int kCompactBlock = kCompactThreads * kCompactPer;
 
+constexpr float kInf = __builtin_inff();
+
+// lane j's value, the same in every lane (j uniform)
+__device__ __forceinline__ float lane_at(float v, int32_t j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
 // max that propagates NaN (as a maximum over an array does)
 __device__ __forceinline__ float nanmax(float a, float b) {
   if (a != a) return a;
@@ -59,11 +66,32 @@ __global__ __launch_bounds__(kFilterThreads) void k_line_filter(LineFilterArgs a
   }
 }
 
+// Inclusive prefix over the wavefront's lanes (Hillis-Steele): lane j gets the
+// combination of lanes 0..j.  kMin keeps the left value unless the right is smaller,
+// otherwise unless the right is larger, so among equal values the leftmost survives;
+// the keys hold no NaN, which makes either combination associative.
+template <bool kMin>
+__device__ __forceinline__ float lane_prefix(float x, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const float l = __shfl_up(x, d);
+    if (lane >= d) x = (kMin ? (x < l) : (x > l)) ? x : l;
+  }
+  return x;
+}
+
 // Peak library.  One wavefront per line (one per workgroup): each chunk of 64 samples is
-// computed lane-parallel exactly as in the filter, then every lane scans the chunk in
-// order (the values broadcast by readlane), so the scan state stays uniform.  A peak is
-// a rise above fl32(trough * up) followed by a fall below fl32(top * down); the first
-// sample starts the first trough; equal maxima keep the first.
+// computed lane-parallel exactly as in the filter.  A peak is a rise above fl32(trough *
+// up) followed by a fall below fl32(top * down); the first sample starts the first
+// trough; equal maxima keep the first.  The rule is a left-to-right scan, but between
+// two of its events (a rise, a fall) the state changes only by a running minimum (the
+// trough) or a running maximum (the top and its index), so each chunk is taken one
+// event at a time: a prefix minimum or maximum over the lanes gives every sample the
+// trough or top the scan would hold before it, the first lane whose sample rises or
+// falls against that value (found by ballot) is the next event, and the scan resumes
+// after it.  A chunk costs one prefix per event plus one, not one step per sample.  NaN
+// samples neither lower the trough, raise the top nor trigger an event, as in the
+// scan; a NaN first sample leaves the trough NaN and the line without peaks.
 __global__ __launch_bounds__(kWave) void k_line_peaks(LinePeakArgs a) {
   const LineFilterArgs& f = a.f;
   const int lane = threadIdx.x;
@@ -88,30 +116,56 @@ __global__ __launch_bounds__(kWave) void k_line_peaks(LinePeakArgs a) {
         best = nanmax(best, A);
       }
       const int32_t nk = min(kWave, f.ns - c0);
-      for (int32_t j = 0; j < nk; ++j) {
-        const float v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A), j));
-        const int32_t i = c0 + j;
-        if (i == 0) {
-          trough = v;
-        } else if (!rising) {
-          if (v < trough) {
-            trough = v;
-          } else if (v > trough * a.up) {
-            rising = true;
-            top = v;
-            top_i = i;
+      int32_t s = 0;  // first sample of the chunk not yet scanned
+      if (c0 == 0) {
+        trough = lane_at(A, 0);
+        s = 1;
+      }
+      const bool real = lane < nk && A == A;
+      while (s < nk) {
+        const bool act = lane >= s && lane < nk;
+        if (!rising) {
+          if (trough != trough) break;  // no sample compares with a NaN trough
+          const float p = lane_prefix<true>(act && real ? A : kInf, lane);
+          float T = __shfl_up(p, 1);
+          if (lane == 0) T = kInf;
+          T = T < trough ? T : trough;  // the trough before this lane's sample
+          const uint64_t ev = __builtin_amdgcn_ballot_w64(act && !(A < T) && A > T * a.up);
+          if (ev == 0) {
+            const float m = lane_at(p, nk - 1);
+            if (m < trough) trough = m;
+            break;
           }
-        } else if (v > top) {
-          top = v;
-          top_i = i;
-        } else if (v < top * a.down) {
+          const int32_t j = __builtin_ctzll(ev);
+          top = lane_at(A, j);
+          top_i = c0 + j;
+          rising = true;
+          s = j + 1;
+        } else {
+          const float p = lane_prefix<false>(act && real ? A : -kInf, lane);
+          float T = __shfl_up(p, 1);
+          if (lane == 0) T = -kInf;
+          T = T > top ? T : top;  // the top before this lane's sample
+          const uint64_t ev = __builtin_amdgcn_ballot_w64(act && !(A > T) && A < T * a.down);
+          const int32_t end = ev ? __builtin_ctzll(ev) : nk;  // samples s .. end-1 precede it
+          if (end > s) {
+            const float m = lane_at(p, end - 1);
+            if (m > top) {  // the first sample equal to the new maximum
+              const int32_t j = __builtin_ctzll(
+                  __builtin_amdgcn_ballot_w64(lane >= s && lane < end && A == m));
+              top = lane_at(A, j);
+              top_i = c0 + j;
+            }
+          }
+          if (ev == 0) break;
           if (lane == 0 && count < a.kmax) {
             a.ptau[l * a.kmax + count] = lo + (float)top_i * f.h;
             a.pA[l * a.kmax + count] = top;
           }
           ++count;
           rising = false;
-          trough = v;
+          trough = lane_at(A, end);
+          s = end + 1;
         }
       }
     }

@@ -120,6 +120,25 @@ def test_peak_library_tiny_map(h):
         assert np.array_equal(st[~np.isnan(st)], ost[~np.isnan(ost)])
 
 
+def test_peak_library_nan_patches_and_plateaus():
+    """Samples that are NaN neither lower the trough, raise the top nor end a rise, and
+    equal maxima keep the first; a plateau and NaN patches planted in the tiny map put
+    both inside rises and troughs of many lines."""
+    c = W.config("tiny")
+    note("peaks: tiny oracle map with NaN patches and plateaus")
+    _, _, amap = oracle_map(c["s"], c["q"], c["rays"], c["window"], 0.0)
+    amap = np.array(amap, dtype=np.float32)
+    ny, nx = amap.shape
+    amap[ny // 2 - 3:ny // 2 + 3, nx // 3:nx // 3 + 5] = np.nan
+    amap[ny // 4:ny // 4 + 2, :] = np.nan
+    amap[3 * ny // 4:3 * ny // 4 + 6, nx // 2 - 8:nx // 2 + 8] = np.float32(7.5)
+    caus = M.caustics(c["s"], c["q"])
+    lines = caustic_lines(caus, np.array([0.0, 0.3, 1.0]), np.linspace(0.0, 2 * np.pi, 41)[:-1])
+    for h in (0.0, 0.05):
+        _, npk, _, _, _, (oc, _, _) = peaks_case(amap, c["window"], lines, 2.0, 1, h, 8)
+        assert oc.max() >= 2
+
+
 def test_peak_library_large_map_and_simplex_from_peak_starts():
     c = W.config("large")
     win = c["window"]
