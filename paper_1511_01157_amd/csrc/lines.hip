@@ -80,7 +80,7 @@ __device__ __forceinline__ float lane_prefix(float x, int lane) {
   return x;
 }
 
-// Peak library.  One wavefront per line (one per workgroup): each chunk of 64 samples is
+// Peak library.  One wavefront per line (four per workgroup): each chunk of 64 samples is
 // computed lane-parallel exactly as in the filter.  A peak is a rise above fl32(trough *
 // up) followed by a fall below fl32(top * down); the first sample starts the first
 // trough; equal maxima keep the first.  The rule is a left-to-right scan, but between
@@ -92,11 +92,13 @@ __device__ __forceinline__ float lane_prefix(float x, int lane) {
 // after it.  A chunk costs one prefix per event plus one, not one step per sample.  NaN
 // samples neither lower the trough, raise the top nor trigger an event, as in the
 // scan; a NaN first sample leaves the trough NaN and the line without peaks.
-__global__ __launch_bounds__(kWave) void k_line_peaks(LinePeakArgs a) {
+__global__ __launch_bounds__(kFilterThreads) void k_line_peaks(LinePeakArgs a) {
   const LineFilterArgs& f = a.f;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = (int64_t)gridDim.x * (kFilterThreads / kWave);
   const float nan = __builtin_nanf("");
-  for (int64_t l = blockIdx.x; l < f.n; l += gridDim.x) {
+  for (int64_t l = blockIdx.x * (int64_t)(kFilterThreads / kWave) + threadIdx.x / kWave; l < f.n;
+       l += waves) {
     const double u0 = f.lines[3 * l], al = f.lines[3 * l + 1];
     double sn, cn;
     sincos(al, &sn, &cn);
@@ -318,8 +320,10 @@ hipError_t launch_line_peaks(const LinePeakArgs& a, hipStream_t st) {
   if (!a.f.lines || !a.f.best || !a.f.keep || !a.npeaks || !a.ptau || !a.pA || a.f.ns < 2 ||
       !a.f.m.quad || a.kmax < 1)
     return hipErrorInvalidValue;
-  const int64_t blocks = a.f.n < (1 << 20) ? a.f.n : (1 << 20);
-  hipLaunchKernelGGL(k_line_peaks, dim3((unsigned)blocks), dim3(kWave), 0, st, a);
+  const int64_t per_block = kFilterThreads / kWave;
+  int64_t blocks = (a.f.n + per_block - 1) / per_block;
+  if (blocks > (1 << 20)) blocks = 1 << 20;
+  hipLaunchKernelGGL(k_line_peaks, dim3((unsigned)blocks), dim3(kFilterThreads), 0, st, a);
   return hipGetLastError();
 }
 
